@@ -1,0 +1,87 @@
+"""Multilevel Monte Carlo estimator (paper section 3) -- TEST INFRASTRUCTURE ONLY.
+
+  Y_l^(i) = g_l^(i) - g_{l-1}^(i), same random input on both grids, g_{-1} = 0
+  estimate of E[g_L] = sum_l mean_i Y_l^(i)                     (eqs. EgL and A)
+  V_l = unbiased sample variance of Y_l,  Var[Y] = sum_l V_l / m_l  (eq. goal_variance)
+  cost S = sum_l m_l s_l
+  optimal m_l = 2 eps^-2 sqrt(V_l / s_l) sum_i sqrt(V_i s_i)       (eq. M_ell)
+  optimal cost S = 2 eps^-2 (sum_l sqrt(V_l s_l))^2                 (eq. total_cost_MLMC)
+  MSE = Var[Y] + bias^2                                            (eq. MSE)
+
+Bias estimate (the workload refines by 2 per level, first-order scheme):
+|E[g_L - g]| ~ |mean Y_L| / (2^alpha - 1).
+
+Field statistics use piecewise-constant injection (each coarse cell copied to
+its 2 x 2 children) and, for the variance field, the difference of unbiased
+sample variances of the coupled fine/coarse fields on each level.
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+
+
+def estimate(g_fine, g_coarse, alpha: float = 1.0):
+    """g_fine[l]: array [m_l]; g_coarse[l]: array [m_l] or None for l = 0.
+
+    Returns dict(mean, var_of_estimator, bias, rmse, V, Ymean).
+    """
+    L = len(g_fine) - 1
+    Ymean, V = [], []
+    for l in range(L + 1):
+        y = np.asarray(g_fine[l], dtype=np.float64)
+        if l > 0:
+            y = y - np.asarray(g_coarse[l], dtype=np.float64)
+        m = y.size
+        mu = y.sum() / m
+        Ymean.append(mu)
+        V.append(((y - mu) ** 2).sum() / (m - 1) if m > 1 else 0.0)
+    m = np.array([np.asarray(g).size for g in g_fine], dtype=np.float64)
+    V = np.array(V)
+    var_est = float(np.sum(V / m))
+    bias = abs(Ymean[L]) / (2.0 ** alpha - 1.0) if L > 0 else 0.0
+    return dict(mean=float(np.sum(Ymean)), var_of_estimator=var_est, bias=bias,
+                rmse=math.sqrt(var_est + bias * bias), V=V, Ymean=np.array(Ymean))
+
+
+def inject(field, times: int = 1):
+    """Piecewise-constant coarse -> fine transfer of a [ny, nx] field (2 x 2 children)."""
+    f = np.asarray(field)
+    for _ in range(times):
+        f = np.repeat(np.repeat(f, 2, axis=-2), 2, axis=-1)
+    return f
+
+
+def field_estimate(c_fine, c_coarse):
+    """c_fine[l]: [m_l, ny_l, nx_l]; c_coarse[l]: [m_l, ny_{l-1}, nx_{l-1}] or None.
+
+    Returns (mean_field, var_field) on the finest grid.
+    """
+    L = len(c_fine) - 1
+    mean = None
+    var = None
+    for l in range(L + 1):
+        f = np.asarray(c_fine[l], dtype=np.float64)
+        m = f.shape[0]
+        dm = f.mean(axis=0)
+        dv = f.var(axis=0, ddof=1) if m > 1 else np.zeros_like(dm)
+        if l > 0:
+            cc = np.asarray(c_coarse[l], dtype=np.float64)
+            dm = dm - inject(cc.mean(axis=0))
+            dv = dv - inject(cc.var(axis=0, ddof=1) if m > 1 else np.zeros_like(cc[0]))
+        dm = inject(dm, L - l)
+        dv = inject(dv, L - l)
+        mean = dm if mean is None else mean + dm
+        var = dv if var is None else var + dv
+    return mean, var
+
+
+def optimal_samples(V, s, eps):
+    """m_l = ceil(2 eps^-2 sqrt(V_l/s_l) sum_i sqrt(V_i s_i)) and the model costs."""
+    V = np.asarray(V, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    tot = np.sum(np.sqrt(V * s))
+    m_real = 2.0 / eps ** 2 * np.sqrt(V / s) * tot
+    m = np.ceil(m_real).astype(np.int64)
+    return dict(m=m, m_real=m_real, cost=float(np.sum(m * s)),
+                cost_opt=float(2.0 / eps ** 2 * tot ** 2))

@@ -1,0 +1,335 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (CPU only).
+
+Every check here is independent of the oracle's own formulas: closed forms,
+invariants, brute force, library routines or numbers printed in the paper.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from henry_inputs import draw_theta, level_grid
+from oracle import adjoint as A
+from oracle import henry as H
+from oracle import kl as KL
+from oracle import mlmc as M
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _table(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ---------------------------------------------------------------- constants
+def test_table1_constants_and_kozeny_carman():
+    """Table 1 values; the mean permeability is Kozeny-Carman of the mean porosity (eq. e_perm_Kozeny_Carman)."""
+    t = {r[0]: float(r[1]) for r in _table("paper_table1.txt")}
+    pr = H.Problem()
+    assert pr.phi_mean == t["phi_mean"]
+    assert pr.Dm == pytest.approx(t["D"], rel=1e-12)
+    assert pr.K_mean == t["K_hat"]
+    assert pr.rho0 == t["rho0"] and pr.mu == t["mu"]
+    # the studied workload rounds rho1 to 1025 (Table 1 prints 1024.99)
+    assert abs(pr.rho1 - t["rho1"]) < 0.011
+    kc = t["kappa_KC"] * t["phi_mean"] ** 3 / (1.0 - t["phi_mean"] ** 2)
+    assert kc == pytest.approx(t["K_hat"], rel=1e-6)
+
+
+# ---------------------------------------------------------------- KL basis
+def test_kl_roots_satisfy_transcendental_equations():
+    for a in (1.0, 0.5):
+        c = 2.0
+        for w, par, lam, _ in KL.roots_1d(a, 0.5, 10):
+            if par == 0:
+                r = (c * math.cos(w * a) - w * math.sin(w * a)) / max(c, w)
+            else:
+                r = (w * math.cos(w * a) + c * math.sin(w * a)) / max(c, w)
+            assert abs(r) < 1e-14
+            assert lam == pytest.approx(2 * c / (w * w + c * c), rel=1e-15)
+
+
+def test_kl_1d_orthonormal_and_eigen_by_quadrature():
+    """f is an eigenfunction: int exp(-|s-t|/b) f(t) dt = lam f(s), checked by adaptive quadrature."""
+    a, b = 1.0, 0.5
+    modes = KL.roots_1d(a, b, 6)
+    for i, mi in enumerate(modes):
+        for j, mj in enumerate(modes):
+            v, _ = integrate.quad(lambda s: KL.eval_1d(mi, s, 0.0) * KL.eval_1d(mj, s, 0.0), -a, a, limit=200)
+            assert abs(v - (1.0 if i == j else 0.0)) < 1e-10
+        for s0 in (-0.7, 0.1, 0.9):
+            lhs = sum(integrate.quad(lambda t: math.exp(-abs(s0 - t) / b) * KL.eval_1d(mi, t, 0.0), lo, hi,
+                                     limit=200)[0] for lo, hi in ((-a, s0), (s0, a)))
+            assert lhs == pytest.approx(mi[2] * KL.eval_1d(mi, s0, 0.0), abs=1e-10)
+
+
+def test_kl_nystrom_and_trace():
+    """Eigenvalues of the midpoint-rule kernel matrix approach the analytic ones; trace = domain length."""
+    a, b, n = 1.0, 0.5, 2000
+    s = -a + (np.arange(n) + 0.5) * (2 * a / n)
+    Kmat = np.exp(-np.abs(s[:, None] - s[None, :]) / b) * (2 * a / n)
+    ev = np.sort(np.linalg.eigvalsh(Kmat))[::-1][:6]
+    lam = np.array([m[2] for m in KL.roots_1d(a, b, 6)])
+    assert np.allclose(ev, lam, rtol=2e-5)
+    # sum of all eigenvalues = int C(s, s) ds = 2a: the deficit of the partial sums decays like 1/N
+    lam_many = np.array([m[2] for m in KL.roots_1d(a, b, 4000)])
+    d1, d4 = 2 * a - lam_many[:1000].sum(), 2 * a - lam_many.sum()
+    assert 0 < d4 < 5e-4 and 3.8 < d1 / d4 < 4.2
+
+
+def test_kl_2d_orthonormal_on_fine_grid():
+    kl = KL.KL2D()
+    nx, ny = 512, 256
+    x = (np.arange(nx) + 0.5) * 2.0 / nx
+    y = -1.0 + (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    E = kl.table(X, Y).reshape(8, -1)
+    G = E @ E.T * (2.0 / nx) * (1.0 / ny)
+    assert np.abs(G - np.eye(8)).max() < 1e-5
+    assert np.all(np.diff(kl.lam) <= 0)
+
+
+def test_fields_theta_zero_and_ranges():
+    pr = H.Problem()
+    g = H.Grid(*level_grid(2))
+    phi, K, u = H.sample_fields(pr, g, np.zeros(13))
+    assert np.all(phi == 0.35) and u == pr.q_in
+    assert np.abs(K / pr.K_mean - 1.0).max() < 1e-15   # exp(ln K) rounds
+    th = draw_theta(0, 64)
+    for t in th:
+        phi, K, u = H.sample_fields(pr, g, t)
+        assert 0.2 < phi.min() and phi.max() < 0.5
+        assert u == pytest.approx(6.6e-5 * (1 + 0.1 * t[12]))
+
+
+# ---------------------------------------------------------------- discrete operator
+def _some_state(ns=3, grid=(16, 8, 12), seed=7):
+    pr = H.Problem()
+    g = H.Grid(*grid)
+    th = draw_theta(seed, 2)[1]
+    phi, K, u = H.sample_fields(pr, g, th)
+    d = H.Discretisation(pr, g, phi, K, u)
+    r = H.solve_sample(pr, g, th, nsteps=ns, keep_states=True)
+    return pr, g, d, r
+
+
+def test_jacobian_matches_finite_differences_of_residual():
+    pr, g, d, r = _some_state()
+    p, c = r.states[-1]
+    c_old = r.states[-2][1]
+    rng = np.random.default_rng(0)
+    p = p + rng.normal(size=p.shape) * 10.0
+    c = c + rng.normal(size=c.shape) * 0.01
+    J = d.jacobian(p, c).toarray()
+    n = d.nc
+    for k in range(0, 2 * n, 7):
+        e = 1e-6 if k % 2 else 1e-2
+        pp, cp, pm, cm = p.copy(), c.copy(), p.copy(), c.copy()
+        if k % 2:
+            cp[k // 2] += e; cm[k // 2] -= e
+        else:
+            pp[k // 2] += e; pm[k // 2] -= e
+        a1, b1 = d.residual(pp, cp, c_old)
+        a0, b0 = d.residual(pm, cm, c_old)
+        col = np.empty(2 * n); col[0::2] = (a1 - a0) / (2 * e); col[1::2] = (b1 - b0) / (2 * e)
+        assert np.abs(col - J[:, k]).max() <= 1e-8 * np.abs(J).max()
+
+
+def test_hydrostatic_seawater_is_exact_steady_state():
+    """c = 1 everywhere, no recharge, c_left = 1: p = -rho1 g y and u = 0 to round-off."""
+    pr = H.Problem(q_in=0.0, c_left=1.0)
+    g = H.Grid(32, 16, 48)
+    phi, K, u = H.sample_fields(pr, g, draw_theta(3, 1)[0])
+    d = H.Discretisation(pr, g, phi, K, u)
+    _, Y = H.cell_centres(pr, g)
+    p_h = (-pr.rho1 * pr.g * Y).ravel()
+    c1 = np.ones(d.nc)
+    Rp, Rc = d.residual(p_h, c1, c1)
+    scale = pr.rho0 * pr.K_mean / pr.mu * pr.rho1 * pr.g * (1.0 / 16)
+    assert np.abs(Rp).max() < 1e-12 * scale and np.abs(Rc).max() < 1e-12 * scale
+    f = d._face(p_h, c1, d.nP, d.nQ, True)
+    assert np.abs(f["u"]).max() < 1e-15
+    # Newton from a perturbed pressure returns to it
+    p0 = p_h + 50.0 * np.sin(np.arange(d.nc))
+    p, c, its, ok = H.newton_step(d, p0, c1, c1, H.SolveOptions(newton_tol=1e-12))
+    assert ok and np.abs(p - p_h).max() < 1e-9 * pr.rho1 * pr.g and np.abs(c - 1).max() < 1e-12
+
+
+def test_hydrostatic_fresh_water():
+    pr = H.Problem(q_in=0.0, rho1=1000.0)
+    g = H.Grid(32, 16, 48)
+    phi, K, u = H.sample_fields(pr, g, draw_theta(3, 1)[0])
+    d = H.Discretisation(pr, g, phi, K, u)
+    _, Y = H.cell_centres(pr, g)
+    p_h = (-pr.rho0 * pr.g * Y).ravel()
+    z = np.zeros(d.nc)
+    p, c, its, ok = H.newton_step(d, p_h + 10.0, z, z, H.SolveOptions(newton_tol=1e-12))
+    assert ok and np.abs(p - p_h).max() < 1e-9 * pr.rho0 * pr.g and np.abs(c).max() < 1e-14
+
+
+def _ogata_banks(x, t, v, D):
+    """1-D advection-diffusion, c(0, t) = 1, c(x, 0) = 0 on x > 0 (Ogata & Banks 1961)."""
+    s = 2.0 * np.sqrt(D * t)
+    z1 = (x - v * t) / s
+    z2 = (x + v * t) / s
+    return 0.5 * (special.erfc(z1) + np.exp(v * x / D - z2 * z2) * special.erfcx(z2))
+
+
+def test_constant_density_reduces_to_advection_diffusion():
+    """rho1 = rho0, theta = 0, c_left = 1: y-independent, first-order convergence to the erfc solution
+    (paper eq. 1st_ord_conv), and Richardson extrapolation of two grids converges at second order."""
+    pr = H.Problem(rho1=1000.0, c_left=1.0, T=3600.0)
+    v = pr.q_in / pr.phi_mean
+    sols, errs = {}, []
+    for nx, nsteps in ((100, 36), (200, 72), (400, 144)):
+        g = H.Grid(nx, 2, nsteps)
+        r = H.solve_sample(pr, g, np.zeros(13), H.SolveOptions(newton_tol=1e-12))
+        c = r.c.reshape(2, nx)
+        assert np.abs(c[0] - c[1]).max() < 1e-12
+        x = (np.arange(nx) + 0.5) * 2.0 / nx
+        m = x < 1.5                     # away from the outflow boundary (semi-infinite solution)
+        errs.append(np.abs(c[0] - _ogata_banks(x, pr.T, v, pr.Dm))[m].max())
+        sols[nx] = c[0]
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3
+    rich = []
+    for nc in (100, 200):
+        cf = sols[2 * nc]
+        x = (np.arange(nc) + 0.5) * 2.0 / nc
+        m = x < 1.5
+        extrap = 2.0 * 0.5 * (cf[0::2] + cf[1::2]) - sols[nc]
+        rich.append(np.abs(extrap - _ogata_banks(x, pr.T, v, pr.Dm))[m].max())
+    assert rich[0] < errs[0] / 8 and 3.0 < rich[0] / rich[1] < 4.5
+
+
+def test_mass_balance_bounds_and_convergence_level0():
+    """Conservation (storage change = boundary fluxes) and c in [0, 1] on real level-0 samples."""
+    pr = H.Problem()
+    g = H.Grid(*level_grid(0))
+    th = draw_theta(0, 16)
+    for s in (0, 5):
+        r = H.solve_sample(pr, g, th[s])
+        assert r.converged
+        assert r.max_fluid_defect < 1e-10 and r.max_salt_defect < 1e-10
+        assert -1e-10 <= r.c_min and r.c_max <= 1 + 1e-10
+        assert 0 < r.qoi < 1025.0
+
+
+def test_dirichlet_right_variant_keeps_bounds():
+    pr = H.Problem(right_c_dirichlet=True)
+    g = H.Grid(32, 16, 12)
+    r = H.solve_sample(pr, g, draw_theta(0, 2)[1])
+    assert r.converged and r.max_salt_defect < 1e-10
+    assert -1e-10 <= r.c_min and r.c_max <= 1 + 1e-10
+
+
+# ---------------------------------------------------------------- MLMC
+def test_mlmc_single_level_is_sample_mean_and_variance():
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=37)
+    e = M.estimate([g], [None])
+    assert e["mean"] == pytest.approx(np.mean(g), rel=1e-14)
+    assert e["V"][0] == pytest.approx(np.var(g, ddof=1), rel=1e-13)
+    assert e["var_of_estimator"] == pytest.approx(np.var(g, ddof=1) / 37, rel=1e-13)
+
+
+def test_mlmc_telescoping_identity():
+    """Same inputs on every level: the telescoping sum collapses to the finest-level mean."""
+    rng = np.random.default_rng(4)
+    m = 50
+    gl = [rng.normal(size=m) + l for l in range(4)]
+    fine = [gl[0]] + [gl[l] for l in range(1, 4)]
+    coarse = [None] + [gl[l - 1] for l in range(1, 4)]
+    e = M.estimate(fine, coarse)
+    assert e["mean"] == pytest.approx(np.mean(gl[3]), abs=1e-13)
+    cf = [rng.normal(size=(m, 2 << l, 4 << l)) for l in range(3)]
+    mean, var = M.field_estimate([cf[0], cf[1], cf[2]], [None, cf[0], cf[1]])
+    assert np.allclose(mean, cf[2].mean(0), atol=1e-13)
+    assert np.allclose(var, cf[2].var(0, ddof=1), atol=1e-12)
+
+
+def test_injection_conserves_integrals():
+    rng = np.random.default_rng(5)
+    f = rng.normal(size=(4, 8))
+    fi = M.inject(f, 2)
+    assert fi.shape == (16, 32) and fi.sum() / 16 == pytest.approx(f.sum(), rel=1e-14)
+
+
+def test_optimal_samples_formula_is_the_constrained_optimum():
+    """eq. M_ell: Var[Y] = eps^2/2 at the real-valued optimum and no feasible perturbation is cheaper."""
+    V = np.array([2.0, 0.4, 0.06, 0.01])
+    s = np.array([1.0, 8.0, 64.0, 512.0])
+    eps = 0.05
+    o = M.optimal_samples(V, s, eps)
+    mr = o["m_real"]
+    assert np.sum(V / mr) == pytest.approx(eps ** 2 / 2, rel=1e-13)
+    assert np.sum(mr * s) == pytest.approx(o["cost_opt"], rel=1e-13)
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        m2 = mr * np.exp(0.2 * rng.normal(size=4))
+        m2 *= np.sum(V / m2) / (eps ** 2 / 2)      # rescale onto the variance constraint
+        assert np.sum(m2 * s) >= o["cost_opt"] * (1 - 1e-12)
+
+
+def test_optimal_samples_reproduce_table3_eps_scaling():
+    """Table 3: levels and costs at eps = 0.01 fix V_l up to a constant; eq. M_ell at eps = 0.007 then
+    reproduces the printed m_l (within the ceiling), and Table 2's times give the printed MLMC cost."""
+    t3 = {float(r[0]): r for r in _table("paper_table3.txt")}
+    s = np.array([float(r[4]) for r in _table("paper_table2.txt")])
+    m01 = np.array([float(x) for x in t3[0.01][4:8]])
+    m007 = np.array([float(x) for x in t3[0.007][4:8]])
+    kappa = 0.01 ** 2 / (2.0 * np.sum(m01 * s))
+    V = kappa * m01 ** 2 * s
+    o = M.optimal_samples(V, s, 0.007)
+    r = (0.01 / 0.007) ** 2
+    assert np.all(np.abs(o["m"] - m007) <= r + 1)
+    for eps in (0.01, 0.007):
+        m = np.array([float(x) for x in t3[eps][4:8]])
+        assert np.sum(m * s) == pytest.approx(float(t3[eps][2]), rel=0.12)
+
+
+@pytest.mark.slow
+def test_mlmc_agrees_with_plain_mc_on_tiny_levels():
+    pr = H.Problem(T=7200.0)
+    g0, g1 = H.Grid(8, 4, 6), H.Grid(16, 8, 12)
+    th_mc = draw_theta(11, 48, level=1)
+    q_mc = np.array([H.solve_sample(pr, g1, t).qoi for t in th_mc])
+    th0 = draw_theta(12, 96, level=0)
+    th1 = draw_theta(12, 16, level=1)
+    q0 = np.array([H.solve_sample(pr, g0, t).qoi for t in th0])
+    q1f = np.array([H.solve_sample(pr, g1, t).qoi for t in th1])
+    q1c = np.array([H.solve_sample(pr, g0, t).qoi for t in th1])
+    e = M.estimate([q0, q1f], [None, q1c])
+    sd = math.sqrt(e["var_of_estimator"] + np.var(q_mc, ddof=1) / q_mc.size)
+    assert abs(e["mean"] - q_mc.mean()) < 3 * sd
+    assert e["V"][1] < 0.25 * e["V"][0]
+
+
+# ---------------------------------------------------------------- adjoint
+def test_adjoint_matches_central_differences():
+    pr = H.Problem()
+    g = H.Grid(16, 8, 12)
+    th = draw_theta(7, 2)[1]
+    q, ga = A.adjoint_gradient(pr, g, th)
+    gf = A.fd_gradient(pr, g, th, h=1e-6)
+    assert np.abs(ga - gf).max() <= 1e-6 * np.abs(gf).max()
+
+
+def test_adjoint_taylor_remainder_is_second_order():
+    pr = H.Problem()
+    g = H.Grid(16, 8, 8)
+    th = draw_theta(9, 1)[0]
+    q, ga = A.adjoint_gradient(pr, g, th)
+    d = np.random.default_rng(1).normal(size=13)
+    opts = H.SolveOptions(stagnate=True)
+    rem = []
+    for eps in (1e-2, 5e-3, 2.5e-3):
+        qe = H.solve_sample(pr, g, th + eps * d, opts).qoi
+        rem.append(abs(qe - q - eps * ga @ d))
+    assert 3.0 < rem[0] / rem[1] < 5.0 and 3.0 < rem[1] / rem[2] < 5.0
