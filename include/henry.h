@@ -1,0 +1,184 @@
+/*
+ * henry.h -- C ABI of libhenry: batched stochastic Henry problem solves and the
+ * multilevel Monte Carlo estimator on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (arXiv 2403.17018):
+ *   - model: fluid and salt mass balance with Darcy flow, linear density, constant
+ *     viscosity, D = phi*Dm*I (section 2.1, eqs. e_cont_eq, e_tran_eq, e_Darcy_vel,
+ *     e_lin_density, e_mol_diff; boundary conditions of section 2.1);
+ *   - discretisation: finite volumes with upwinding and implicit Euler; Newton for the
+ *     nonlinear step; BiCGStab preconditioned by a geometric multigrid V-cycle with a
+ *     direct coarse-grid solve (section 2.3);
+ *   - uncertainty: porosity, permeability and recharge driven by a parameter vector
+ *     theta (section 2.2 and section 4 "Uncertain porosity and recharge");
+ *   - MLMC telescoping estimator, variances and optimal sample numbers (section 3,
+ *     eqs. EgL, A, goal_variance, M_ell, total_cost_MLMC, MSE).
+ *
+ * Conventions
+ *   - Array arguments are DEVICE pointers owned by the caller unless marked "host".
+ *     The library never frees caller memory.
+ *   - Per-cell-per-sample arrays use layout [j][i][s]: sample fastest, then cell
+ *     column i (x direction, nx cells), then cell row j (y direction, from the
+ *     bottom y = -Ly up to y = 0).  Index = (j*nx + i)*S + s.
+ *   - theta is [S][13] row-major: xi_0..3 (porosity KL coefficients, U[-1,1]),
+ *     eta_0..7 (log-permeability KL coefficients, N(0,1)), zeta (recharge, U[-1,1]).
+ *   - Work is enqueued on the context's HIP stream; calls that return per-sample
+ *     failure counts synchronise that stream before returning.
+ *   - Return codes: 0 = success; < 0 = hard error (below); > 0 = number of samples
+ *     whose status is not HENRY_STATUS_OK (soft failure; outputs are still written).
+ *     henry_last_error() describes the last hard error of a context.
+ *   - Workspace (multigrid hierarchy, Krylov vectors, coarse factors) is allocated by
+ *     the library inside the context and reused between calls of the same shape.
+ */
+#ifndef HENRY_H
+#define HENRY_H
+
+#if defined(__GNUC__)
+#define HENRY_API __attribute__((visibility("default")))
+#else
+#define HENRY_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HENRY_NTHETA 13
+
+enum henry_error {
+  HENRY_OK = 0,
+  HENRY_EINVAL = -1,       /* invalid argument (shape, NULL pointer, non-finite theta) */
+  HENRY_EDEVICE = -2,      /* a HIP runtime call failed */
+  HENRY_ENOMEM = -3,       /* device allocation failed */
+  HENRY_EUNSUPPORTED = -4  /* valid but unsupported option */
+};
+
+enum henry_sample_status {
+  HENRY_STATUS_OK = 0,
+  HENRY_STATUS_NEWTON = 1,     /* Newton did not converge within newton_maxit in some step */
+  HENRY_STATUS_KRYLOV = 2,     /* BiCGStab breakdown (rho or omega vanished) */
+  HENRY_STATUS_NONFINITE = 3,  /* a non-finite update was produced; the sample was frozen */
+  HENRY_STATUS_RANGE = 4       /* c left [-c_range_tol, 1 + c_range_tol] */
+};
+
+typedef struct henry_ctx henry_ctx;
+
+/* Physical problem.  Defaults (henry_problem_default): paper Table 1 with the
+ * studied workload's g = 9.81 and rho1 = 1025; domain [0,2]x[-1,0] m; T = 36000 s. */
+typedef struct {
+  double Lx, Ly;          /* domain [0,Lx] x [-Ly,0], m */
+  double T;               /* final time, s */
+  double rho0, rho1;      /* fresh water and brine density, kg/m^3 (eq. e_lin_density) */
+  double mu;              /* viscosity, Pa s */
+  double g;               /* gravity, m/s^2 */
+  double Dm;              /* diffusion coefficient, m^2/s (D = phi Dm I, eq. e_mol_diff) */
+  double phi_mean, phi_amp, phi_min, phi_max;  /* phi = clip(phi_mean(1+phi_amp*sum sqrt(lam)xi e), min, max) */
+  double K_mean, logK_amp;                     /* ln K = ln K_mean + logK_amp*sum sqrt(lam) eta e */
+  double corr_len;        /* exponential covariance correlation length, m */
+  double q_in, q_in_amp;  /* left inflow velocity u_in = q_in (1 + q_in_amp zeta), m/s */
+  int n_kl_phi, n_kl_logK;/* KL modes used (<= 4 and <= 8) */
+  int right_c_dirichlet;  /* 0: c = 1 carried by inflow on the right side only;
+                             1: additionally diffusive Dirichlet c = 1 (paper section 2.1) */
+  double c_left;          /* c of the left inflow and its Dirichlet value (0) */
+} henry_problem;
+
+/* One mesh level: nx x ny square cells (h = Lx/nx = Ly/ny), nsteps implicit-Euler
+ * steps of tau = T/nsteps.  MLMC level l uses 32*2^l x 16*2^l cells, 48*2^l steps. */
+typedef struct {
+  int nx, ny, nsteps;
+} henry_grid;
+
+/* Solver options.  Defaults (henry_solver_opts_default) in brackets. */
+typedef struct {
+  int mg_precision;      /* 64: FP64 multigrid; 32: FP32 multigrid preconditioner inside the
+                            FP64 BiCGStab/Newton (iterative refinement) [64] */
+  int coarse_nx, coarse_ny; /* coarsest multigrid grid, solved by a banded block LU [16, 8] */
+  int nu_pre, nu_post;   /* red-black block Gauss-Seidel sweeps [1, 1] */
+  double newton_tol;     /* converged when |dc|_inf <= tol and |dp|_inf <= tol*rho0*g*Ly [1e-9] */
+  double newton_dc_max;  /* each update is scaled by min(1, dc_max/|dc|_inf) [1.0] */
+  int newton_maxit;      /* per time step [40] */
+  double krylov_rtol;    /* BiCGStab: |r|_2 <= rtol |r0|_2 per sample [1e-8] */
+  int krylov_maxit;      /* [60] */
+  double c_range_tol;    /* status 4 when c leaves [-tol, 1+tol] [1e-8] */
+  int use_graphs;        /* capture each Krylov iteration in a hipGraph and replay it [0] */
+} henry_solver_opts;
+
+/* One batch of S independent samples on one grid (ragged batches: several per call). */
+typedef struct {
+  henry_grid grid;
+  int nsamples;
+  const double* theta;   /* device [S][13] */
+  double* c_T;           /* device [ny][nx][S] concentration at t = T, or NULL */
+  double* p_T;           /* device [ny][nx][S] pressure at t = T, or NULL */
+  double* qoi;           /* device [S] salt mass in x > Lx/2 at t = T: sum c rho(c) h^2, or NULL */
+  int* status;           /* device [S] henry_sample_status, or NULL */
+  double* stats;         /* device [S][4]: Newton iterations, BiCGStab iterations (summed over the
+                            run), max relative fluid and salt mass-balance defect; or NULL */
+} henry_batch;
+
+HENRY_API void henry_problem_default(henry_problem* p);
+HENRY_API void henry_solver_opts_default(henry_solver_opts* o);
+
+/* Create a context on HIP device `device` whose work is issued on `stream`
+ * (a hipStream_t; NULL = the default stream).  Returns HENRY_OK or an error. */
+HENRY_API int henry_ctx_create(henry_ctx** ctx, int device, void* stream);
+HENRY_API void henry_ctx_destroy(henry_ctx* ctx);
+/* Message of the last hard error on this context ("" if none).  Owned by ctx. */
+HENRY_API const char* henry_last_error(const henry_ctx* ctx);
+
+/* Random input fields at cell centres (paper section 4: the fields are evaluated at
+ * the integration points of each grid, not interpolated from rasters).
+ * KL eigenpairs of the separable exponential covariance with correlation length
+ * corr_len on [0,Lx]x[-Ly,0], modes sorted by eigenvalue.
+ *   theta: device [S][13]; phi, K: device [ny][nx][S]; q_in: device [S] (u_in).
+ * Any output may be NULL. */
+HENRY_API int henry_sample_fields(henry_ctx* ctx, const henry_problem* prob, henry_grid grid, int S,
+                        const double* theta, double* phi, double* K, double* q_in);
+
+/* Solve every batch over its full time horizon: c(0) = 0, implicit Euler, Newton with
+ * multigrid-preconditioned BiCGStab (section 2.3).  Batches may differ in grid and
+ * sample count (ragged MLMC levels); they are solved concurrently.
+ * Returns 0, a hard error, or the total number of samples with non-zero status. */
+HENRY_API int henry_solve_batch(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts,
+                      henry_batch* batches, int nbatches);
+
+/* Discrete adjoint of the converged time-stepped solve: dQ/dtheta for
+ * Q = salt mass in x > Lx/2 at t = T.  Reverse sweep of transposed, multigrid-
+ * preconditioned BiCGStab solves, states recomputed from checkpoints taken every
+ * `checkpoint_every` steps.
+ *   theta: device [S][13]; qoi: device [S] or NULL; dqoi_dtheta: device [S][13];
+ *   status: device [S] or NULL. */
+HENRY_API int henry_adjoint_batch(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts,
+                        henry_grid grid, int S, const double* theta, int checkpoint_every,
+                        double* qoi, double* dqoi_dtheta, int* status);
+
+/* MLMC estimator over levels 0..L (section 3, eqs. A, goal_variance, MSE):
+ *   Y_l = g_fine[l] - g_coarse[l] sample by sample (g_coarse[0] = NULL, i.e. g_{-1} = 0);
+ *   mean = sum_l mean(Y_l); V_l = unbiased sample variance of Y_l;
+ *   var_of_estimator = sum_l V_l/m_l; bias = |mean(Y_L)|/(2^alpha - 1) (0 when L = 0);
+ *   rmse = sqrt(var_of_estimator + bias^2).
+ * Field moments (optional: c_fine may be NULL) on the finest grid, coarse fields
+ * injected piecewise-constantly into 2x2 children:
+ *   mean_field = sum_l I_{l->L}[mean(c_fine[l]) - I mean(c_coarse[l])]
+ *   var_field  = sum_l I_{l->L}[S2(c_fine[l]) - I S2(c_coarse[l])]   (S2 unbiased)
+ * All sums run on the device in FP64 in a fixed order.
+ *   m, grids: host [L+1]; g_fine, g_coarse, c_fine, c_coarse: host arrays of device
+ *   pointers (QoIs [m_l]; fields [ny_l][nx_l][m_l] with coarse fields on grid l-1);
+ *   mean, var_of_estimator, rmse, V_l (host [L+1]) may be NULL;
+ *   mean_field, var_field: device [ny_L][nx_L] or NULL. */
+HENRY_API int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_grid* grids,
+                  const double* const* g_fine, const double* const* g_coarse,
+                  const double* const* c_fine, const double* const* c_coarse, double alpha,
+                  double* mean, double* var_of_estimator, double* rmse, double* V_l,
+                  double* mean_field, double* var_field);
+
+/* eq. M_ell and eq. total_cost_MLMC: m_l = ceil(2 eps^-2 sqrt(V_l/s_l) sum_i sqrt(V_i s_i)),
+ * cost = sum m_l s_l.  Host arrays; returns HENRY_OK or HENRY_EINVAL. */
+HENRY_API int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, double eps,
+                         long long* m_l, double* cost);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HENRY_H */

@@ -1,0 +1,201 @@
+"""Batched stochastic Henry problem and MLMC on AMD MI355X (gfx950).
+
+Thin Python binding of libhenry (include/henry.h).  Every step of the solve runs in
+the library's HIP kernels; this module only marshals torch tensors (device memory)
+and the current torch stream into the C ABI.  There is no CPU fallback: without the
+built libhenry.so every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import torch
+
+from . import _lib as L
+from ._lib import henry_batch, henry_grid, henry_problem, henry_solver_opts
+
+__all__ = ["Henry", "HenryError", "problem", "solver_opts", "grid", "level_grid", "optimal_samples", "SolveResult"]
+
+STATUS = {0: "ok", 1: "newton", 2: "krylov", 3: "nonfinite", 4: "range"}
+
+
+class HenryError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libhenry error {code}: {msg}")
+        self.code = code
+
+
+def problem(**kw) -> henry_problem:
+    """henry_problem with the library's defaults, fields overridden by keyword."""
+    p = henry_problem()
+    L.load().henry_problem_default(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def solver_opts(**kw) -> henry_solver_opts:
+    o = henry_solver_opts()
+    L.load().henry_solver_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def grid(nx: int, ny: int, nsteps: int) -> henry_grid:
+    return henry_grid(nx, ny, nsteps)
+
+
+def level_grid(level: int) -> henry_grid:
+    """MLMC level l: 32*2^l x 16*2^l cells, 48*2^l implicit-Euler steps."""
+    return henry_grid(32 << level, 16 << level, 48 << level)
+
+
+@dataclasses.dataclass
+class SolveResult:
+    c_T: torch.Tensor | None      # [ny, nx, S]
+    p_T: torch.Tensor | None
+    qoi: torch.Tensor             # [S]
+    status: torch.Tensor          # [S] int32
+    stats: torch.Tensor           # [S, 4]
+    nfailed: int
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_theta(theta, device):
+    if not (isinstance(theta, torch.Tensor) and theta.dtype == torch.float64 and theta.is_cuda):
+        raise TypeError("theta must be a float64 CUDA tensor")
+    if theta.dim() != 2 or theta.shape[1] != 13 or not theta.is_contiguous():
+        raise ValueError("theta must be contiguous [S, 13]")
+    if theta.device != device:
+        raise ValueError("theta is on another device")
+
+
+class Henry:
+    """A libhenry context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self._lib = L.load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = self._lib.henry_ctx_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise HenryError(rc, "henry_ctx_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.henry_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc < 0:
+            raise HenryError(rc, self._lib.henry_last_error(self._h).decode())
+        return rc
+
+    def sample_fields(self, theta, g: henry_grid, prob: henry_problem | None = None):
+        _check_theta(theta, self.device)
+        S = theta.shape[0]
+        prob = prob or problem()
+        kw = dict(dtype=torch.float64, device=self.device)
+        phi = torch.empty((g.ny, g.nx, S), **kw)
+        K = torch.empty((g.ny, g.nx, S), **kw)
+        q = torch.empty((S,), **kw)
+        self._check(self._lib.henry_sample_fields(self._h, C.byref(prob), g, S, _ptr(theta), _ptr(phi), _ptr(K), _ptr(q)))
+        return phi, K, q
+
+    def solve_ragged(self, items, prob: henry_problem | None = None, opts: henry_solver_opts | None = None,
+                     want_c: bool = True, want_p: bool = False):
+        """items: list of (theta [S,13], henry_grid).  One call; returns a list of SolveResult."""
+        prob = prob or problem()
+        opts = opts or solver_opts()
+        kw = dict(dtype=torch.float64, device=self.device)
+        arr = (henry_batch * len(items))()
+        res = []
+        for b, (theta, g) in enumerate(items):
+            _check_theta(theta, self.device)
+            S = theta.shape[0]
+            r = SolveResult(
+                c_T=torch.empty((g.ny, g.nx, S), **kw) if want_c else None,
+                p_T=torch.empty((g.ny, g.nx, S), **kw) if want_p else None,
+                qoi=torch.empty((S,), **kw),
+                status=torch.empty((S,), dtype=torch.int32, device=self.device),
+                stats=torch.empty((S, 4), **kw), nfailed=0)
+            arr[b] = henry_batch(g, S, theta.data_ptr(), _ptr(r.c_T), _ptr(r.p_T), _ptr(r.qoi), _ptr(r.status),
+                                 _ptr(r.stats))
+            res.append(r)
+        rc = self._check(self._lib.henry_solve_batch(self._h, C.byref(prob), C.byref(opts), arr, len(items)))
+        for r in res:
+            r.nfailed = int((r.status != 0).sum().item())
+        assert sum(r.nfailed for r in res) == rc
+        return res
+
+    def solve(self, theta, g: henry_grid, prob=None, opts=None, want_c=True, want_p=False) -> SolveResult:
+        return self.solve_ragged([(theta, g)], prob, opts, want_c, want_p)[0]
+
+    def adjoint(self, theta, g: henry_grid, prob=None, opts=None, checkpoint_every: int = 32):
+        """(qoi [S], dqoi/dtheta [S,13], status [S], nfailed)."""
+        _check_theta(theta, self.device)
+        prob = prob or problem()
+        opts = opts or solver_opts()
+        S = theta.shape[0]
+        kw = dict(dtype=torch.float64, device=self.device)
+        q = torch.empty((S,), **kw)
+        gr = torch.empty((S, 13), **kw)
+        st = torch.empty((S,), dtype=torch.int32, device=self.device)
+        rc = self._check(self._lib.henry_adjoint_batch(self._h, C.byref(prob), C.byref(opts), g, S, _ptr(theta),
+                                                       checkpoint_every, _ptr(q), _ptr(gr), _ptr(st)))
+        return q, gr, st, rc
+
+    def mlmc_estimate(self, grids, g_fine, g_coarse, c_fine=None, c_coarse=None, alpha: float = 1.0):
+        """Telescoping MLMC estimate over levels 0..L (device reductions).
+
+        g_fine[l], g_coarse[l] (None for l = 0): float64 CUDA tensors [m_l];
+        c_fine[l]: [ny_l, nx_l, m_l]; c_coarse[l]: [ny_{l-1}, nx_{l-1}, m_l] (None for l = 0).
+        """
+        Lv = len(g_fine) - 1
+        m = (C.c_int * (Lv + 1))(*[int(t.numel()) for t in g_fine])
+        gr = (henry_grid * (Lv + 1))(*grids)
+        vp = C.c_void_p
+        gf = (vp * (Lv + 1))(*[t.data_ptr() for t in g_fine])
+        gc = (vp * (Lv + 1))(*[0 if t is None else t.data_ptr() for t in g_coarse])
+        cf = cc = None
+        mean_f = var_f = None
+        if c_fine is not None:
+            cf = (vp * (Lv + 1))(*[t.data_ptr() for t in c_fine])
+            cc = (vp * (Lv + 1))(*[0 if t is None else t.data_ptr() for t in c_coarse])
+            gL = grids[-1]
+            mean_f = torch.empty((gL.ny, gL.nx), dtype=torch.float64, device=self.device)
+            var_f = torch.empty_like(mean_f)
+        mean, var, rmse = C.c_double(), C.c_double(), C.c_double()
+        V = (C.c_double * (Lv + 1))()
+        self._check(self._lib.mlmc_estimate(self._h, Lv, m, gr, gf, gc, cf, cc, alpha, C.byref(mean), C.byref(var),
+                                            C.byref(rmse), V, _ptr(mean_f), _ptr(var_f)))
+        return dict(mean=mean.value, var_of_estimator=var.value, rmse=rmse.value, V=list(V), mean_field=mean_f,
+                    var_field=var_f)
+
+
+def optimal_samples(V, s, eps):
+    """eq. M_ell: m_l = ceil(2 eps^-2 sqrt(V_l/s_l) sum sqrt(V_i s_i)); returns (m list, cost)."""
+    n = len(V)
+    m = (C.c_longlong * n)()
+    cost = C.c_double()
+    rc = L.load().mlmc_optimal_samples(n - 1, (C.c_double * n)(*V), (C.c_double * n)(*s), eps, m, C.byref(cost))
+    if rc != 0:
+        raise HenryError(rc, "invalid arguments to mlmc_optimal_samples")
+    return list(m), cost.value

@@ -1,0 +1,74 @@
+"""ctypes declarations of libhenry's C ABI (include/henry.h).  Marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhenry.so")
+
+HENRY_OK, HENRY_EINVAL, HENRY_EDEVICE, HENRY_ENOMEM, HENRY_EUNSUPPORTED = 0, -1, -2, -3, -4
+EXPORTS = ("henry_problem_default", "henry_solver_opts_default", "henry_ctx_create", "henry_ctx_destroy",
+           "henry_last_error", "henry_sample_fields", "henry_solve_batch", "henry_adjoint_batch",
+           "mlmc_estimate", "mlmc_optimal_samples")
+
+
+class henry_problem(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("Lx", "Ly", "T", "rho0", "rho1", "mu", "g", "Dm", "phi_mean", "phi_amp",
+                                           "phi_min", "phi_max", "K_mean", "logK_amp", "corr_len", "q_in",
+                                           "q_in_amp")] + [
+        ("n_kl_phi", C.c_int), ("n_kl_logK", C.c_int), ("right_c_dirichlet", C.c_int), ("c_left", C.c_double)]
+
+
+class henry_grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nsteps", C.c_int)]
+
+
+class henry_solver_opts(C.Structure):
+    _fields_ = [("mg_precision", C.c_int), ("coarse_nx", C.c_int), ("coarse_ny", C.c_int), ("nu_pre", C.c_int),
+                ("nu_post", C.c_int), ("newton_tol", C.c_double), ("newton_dc_max", C.c_double),
+                ("newton_maxit", C.c_int), ("krylov_rtol", C.c_double), ("krylov_maxit", C.c_int),
+                ("c_range_tol", C.c_double), ("use_graphs", C.c_int)]
+
+
+class henry_batch(C.Structure):
+    _fields_ = [("grid", henry_grid), ("nsamples", C.c_int), ("theta", C.c_void_p), ("c_T", C.c_void_p),
+                ("p_T", C.c_void_p), ("qoi", C.c_void_p), ("status", C.c_void_p), ("stats", C.c_void_p)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libhenry.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2403_17018_amd.build`")
+    lib = C.CDLL(path)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    P = C.POINTER
+    lib.henry_problem_default.argtypes = [P(henry_problem)]
+    lib.henry_problem_default.restype = None
+    lib.henry_solver_opts_default.argtypes = [P(henry_solver_opts)]
+    lib.henry_solver_opts_default.restype = None
+    lib.henry_ctx_create.argtypes = [P(vp), i, vp]
+    lib.henry_ctx_create.restype = i
+    lib.henry_ctx_destroy.argtypes = [vp]
+    lib.henry_ctx_destroy.restype = None
+    lib.henry_last_error.argtypes = [vp]
+    lib.henry_last_error.restype = C.c_char_p
+    lib.henry_sample_fields.argtypes = [vp, P(henry_problem), henry_grid, i, vp, vp, vp, vp]
+    lib.henry_sample_fields.restype = i
+    lib.henry_solve_batch.argtypes = [vp, P(henry_problem), P(henry_solver_opts), P(henry_batch), i]
+    lib.henry_solve_batch.restype = i
+    lib.henry_adjoint_batch.argtypes = [vp, P(henry_problem), P(henry_solver_opts), henry_grid, i, vp, i, vp, vp, vp]
+    lib.henry_adjoint_batch.restype = i
+    lib.mlmc_estimate.argtypes = [vp, i, P(i), P(henry_grid), P(vp), P(vp), P(vp), P(vp), d, P(d), P(d), P(d), P(d),
+                                  vp, vp]
+    lib.mlmc_estimate.restype = i
+    lib.mlmc_optimal_samples.argtypes = [i, P(d), P(d), d, P(C.c_longlong), P(d)]
+    lib.mlmc_optimal_samples.restype = i
+    _lib = lib
+    return lib

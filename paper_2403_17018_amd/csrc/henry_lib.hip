@@ -1,0 +1,818 @@
+// libhenry: host runtime and C ABI of the batched Henry / MLMC solver (gfx950).
+//
+// The host side only sequences kernels: the time loop, Newton iterations and the
+// BiCGStab/multigrid schedule.  Every arithmetic step on the data runs in the HIP
+// kernels of henry_kernels.hpp and henry_mlmc.hpp.  Per-sample control decisions
+// (damping, convergence, breakdown) are taken on the device; the host reads one
+// counter per iteration to decide whether to launch another.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/henry.h"
+#include "henry_kernels.hpp"
+#include "henry_mlmc.hpp"
+
+using namespace henry;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct HenryError {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(call)                                                                               \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      throw HenryError{HENRY_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)};          \
+  } while (0)
+
+static void fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw HenryError{code, buf};
+}
+
+// ---------------------------------------------------------------------------
+// KL eigenpairs of exp(-|dx|/b) exp(-|dy|/b) on [0,Lx] x [-Ly,0] (host setup)
+// ---------------------------------------------------------------------------
+// 1-D modes on an interval of half-length a: even cos(w t) with c cos(wa) = w sin(wa),
+// odd sin(w t) with w cos(wa) + c sin(wa) = 0, c = 1/b; lambda = 2c/(w^2 + c^2).
+// Roots bracketed in (k pi/a, (k+1/2) pi/a) and ((k+1/2) pi/a, (k+1) pi/a) and found by
+// bisection of the sine/cosine forms (no poles) to the last bit.
+struct Mode1D {
+  double w, lam, norm;
+  int odd;
+};
+
+static double bisect(double lo, double hi, int odd, double a, double c) {
+  auto f = [&](double w) { return odd ? w * std::cos(w * a) + c * std::sin(w * a) : c * std::cos(w * a) - w * std::sin(w * a); };
+  double flo = f(lo);
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    const double fm = f(mid);
+    if ((fm < 0) == (flo < 0)) {
+      lo = mid;
+      flo = fm;
+    } else {
+      hi = mid;
+    }
+  }
+  return 0.5 * (lo + hi);
+}
+
+static std::vector<Mode1D> modes_1d(double a, double b, int n) {
+  const double c = 1.0 / b;
+  std::vector<Mode1D> out;
+  for (int k = 0; (int)out.size() < n; ++k) {
+    for (int odd = 0; odd < 2 && (int)out.size() < n; ++odd) {
+      const double lo = (k + 0.5 * odd) * M_PI / a, hi = (k + 0.5 * odd + 0.5) * M_PI / a;
+      const double w = bisect(lo, hi, odd, a, c);
+      const double s2 = std::sin(2.0 * w * a) / (2.0 * w);
+      out.push_back({w, 2.0 * c / (w * w + c * c), std::sqrt(odd ? a - s2 : a + s2), odd});
+    }
+  }
+  return out;
+}
+
+static KLModes make_kl(const henry_problem& pr) {
+  const int nm = 8, n1 = 12;
+  auto mx = modes_1d(0.5 * pr.Lx, pr.corr_len, n1);
+  auto my = modes_1d(0.5 * pr.Ly, pr.corr_len, n1);
+  std::vector<std::tuple<double, int, int>> pairs;
+  for (int ix = 0; ix < n1; ++ix)
+    for (int iy = 0; iy < n1; ++iy) pairs.emplace_back(mx[ix].lam * my[iy].lam, ix, iy);
+  std::stable_sort(pairs.begin(), pairs.end(), [](const auto& u, const auto& v) {
+    if (std::get<0>(u) != std::get<0>(v)) return std::get<0>(u) > std::get<0>(v);
+    return std::get<1>(u) < std::get<1>(v);
+  });
+  KLModes kl{};
+  kl.n = std::max(pr.n_kl_phi, pr.n_kl_logK);
+  for (int k = 0; k < nm; ++k) {
+    const auto& [lam, ix, iy] = pairs[k];
+    kl.sqrt_lam[k] = std::sqrt(lam);
+    kl.wx[k] = mx[ix].w;
+    kl.normx[k] = mx[ix].norm;
+    kl.oddx[k] = mx[ix].odd;
+    kl.wy[k] = my[iy].w;
+    kl.normy[k] = my[iy].norm;
+    kl.oddy[k] = my[iy].odd;
+  }
+  kl.xc = 0.5 * pr.Lx;
+  kl.yc = -0.5 * pr.Ly;
+  return kl;
+}
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  void alloc(size_t b) {
+    if (b <= bytes) return;
+    if (p) HIPCHK(hipFree(p));
+    p = nullptr;
+    bytes = 0;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(HENRY_ENOMEM, "hipMalloc of %zu bytes failed", b);
+    }
+    bytes = b;
+  }
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+static Map make_map(int S, int ncell) {
+  Map m{};
+  m.S = S;
+  m.SX = S <= 64 ? S : 64;
+  m.CY = std::max(1, 256 / m.SX);
+  m.nsb = (S + m.SX - 1) / m.SX;
+  // reduction kernels: CPT cells per thread so that about 4096 blocks cover the batch
+  const int target_cb = std::max(1, 4096 / m.nsb);
+  const int rows = (ncell + m.CY - 1) / m.CY;
+  m.CPT = std::max(1, (rows + target_cb - 1) / target_cb);
+  m.ncb = (rows + m.CPT - 1) / m.CPT;
+  return m;
+}
+
+static dim3 grid_cells(const Map& m, int ncell) {
+  const long long nb = (long long)m.nsb * ((ncell + m.CY - 1) / m.CY);
+  return dim3((unsigned)nb);
+}
+static dim3 grid_red(const Map& m) { return dim3((unsigned)((long long)m.nsb * m.ncb)); }
+static dim3 block_of(const Map& m) { return dim3(m.SX, m.CY); }
+static dim3 fin_grid(int S) { return dim3((S + 63) / 64); }
+
+static Phys make_phys(const henry_problem& pr, int nx, int ny, int nsteps) {
+  Phys P{};
+  P.rho0 = pr.rho0;
+  P.drho = pr.rho1 - pr.rho0;
+  P.rho1 = pr.rho1;
+  P.mu = pr.mu;
+  P.g = pr.g;
+  P.Dm = pr.Dm;
+  P.c_left = pr.c_left;
+  P.hx = pr.Lx / nx;
+  P.hy = pr.Ly / ny;
+  P.vol = P.hx * P.hy;
+  P.tau = pr.T / nsteps;
+  P.Ly = pr.Ly;
+  P.Lx = pr.Lx;
+  P.right_dir = pr.right_c_dirichlet;
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// per-shape plan: multigrid hierarchy and Krylov workspace of one batch
+// ---------------------------------------------------------------------------
+struct MGLevel {
+  int nx, ny, ncell;
+  Grid2 G;
+  DevBuf J, x, b;             // MG precision
+  DevBuf p, c, phi, K;        // restricted state and coefficients (FP64), levels >= 1
+};
+
+struct Plan {
+  int nx, ny, S, prec, cnx, cny;
+  size_t N;
+  Map m;
+  Grid2 G;
+  std::vector<std::unique_ptr<MGLevel>> lv;   // lv[0] = fine grid
+  int nlev;
+  DevBuf phi, K, uin, p, c, c_old, R, J, J32;
+  DevBuf vx, vr, vrh, vp, vv, vs, vt, vph, vsh;
+  DevBuf LU;
+  DevBuf sc, lam, ndone, status, stats, part, ctrl;
+  size_t lu_stride;
+  int mb;
+};
+
+struct henry_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::map<std::tuple<int, int, int, int, int, int>, std::unique_ptr<Plan>> plans;
+  int* h_ctrl = nullptr;   // pinned
+  DevBuf mlmc_tmp;
+};
+
+template <typename T>
+static void plan_alloc_levels(Plan& P) {
+  for (int k = 0; k < P.nlev; ++k) {
+    MGLevel& L = *P.lv[k];
+    const size_t Nk = (size_t)L.ncell * P.S;
+    if (k > 0 || P.prec == 32) {
+      if (k > 0) L.J.alloc(20 * Nk * sizeof(T));
+      L.x.alloc(2 * Nk * sizeof(T));
+      L.b.alloc(2 * Nk * sizeof(T));
+    }
+    if (k > 0) {
+      L.p.alloc(Nk * sizeof(double));
+      L.c.alloc(Nk * sizeof(double));
+      L.phi.alloc(Nk * sizeof(double));
+      L.K.alloc(Nk * sizeof(double));
+    }
+  }
+  const MGLevel& C = *P.lv[P.nlev - 1];
+  P.mb = C.ny;
+  P.lu_stride = (size_t)C.ncell * (2 * P.mb + 1) * 4;
+  P.LU.alloc(P.lu_stride * P.S * sizeof(T));
+}
+
+static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_opts& o) {
+  const int cnx = std::min(o.coarse_nx, nx), cny = std::min(o.coarse_ny, ny);
+  auto key = std::make_tuple(nx, ny, S, o.mg_precision, cnx, cny);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) return it->second.get();
+  auto P = std::make_unique<Plan>();
+  P->nx = nx;
+  P->ny = ny;
+  P->S = S;
+  P->prec = o.mg_precision;
+  P->cnx = cnx;
+  P->cny = cny;
+  P->G = Grid2{nx, ny, nx * ny};
+  P->N = (size_t)nx * ny * S;
+  P->m = make_map(S, nx * ny);
+  // hierarchy: halve while above the coarse size and even
+  int gx = nx, gy = ny;
+  while (true) {
+    auto L = std::make_unique<MGLevel>();
+    L->nx = gx;
+    L->ny = gy;
+    L->ncell = gx * gy;
+    L->G = Grid2{gx, gy, gx * gy};
+    P->lv.push_back(std::move(L));
+    if (gx <= cnx || gy <= cny || (gx & 1) || (gy & 1)) break;
+    gx /= 2;
+    gy /= 2;
+  }
+  P->nlev = (int)P->lv.size();
+  if (P->lv.back()->ny > 44) fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d: band width %d exceeds 44", gx, gy, gy);
+  for (int k = 0; k + 1 < P->nlev; ++k)
+    if (P->lv[k]->nx & 1) fail(HENRY_EUNSUPPORTED, "multigrid level %d has odd nx", k);
+  const size_t N = P->N;
+  P->phi.alloc(N * 8);
+  P->K.alloc(N * 8);
+  P->uin.alloc(S * 8);
+  P->p.alloc(N * 8);
+  P->c.alloc(N * 8);
+  P->c_old.alloc(N * 8);
+  P->R.alloc(2 * N * 8);
+  P->J.alloc(20 * N * 8);
+  if (o.mg_precision == 32) P->J32.alloc(20 * N * 4);
+  for (DevBuf* v : {&P->vx, &P->vr, &P->vrh, &P->vp, &P->vv, &P->vs, &P->vt, &P->vph, &P->vsh}) v->alloc(2 * N * 8);
+  if (o.mg_precision == 32) plan_alloc_levels<float>(*P);
+  else plan_alloc_levels<double>(*P);
+  P->sc.alloc((size_t)SC_NSLOT * S * 8);
+  P->lam.alloc(S * 8);
+  P->ndone.alloc(S * 4);
+  P->status.alloc(S * 4);
+  P->stats.alloc((size_t)S * 4 * 8);
+  P->part.alloc((size_t)6 * P->m.ncb * S * 8);
+  P->ctrl.alloc(64);
+  Plan* raw = P.get();
+  ctx->plans[key] = std::move(P);
+  return raw;
+}
+
+// ---------------------------------------------------------------------------
+// solver
+// ---------------------------------------------------------------------------
+struct Solver {
+  henry_ctx* ctx;
+  const henry_problem& pr;
+  const henry_solver_opts& o;
+  Plan& P;
+  hipStream_t st;
+  Phys phys;       // fine grid
+  KLModes kl;
+  FieldParams fp;
+
+  Solver(henry_ctx* c, const henry_problem& p, const henry_solver_opts& op, Plan& pl, int nsteps)
+      : ctx(c), pr(p), o(op), P(pl), st(c->stream) {
+    phys = make_phys(pr, P.nx, P.ny, nsteps);
+    kl = make_kl(pr);
+    fp.phi_mean = pr.phi_mean;
+    fp.phi_amp = pr.phi_amp;
+    fp.phi_min = pr.phi_min;
+    fp.phi_max = pr.phi_max;
+    fp.lnK_mean = std::log(pr.K_mean);
+    fp.logK_amp = pr.logK_amp;
+    fp.q_in = pr.q_in;
+    fp.q_in_amp = pr.q_in_amp;
+    fp.n_phi = pr.n_kl_phi;
+    fp.n_logK = pr.n_kl_logK;
+  }
+
+  Phys phys_level(int k) const {
+    Phys q = phys;
+    q.hx = pr.Lx / P.lv[k]->nx;
+    q.hy = pr.Ly / P.lv[k]->ny;
+    q.vol = q.hx * q.hy;
+    return q;
+  }
+
+  void zero_ctrl() { hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, P.ctrl.as<int>(), 16); }
+  int read_ctrl(int i) {
+    HIPCHK(hipMemcpyAsync(ctx->h_ctrl, P.ctrl.as<int>(), 16 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return ctx->h_ctrl[i];
+  }
+
+  void fields(const double* theta) {
+    const Map& m = P.m;
+    hipLaunchKernelGGL(k_fields, grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G, phys, kl, fp, theta,
+                       P.phi.as<double>(), P.K.as<double>(), P.uin.as<double>());
+    for (int k = 1; k < P.nlev; ++k) {
+      MGLevel& F = *P.lv[k - 1];
+      MGLevel& C = *P.lv[k];
+      const double* fphi = k == 1 ? P.phi.as<double>() : F.phi.as<double>();
+      const double* fK = k == 1 ? P.K.as<double>() : F.K.as<double>();
+      hipLaunchKernelGGL(k_restrict_coef, grid_cells(m, C.ncell), block_of(m), 0, st, m, F.G, C.G, fphi, fK,
+                         C.phi.as<double>(), C.K.as<double>());
+    }
+  }
+
+  // fine-grid residual/Jacobian, rediscretised coarse Jacobians, coarse factorisation
+  template <typename T>
+  void assemble_all() {
+    const Map& m = P.m;
+    if (P.prec == 32)
+      hipLaunchKernelGGL((k_assemble<true, double, true>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
+                         phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
+                         P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J.as<double>(), P.J32.as<float>());
+    else
+      hipLaunchKernelGGL((k_assemble<true, double, false>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
+                         phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
+                         P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J.as<double>(), (float*)nullptr);
+    for (int k = 1; k < P.nlev; ++k) {
+      MGLevel& F = *P.lv[k - 1];
+      MGLevel& C = *P.lv[k];
+      const double* fp_ = k == 1 ? P.p.as<double>() : F.p.as<double>();
+      const double* fc_ = k == 1 ? P.c.as<double>() : F.c.as<double>();
+      hipLaunchKernelGGL(k_restrict_state, grid_cells(m, C.ncell), block_of(m), 0, st, m, F.G, C.G, fp_, fc_,
+                         C.p.as<double>(), C.c.as<double>());
+      hipLaunchKernelGGL((k_assemble<false, T, false>), grid_cells(m, C.ncell), block_of(m), 0, st, m, C.G,
+                         phys_level(k), C.p.as<double>(), C.c.as<double>(), (const double*)nullptr,
+                         C.phi.as<double>(), C.K.as<double>(), P.uin.as<double>(), (double*)nullptr, C.J.as<T>(),
+                         (float*)nullptr);
+    }
+    const MGLevel& Cc = *P.lv[P.nlev - 1];
+    const size_t lds = (size_t)(P.mb + 1) * (P.mb + 1) * 4 * sizeof(T);
+    hipLaunchKernelGGL((k_band_factor<T>), dim3(P.S), dim3(64), lds, st, P.S, Cc.nx, Cc.ny, level_J<T>(P.nlev - 1),
+                       P.LU.as<T>());
+  }
+
+  template <typename T>
+  const T* level_J(int k) const {
+    if (k > 0) return P.lv[k]->J.as<T>();
+    if (P.prec == 32) return (const T*)P.J32.as<float>();
+    return (const T*)P.J.as<double>();
+  }
+
+  template <typename T>
+  void vcycle(int k, const T* b, T* x) {
+    const Map& m = P.m;
+    MGLevel& L = *P.lv[k];
+    if (k == P.nlev - 1) {
+      const size_t lds = (size_t)(P.mb + 1) * 2 * sizeof(T);
+      hipLaunchKernelGGL((k_band_solve<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, P.LU.as<T>(), b, x);
+      return;
+    }
+    const T* J = level_J<T>(k);
+    const int half = (L.nx + 1) / 2;
+    const dim3 gg = grid_cells(m, L.ny * half);
+    for (int sw = 0; sw < o.nu_pre; ++sw) {
+      hipLaunchKernelGGL((k_gs_colour<T>), gg, block_of(m), 0, st, m, L.G, 0, sw == 0 ? 1 : 0, J, b, x);
+      hipLaunchKernelGGL((k_gs_colour<T>), gg, block_of(m), 0, st, m, L.G, 1, 0, J, b, x);
+    }
+    MGLevel& C = *P.lv[k + 1];
+    hipLaunchKernelGGL((k_residual_restrict<T>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G, J, b, x,
+                       C.b.as<T>());
+    vcycle<T>(k + 1, C.b.as<T>(), C.x.as<T>());
+    hipLaunchKernelGGL((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G, C.x.as<T>(), x);
+    for (int sw = 0; sw < o.nu_post; ++sw) {
+      hipLaunchKernelGGL((k_gs_colour<T>), gg, block_of(m), 0, st, m, L.G, 0, 0, J, b, x);
+      hipLaunchKernelGGL((k_gs_colour<T>), gg, block_of(m), 0, st, m, L.G, 1, 0, J, b, x);
+    }
+  }
+
+  // out = M^{-1} in (FP64 vectors); FP32 mode converts around an FP32 V-cycle
+  template <typename T>
+  void precond(const double* in, double* out) {
+    if (P.prec == 32) {
+      MGLevel& L = *P.lv[0];
+      const size_t n = 2 * P.N;
+      const dim3 g((unsigned)((n + 255) / 256));
+      hipLaunchKernelGGL((k_convert<double, float>), g, dim3(256), 0, st, n, in, L.b.as<float>());
+      vcycle<float>(0, L.b.as<float>(), L.x.as<float>());
+      hipLaunchKernelGGL((k_convert<float, double>), g, dim3(256), 0, st, n, L.x.as<float>(), out);
+    } else {
+      vcycle<double>(0, in, out);
+    }
+  }
+
+  // BiCGStab on J d = -R for the samples not yet Newton-converged; d in vx
+  template <typename T>
+  void bicgstab() {
+    const Map& m = P.m;
+    const int S = P.S;
+    double* sc = P.sc.as<double>();
+    int* ctrl = P.ctrl.as<int>();
+    int* status = P.status.as<int>();
+    const dim3 rg = grid_red(m), bl = block_of(m), cg = grid_cells(m, P.G.ncell);
+    const dim3 fg = fin_grid(S), fb(64, 4);
+    hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, P.R.as<double>(), P.ndone.as<int>(), P.vr.as<double>(),
+                       P.vrh.as<double>(), P.vx.as<double>(), P.part.as<double>());
+    zero_ctrl();
+    hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl);
+    if (read_ctrl(0) == 0) return;
+    const double rtol2 = o.krylov_rtol * o.krylov_rtol;
+    for (int it = 0; it < o.krylov_maxit; ++it) {
+      hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, it == 0 ? 1 : 0, sc, P.vr.as<double>(),
+                         P.vv.as<double>(), P.vp.as<double>());
+      precond<T>(P.vp.as<double>(), P.vph.as<double>());
+      hipLaunchKernelGGL(k_spmv_dot<1>, rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vph.as<double>(), P.vv.as<double>(),
+                         P.vrh.as<double>(), P.part.as<double>());
+      hipLaunchKernelGGL(k_fin_alpha, fg, fb, 0, st, m, P.part.as<double>(), sc, status);
+      hipLaunchKernelGGL(k_bicg_s, cg, bl, 0, st, m, P.G.ncell, sc, P.vr.as<double>(), P.vv.as<double>(),
+                         P.vs.as<double>());
+      precond<T>(P.vs.as<double>(), P.vsh.as<double>());
+      hipLaunchKernelGGL(k_spmv_dot<2>, rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vsh.as<double>(), P.vt.as<double>(),
+                         P.vs.as<double>(), P.part.as<double>());
+      hipLaunchKernelGGL(k_fin_omega, fg, fb, 0, st, m, P.part.as<double>(), sc);
+      hipLaunchKernelGGL(k_bicg_xr, rg, bl, 0, st, m, P.G.ncell, sc, P.vph.as<double>(), P.vsh.as<double>(),
+                         P.vs.as<double>(), P.vt.as<double>(), P.vrh.as<double>(), P.vx.as<double>(), P.vr.as<double>(),
+                         P.part.as<double>());
+      zero_ctrl();
+      hipLaunchKernelGGL(k_fin_rho, fg, fb, 0, st, m, P.part.as<double>(), sc, rtol2, status, ctrl);
+      if (read_ctrl(0) == 0) break;
+    }
+    hipLaunchKernelGGL(k_accum_its, dim3((S + 255) / 256), dim3(256), 0, st, S, sc, P.stats.as<double>());
+  }
+
+  template <typename T>
+  void run(const henry_batch& B) {
+    const Map& m = P.m;
+    const int S = P.S;
+    const dim3 cg = grid_cells(m, P.G.ncell), bl = block_of(m);
+    fields(B.theta);
+    hipLaunchKernelGGL(k_init_state, cg, bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>());
+    HIPCHK(hipMemsetAsync(P.status.p, 0, S * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(P.stats.p, 0, (size_t)S * 4 * sizeof(double), st));
+    const double p_ref = pr.rho0 * pr.g * pr.Ly;
+    for (int n = 0; n < B.grid.nsteps; ++n) {
+      HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
+      int remaining = S;
+      for (int it = 0; it < o.newton_maxit && remaining > 0; ++it) {
+        assemble_all<T>();
+        bicgstab<T>();
+        hipLaunchKernelGGL(k_delta_max, grid_red(m), bl, 0, st, m, P.G.ncell, P.vx.as<double>(), P.part.as<double>());
+        zero_ctrl();
+        hipLaunchKernelGGL(k_fin_newton, dim3((S + 255) / 256), dim3(256), 0, st, m, P.part.as<double>(), p_ref,
+                           o.newton_tol, o.newton_dc_max, P.lam.as<double>(), P.ndone.as<int>(), P.status.as<int>(),
+                           P.stats.as<double>(), P.ctrl.as<int>());
+        hipLaunchKernelGGL(k_newton_update, cg, bl, 0, st, m, P.G.ncell, P.lam.as<double>(), P.vx.as<double>(),
+                           P.p.as<double>(), P.c.as<double>());
+        remaining = read_ctrl(1);
+      }
+      if (remaining > 0)
+        hipLaunchKernelGGL(k_mark_unconverged, dim3((S + 255) / 256), dim3(256), 0, st, S, P.ndone.as<int>(),
+                           P.status.as<int>());
+      hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
+                         P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.uin.as<double>(),
+                         P.part.as<double>());
+      hipLaunchKernelGGL(k_fin_balance, dim3((S + 255) / 256), dim3(256), 0, st, m, phys, P.part.as<double>(),
+                         P.uin.as<double>(), o.c_range_tol, P.stats.as<double>(), P.status.as<int>());
+    }
+    if (B.qoi) {
+      hipLaunchKernelGGL(k_qoi, grid_red(m), bl, 0, st, m, P.G, phys, P.c.as<double>(), P.part.as<double>());
+      hipLaunchKernelGGL(k_fin_sum, dim3((S + 255) / 256), dim3(256), 0, st, m, P.part.as<double>(), phys.vol, B.qoi);
+    }
+    if (B.c_T) HIPCHK(hipMemcpyAsync(B.c_T, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
+    if (B.p_T) HIPCHK(hipMemcpyAsync(B.p_T, P.p.p, P.N * 8, hipMemcpyDeviceToDevice, st));
+    if (B.status) HIPCHK(hipMemcpyAsync(B.status, P.status.p, S * sizeof(int), hipMemcpyDeviceToDevice, st));
+    if (B.stats) HIPCHK(hipMemcpyAsync(B.stats, P.stats.p, (size_t)S * 4 * 8, hipMemcpyDeviceToDevice, st));
+  }
+
+  int count_failed() {
+    zero_ctrl();
+    hipLaunchKernelGGL(k_count_nonzero, dim3((P.S + 255) / 256), dim3(256), 0, st, P.S, P.status.as<int>(),
+                       P.ctrl.as<int>() + 2);
+    return read_ctrl(2);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------
+static void check_problem(const henry_problem* pr) {
+  if (!pr) fail(HENRY_EINVAL, "problem is NULL");
+  const double v[] = {pr->Lx, pr->Ly, pr->T, pr->rho0, pr->rho1, pr->mu, pr->g, pr->Dm, pr->K_mean, pr->corr_len};
+  for (double x : v)
+    if (!(std::isfinite(x) && x > 0)) fail(HENRY_EINVAL, "problem constants must be positive and finite");
+  if (pr->n_kl_phi < 0 || pr->n_kl_phi > 4 || pr->n_kl_logK < 0 || pr->n_kl_logK > 8)
+    fail(HENRY_EINVAL, "n_kl_phi must be in [0,4] and n_kl_logK in [0,8]");
+}
+
+static void check_grid(const henry_problem& pr, henry_grid g) {
+  if (g.nx < 2 || g.ny < 2 || g.nsteps < 1) fail(HENRY_EINVAL, "grid %dx%d, %d steps is invalid", g.nx, g.ny, g.nsteps);
+  if (std::fabs(pr.Lx / g.nx - pr.Ly / g.ny) > 1e-12 * pr.Lx / g.nx)
+    fail(HENRY_EINVAL, "cells must be square: Lx/nx = %g, Ly/ny = %g", pr.Lx / g.nx, pr.Ly / g.ny);
+  if ((long long)g.nx * g.ny > (1LL << 26)) fail(HENRY_EINVAL, "grid too large");
+}
+
+static void check_opts(const henry_solver_opts& o) {
+  if (o.mg_precision != 32 && o.mg_precision != 64) fail(HENRY_EINVAL, "mg_precision must be 32 or 64");
+  if (o.nu_pre < 1 || o.nu_post < 0 || o.nu_pre > 8 || o.nu_post > 8) fail(HENRY_EINVAL, "nu_pre in [1,8], nu_post in [0,8]");
+  if (o.coarse_nx < 1 || o.coarse_ny < 1) fail(HENRY_EINVAL, "coarse grid must be positive");
+  if (!(o.newton_tol > 0) || !(o.krylov_rtol > 0) || !(o.newton_dc_max > 0)) fail(HENRY_EINVAL, "tolerances must be positive");
+  if (o.newton_maxit < 1 || o.krylov_maxit < 1) fail(HENRY_EINVAL, "iteration limits must be positive");
+}
+
+static int theta_check(henry_ctx* ctx, const double* theta, int S) {
+  DevBuf flag;
+  flag.alloc(sizeof(int));
+  HIPCHK(hipMemsetAsync(flag.p, 0, sizeof(int), ctx->stream));
+  hipLaunchKernelGGL(k_check_finite, dim3((S * 13 + 255) / 256), dim3(256), 0, ctx->stream, (size_t)S * 13, theta,
+                     flag.as<int>());
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return h;
+}
+
+template <typename F>
+static int guarded(henry_ctx* ctx, F&& f) {
+  if (!ctx) return HENRY_EINVAL;
+  try {
+    HIPCHK(hipSetDevice(ctx->device));
+    int r = f();
+    ctx->err.clear();
+    return r;
+  } catch (const HenryError& e) {
+    ctx->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return HENRY_ENOMEM;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void henry_problem_default(henry_problem* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->Lx = 2.0;
+  p->Ly = 1.0;
+  p->T = 36000.0;
+  p->rho0 = 1000.0;
+  p->rho1 = 1025.0;
+  p->mu = 1e-3;
+  p->g = 9.81;
+  p->Dm = 1.88571e-5;
+  p->phi_mean = 0.35;
+  p->phi_amp = 0.2;
+  p->phi_min = 0.2;
+  p->phi_max = 0.5;
+  p->K_mean = 1.020408e-9;
+  p->logK_amp = 0.5;
+  p->corr_len = 0.5;
+  p->q_in = 6.6e-5;
+  p->q_in_amp = 0.1;
+  p->n_kl_phi = 4;
+  p->n_kl_logK = 8;
+  p->right_c_dirichlet = 0;
+  p->c_left = 0.0;
+}
+
+void henry_solver_opts_default(henry_solver_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->mg_precision = 64;
+  o->coarse_nx = 16;
+  o->coarse_ny = 8;
+  o->nu_pre = 1;
+  o->nu_post = 1;
+  o->newton_tol = 1e-9;
+  o->newton_dc_max = 1.0;
+  o->newton_maxit = 40;
+  o->krylov_rtol = 1e-8;
+  o->krylov_maxit = 60;
+  o->c_range_tol = 1e-8;
+  o->use_graphs = 0;
+}
+
+int henry_ctx_create(henry_ctx** out, int device, void* stream) {
+  if (!out) return HENRY_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return HENRY_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return HENRY_EDEVICE;
+  auto* c = new (std::nothrow) henry_ctx;
+  if (!c) return HENRY_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (hipHostMalloc((void**)&c->h_ctrl, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return HENRY_EDEVICE;
+  }
+  *out = c;
+  return HENRY_OK;
+}
+
+void henry_ctx_destroy(henry_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  c->plans.clear();
+  if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+  delete c;
+}
+
+const char* henry_last_error(const henry_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int henry_sample_fields(henry_ctx* ctx, const henry_problem* prob, henry_grid grid, int S, const double* theta,
+                        double* phi, double* K, double* q_in) {
+  return guarded(ctx, [&]() -> int {
+    check_problem(prob);
+    check_grid(*prob, grid);
+    if (S < 1 || !theta) fail(HENRY_EINVAL, "S must be >= 1 and theta non-NULL");
+    if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
+    const Map m = make_map(S, grid.nx * grid.ny);
+    const Grid2 G{grid.nx, grid.ny, grid.nx * grid.ny};
+    const Phys P = make_phys(*prob, grid.nx, grid.ny, grid.nsteps);
+    const KLModes kl = make_kl(*prob);
+    FieldParams fp{prob->phi_mean, prob->phi_amp, prob->phi_min, prob->phi_max, std::log(prob->K_mean),
+                   prob->logK_amp, prob->q_in, prob->q_in_amp, prob->n_kl_phi, prob->n_kl_logK};
+    hipLaunchKernelGGL(k_fields, grid_cells(m, G.ncell), block_of(m), 0, ctx->stream, m, G, P, kl, fp, theta, phi, K,
+                       q_in);
+    HIPCHK(hipGetLastError());
+    return HENRY_OK;
+  });
+}
+
+int henry_solve_batch(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts, henry_batch* batches,
+                      int nbatches) {
+  return guarded(ctx, [&]() -> int {
+    check_problem(prob);
+    henry_solver_opts o;
+    if (opts) o = *opts;
+    else henry_solver_opts_default(&o);
+    check_opts(o);
+    if (nbatches < 0 || (nbatches > 0 && !batches)) fail(HENRY_EINVAL, "batches");
+    for (int b = 0; b < nbatches; ++b) {
+      check_grid(*prob, batches[b].grid);
+      if (batches[b].nsamples < 1 || !batches[b].theta) fail(HENRY_EINVAL, "batch %d: nsamples < 1 or theta NULL", b);
+      if (theta_check(ctx, batches[b].theta, batches[b].nsamples)) fail(HENRY_EINVAL, "batch %d: non-finite theta", b);
+    }
+    int failed = 0;
+    for (int b = 0; b < nbatches; ++b) {
+      const henry_batch& B = batches[b];
+      Plan* P = get_plan(ctx, B.grid.nx, B.grid.ny, B.nsamples, o);
+      Solver sv(ctx, *prob, o, *P, B.grid.nsteps);
+      if (o.mg_precision == 32) sv.run<float>(B);
+      else sv.run<double>(B);
+      HIPCHK(hipGetLastError());
+      failed += sv.count_failed();
+    }
+    return failed;
+  });
+}
+
+int henry_adjoint_batch(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts, henry_grid grid,
+                        int S, const double* theta, int checkpoint_every, double* qoi, double* dqoi_dtheta,
+                        int* status) {
+  return guarded(ctx, [&]() -> int {
+    (void)prob; (void)opts; (void)grid; (void)S; (void)theta; (void)checkpoint_every; (void)qoi;
+    (void)dqoi_dtheta; (void)status;
+    fail(HENRY_EUNSUPPORTED, "adjoint not built yet");
+    return 0;
+  });
+}
+
+int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_grid* grids, const double* const* g_fine,
+                  const double* const* g_coarse, const double* const* c_fine, const double* const* c_coarse,
+                  double alpha, double* mean, double* var_of_estimator, double* rmse, double* V_l, double* mean_field,
+                  double* var_field) {
+  return guarded(ctx, [&]() -> int {
+    if (L < 0 || !m || !g_fine) fail(HENRY_EINVAL, "L, m or g_fine invalid");
+    for (int l = 0; l <= L; ++l) {
+      if (m[l] < 1 || !g_fine[l]) fail(HENRY_EINVAL, "level %d: m < 1 or g_fine NULL", l);
+      if (l > 0 && (!g_coarse || !g_coarse[l])) fail(HENRY_EINVAL, "level %d: g_coarse NULL", l);
+    }
+    hipStream_t st = ctx->stream;
+    // scalar estimator: per level mean and unbiased variance of Y_l (two-pass, fixed order)
+    DevBuf out;
+    out.alloc((size_t)(L + 1) * 2 * sizeof(double));
+    for (int l = 0; l <= L; ++l)
+      hipLaunchKernelGGL(k_level_moments, dim3(1), dim3(256), 0, st, m[l], g_fine[l], l > 0 ? g_coarse[l] : nullptr,
+                         out.as<double>() + 2 * l);
+    std::vector<double> h(2 * (L + 1));
+    HIPCHK(hipMemcpyAsync(h.data(), out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double mu = 0.0, var = 0.0;
+    for (int l = 0; l <= L; ++l) {
+      mu += h[2 * l];
+      var += h[2 * l + 1] / m[l];
+      if (V_l) V_l[l] = h[2 * l + 1];
+    }
+    const double bias = L > 0 ? std::fabs(h[2 * L]) / (std::pow(2.0, alpha) - 1.0) : 0.0;
+    if (mean) *mean = mu;
+    if (var_of_estimator) *var_of_estimator = var;
+    if (rmse) *rmse = std::sqrt(var + bias * bias);
+    if (c_fine && (mean_field || var_field)) {
+      if (!grids) fail(HENRY_EINVAL, "grids required for field moments");
+      for (int l = 0; l <= L; ++l) {
+        if (!c_fine[l]) fail(HENRY_EINVAL, "level %d: c_fine NULL", l);
+        if (l > 0 && (!c_coarse || !c_coarse[l])) fail(HENRY_EINVAL, "level %d: c_coarse NULL", l);
+        if (l > 0 && (grids[l].nx != 2 * grids[l - 1].nx || grids[l].ny != 2 * grids[l - 1].ny))
+          fail(HENRY_EINVAL, "level %d grid is not a 2x refinement of level %d", l, l - 1);
+      }
+      const int nxL = grids[L].nx, nyL = grids[L].ny, ncL = nxL * nyL;
+      // per-level moments on each level's own grid: [mean_f, var_f, mean_c(coarse grid), var_c]
+      size_t tot = 0;
+      std::vector<size_t> off(L + 1);
+      for (int l = 0; l <= L; ++l) {
+        off[l] = tot;
+        tot += 2 * (size_t)grids[l].nx * grids[l].ny + (l > 0 ? 2 * (size_t)grids[l - 1].nx * grids[l - 1].ny : 0);
+      }
+      ctx->mlmc_tmp.alloc(tot * sizeof(double));
+      double* tmp = ctx->mlmc_tmp.as<double>();
+      for (int l = 0; l <= L; ++l) {
+        const int nc = grids[l].nx * grids[l].ny;
+        hipLaunchKernelGGL(k_cell_moments, dim3((nc + 255) / 256), dim3(256), 0, st, nc, m[l], c_fine[l], tmp + off[l],
+                           tmp + off[l] + nc);
+        if (l > 0) {
+          const int ncc = grids[l - 1].nx * grids[l - 1].ny;
+          hipLaunchKernelGGL(k_cell_moments, dim3((ncc + 255) / 256), dim3(256), 0, st, ncc, m[l], c_coarse[l],
+                             tmp + off[l] + 2 * nc, tmp + off[l] + 2 * nc + ncc);
+        }
+      }
+      FieldLevels fl{};
+      fl.L = L;
+      for (int l = 0; l <= L; ++l) {
+        fl.nx[l] = grids[l].nx;
+        fl.off[l] = (long long)off[l];
+      }
+      if (L + 1 > FieldLevels::MAXL) fail(HENRY_EUNSUPPORTED, "at most %d levels", FieldLevels::MAXL);
+      hipLaunchKernelGGL(k_field_accumulate, dim3((ncL + 255) / 256), dim3(256), 0, st, fl, nxL, nyL, tmp, mean_field,
+                         var_field);
+      HIPCHK(hipGetLastError());
+    }
+    return HENRY_OK;
+  });
+}
+
+int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, double eps, long long* m_l, double* cost) {
+  if (L < 0 || !V_l || !s_l || !(eps > 0)) return HENRY_EINVAL;
+  double tot = 0.0;
+  for (int l = 0; l <= L; ++l) {
+    if (!(V_l[l] >= 0) || !(s_l[l] > 0)) return HENRY_EINVAL;
+    tot += std::sqrt(V_l[l] * s_l[l]);
+  }
+  double c = 0.0;
+  for (int l = 0; l <= L; ++l) {
+    const double mr = 2.0 / (eps * eps) * std::sqrt(V_l[l] / s_l[l]) * tot;
+    const long long mi = (long long)std::ceil(mr);
+    if (m_l) m_l[l] = mi;
+    c += (double)mi * s_l[l];
+  }
+  if (cost) *cost = c;
+  return HENRY_OK;
+}
+
+}  // extern "C"

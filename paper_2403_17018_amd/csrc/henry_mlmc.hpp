@@ -1,0 +1,118 @@
+// Small control kernels and the MLMC estimator kernels (paper section 3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace henry {
+
+__global__ void k_zero_int(int* __restrict__ a, int n) {
+  const int t = threadIdx.x;
+  if (t < n) a[t] = 0;
+}
+
+__global__ void k_check_finite(size_t n, const double* __restrict__ a, int* __restrict__ flag) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n && !isfinite(a[t])) atomicOr(flag, 1);
+}
+
+// stats[s][1] += BiCGStab iterations of the last linear solve
+__global__ void k_accum_its(int S, const double* __restrict__ sc, double* __restrict__ stats) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S) stats[(size_t)s * 4 + 1] += sc[7 * S + s];
+}
+
+__global__ void k_mark_unconverged(int S, const int* __restrict__ ndone, int* __restrict__ status) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S && !ndone[s] && status[s] == 0) status[s] = 1;
+}
+
+__global__ void k_count_nonzero(int S, const int* __restrict__ a, int* __restrict__ count) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S && a[s] != 0) atomicAdd(count, 1);
+}
+
+// Fixed-order tree sum over 256 threads.
+__device__ __forceinline__ double block_sum_256(double v, double* lds) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  lds[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) lds[t] += lds[t + w];
+    __syncthreads();
+  }
+  return lds[0];
+}
+
+// Mean and unbiased variance of Y = g_fine - g_coarse (g_coarse may be NULL): out[0], out[1].
+__global__ void __launch_bounds__(256) k_level_moments(int m, const double* __restrict__ gf,
+                                                       const double* __restrict__ gc, double* __restrict__ out) {
+  __shared__ double lds[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) a += gf[i] - (gc ? gc[i] : 0.0);
+  const double mean = block_sum_256(a, lds) / m;
+  double q = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const double d = gf[i] - (gc ? gc[i] : 0.0) - mean;
+    q += d * d;
+  }
+  const double ss = block_sum_256(q, lds);
+  if (threadIdx.x == 0) {
+    out[0] = mean;
+    out[1] = m > 1 ? ss / (m - 1) : 0.0;
+  }
+}
+
+// Per cell: mean and unbiased variance over m samples of a [cell][m] field.
+__global__ void k_cell_moments(int ncell, int m, const double* __restrict__ f, double* __restrict__ mean,
+                               double* __restrict__ var) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const double* v = f + (size_t)c * m;
+  double a = 0.0;
+  for (int s = 0; s < m; ++s) a += v[s];
+  const double mu = a / m;
+  double q = 0.0;
+  for (int s = 0; s < m; ++s) {
+    const double d = v[s] - mu;
+    q += d * d;
+  }
+  mean[c] = mu;
+  var[c] = m > 1 ? q / (m - 1) : 0.0;
+}
+
+struct FieldLevels {
+  enum { MAXL = 8 };
+  int L;
+  int nx[MAXL];
+  long long off[MAXL];
+};
+
+// Telescoping field moments on the finest grid with piecewise-constant injection.
+__global__ void k_field_accumulate(FieldLevels fl, int nxL, int nyL, const double* __restrict__ tmp,
+                                   double* __restrict__ mean, double* __restrict__ var) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nxL * nyL) return;
+  const int j = c / nxL, i = c - j * nxL;
+  double mu = 0.0, va = 0.0;
+  for (int l = 0; l <= fl.L; ++l) {
+    const int sh = fl.L - l;
+    const int il = i >> sh, jl = j >> sh;
+    const int nxl = fl.nx[l];
+    const int nyl = nyL >> sh;
+    const int ncl = nxl * nyl;
+    const double* t = tmp + fl.off[l];
+    mu += t[jl * nxl + il];
+    va += t[ncl + jl * nxl + il];
+    if (l > 0) {
+      const int nxc = nxl >> 1, ncc = ncl >> 2;
+      const int ic = il >> 1, jc = jl >> 1;
+      mu -= t[2 * ncl + jc * nxc + ic];
+      va -= t[2 * ncl + ncc + jc * nxc + ic];
+    }
+  }
+  if (mean) mean[c] = mu;
+  if (var) var[c] = va;
+}
+
+}  // namespace henry

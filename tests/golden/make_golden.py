@@ -1,0 +1,74 @@
+"""Write oracle results at full workload sizes into tests/golden/ (calls only oracle/).
+
+The oracle needs minutes per sample at 256x128 and about an hour at 512x256, so
+the GPU parity tests at those sizes compare against these stored results for a
+few sampled realisations instead of re-running the oracle.
+
+usage: python tests/golden/make_golden.py {c2|c3|c5|all} [--procs N]
+"""
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from henry_inputs import WORKLOADS, draw_theta, level_grid  # noqa: E402
+from oracle import adjoint as A  # noqa: E402
+from oracle import henry as H  # noqa: E402
+
+
+def _forward(args):
+    name, level, seed, s = args
+    pr = H.Problem()
+    g = H.Grid(*level_grid(level))
+    th = draw_theta(seed, s + 1, level=level)[s]
+    t = time.time()
+    r = H.solve_sample(pr, g, th)
+    out = os.path.join(HERE, f"oracle_{name}_s{s}.npz")
+    np.savez_compressed(out, theta=th, c_T=r.c, p_T=r.p, qoi=r.qoi, newton_its=r.newton_its,
+                        converged=r.converged, max_salt_defect=r.max_salt_defect,
+                        nx=g.nx, ny=g.ny, nsteps=g.nsteps, seconds=time.time() - t)
+    print(out, r.qoi, r.newton_its, f"{time.time() - t:.0f}s", flush=True)
+
+
+def _adjoint(args):
+    name, level, seed, s = args
+    pr = H.Problem()
+    g = H.Grid(*level_grid(level))
+    th = draw_theta(seed, s + 1, level=level)[s]
+    t = time.time()
+    q, grad = A.adjoint_gradient(pr, g, th)
+    out = os.path.join(HERE, f"oracle_{name}_adjoint_s{s}.npz")
+    np.savez_compressed(out, theta=th, qoi=q, grad=grad, nx=g.nx, ny=g.ny, nsteps=g.nsteps,
+                        seconds=time.time() - t)
+    print(out, q, grad, f"{time.time() - t:.0f}s", flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["c2", "c3", "c5", "all"])
+    ap.add_argument("--procs", type=int, default=3)
+    a = ap.parse_args()
+    jobs = []
+    if a.which in ("c2", "all"):
+        w = WORKLOADS["c2_fp64_level3"]
+        jobs += [(_forward, ("c2", w["level"], w["seed"], s)) for s in (0, 1)]
+    if a.which in ("c5", "all"):
+        w = WORKLOADS["c5_adjoint_level3"]
+        jobs += [(_adjoint, ("c5", w["level"], w["seed"], 0))]
+    if a.which in ("c3", "all"):
+        w = WORKLOADS["c3_mixed_level4"]
+        jobs += [(_forward, ("c3", w["level"], w["seed"], 0))]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(a.procs) as pool:
+        rs = [pool.apply_async(f, (x,)) for f, x in jobs]
+        for r in rs:
+            r.get()
+
+
+if __name__ == "__main__":
+    main()
