@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched Henry solve on one MI355X.
+
+A step is one full pass of the hot path over one batch: random fields, the whole
+implicit-Euler time horizon (Newton, multigrid-preconditioned BiCGStab, coarse
+banded LU), mass balance and QoI, then the MLMC estimator over the batch.
+Default workload: MLMC level 3 (256x128 cells, 384 steps, 512 samples, seed 1), FP64.
+The metric is sample-timesteps/s = samples * time steps / wall time.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c1|c4]
+"""
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import tempfile
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from henry_inputs import WORKLOADS, draw_theta, level_grid  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+# algorithmic bytes per unit of each kernel class (FP64 / FP32 multigrid), see the design doc
+BYTES = {
+    64: dict(gs=208, spmv=208, assemble=216, restrict=196, prolong=36),
+    32: dict(gs=104, spmv=208, assemble=296, restrict=98, prolong=18),
+}
+KERNEL_NAME = dict(gs="k_gs_colour", spmv="k_spmv_dot", assemble="k_assemble", restrict="k_residual_restrict",
+                   prolong="k_prolong_correct")
+
+
+def cpu_baseline(level, seed, nsamples_avail, steps_total):
+    """Oracle on the host cores: `procs` samples of the same workload for the first few steps."""
+    procs = min(16, os.cpu_count() or 1)
+    nx, ny, _ = level_grid(level)
+    nsteps_run = 10 if level >= 3 else min(steps_total, 48)
+    code = f"""
+import sys, time, numpy as np
+sys.path.insert(0, {ROOT!r})
+from henry_inputs import draw_theta
+from oracle import henry as H
+import multiprocessing as mp
+th = draw_theta({seed}, {min(procs, nsamples_avail)}, level={level})
+pr = H.Problem(); g = H.Grid({nx}, {ny}, {steps_total})
+def one(t):
+    return H.solve_sample(pr, g, t, nsteps={nsteps_run}).newton_its
+t0 = time.time()
+with mp.get_context('fork').Pool({procs}) as p:
+    its = p.map(one, list(th))
+print(time.time() - t0, sum(its))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, check=True)
+    wall, its = out.stdout.split()
+    ns = min(procs, nsamples_avail)
+    return {"value": ns * nsteps_run / float(wall), "unit": "sample-timesteps/s", "cores": procs, "kind": "oracle",
+            "sample": f"{ns} samples x first {nsteps_run} of {steps_total} steps on {nx}x{ny} cells, one sample per "
+                      f"process (SuperLU Newton, {int(its)} Newton iterations); the first steps are the costliest, "
+                      f"so this understates the full-horizon rate"}
+
+
+def pmc_traffic(kernel, prec):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel source is unchanged."""
+    f = os.path.join(ROOT, "profiles", f"pmc_{kernel}_fp{prec}.json")
+    if not os.path.exists(f):
+        return None
+    d = json.load(open(f))
+    src = open(os.path.join(ROOT, "paper_2403_17018_amd", "csrc", "henry_kernels.hpp"), "rb").read()
+    if d.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--precision", type=int, default=None, help="multigrid precision (default: the workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(samples would shard across GPUs with one all-reduce of the MLMC sums)", file=sys.stderr)
+        sys.exit(2)
+    name = {"c1": "c1_fp64_level0", "c2": "c2_fp64_level3", "c3": "c3_mixed_level4"}[args.workload]
+    w = WORKLOADS[name]
+    prec = args.precision or w["mg_precision"]
+    level, S, seed = w["level"], w["nsamples"], w["seed"]
+    nx, ny, nsteps = level_grid(level)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(level, seed, S, nsteps)
+
+    import torch
+    import paper_2403_17018_amd as P
+
+    theta = torch.from_numpy(draw_theta(seed, S, level=level)).cuda()
+    hx = P.Henry(0)
+    g = P.grid(nx, ny, nsteps)
+    opts = P.solver_opts(mg_precision=prec)
+
+    def step():
+        r = hx.solve(theta, g, opts=opts, want_c=True)
+        est = hx.mlmc_estimate([g], [r.qoi], [None], [r.c_T], [None])
+        return r, est
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r, est = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = hx.profile_read()
+    hx.profile(False)
+    dt = (t1 - t0) / args.steps
+    nfailed = r.nfailed
+    st = r.stats.cpu()
+    # dominant kernel class by summed time
+    cls = max(BYTES[prec], key=lambda k: prof[k][2])
+    n, units, ms = prof[cls]
+    per_launch_bytes = units / n * BYTES[prec][cls]
+    achieved = per_launch_bytes / (ms / n * 1e-3) / 1e9
+    traffic = pmc_traffic(KERNEL_NAME[cls], prec)
+    out = {
+        "metric": "sample-timesteps/s",
+        "value": S * nsteps / dt,
+        "unit": "sample-timesteps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 64 else "f64+f32mg",
+        "data": "synthetic",
+        "config": {"workload": f"{name}: MLMC level {level}, {nx}x{ny} cells, {nsteps} implicit-Euler steps, "
+                               f"{S} samples (seed {seed}), {'FP64' if prec == 64 else 'FP32'} multigrid",
+                   "samples": S, "cells": nx * ny, "time_steps": nsteps, "mg_precision": prec,
+                   "parallelism": "samples batched on one GPU"},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAME[cls], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_us": ms / n * 1e3, "launches": n, "algorithmic_bytes_per_launch": per_launch_bytes},
+        "kernel_classes_ms": {k: round(v[2], 3) for k, v in prof.items()},
+        "newton_its_per_step": float(st[:, 0].mean()) / nsteps,
+        "krylov_its_per_newton": float(st[:, 1].sum() / st[:, 0].sum()),
+        "max_salt_defect": float(st[:, 3].max()),
+        "failed_samples": nfailed,
+        "mlmc_mean_qoi": est["mean"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

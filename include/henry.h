@@ -177,6 +177,25 @@ HENRY_API int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_gri
 HENRY_API int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, double eps,
                          long long* m_l, double* cost);
 
+/* Kernel-class timing on the context's stream (instrumentation for benchmarks).
+ * henry_profile(ctx, 1) resets the counters and brackets every later launch of the
+ * classes below with HIP events; henry_profile(ctx, 0) stops.  henry_profile_read()
+ * returns, for one class: launches, units processed (cell-samples; for the smoother,
+ * cells of the swept colour x samples) and the summed event time in ms.  Both calls
+ * synchronise the stream. */
+enum henry_prof_class {
+  HENRY_PROF_ASSEMBLE = 0,    /* fine-grid residual + Jacobian assembly */
+  HENRY_PROF_GS = 1,          /* fine-grid red-black GS passes that read neighbours */
+  HENRY_PROF_SPMV = 2,        /* fine-grid FP64 block SpMV with fused dots */
+  HENRY_PROF_RESTRICT = 3,    /* fine-grid fused residual + restriction */
+  HENRY_PROF_PROLONG = 4,     /* prolongation + correction onto the fine grid */
+  HENRY_PROF_BAND_FACTOR = 5, /* coarse banded LU factorisation */
+  HENRY_PROF_BAND_SOLVE = 6,  /* coarse banded triangular solves */
+  HENRY_PROF_NCLASS = 7
+};
+HENRY_API int henry_profile(henry_ctx* ctx, int enable);
+HENRY_API int henry_profile_read(henry_ctx* ctx, int cls, long long* launches, long long* units, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -190,6 +190,20 @@ class Henry:
                     var_field=var_f)
 
 
+    def profile(self, enable: bool):
+        """Start (reset) or stop event timing of kernel classes on this context's stream."""
+        self._check(self._lib.henry_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{class: (launches, units, total_ms)} for the classes in _lib.PROF_CLASSES."""
+        out = {}
+        for k, name in enumerate(L.PROF_CLASSES):
+            n, u, ms = C.c_longlong(), C.c_longlong(), C.c_double()
+            self._check(self._lib.henry_profile_read(self._h, k, C.byref(n), C.byref(u), C.byref(ms)))
+            out[name] = (n.value, u.value, ms.value)
+        return out
+
+
 def optimal_samples(V, s, eps):
     """eq. M_ell: m_l = ceil(2 eps^-2 sqrt(V_l/s_l) sum sqrt(V_i s_i)); returns (m list, cost)."""
     n = len(V)

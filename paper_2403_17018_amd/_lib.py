@@ -10,7 +10,8 @@ LIB_PATH = os.path.join(HERE, "libhenry.so")
 HENRY_OK, HENRY_EINVAL, HENRY_EDEVICE, HENRY_ENOMEM, HENRY_EUNSUPPORTED = 0, -1, -2, -3, -4
 EXPORTS = ("henry_problem_default", "henry_solver_opts_default", "henry_ctx_create", "henry_ctx_destroy",
            "henry_last_error", "henry_sample_fields", "henry_solve_batch", "henry_adjoint_batch",
-           "mlmc_estimate", "mlmc_optimal_samples")
+           "mlmc_estimate", "mlmc_optimal_samples", "henry_profile", "henry_profile_read")
+PROF_CLASSES = ("assemble", "gs", "spmv", "restrict", "prolong", "band_factor", "band_solve")
 
 
 class henry_problem(C.Structure):
@@ -70,5 +71,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlmc_estimate.restype = i
     lib.mlmc_optimal_samples.argtypes = [i, P(d), P(d), d, P(C.c_longlong), P(d)]
     lib.mlmc_optimal_samples.restype = i
+    lib.henry_profile.argtypes = [vp, i]
+    lib.henry_profile.restype = i
+    lib.henry_profile_read.argtypes = [vp, i, P(C.c_longlong), P(C.c_longlong), P(d)]
+    lib.henry_profile_read.restype = i
     _lib = lib
     return lib

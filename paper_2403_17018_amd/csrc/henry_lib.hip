@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -214,6 +215,66 @@ struct Plan {
   int mb;
 };
 
+// Optional event timing of kernel classes on the context's stream.  A ring of event
+// pairs per class is drained lazily (the oldest pair has normally completed), so
+// timing does not serialise the host with the device.
+struct Profiler {
+  static constexpr int RING = 256;
+  struct Slot {
+    hipEvent_t a = nullptr, b = nullptr;
+  };
+  struct Cls {
+    std::vector<Slot> ring;
+    size_t head = 0, used = 0;
+    long long launches = 0, units = 0;
+    double ms = 0.0;
+  };
+  bool on = false;
+  Cls c[HENRY_PROF_NCLASS];
+
+  void drain_one(Cls& k, Slot& sl) {
+    HIPCHK(hipEventSynchronize(sl.b));
+    float e = 0.f;
+    HIPCHK(hipEventElapsedTime(&e, sl.a, sl.b));
+    k.ms += e;
+  }
+  Slot& acquire(int cls) {
+    Cls& k = c[cls];
+    if (k.ring.size() < RING) {
+      k.ring.emplace_back();
+      Slot& sl = k.ring.back();
+      HIPCHK(hipEventCreate(&sl.a));
+      HIPCHK(hipEventCreate(&sl.b));
+      k.used++;
+      return sl;
+    }
+    Slot& sl = k.ring[k.head];
+    k.head = (k.head + 1) % RING;
+    drain_one(k, sl);
+    return sl;
+  }
+  void flush() {
+    for (auto& k : c) {
+      const size_t n = k.ring.size();
+      if (n < RING) {
+        for (size_t i = 0; i < n; ++i) drain_one(k, k.ring[i]);
+      } else {
+        for (size_t i = 0; i < RING; ++i) drain_one(k, k.ring[(k.head + i) % RING]);
+      }
+      for (auto& sl : k.ring) {
+        (void)hipEventDestroy(sl.a);
+        (void)hipEventDestroy(sl.b);
+      }
+      k.ring.clear();
+      k.head = k.used = 0;
+    }
+  }
+  void reset() {
+    flush();
+    for (auto& k : c) k.launches = k.units = 0, k.ms = 0.0;
+  }
+};
+
 struct henry_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -221,7 +282,23 @@ struct henry_ctx {
   std::map<std::tuple<int, int, int, int, int, int>, std::unique_ptr<Plan>> plans;
   int* h_ctrl = nullptr;   // pinned
   DevBuf mlmc_tmp;
+  Profiler prof;
 };
+
+// Launch `f` and, when profiling, bracket it with events of class `cls`.
+template <typename F>
+static void timed(henry_ctx* ctx, int cls, long long units, F&& f) {
+  if (!ctx->prof.on) {
+    f();
+    return;
+  }
+  auto& sl = ctx->prof.acquire(cls);
+  HIPCHK(hipEventRecord(sl.a, ctx->stream));
+  f();
+  HIPCHK(hipEventRecord(sl.b, ctx->stream));
+  ctx->prof.c[cls].launches++;
+  ctx->prof.c[cls].units += units;
+}
 
 template <typename T>
 static void plan_alloc_levels(Plan& P) {
@@ -365,14 +442,16 @@ struct Solver {
   template <typename T>
   void assemble_all() {
     const Map& m = P.m;
-    if (P.prec == 32)
-      hipLaunchKernelGGL((k_assemble<true, double, true>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
-                         phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
-                         P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J.as<double>(), P.J32.as<float>());
-    else
-      hipLaunchKernelGGL((k_assemble<true, double, false>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
-                         phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
-                         P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J.as<double>(), (float*)nullptr);
+    timed(ctx, HENRY_PROF_ASSEMBLE, (long long)P.N, [&] {
+      if (P.prec == 32)
+        hipLaunchKernelGGL((k_assemble<true, double, true>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
+                           phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
+                           P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J.as<double>(), P.J32.as<float>());
+      else
+        hipLaunchKernelGGL((k_assemble<true, double, false>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
+                           phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
+                           P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J.as<double>(), (float*)nullptr);
+    });
     for (int k = 1; k < P.nlev; ++k) {
       MGLevel& F = *P.lv[k - 1];
       MGLevel& C = *P.lv[k];
@@ -387,8 +466,10 @@ struct Solver {
     }
     const MGLevel& Cc = *P.lv[P.nlev - 1];
     const size_t lds = (size_t)(P.mb + 1) * (P.mb + 1) * 4 * sizeof(T);
-    hipLaunchKernelGGL((k_band_factor<T>), dim3(P.S), dim3(64), lds, st, P.S, Cc.nx, Cc.ny, level_J<T>(P.nlev - 1),
-                       P.LU.as<T>());
+    timed(ctx, HENRY_PROF_BAND_FACTOR, (long long)Cc.ncell * P.S, [&] {
+      hipLaunchKernelGGL((k_band_factor<T>), dim3(P.S), dim3(64), lds, st, P.S, Cc.nx, Cc.ny, level_J<T>(P.nlev - 1),
+                         P.LU.as<T>());
+    });
   }
 
   template <typename T>
@@ -404,24 +485,42 @@ struct Solver {
     MGLevel& L = *P.lv[k];
     if (k == P.nlev - 1) {
       const size_t lds = (size_t)(P.mb + 1) * 2 * sizeof(T);
-      hipLaunchKernelGGL((k_band_solve<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, P.LU.as<T>(), b, x);
+      timed(ctx, HENRY_PROF_BAND_SOLVE, (long long)L.ncell * P.S, [&] {
+        hipLaunchKernelGGL((k_band_solve<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, P.LU.as<T>(), b, x);
+      });
       return;
     }
     const T* J = level_J<T>(k);
     const int half = (L.nx + 1) / 2;
     const dim3 gg = grid_cells(m, L.ny * half);
+    // fine-grid smoother passes that read neighbours are timed as one class
+    const long long half_units = (long long)L.ny * half * P.S;
+    auto gs = [&](int colour, int xz) {
+      auto f = [&] { hipLaunchKernelGGL((k_gs_colour<T>), gg, block_of(m), 0, st, m, L.G, colour, xz, J, b, x); };
+      if (k == 0 && !xz) timed(ctx, HENRY_PROF_GS, half_units, f);
+      else f();
+    };
     for (int sw = 0; sw < o.nu_pre; ++sw) {
-      hipLaunchKernelGGL((k_gs_colour<T>), gg, block_of(m), 0, st, m, L.G, 0, sw == 0 ? 1 : 0, J, b, x);
-      hipLaunchKernelGGL((k_gs_colour<T>), gg, block_of(m), 0, st, m, L.G, 1, 0, J, b, x);
+      gs(0, sw == 0 ? 1 : 0);
+      gs(1, 0);
     }
     MGLevel& C = *P.lv[k + 1];
-    hipLaunchKernelGGL((k_residual_restrict<T>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G, J, b, x,
-                       C.b.as<T>());
+    auto rr = [&] {
+      hipLaunchKernelGGL((k_residual_restrict<T>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G, J, b, x,
+                         C.b.as<T>());
+    };
+    if (k == 0) timed(ctx, HENRY_PROF_RESTRICT, (long long)L.ncell * P.S, rr);
+    else rr();
     vcycle<T>(k + 1, C.b.as<T>(), C.x.as<T>());
-    hipLaunchKernelGGL((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G, C.x.as<T>(), x);
+    auto pc = [&] {
+      hipLaunchKernelGGL((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G, C.x.as<T>(),
+                         x);
+    };
+    if (k == 0) timed(ctx, HENRY_PROF_PROLONG, (long long)L.ncell * P.S, pc);
+    else pc();
     for (int sw = 0; sw < o.nu_post; ++sw) {
-      hipLaunchKernelGGL((k_gs_colour<T>), gg, block_of(m), 0, st, m, L.G, 0, 0, J, b, x);
-      hipLaunchKernelGGL((k_gs_colour<T>), gg, block_of(m), 0, st, m, L.G, 1, 0, J, b, x);
+      gs(0, 0);
+      gs(1, 0);
     }
   }
 
@@ -460,14 +559,18 @@ struct Solver {
       hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, it == 0 ? 1 : 0, sc, P.vr.as<double>(),
                          P.vv.as<double>(), P.vp.as<double>());
       precond<T>(P.vp.as<double>(), P.vph.as<double>());
-      hipLaunchKernelGGL(k_spmv_dot<1>, rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vph.as<double>(), P.vv.as<double>(),
-                         P.vrh.as<double>(), P.part.as<double>());
+      timed(ctx, HENRY_PROF_SPMV, (long long)P.N, [&] {
+        hipLaunchKernelGGL(k_spmv_dot<1>, rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vph.as<double>(),
+                           P.vv.as<double>(), P.vrh.as<double>(), P.part.as<double>());
+      });
       hipLaunchKernelGGL(k_fin_alpha, fg, fb, 0, st, m, P.part.as<double>(), sc, status);
       hipLaunchKernelGGL(k_bicg_s, cg, bl, 0, st, m, P.G.ncell, sc, P.vr.as<double>(), P.vv.as<double>(),
                          P.vs.as<double>());
       precond<T>(P.vs.as<double>(), P.vsh.as<double>());
-      hipLaunchKernelGGL(k_spmv_dot<2>, rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vsh.as<double>(), P.vt.as<double>(),
-                         P.vs.as<double>(), P.part.as<double>());
+      timed(ctx, HENRY_PROF_SPMV, (long long)P.N, [&] {
+        hipLaunchKernelGGL(k_spmv_dot<2>, rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vsh.as<double>(),
+                           P.vt.as<double>(), P.vs.as<double>(), P.part.as<double>());
+      });
       hipLaunchKernelGGL(k_fin_omega, fg, fb, 0, st, m, P.part.as<double>(), sc);
       hipLaunchKernelGGL(k_bicg_xr, rg, bl, 0, st, m, P.G.ncell, sc, P.vph.as<double>(), P.vsh.as<double>(),
                          P.vs.as<double>(), P.vt.as<double>(), P.vrh.as<double>(), P.vx.as<double>(), P.vr.as<double>(),
@@ -489,7 +592,13 @@ struct Solver {
     HIPCHK(hipMemsetAsync(P.status.p, 0, S * sizeof(int), st));
     HIPCHK(hipMemsetAsync(P.stats.p, 0, (size_t)S * 4 * sizeof(double), st));
     const double p_ref = pr.rho0 * pr.g * pr.Ly;
+    const char* pe = std::getenv("HENRY_PROGRESS");
+    const int every = pe ? std::max(1, std::atoi(pe)) : 0;
     for (int n = 0; n < B.grid.nsteps; ++n) {
+      if (every && (n % every == 0 || n == B.grid.nsteps - 1)) {
+        std::fprintf(stderr, "[henry] %dx%d S=%d fp%d step %d/%d\n", P.nx, P.ny, S, P.prec, n + 1, B.grid.nsteps);
+        std::fflush(stderr);
+      }
       HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
       int remaining = S;
@@ -658,6 +767,10 @@ void henry_ctx_destroy(henry_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  try {
+    c->prof.flush();
+  } catch (const HenryError&) {
+  }
   c->plans.clear();
   if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
   delete c;
@@ -793,6 +906,41 @@ int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_grid* grids, 
                          var_field);
       HIPCHK(hipGetLastError());
     }
+    return HENRY_OK;
+  });
+}
+
+int henry_profile(henry_ctx* ctx, int enable) {
+  return guarded(ctx, [&]() -> int {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (enable) {
+      ctx->prof.reset();
+      ctx->prof.on = true;
+    } else {
+      ctx->prof.on = false;
+    }
+    return HENRY_OK;
+  });
+}
+
+int henry_profile_read(henry_ctx* ctx, int cls, long long* launches, long long* units, double* total_ms) {
+  return guarded(ctx, [&]() -> int {
+    if (cls < 0 || cls >= HENRY_PROF_NCLASS) fail(HENRY_EINVAL, "profile class %d", cls);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    auto& k = ctx->prof.c[cls];
+    // drain completed pairs without dropping the class's accumulated totals
+    const size_t n = k.ring.size();
+    for (size_t i = 0; i < n; ++i) {
+      auto& sl = k.ring[(k.head + i) % n];
+      ctx->prof.drain_one(k, sl);
+      (void)hipEventDestroy(sl.a);
+      (void)hipEventDestroy(sl.b);
+    }
+    k.ring.clear();
+    k.head = k.used = 0;
+    if (launches) *launches = k.launches;
+    if (units) *units = k.units;
+    if (total_ms) *total_ms = k.ms;
     return HENRY_OK;
   });
 }
