@@ -370,10 +370,12 @@ __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, int colour, i
 }
 
 // Fused residual and restriction: b_H(I,J) = sum over the 2x2 children of (b - A x).
+// red_only: the last smoothing pass was the black one, which leaves a zero residual
+// on black cells, so only the two red children are evaluated.
 template <typename T>
-__global__ void __launch_bounds__(256) k_residual_restrict(Map m, Grid2 Gf, Grid2 Gc, const T* __restrict__ J,
-                                                           const T* __restrict__ b, const T* __restrict__ x,
-                                                           T* __restrict__ bH) {
+__global__ void __launch_bounds__(256) k_residual_restrict(Map m, Grid2 Gf, Grid2 Gc, int red_only,
+                                                           const T* __restrict__ J, const T* __restrict__ b,
+                                                           const T* __restrict__ x, T* __restrict__ bH) {
   int s, cc, sb, cb;
   if (!map_cell(m, Gc.ncell, s, cc, sb, cb)) return;
   const int S = m.S;
@@ -383,6 +385,7 @@ __global__ void __launch_bounds__(256) k_residual_restrict(Map m, Grid2 Gf, Grid
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int i = 2 * Ic + (q & 1), j = 2 * Jc + (q >> 1);
+    if (red_only && ((i + j) & 1)) continue;
     const size_t id = ((size_t)j * Gf.nx + i) * S + s;
     T a0, a1;
     apply_row<T, T>(J, x, Nf, id, i, j, Gf.nx, Gf.ny, S, a0, a1, false);
@@ -573,86 +576,80 @@ __global__ void __launch_bounds__(64) k_band_factor(int S, int nxc, int nyc, con
 }
 
 // Forward/backward substitution with the banded factors: x = (LU)^{-1} b, one
-// wavefront per sample, a circular (m+1)-block window of partial sums in LDS.
+// wavefront per sample.  The whole right-hand side lives in LDS; the factor blocks
+// are staged into LDS in chunks of CH block rows, so a global-load latency is paid
+// once per chunk instead of once per row.  One barrier per row.
+// LDS layout (T): y[2n] | x[2n] | stage[CH*mb*4 + (CH+mb)*mb*4 + CH*4]
 template <typename T>
-__global__ void __launch_bounds__(64) k_band_solve(int S, int nxc, int nyc, const T* __restrict__ LU,
+__global__ void __launch_bounds__(64) k_band_solve(int S, int nxc, int nyc, int CH, const T* __restrict__ LU,
                                                    const T* __restrict__ b, T* __restrict__ x) {
   extern __shared__ unsigned char smem_raw[];
-  T* yw = reinterpret_cast<T*>(smem_raw);
   const int s = blockIdx.x;
   const int lane = threadIdx.x;
-  const int n = nxc * nyc, mb = nyc, w = mb + 1;
+  const int n = nxc * nyc, mb = nyc;
+  T* y = reinterpret_cast<T*>(smem_raw);
+  T* xs = y + 2 * n;
+  T* Ls = xs + 2 * n;                    // [CH][mb][4]
+  T* Us = Ls + (size_t)CH * mb * 4;      // [CH+mb][mb][4]
+  T* Ds = Us + (size_t)(CH + mb) * mb * 4;  // [CH][4]
   const size_t N = (size_t)n * S;
   const T* Dg = LU + (size_t)s * n * (2 * mb + 1) * 4;
   const T* Lg = Dg + (size_t)n * 4;
   const T* Ug = Lg + (size_t)n * mb * 4;
-  auto gidx = [&](int q) -> size_t {
+  for (int q = lane; q < n; q += 64) {
     const int i = q / nyc, j = q - i * nyc;
-    return ((size_t)j * nxc + i) * S + s;
-  };
-  // forward: y = L^{-1} b (unit lower), column oriented; y_k stored in x
-  for (int t = lane; t < w && t < n; t += 64) {
-    const size_t g = gidx(t);
-    yw[2 * t] = b[g];
-    yw[2 * t + 1] = b[N + g];
+    const size_t g = ((size_t)j * nxc + i) * S + s;
+    y[2 * q] = b[g];
+    y[2 * q + 1] = b[N + g];
   }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const int rk = k % w;
-    const T y0 = yw[2 * rk], y1 = yw[2 * rk + 1];
-    const int nrow = (n - 1 - k) < mb ? (n - 1 - k) : mb;
-    if (lane == 0) {
-      const size_t g = gidx(k);
-      x[g] = y0;
-      x[N + g] = y1;
-    }
+  // forward: y = L^{-1} b, column oriented
+  for (int k0 = 0; k0 < n; k0 += CH) {
+    const int k1 = (k0 + CH < n ? k0 + CH : n);
+    for (int t = lane; t < (k1 - k0) * mb * 4; t += 64) Ls[t] = Lg[(size_t)k0 * mb * 4 + t];
     __syncthreads();
-    for (int t = lane; t < nrow; t += 64) {
-      const int ri = (k + 1 + t) % w;
-      const T* L = Lg + ((size_t)k * mb + t) * 4;
-      yw[2 * ri] -= L[0] * y0 + L[1] * y1;
-      yw[2 * ri + 1] -= L[2] * y0 + L[3] * y1;
+    for (int k = k0; k < k1; ++k) {
+      const T y0 = y[2 * k], y1 = y[2 * k + 1];
+      const int nrow = (n - 1 - k) < mb ? (n - 1 - k) : mb;
+      if (lane < nrow) {
+        const T* L = Ls + ((k - k0) * mb + lane) * 4;
+        const int r = k + 1 + lane;
+        y[2 * r] -= L[0] * y0 + L[1] * y1;
+        y[2 * r + 1] -= L[2] * y0 + L[3] * y1;
+      }
+      __syncthreads();
     }
-    if (lane == 0 && k + w < n) {
-      const size_t g = gidx(k + w);
-      yw[2 * rk] = b[g];
-      yw[2 * rk + 1] = b[N + g];
-    }
-    __syncthreads();
   }
-  // backward: x = U^{-1} y with U = Dinv^{-1} + strict upper part, column oriented
-  for (int t = lane; t < w && t < n; t += 64) {
-    const int q = n - 1 - t;
-    const size_t g = gidx(q);
-    yw[2 * (q % w)] = x[g];
-    yw[2 * (q % w) + 1] = x[N + g];
+  // backward: x = U^{-1} y, U = Dinv^{-1} + strict upper part, column oriented.
+  // Steps k in [k0, k1) (descending) need Dinv_k and U rows [k0 - mb, k1 - 1].
+  for (int k1 = n; k1 > 0; k1 -= CH) {
+    const int k0 = (k1 - CH > 0 ? k1 - CH : 0);
+    const int r0 = (k0 - mb > 0 ? k0 - mb : 0);
+    for (int t = lane; t < (k1 - r0) * mb * 4; t += 64) Us[t] = Ug[(size_t)r0 * mb * 4 + t];
+    for (int t = lane; t < (k1 - k0) * 4; t += 64) Ds[t] = Dg[(size_t)k0 * 4 + t];
+    __syncthreads();
+    for (int k = k1 - 1; k >= k0; --k) {
+      const T* Di = Ds + (k - k0) * 4;
+      const T v0 = y[2 * k], v1 = y[2 * k + 1];
+      const T x0 = Di[0] * v0 + Di[1] * v1, x1 = Di[2] * v0 + Di[3] * v1;
+      const int nrow = k < mb ? k : mb;
+      if (lane < nrow) {
+        const int row = k - 1 - lane;    // U_{row, k} = U block (row, lane)
+        const T* U = Us + ((row - r0) * mb + lane) * 4;
+        y[2 * row] -= U[0] * x0 + U[1] * x1;
+        y[2 * row + 1] -= U[2] * x0 + U[3] * x1;
+      }
+      if (lane == 0) {
+        xs[2 * k] = x0;
+        xs[2 * k + 1] = x1;
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
-  for (int k = n - 1; k >= 0; --k) {
-    const int rk = k % w;
-    const T* Di = Dg + (size_t)k * 4;
-    const T v0 = yw[2 * rk], v1 = yw[2 * rk + 1];
-    const T x0 = Di[0] * v0 + Di[1] * v1, x1 = Di[2] * v0 + Di[3] * v1;
-    __syncthreads();
-    if (lane == 0) {
-      const size_t g = gidx(k);
-      x[g] = x0;
-      x[N + g] = x1;
-    }
-    const int nrow = k < mb ? k : mb;
-    for (int t = lane; t < nrow; t += 64) {
-      const int row = k - 1 - t;
-      const T* U = Ug + ((size_t)row * mb + t) * 4;   // U_{row, row+1+t} with row+1+t = k
-      const int ri = row % w;
-      yw[2 * ri] -= U[0] * x0 + U[1] * x1;
-      yw[2 * ri + 1] -= U[2] * x0 + U[3] * x1;
-    }
-    if (lane == 0 && k - w >= 0) {
-      const size_t g = gidx(k - w);
-      yw[2 * rk] = x[g];
-      yw[2 * rk + 1] = x[N + g];
-    }
-    __syncthreads();
+  for (int q = lane; q < n; q += 64) {
+    const int i = q / nyc, j = q - i * nyc;
+    const size_t g = ((size_t)j * nxc + i) * S + s;
+    x[g] = xs[2 * q];
+    x[N + g] = xs[2 * q + 1];
   }
 }
 
@@ -806,9 +803,20 @@ __device__ __forceinline__ void reduce_partials(const Map& m, const double* __re
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] = 0.0;
   if (s < m.S) {
-    for (int cb = threadIdx.y; cb < m.ncb; cb += blockDim.y) {
+    const int st = blockDim.y;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) v[q] += part[((size_t)q * m.ncb + cb) * m.S + s];
+    for (int q = 0; q < NQ; ++q) {
+      const double* pq = part + (size_t)q * m.ncb * m.S + s;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int cb = threadIdx.y;
+      for (; cb + 3 * st < m.ncb; cb += 4 * st) {
+        a0 += pq[(size_t)cb * m.S];
+        a1 += pq[(size_t)(cb + st) * m.S];
+        a2 += pq[(size_t)(cb + 2 * st) * m.S];
+        a3 += pq[(size_t)(cb + 3 * st) * m.S];
+      }
+      for (; cb < m.ncb; cb += st) a0 += pq[(size_t)cb * m.S];
+      v[q] = (a0 + a1) + (a2 + a3);
     }
   }
   block_sum_y<NQ>(v, lds);
@@ -816,10 +824,32 @@ __device__ __forceinline__ void reduce_partials(const Map& m, const double* __re
   for (int q = 0; q < NQ; ++q) out[q] = v[q];
 }
 
-// Finalisation kernels: blockDim = (64, 4), grid = ceil(S/64).  ctrl[0] counts active samples.
-__global__ void __launch_bounds__(256) k_fin_init(Map m, const double* __restrict__ part, double* __restrict__ sc,
+template <int NQ>
+__device__ __forceinline__ void reduce_partials_max(const Map& m, const double* __restrict__ part, int s,
+                                                    double (&out)[NQ], double* lds) {
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  if (s < m.S) {
+    for (int cb = threadIdx.y; cb < m.ncb; cb += blockDim.y) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const double a = part[((size_t)q * m.ncb + cb) * m.S + s];
+        v[q] = (a > v[q] || a != a) ? a : v[q];
+      }
+    }
+  }
+  block_max_y<NQ>(v, lds);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) out[q] = v[q];
+}
+
+// Finalisation kernels: blockDim = (64, FIN_Y), grid = ceil(S/64).  ctrl[0] counts active samples.
+constexpr int FIN_Y = 16;
+
+__global__ void __launch_bounds__(64 * FIN_Y) k_fin_init(Map m, const double* __restrict__ part, double* __restrict__ sc,
                                                   int* __restrict__ ctrl) {
-  __shared__ double lds[256];
+  __shared__ double lds[64 * FIN_Y];
   const int s = blockIdx.x * 64 + threadIdx.x;
   double v[1];
   reduce_partials<1>(m, part, s, v, lds);
@@ -838,9 +868,9 @@ __global__ void __launch_bounds__(256) k_fin_init(Map m, const double* __restric
   }
 }
 
-__global__ void __launch_bounds__(256) k_fin_alpha(Map m, const double* __restrict__ part, double* __restrict__ sc,
-                                                   int* __restrict__ status) {
-  __shared__ double lds[256];
+__global__ void __launch_bounds__(64 * FIN_Y) k_fin_alpha(Map m, const double* __restrict__ part,
+                                                          double* __restrict__ sc, int* __restrict__ status) {
+  __shared__ double lds[64 * FIN_Y];
   const int s = blockIdx.x * 64 + threadIdx.x;
   double v[1];
   reduce_partials<1>(m, part, s, v, lds);
@@ -859,8 +889,9 @@ __global__ void __launch_bounds__(256) k_fin_alpha(Map m, const double* __restri
   }
 }
 
-__global__ void __launch_bounds__(256) k_fin_omega(Map m, const double* __restrict__ part, double* __restrict__ sc) {
-  __shared__ double lds[2 * 256];
+__global__ void __launch_bounds__(64 * FIN_Y) k_fin_omega(Map m, const double* __restrict__ part,
+                                                          double* __restrict__ sc) {
+  __shared__ double lds[2 * 64 * FIN_Y];
   const int s = blockIdx.x * 64 + threadIdx.x;
   double v[2];
   reduce_partials<2>(m, part, s, v, lds);
@@ -872,9 +903,10 @@ __global__ void __launch_bounds__(256) k_fin_omega(Map m, const double* __restri
   }
 }
 
-__global__ void __launch_bounds__(256) k_fin_rho(Map m, const double* __restrict__ part, double* __restrict__ sc,
-                                                 double rtol2, int* __restrict__ status, int* __restrict__ ctrl) {
-  __shared__ double lds[2 * 256];
+__global__ void __launch_bounds__(64 * FIN_Y) k_fin_rho(Map m, const double* __restrict__ part,
+                                                        double* __restrict__ sc, double rtol2, int* __restrict__ status,
+                                                        int* __restrict__ ctrl) {
+  __shared__ double lds[2 * 64 * FIN_Y];
   const int s = blockIdx.x * 64 + threadIdx.x;
   double v[2];
   reduce_partials<2>(m, part, s, v, lds);
@@ -941,18 +973,16 @@ __global__ void __launch_bounds__(256) k_delta_max(Map m, int ncell, const doubl
 // Per sample: damping factor lambda = min(1, dc_max/|dc|_inf); convergence on the
 // undamped update; non-finite updates freeze the sample.  ctrl[1] counts samples
 // still iterating.  stats[s][0] counts Newton iterations.
-__global__ void __launch_bounds__(256) k_fin_newton(Map m, const double* __restrict__ part, double p_ref, double tol,
-                                                    double dc_max, double* __restrict__ lam, int* __restrict__ ndone,
-                                                    int* __restrict__ status, double* __restrict__ stats,
-                                                    int* __restrict__ ctrl) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= m.S) return;
-  double mp = 0.0, mc = 0.0;
-  for (int cb = 0; cb < m.ncb; ++cb) {
-    const double a = part[(size_t)cb * m.S + s], b = part[((size_t)m.ncb + cb) * m.S + s];
-    mp = (a > mp || a != a) ? a : mp;
-    mc = (b > mc || b != b) ? b : mc;
-  }
+__global__ void __launch_bounds__(64 * FIN_Y) k_fin_newton(Map m, const double* __restrict__ part, double p_ref,
+                                                           double tol, double dc_max, double* __restrict__ lam,
+                                                           int* __restrict__ ndone, int* __restrict__ status,
+                                                           double* __restrict__ stats, int* __restrict__ ctrl) {
+  __shared__ double lds[2 * 64 * FIN_Y];
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  double v[2];
+  reduce_partials_max<2>(m, part, s, v, lds);
+  if (threadIdx.y != 0 || s >= m.S) return;
+  const double mp = v[0], mc = v[1];
   if (ndone[s]) {
     lam[s] = 0.0;
     return;
@@ -1033,25 +1063,23 @@ __global__ void __launch_bounds__(256) k_balance(Map m, Grid2 G, Phys P, const d
   if (threadIdx.y == 0 && sv) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) part[((size_t)q * m.ncb + cblk) * m.S + s] = acc[q];
-    part[((size_t)4 * m.ncb + cblk) * m.S + s] = -mn[0];
+    part[((size_t)4 * m.ncb + cblk) * m.S + s] = mn[0];   // -min c
     part[((size_t)5 * m.ncb + cblk) * m.S + s] = mx[0];
   }
 }
 
 // stats[s][2..3] = running max of |storage change + tau * boundary outflux| / (tau rho0 u_in Ly)
-__global__ void k_fin_balance(Map m, Phys P, const double* __restrict__ part, const double* __restrict__ uin,
-                              double c_tol, double* __restrict__ stats, int* __restrict__ status) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= m.S) return;
-  double a[4] = {0, 0, 0, 0};
-  double mn = 0.0, mx = 0.0;
-  for (int cb = 0; cb < m.ncb; ++cb) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] += part[((size_t)q * m.ncb + cb) * m.S + s];
-    const double lo = part[((size_t)4 * m.ncb + cb) * m.S + s], hi = part[((size_t)5 * m.ncb + cb) * m.S + s];
-    mn = (lo < mn || lo != lo) ? lo : mn;
-    mx = (hi > mx || hi != hi) ? hi : mx;
-  }
+__global__ void __launch_bounds__(64 * FIN_Y) k_fin_balance(Map m, Phys P, const double* __restrict__ part,
+                                                            const double* __restrict__ uin, double c_tol,
+                                                            double* __restrict__ stats, int* __restrict__ status) {
+  __shared__ double lds[4 * 64 * FIN_Y];
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  double a[4];
+  reduce_partials<4>(m, part, s, a, lds);
+  double e[2];
+  reduce_partials_max<2>(m, part + (size_t)4 * m.ncb * m.S, s, e, lds);   // [4] = -min c, [5] = max c
+  if (threadIdx.y != 0 || s >= m.S) return;
+  const double mn = -e[0], mx = e[1];
   const double scale = P.tau * P.rho0 * uin[s] * P.Ly;
   const double df = fabs(a[0] + a[2]) / scale, ds = fabs(a[1] + a[3]) / scale;
   double* st = stats + (size_t)s * 4;
@@ -1081,12 +1109,13 @@ __global__ void __launch_bounds__(256) k_qoi(Map m, Grid2 G, Phys P, const doubl
   if (threadIdx.y == 0 && sv) part[(size_t)cblk * m.S + s] = acc[0];
 }
 
-__global__ void k_fin_sum(Map m, const double* __restrict__ part, double scale, double* __restrict__ out) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= m.S) return;
-  double a = 0.0;
-  for (int cb = 0; cb < m.ncb; ++cb) a += part[(size_t)cb * m.S + s];
-  out[s] = a * scale;
+__global__ void __launch_bounds__(64 * FIN_Y) k_fin_sum(Map m, const double* __restrict__ part, double scale,
+                                                        double* __restrict__ out) {
+  __shared__ double lds[64 * FIN_Y];
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  double a[1];
+  reduce_partials<1>(m, part, s, a, lds);
+  if (threadIdx.y == 0 && s < m.S) out[s] = a[0] * scale;
 }
 
 }  // namespace henry

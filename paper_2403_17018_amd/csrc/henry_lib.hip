@@ -155,8 +155,12 @@ static Map make_map(int S, int ncell) {
   m.SX = S <= 64 ? S : 64;
   m.CY = std::max(1, 256 / m.SX);
   m.nsb = (S + m.SX - 1) / m.SX;
-  // reduction kernels: CPT cells per thread so that about 4096 blocks cover the batch
-  const int target_cb = std::max(1, 4096 / m.nsb);
+  // reduction kernels: CPT cells per thread so that about `target` blocks cover the batch
+  static const int target = [] {
+    const char* e = std::getenv("HENRY_RED_BLOCKS");
+    return e ? std::max(64, std::atoi(e)) : 4096;
+  }();
+  const int target_cb = std::max(1, target / m.nsb);
   const int rows = (ncell + m.CY - 1) / m.CY;
   m.CPT = std::max(1, (rows + target_cb - 1) / target_cb);
   m.ncb = (rows + m.CPT - 1) / m.CPT;
@@ -170,6 +174,18 @@ static dim3 grid_cells(const Map& m, int ncell) {
 static dim3 grid_red(const Map& m) { return dim3((unsigned)((long long)m.nsb * m.ncb)); }
 static dim3 block_of(const Map& m) { return dim3(m.SX, m.CY); }
 static dim3 fin_grid(int S) { return dim3((S + 63) / 64); }
+
+// LDS of the banded solve: y and x (2n each) plus CH rows of L, CH + mb rows of U, CH Dinv.
+template <typename T>
+static size_t band_solve_lds(int n, int mb, int CH) {
+  return (size_t)(4 * n + CH * mb * 4 + (CH + mb) * mb * 4 + CH * 4) * sizeof(T);
+}
+template <typename T>
+static int band_chunk(int n, int mb) {
+  int CH = 64;
+  while (CH > 1 && band_solve_lds<T>(n, mb, CH) > 64 * 1024) CH /= 2;
+  return CH;
+}
 
 static Phys make_phys(const henry_problem& pr, int nx, int ny, int nsteps) {
   Phys P{};
@@ -353,6 +369,11 @@ static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_
   }
   P->nlev = (int)P->lv.size();
   if (P->lv.back()->ny > 44) fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d: band width %d exceeds 44", gx, gy, gy);
+  {
+    const int n = P->lv.back()->ncell, mb = P->lv.back()->ny;
+    const size_t need = o.mg_precision == 32 ? band_solve_lds<float>(n, mb, 1) : band_solve_lds<double>(n, mb, 1);
+    if (need > 64 * 1024) fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d too large for the LDS banded solve", gx, gy);
+  }
   for (int k = 0; k + 1 < P->nlev; ++k)
     if (P->lv[k]->nx & 1) fail(HENRY_EUNSUPPORTED, "multigrid level %d has odd nx", k);
   const size_t N = P->N;
@@ -484,9 +505,10 @@ struct Solver {
     const Map& m = P.m;
     MGLevel& L = *P.lv[k];
     if (k == P.nlev - 1) {
-      const size_t lds = (size_t)(P.mb + 1) * 2 * sizeof(T);
+      const int CH = band_chunk<T>(L.ncell, P.mb);
+      const size_t lds = band_solve_lds<T>(L.ncell, P.mb, CH);
       timed(ctx, HENRY_PROF_BAND_SOLVE, (long long)L.ncell * P.S, [&] {
-        hipLaunchKernelGGL((k_band_solve<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, P.LU.as<T>(), b, x);
+        hipLaunchKernelGGL((k_band_solve<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, CH, P.LU.as<T>(), b, x);
       });
       return;
     }
@@ -506,8 +528,8 @@ struct Solver {
     }
     MGLevel& C = *P.lv[k + 1];
     auto rr = [&] {
-      hipLaunchKernelGGL((k_residual_restrict<T>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G, J, b, x,
-                         C.b.as<T>());
+      hipLaunchKernelGGL((k_residual_restrict<T>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G, 1, J, b,
+                         x, C.b.as<T>());
     };
     if (k == 0) timed(ctx, HENRY_PROF_RESTRICT, (long long)L.ncell * P.S, rr);
     else rr();
@@ -548,7 +570,7 @@ struct Solver {
     int* ctrl = P.ctrl.as<int>();
     int* status = P.status.as<int>();
     const dim3 rg = grid_red(m), bl = block_of(m), cg = grid_cells(m, P.G.ncell);
-    const dim3 fg = fin_grid(S), fb(64, 4);
+    const dim3 fg = fin_grid(S), fb(64, FIN_Y);
     hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, P.R.as<double>(), P.ndone.as<int>(), P.vr.as<double>(),
                        P.vrh.as<double>(), P.vx.as<double>(), P.part.as<double>());
     zero_ctrl();
@@ -607,7 +629,7 @@ struct Solver {
         bicgstab<T>();
         hipLaunchKernelGGL(k_delta_max, grid_red(m), bl, 0, st, m, P.G.ncell, P.vx.as<double>(), P.part.as<double>());
         zero_ctrl();
-        hipLaunchKernelGGL(k_fin_newton, dim3((S + 255) / 256), dim3(256), 0, st, m, P.part.as<double>(), p_ref,
+        hipLaunchKernelGGL(k_fin_newton, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), p_ref,
                            o.newton_tol, o.newton_dc_max, P.lam.as<double>(), P.ndone.as<int>(), P.status.as<int>(),
                            P.stats.as<double>(), P.ctrl.as<int>());
         hipLaunchKernelGGL(k_newton_update, cg, bl, 0, st, m, P.G.ncell, P.lam.as<double>(), P.vx.as<double>(),
@@ -620,12 +642,12 @@ struct Solver {
       hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
                          P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.uin.as<double>(),
                          P.part.as<double>());
-      hipLaunchKernelGGL(k_fin_balance, dim3((S + 255) / 256), dim3(256), 0, st, m, phys, P.part.as<double>(),
+      hipLaunchKernelGGL(k_fin_balance, fin_grid(S), dim3(64, FIN_Y), 0, st, m, phys, P.part.as<double>(),
                          P.uin.as<double>(), o.c_range_tol, P.stats.as<double>(), P.status.as<int>());
     }
     if (B.qoi) {
       hipLaunchKernelGGL(k_qoi, grid_red(m), bl, 0, st, m, P.G, phys, P.c.as<double>(), P.part.as<double>());
-      hipLaunchKernelGGL(k_fin_sum, dim3((S + 255) / 256), dim3(256), 0, st, m, P.part.as<double>(), phys.vol, B.qoi);
+      hipLaunchKernelGGL(k_fin_sum, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), phys.vol, B.qoi);
     }
     if (B.c_T) HIPCHK(hipMemcpyAsync(B.c_T, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
     if (B.p_T) HIPCHK(hipMemcpyAsync(B.p_T, P.p.p, P.N * 8, hipMemcpyDeviceToDevice, st));
