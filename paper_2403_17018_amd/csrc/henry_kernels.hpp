@@ -304,39 +304,31 @@ __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const 
 // a4/a5: block stencil operations (SpMV, red-black block Gauss-Seidel, transfers)
 // ==========================================================================
 // (A x)_P for one cell-sample: centre block + the 4 neighbour blocks that exist.
-template <typename T, typename TA>
+// TR: (A^T x)_P, gathering the transposed blocks A_{Q,P} stored in the neighbours'
+// rows (Q east of P holds A_{Q,P} in its west slot, and so on), so no atomics.
+template <typename T, typename TA, bool TR = false>
 __device__ __forceinline__ void apply_row(const T* __restrict__ J, const T* __restrict__ x, size_t N, size_t id, int i,
                                           int j, int nx, int ny, int S, TA& y0, TA& y1, bool skip_centre) {
   TA a0 = 0, a1 = 0;
-  if (!skip_centre) {
-    const TA x0 = x[id], x1 = x[N + id];
-    a0 = (TA)J[0 * N + id] * x0 + (TA)J[1 * N + id] * x1;
-    a1 = (TA)J[2 * N + id] * x0 + (TA)J[3 * N + id] * x1;
-  }
-  if (i > 0) {
-    const size_t q = id - S;
-    const TA x0 = x[q], x1 = x[N + q];
-    a0 += (TA)J[4 * N + id] * x0 + (TA)J[5 * N + id] * x1;
-    a1 += (TA)J[6 * N + id] * x0 + (TA)J[7 * N + id] * x1;
-  }
-  if (i < nx - 1) {
-    const size_t q = id + S;
-    const TA x0 = x[q], x1 = x[N + q];
-    a0 += (TA)J[8 * N + id] * x0 + (TA)J[9 * N + id] * x1;
-    a1 += (TA)J[10 * N + id] * x0 + (TA)J[11 * N + id] * x1;
-  }
-  if (j > 0) {
-    const size_t q = id - (size_t)nx * S;
-    const TA x0 = x[q], x1 = x[N + q];
-    a0 += (TA)J[12 * N + id] * x0 + (TA)J[13 * N + id] * x1;
-    a1 += (TA)J[14 * N + id] * x0 + (TA)J[15 * N + id] * x1;
-  }
-  if (j < ny - 1) {
-    const size_t q = id + (size_t)nx * S;
-    const TA x0 = x[q], x1 = x[N + q];
-    a0 += (TA)J[16 * N + id] * x0 + (TA)J[17 * N + id] * x1;
-    a1 += (TA)J[18 * N + id] * x0 + (TA)J[19 * N + id] * x1;
-  }
+  // block at (slot, row q): y += B x_q or B^T x_q
+  auto acc = [&](int slot, size_t q, size_t xq) {
+    const TA x0 = x[xq], x1 = x[N + xq];
+    const TA b0 = (TA)J[(slot * 4 + 0) * N + q], b1 = (TA)J[(slot * 4 + 1) * N + q];
+    const TA b2 = (TA)J[(slot * 4 + 2) * N + q], b3 = (TA)J[(slot * 4 + 3) * N + q];
+    if (TR) {
+      a0 += b0 * x0 + b2 * x1;
+      a1 += b1 * x0 + b3 * x1;
+    } else {
+      a0 += b0 * x0 + b1 * x1;
+      a1 += b2 * x0 + b3 * x1;
+    }
+  };
+  if (!skip_centre) acc(0, id, id);
+  const size_t row = (size_t)nx * S;
+  if (i > 0) acc(TR ? 2 : 1, TR ? id - S : id, id - S);
+  if (i < nx - 1) acc(TR ? 1 : 2, TR ? id + S : id, id + S);
+  if (j > 0) acc(TR ? 4 : 3, TR ? id - row : id, id - row);
+  if (j < ny - 1) acc(TR ? 3 : 4, TR ? id + row : id, id + row);
   y0 = a0;
   y1 = a1;
 }
@@ -344,7 +336,7 @@ __device__ __forceinline__ void apply_row(const T* __restrict__ J, const T* __re
 // One colour of a red-black 2x2-block Gauss-Seidel sweep: x_P = D_P^{-1}(b_P - sum_nb A_nb x_nb)
 // for every cell with (i + j) % 2 == colour.  x_zero: x is zero on entry (first pass
 // of a V-cycle level), so neighbours are not read.
-template <typename T>
+template <typename T, bool TR = false>
 __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, int colour, int x_zero, const T* __restrict__ J,
                                                    const T* __restrict__ b, T* __restrict__ x) {
   int s, mc, sb, cb;
@@ -359,11 +351,12 @@ __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, int colour, i
   T r0 = b[id], r1 = b[N + id];
   if (!x_zero) {
     T a0, a1;
-    apply_row<T, T>(J, x, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
+    apply_row<T, T, TR>(J, x, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
     r0 -= a0;
     r1 -= a1;
   }
-  const T d00 = J[id], d01 = J[N + id], d10 = J[2 * N + id], d11 = J[3 * N + id];
+  const T d00 = J[id], d11 = J[3 * N + id];
+  const T d01 = TR ? J[2 * N + id] : J[N + id], d10 = TR ? J[N + id] : J[2 * N + id];
   const T det = d00 * d11 - d01 * d10;
   x[id] = (d11 * r0 - d01 * r1) / det;
   x[N + id] = (d00 * r1 - d10 * r0) / det;
@@ -372,7 +365,7 @@ __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, int colour, i
 // Fused residual and restriction: b_H(I,J) = sum over the 2x2 children of (b - A x).
 // red_only: the last smoothing pass was the black one, which leaves a zero residual
 // on black cells, so only the two red children are evaluated.
-template <typename T>
+template <typename T, bool TR = false>
 __global__ void __launch_bounds__(256) k_residual_restrict(Map m, Grid2 Gf, Grid2 Gc, int red_only,
                                                            const T* __restrict__ J, const T* __restrict__ b,
                                                            const T* __restrict__ x, T* __restrict__ bH) {
@@ -388,7 +381,7 @@ __global__ void __launch_bounds__(256) k_residual_restrict(Map m, Grid2 Gf, Grid
     if (red_only && ((i + j) & 1)) continue;
     const size_t id = ((size_t)j * Gf.nx + i) * S + s;
     T a0, a1;
-    apply_row<T, T>(J, x, Nf, id, i, j, Gf.nx, Gf.ny, S, a0, a1, false);
+    apply_row<T, T, TR>(J, x, Nf, id, i, j, Gf.nx, Gf.ny, S, a0, a1, false);
     s0 += b[id] - a0;
     s1 += b[Nf + id] - a1;
   }
@@ -653,6 +646,82 @@ __global__ void __launch_bounds__(64) k_band_solve(int S, int nxc, int nyc, int 
   }
 }
 
+// Transposed solve x = (LU)^{-T} b = L^{-T} U^{-T} b with the same factors:
+// forward with U^T (lower, diagonal blocks D^T), then backward with L^T (unit upper).
+// LDS layout (T): y[2n] | stage[(CH+mb)*mb*4 + CH*4 + (CH+mb)*mb*4]
+template <typename T>
+__global__ void __launch_bounds__(64) k_band_solve_T(int S, int nxc, int nyc, int CH, const T* __restrict__ LU,
+                                                     const T* __restrict__ b, T* __restrict__ x) {
+  extern __shared__ unsigned char smem_raw[];
+  const int s = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int n = nxc * nyc, mb = nyc;
+  T* y = reinterpret_cast<T*>(smem_raw);
+  T* Us = y + 2 * n;                         // [CH][mb][4]  U rows of the chunk
+  T* Ds = Us + (size_t)CH * mb * 4;          // [CH][4]
+  T* Ls = Ds + (size_t)CH * 4;               // [CH+mb][mb][4] L columns
+  const size_t N = (size_t)n * S;
+  const T* Dg = LU + (size_t)s * n * (2 * mb + 1) * 4;
+  const T* Lg = Dg + (size_t)n * 4;
+  const T* Ug = Lg + (size_t)n * mb * 4;
+  for (int q = lane; q < n; q += 64) {
+    const int i = q / nyc, j = q - i * nyc;
+    const size_t g = ((size_t)j * nxc + i) * S + s;
+    y[2 * q] = b[g];
+    y[2 * q + 1] = b[N + g];
+  }
+  // forward: U^T z = b; z_k = Dinv_k^T b_k, then b_j -= U_{k,j}^T z_k for j = k+1..k+mb
+  for (int k0 = 0; k0 < n; k0 += CH) {
+    const int k1 = (k0 + CH < n ? k0 + CH : n);
+    for (int t = lane; t < (k1 - k0) * mb * 4; t += 64) Us[t] = Ug[(size_t)k0 * mb * 4 + t];
+    for (int t = lane; t < (k1 - k0) * 4; t += 64) Ds[t] = Dg[(size_t)k0 * 4 + t];
+    __syncthreads();
+    for (int k = k0; k < k1; ++k) {
+      const T* Di = Ds + (k - k0) * 4;
+      const T v0 = y[2 * k], v1 = y[2 * k + 1];
+      const T z0 = Di[0] * v0 + Di[2] * v1, z1 = Di[1] * v0 + Di[3] * v1;
+      const int nrow = (n - 1 - k) < mb ? (n - 1 - k) : mb;
+      if (lane < nrow) {
+        const T* U = Us + ((k - k0) * mb + lane) * 4;   // U_{k, k+1+lane}
+        const int r = k + 1 + lane;
+        y[2 * r] -= U[0] * z0 + U[2] * z1;
+        y[2 * r + 1] -= U[1] * z0 + U[3] * z1;
+      }
+      __syncthreads();
+      if (lane == 0) {
+        y[2 * k] = z0;
+        y[2 * k + 1] = z1;
+      }
+      __syncthreads();
+    }
+  }
+  // backward: L^T x = z; x_k = z_k, then z_i -= L_{k,i}^T x_k for i = k-mb..k-1,
+  // with L_{k,i} = column i's block (k - i - 1).  Steps [k0, k1) need columns [k0 - mb, k1 - 1].
+  for (int k1 = n; k1 > 0; k1 -= CH) {
+    const int k0 = (k1 - CH > 0 ? k1 - CH : 0);
+    const int r0 = (k0 - mb > 0 ? k0 - mb : 0);
+    for (int t = lane; t < (k1 - r0) * mb * 4; t += 64) Ls[t] = Lg[(size_t)r0 * mb * 4 + t];
+    __syncthreads();
+    for (int k = k1 - 1; k >= k0; --k) {
+      const T x0 = y[2 * k], x1 = y[2 * k + 1];
+      const int nrow = k < mb ? k : mb;
+      if (lane < nrow) {
+        const int col = k - 1 - lane;              // L_{k, col} = Lg[col][k - col - 1] = Lg[col][lane]
+        const T* L = Ls + ((col - r0) * mb + lane) * 4;
+        y[2 * col] -= L[0] * x0 + L[2] * x1;
+        y[2 * col + 1] -= L[1] * x0 + L[3] * x1;
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = lane; q < n; q += 64) {
+    const int i = q / nyc, j = q - i * nyc;
+    const size_t g = ((size_t)j * nxc + i) * S + s;
+    x[g] = y[2 * q];
+    x[N + g] = y[2 * q + 1];
+  }
+}
+
 // ==========================================================================
 // precision converters (a9)
 // ==========================================================================
@@ -668,8 +737,8 @@ __global__ void k_convert(size_t n, const TI* __restrict__ a, TO* __restrict__ b
 // per-sample scalar slots
 enum { SC_RHO = 0, SC_ALPHA, SC_OMEGA, SC_BETA, SC_R0, SC_RNORM, SC_ACTIVE, SC_ITS, SC_NSLOT };
 
-// r = -R (Newton rhs, zero for converged samples), rhat = r, x = 0; partial |r|^2
-__global__ void __launch_bounds__(256) k_bicg_init(Map m, int ncell, const double* __restrict__ R,
+// r = sign * R (zero for samples with ndone[s] set; ndone may be NULL), rhat = r, x = 0; partial |r|^2
+__global__ void __launch_bounds__(256) k_bicg_init(Map m, int ncell, const double* __restrict__ R, double sign,
                                                    const int* __restrict__ ndone, double* __restrict__ r,
                                                    double* __restrict__ rhat, double* __restrict__ x,
                                                    double* __restrict__ part) {
@@ -679,14 +748,14 @@ __global__ void __launch_bounds__(256) k_bicg_init(Map m, int ncell, const doubl
   const bool sv = s < m.S;
   const size_t N = (size_t)ncell * m.S;
   double acc[1] = {0.0};
-  const double msk = (sv && !ndone[s]) ? 1.0 : 0.0;
+  const double msk = (sv && !(ndone && ndone[s])) ? sign : 0.0;
   for (int k = 0; k < m.CPT; ++k) {
     const int cell = (cblk * m.CPT + k) * m.CY + threadIdx.y;
     if (!sv || cell >= ncell) continue;
     const size_t id = (size_t)cell * m.S + s;
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {
-      const double v = -R[comp * N + id] * msk;
+      const double v = R[comp * N + id] * msk;
       r[comp * N + id] = v;
       rhat[comp * N + id] = v;
       x[comp * N + id] = 0.0;
@@ -714,7 +783,7 @@ __global__ void __launch_bounds__(256) k_bicg_p(Map m, int ncell, int first, con
 }
 
 // y = A x with per-sample partial dot products: NDOT = 1: (d0, y); NDOT = 2: (y, d0), (y, y)
-template <int NDOT>
+template <int NDOT, bool TR = false>
 __global__ void __launch_bounds__(256) k_spmv_dot(Map m, Grid2 G, const double* __restrict__ J,
                                                   const double* __restrict__ x, double* __restrict__ y,
                                                   const double* __restrict__ d0, double* __restrict__ part) {
@@ -732,7 +801,7 @@ __global__ void __launch_bounds__(256) k_spmv_dot(Map m, Grid2 G, const double* 
     const int j = cell / G.nx, i = cell - j * G.nx;
     const size_t id = (size_t)cell * m.S + s;
     double y0, y1;
-    apply_row<double, double>(J, x, N, id, i, j, G.nx, G.ny, m.S, y0, y1, false);
+    apply_row<double, double, TR>(J, x, N, id, i, j, G.nx, G.ny, m.S, y0, y1, false);
     y[id] = y0;
     y[N + id] = y1;
     if (NDOT == 1) {

@@ -22,6 +22,7 @@
 #include "../../include/henry.h"
 #include "henry_kernels.hpp"
 #include "henry_mlmc.hpp"
+#include "henry_adjoint.hpp"
 
 using namespace henry;
 
@@ -298,6 +299,7 @@ struct henry_ctx {
   std::map<std::tuple<int, int, int, int, int, int>, std::unique_ptr<Plan>> plans;
   int* h_ctrl = nullptr;   // pinned
   DevBuf mlmc_tmp;
+  DevBuf adj_ck, adj_seg, adj_g;   // adjoint checkpoints, segment states, sensitivities
   Profiler prof;
 };
 
@@ -394,7 +396,7 @@ static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_
   P->ndone.alloc(S * 4);
   P->status.alloc(S * 4);
   P->stats.alloc((size_t)S * 4 * 8);
-  P->part.alloc((size_t)6 * P->m.ncb * S * 8);
+  P->part.alloc((size_t)12 * P->m.ncb * S * 8);
   P->ctrl.alloc(64);
   Plan* raw = P.get();
   ctx->plans[key] = std::move(P);
@@ -500,7 +502,9 @@ struct Solver {
     return (const T*)P.J.as<double>();
   }
 
-  template <typename T>
+  // One V-cycle x = M^{-1} b on level k (TR: the same cycle built from transposed
+  // operators, a preconditioner for J^T).
+  template <typename T, bool TR = false>
   void vcycle(int k, const T* b, T* x) {
     const Map& m = P.m;
     MGLevel& L = *P.lv[k];
@@ -508,7 +512,11 @@ struct Solver {
       const int CH = band_chunk<T>(L.ncell, P.mb);
       const size_t lds = band_solve_lds<T>(L.ncell, P.mb, CH);
       timed(ctx, HENRY_PROF_BAND_SOLVE, (long long)L.ncell * P.S, [&] {
-        hipLaunchKernelGGL((k_band_solve<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, CH, P.LU.as<T>(), b, x);
+        if (TR)
+          hipLaunchKernelGGL((k_band_solve_T<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, CH, P.LU.as<T>(), b,
+                             x);
+        else
+          hipLaunchKernelGGL((k_band_solve<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, CH, P.LU.as<T>(), b, x);
       });
       return;
     }
@@ -518,7 +526,9 @@ struct Solver {
     // fine-grid smoother passes that read neighbours are timed as one class
     const long long half_units = (long long)L.ny * half * P.S;
     auto gs = [&](int colour, int xz) {
-      auto f = [&] { hipLaunchKernelGGL((k_gs_colour<T>), gg, block_of(m), 0, st, m, L.G, colour, xz, J, b, x); };
+      auto f = [&] {
+        hipLaunchKernelGGL((k_gs_colour<T, TR>), gg, block_of(m), 0, st, m, L.G, colour, xz, J, b, x);
+      };
       if (k == 0 && !xz) timed(ctx, HENRY_PROF_GS, half_units, f);
       else f();
     };
@@ -528,12 +538,12 @@ struct Solver {
     }
     MGLevel& C = *P.lv[k + 1];
     auto rr = [&] {
-      hipLaunchKernelGGL((k_residual_restrict<T>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G, 1, J, b,
-                         x, C.b.as<T>());
+      hipLaunchKernelGGL((k_residual_restrict<T, TR>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G, 1, J,
+                         b, x, C.b.as<T>());
     };
     if (k == 0) timed(ctx, HENRY_PROF_RESTRICT, (long long)L.ncell * P.S, rr);
     else rr();
-    vcycle<T>(k + 1, C.b.as<T>(), C.x.as<T>());
+    vcycle<T, TR>(k + 1, C.b.as<T>(), C.x.as<T>());
     auto pc = [&] {
       hipLaunchKernelGGL((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G, C.x.as<T>(),
                          x);
@@ -547,23 +557,24 @@ struct Solver {
   }
 
   // out = M^{-1} in (FP64 vectors); FP32 mode converts around an FP32 V-cycle
-  template <typename T>
+  template <typename T, bool TR = false>
   void precond(const double* in, double* out) {
     if (P.prec == 32) {
       MGLevel& L = *P.lv[0];
       const size_t n = 2 * P.N;
       const dim3 g((unsigned)((n + 255) / 256));
       hipLaunchKernelGGL((k_convert<double, float>), g, dim3(256), 0, st, n, in, L.b.as<float>());
-      vcycle<float>(0, L.b.as<float>(), L.x.as<float>());
+      vcycle<float, TR>(0, L.b.as<float>(), L.x.as<float>());
       hipLaunchKernelGGL((k_convert<float, double>), g, dim3(256), 0, st, n, L.x.as<float>(), out);
     } else {
-      vcycle<double>(0, in, out);
+      vcycle<double, TR>(0, in, out);
     }
   }
 
-  // BiCGStab on J d = -R for the samples not yet Newton-converged; d in vx
-  template <typename T>
-  void bicgstab() {
+  // Right-preconditioned BiCGStab, per sample: A x = sign * rhs, x in vx, with A = J
+  // (or J^T when TR).  Samples with mask[s] != 0 get a zero right-hand side.
+  template <typename T, bool TR = false>
+  void bicgstab(const double* rhs, double sign, const int* mask) {
     const Map& m = P.m;
     const int S = P.S;
     double* sc = P.sc.as<double>();
@@ -571,8 +582,8 @@ struct Solver {
     int* status = P.status.as<int>();
     const dim3 rg = grid_red(m), bl = block_of(m), cg = grid_cells(m, P.G.ncell);
     const dim3 fg = fin_grid(S), fb(64, FIN_Y);
-    hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, P.R.as<double>(), P.ndone.as<int>(), P.vr.as<double>(),
-                       P.vrh.as<double>(), P.vx.as<double>(), P.part.as<double>());
+    hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, rhs, sign, mask, P.vr.as<double>(), P.vrh.as<double>(),
+                       P.vx.as<double>(), P.part.as<double>());
     zero_ctrl();
     hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl);
     if (read_ctrl(0) == 0) return;
@@ -580,17 +591,17 @@ struct Solver {
     for (int it = 0; it < o.krylov_maxit; ++it) {
       hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, it == 0 ? 1 : 0, sc, P.vr.as<double>(),
                          P.vv.as<double>(), P.vp.as<double>());
-      precond<T>(P.vp.as<double>(), P.vph.as<double>());
+      precond<T, TR>(P.vp.as<double>(), P.vph.as<double>());
       timed(ctx, HENRY_PROF_SPMV, (long long)P.N, [&] {
-        hipLaunchKernelGGL(k_spmv_dot<1>, rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vph.as<double>(),
+        hipLaunchKernelGGL((k_spmv_dot<1, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vph.as<double>(),
                            P.vv.as<double>(), P.vrh.as<double>(), P.part.as<double>());
       });
       hipLaunchKernelGGL(k_fin_alpha, fg, fb, 0, st, m, P.part.as<double>(), sc, status);
       hipLaunchKernelGGL(k_bicg_s, cg, bl, 0, st, m, P.G.ncell, sc, P.vr.as<double>(), P.vv.as<double>(),
                          P.vs.as<double>());
-      precond<T>(P.vs.as<double>(), P.vsh.as<double>());
+      precond<T, TR>(P.vs.as<double>(), P.vsh.as<double>());
       timed(ctx, HENRY_PROF_SPMV, (long long)P.N, [&] {
-        hipLaunchKernelGGL(k_spmv_dot<2>, rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vsh.as<double>(),
+        hipLaunchKernelGGL((k_spmv_dot<2, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vsh.as<double>(),
                            P.vt.as<double>(), P.vs.as<double>(), P.part.as<double>());
       });
       hipLaunchKernelGGL(k_fin_omega, fg, fb, 0, st, m, P.part.as<double>(), sc);
@@ -604,55 +615,144 @@ struct Solver {
     hipLaunchKernelGGL(k_accum_its, dim3((S + 255) / 256), dim3(256), 0, st, S, sc, P.stats.as<double>());
   }
 
+  // fields, coarse coefficients, initial state, cleared status/stats
+  void init(const double* theta) {
+    const Map& m = P.m;
+    fields(theta);
+    hipLaunchKernelGGL(k_init_state, grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G, phys, P.p.as<double>(),
+                       P.c.as<double>());
+    HIPCHK(hipMemsetAsync(P.status.p, 0, P.S * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(P.stats.p, 0, (size_t)P.S * 4 * sizeof(double), st));
+  }
+
+  // one implicit-Euler step n -> n+1: damped Newton with multigrid-preconditioned BiCGStab
   template <typename T>
-  void run(const henry_batch& B) {
+  void time_step(int n, int nsteps) {
     const Map& m = P.m;
     const int S = P.S;
     const dim3 cg = grid_cells(m, P.G.ncell), bl = block_of(m);
-    fields(B.theta);
-    hipLaunchKernelGGL(k_init_state, cg, bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>());
-    HIPCHK(hipMemsetAsync(P.status.p, 0, S * sizeof(int), st));
-    HIPCHK(hipMemsetAsync(P.stats.p, 0, (size_t)S * 4 * sizeof(double), st));
     const double p_ref = pr.rho0 * pr.g * pr.Ly;
+    if (progress_every && (n % progress_every == 0 || n == nsteps - 1)) {
+      std::fprintf(stderr, "[henry] %dx%d S=%d fp%d step %d/%d\n", P.nx, P.ny, S, P.prec, n + 1, nsteps);
+      std::fflush(stderr);
+    }
+    HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
+    int remaining = S;
+    for (int it = 0; it < o.newton_maxit && remaining > 0; ++it) {
+      assemble_all<T>();
+      bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>());
+      hipLaunchKernelGGL(k_delta_max, grid_red(m), bl, 0, st, m, P.G.ncell, P.vx.as<double>(), P.part.as<double>());
+      zero_ctrl();
+      hipLaunchKernelGGL(k_fin_newton, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), p_ref,
+                         o.newton_tol, o.newton_dc_max, P.lam.as<double>(), P.ndone.as<int>(), P.status.as<int>(),
+                         P.stats.as<double>(), P.ctrl.as<int>());
+      hipLaunchKernelGGL(k_newton_update, cg, bl, 0, st, m, P.G.ncell, P.lam.as<double>(), P.vx.as<double>(),
+                         P.p.as<double>(), P.c.as<double>());
+      remaining = read_ctrl(1);
+    }
+    if (remaining > 0)
+      hipLaunchKernelGGL(k_mark_unconverged, dim3((S + 255) / 256), dim3(256), 0, st, S, P.ndone.as<int>(),
+                         P.status.as<int>());
+    hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
+                       P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.uin.as<double>(),
+                       P.part.as<double>());
+    hipLaunchKernelGGL(k_fin_balance, fin_grid(S), dim3(64, FIN_Y), 0, st, m, phys, P.part.as<double>(),
+                       P.uin.as<double>(), o.c_range_tol, P.stats.as<double>(), P.status.as<int>());
+  }
+
+  void qoi(double* out) {
+    const Map& m = P.m;
+    hipLaunchKernelGGL(k_qoi, grid_red(m), block_of(m), 0, st, m, P.G, phys, P.c.as<double>(), P.part.as<double>());
+    hipLaunchKernelGGL(k_fin_sum, fin_grid(P.S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), phys.vol, out);
+  }
+
+  int progress_every = 0;
+
+  template <typename T>
+  void run(const henry_batch& B) {
     const char* pe = std::getenv("HENRY_PROGRESS");
-    const int every = pe ? std::max(1, std::atoi(pe)) : 0;
-    for (int n = 0; n < B.grid.nsteps; ++n) {
-      if (every && (n % every == 0 || n == B.grid.nsteps - 1)) {
-        std::fprintf(stderr, "[henry] %dx%d S=%d fp%d step %d/%d\n", P.nx, P.ny, S, P.prec, n + 1, B.grid.nsteps);
-        std::fflush(stderr);
-      }
-      HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
-      HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
-      int remaining = S;
-      for (int it = 0; it < o.newton_maxit && remaining > 0; ++it) {
-        assemble_all<T>();
-        bicgstab<T>();
-        hipLaunchKernelGGL(k_delta_max, grid_red(m), bl, 0, st, m, P.G.ncell, P.vx.as<double>(), P.part.as<double>());
-        zero_ctrl();
-        hipLaunchKernelGGL(k_fin_newton, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), p_ref,
-                           o.newton_tol, o.newton_dc_max, P.lam.as<double>(), P.ndone.as<int>(), P.status.as<int>(),
-                           P.stats.as<double>(), P.ctrl.as<int>());
-        hipLaunchKernelGGL(k_newton_update, cg, bl, 0, st, m, P.G.ncell, P.lam.as<double>(), P.vx.as<double>(),
-                           P.p.as<double>(), P.c.as<double>());
-        remaining = read_ctrl(1);
-      }
-      if (remaining > 0)
-        hipLaunchKernelGGL(k_mark_unconverged, dim3((S + 255) / 256), dim3(256), 0, st, S, P.ndone.as<int>(),
-                           P.status.as<int>());
-      hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
-                         P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.uin.as<double>(),
-                         P.part.as<double>());
-      hipLaunchKernelGGL(k_fin_balance, fin_grid(S), dim3(64, FIN_Y), 0, st, m, phys, P.part.as<double>(),
-                         P.uin.as<double>(), o.c_range_tol, P.stats.as<double>(), P.status.as<int>());
-    }
-    if (B.qoi) {
-      hipLaunchKernelGGL(k_qoi, grid_red(m), bl, 0, st, m, P.G, phys, P.c.as<double>(), P.part.as<double>());
-      hipLaunchKernelGGL(k_fin_sum, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), phys.vol, B.qoi);
-    }
+    progress_every = pe ? std::max(1, std::atoi(pe)) : 0;
+    init(B.theta);
+    for (int n = 0; n < B.grid.nsteps; ++n) time_step<T>(n, B.grid.nsteps);
+    const int S = P.S;
+    if (B.qoi) qoi(B.qoi);
     if (B.c_T) HIPCHK(hipMemcpyAsync(B.c_T, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
     if (B.p_T) HIPCHK(hipMemcpyAsync(B.p_T, P.p.p, P.N * 8, hipMemcpyDeviceToDevice, st));
     if (B.status) HIPCHK(hipMemcpyAsync(B.status, P.status.p, S * sizeof(int), hipMemcpyDeviceToDevice, st));
     if (B.stats) HIPCHK(hipMemcpyAsync(B.stats, P.stats.p, (size_t)S * 4 * 8, hipMemcpyDeviceToDevice, st));
+  }
+
+  // Discrete adjoint: forward with checkpoints every C steps, then a reverse sweep that
+  // recomputes each segment and solves J_n^T lam_n = rhs_n step by step.
+  template <typename T>
+  void adjoint(const double* theta, int nsteps, int C, double* qoi_out, double* grad, int* status_out) {
+    const char* pe = std::getenv("HENRY_PROGRESS");
+    progress_every = pe ? std::max(1, std::atoi(pe)) : 0;
+    const Map& m = P.m;
+    const int S = P.S;
+    const size_t N = P.N, st2 = 2 * N * sizeof(double);
+    const int ncp = nsteps / C + 1;
+    ctx->adj_ck.alloc((size_t)ncp * st2);
+    ctx->adj_seg.alloc((size_t)(C + 1) * st2);
+    ctx->adj_g.alloc((2 * N + 2 * N + S) * sizeof(double));
+    double* ck = ctx->adj_ck.as<double>();
+    double* seg = ctx->adj_seg.as<double>();
+    double* gphi = ctx->adj_g.as<double>();
+    double* gK = gphi + N;
+    double* rhs = gK + N;            // 2N
+    double* guin = rhs + 2 * N;      // S
+    auto save = [&](double* dst) {
+      HIPCHK(hipMemcpyAsync(dst, P.p.p, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(dst + N, P.c.p, N * 8, hipMemcpyDeviceToDevice, st));
+    };
+    auto load = [&](const double* src) {
+      HIPCHK(hipMemcpyAsync(P.p.p, src, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(P.c.p, src + N, N * 8, hipMemcpyDeviceToDevice, st));
+    };
+    init(theta);
+    save(ck);
+    for (int n = 0; n < nsteps; ++n) {
+      time_step<T>(n, nsteps);
+      if ((n + 1) % C == 0) save(ck + (size_t)((n + 1) / C) * 2 * N);
+    }
+    if (qoi_out) qoi(qoi_out);
+    const dim3 cg = grid_cells(m, P.G.ncell), bl = block_of(m), rg = grid_red(m);
+    const size_t nz = 2 * N + S;
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((2 * N + 255) / 256)), dim3(256), 0, st, 2 * N, gphi);
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, st, (size_t)S, guin);
+    (void)nz;
+    hipLaunchKernelGGL(k_adj_rhs_final, cg, bl, 0, st, m, P.G, phys, P.c.as<double>(), rhs);
+    const int nseg = (nsteps + C - 1) / C;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+      const int n0 = sg * C, n1 = std::min(n0 + C, nsteps);
+      load(ck + (size_t)sg * 2 * N);
+      save(seg);
+      for (int n = n0; n < n1; ++n) {
+        time_step<T>(n, nsteps);
+        save(seg + (size_t)(n + 1 - n0) * 2 * N);
+      }
+      for (int n = n1; n > n0; --n) {
+        const double* un = seg + (size_t)(n - n0) * 2 * N;
+        const double* um = seg + (size_t)(n - 1 - n0) * 2 * N;
+        load(un);
+        HIPCHK(hipMemcpyAsync(P.c_old.p, um + N, N * 8, hipMemcpyDeviceToDevice, st));
+        assemble_all<T>();
+        bicgstab<T, true>(rhs, 1.0, nullptr);   // every sample solves its adjoint system
+        hipLaunchKernelGGL(k_adj_param, rg, bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
+                           P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.vx.as<double>(), gphi, gK,
+                           P.part.as<double>());
+        hipLaunchKernelGGL(k_fin_accum, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), guin);
+        if (n > 1)
+          hipLaunchKernelGGL(k_adj_rhs_prev, cg, bl, 0, st, m, P.G, phys, P.c_old.as<double>(), P.phi.as<double>(),
+                             P.vx.as<double>(), rhs);
+      }
+    }
+    hipLaunchKernelGGL(k_adj_theta, rg, bl, 0, st, m, P.G, phys, kl, fp, theta, P.K.as<double>(), gphi, gK,
+                       P.part.as<double>());
+    hipLaunchKernelGGL(k_fin_theta, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), guin,
+                       pr.q_in * pr.q_in_amp, grad);
+    if (status_out) HIPCHK(hipMemcpyAsync(status_out, P.status.p, S * sizeof(int), hipMemcpyDeviceToDevice, st));
   }
 
   int count_failed() {
@@ -852,10 +952,21 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_problem* prob, const henry_s
                         int S, const double* theta, int checkpoint_every, double* qoi, double* dqoi_dtheta,
                         int* status) {
   return guarded(ctx, [&]() -> int {
-    (void)prob; (void)opts; (void)grid; (void)S; (void)theta; (void)checkpoint_every; (void)qoi;
-    (void)dqoi_dtheta; (void)status;
-    fail(HENRY_EUNSUPPORTED, "adjoint not built yet");
-    return 0;
+    check_problem(prob);
+    henry_solver_opts o;
+    if (opts) o = *opts;
+    else henry_solver_opts_default(&o);
+    check_opts(o);
+    check_grid(*prob, grid);
+    if (S < 1 || !theta || !dqoi_dtheta) fail(HENRY_EINVAL, "S < 1, theta or dqoi_dtheta NULL");
+    if (checkpoint_every < 1) fail(HENRY_EINVAL, "checkpoint_every must be >= 1");
+    if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
+    Plan* P = get_plan(ctx, grid.nx, grid.ny, S, o);
+    Solver sv(ctx, *prob, o, *P, grid.nsteps);
+    if (o.mg_precision == 32) sv.adjoint<float>(theta, grid.nsteps, checkpoint_every, qoi, dqoi_dtheta, status);
+    else sv.adjoint<double>(theta, grid.nsteps, checkpoint_every, qoi, dqoi_dtheta, status);
+    HIPCHK(hipGetLastError());
+    return sv.count_failed();
   });
 }
 
