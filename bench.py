@@ -75,12 +75,51 @@ def pmc_traffic(kernel, prec):
     return d.get("hbm_bytes_per_launch")
 
 
+def bench_mlmc(args):
+    """Full MLMC hierarchy (levels 0..4, 4096/1024/256/64/16 samples, coupled fine/coarse
+    pairs) in one ragged call, then the estimator: wall time to the reported RMSE."""
+    import torch
+    import paper_2403_17018_amd as P
+    w = WORKLOADS["c4_mlmc_levels0to4"]
+    prec = args.precision or 64
+    graphs = 1 if args.graphs is None else args.graphs
+    levels, m, seed = w["levels"], w["nsamples"], w["seed"]
+    thetas = [torch.from_numpy(draw_theta(seed, k, level=l)).cuda() for l, k in zip(levels, m)]
+    hx = P.Henry(0)
+    opts = P.solver_opts(mg_precision=prec, use_graphs=graphs)
+    for _ in range(args.warmup):
+        P.mlmc_run(hx, thetas, levels, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        est = P.mlmc_run(hx, thetas, levels, opts=opts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    work = sum(k * (48 << l) + (k * (48 << (l - 1)) if l > 0 else 0) for l, k in zip(levels, m))
+    out = {
+        "metric": "MLMC wall time to RMSE",
+        "value": dt,
+        "unit": "s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == 64 else "f64+f32mg", "data": "synthetic",
+        "config": {"workload": "c4_mlmc_levels0to4: levels 0..4 (32x16..512x256 cells, 48..768 steps), "
+                               "4096/1024/256/64/16 samples with coupled coarse partners (seed 3), one ragged call",
+                   "mg_precision": prec, "hip_graphs": graphs, "parallelism": "one stream per grid on one GPU"},
+        "rmse": est["rmse"], "mlmc_mean_qoi": est["mean"], "var_of_estimator": est["var_of_estimator"],
+        "V_l": est["V"], "sample_timesteps_per_s": work / dt, "failed_samples": est["nfailed"],
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--graphs", type=int, default=None, help="capture BiCGStab iterations in hipGraphs (c4 default 1)")
     ap.add_argument("--precision", type=int, default=None, help="multigrid precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -88,6 +127,8 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(samples would shard across GPUs with one all-reduce of the MLMC sums)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c4":
+        return bench_mlmc(args)
     name = {"c1": "c1_fp64_level0", "c2": "c2_fp64_level3", "c3": "c3_mixed_level4"}[args.workload]
     w = WORKLOADS[name]
     prec = args.precision or w["mg_precision"]

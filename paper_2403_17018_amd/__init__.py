@@ -15,7 +15,8 @@ import torch
 from . import _lib as L
 from ._lib import henry_batch, henry_grid, henry_problem, henry_solver_opts
 
-__all__ = ["Henry", "HenryError", "problem", "solver_opts", "grid", "level_grid", "optimal_samples", "SolveResult"]
+__all__ = ["Henry", "HenryError", "problem", "solver_opts", "grid", "level_grid", "optimal_samples", "SolveResult",
+           "mlmc_run"]
 
 STATUS = {0: "ok", 1: "newton", 2: "krylov", 3: "nonfinite", 4: "range"}
 
@@ -202,6 +203,36 @@ class Henry:
             self._check(self._lib.henry_profile_read(self._h, k, C.byref(n), C.byref(u), C.byref(ms)))
             out[name] = (n.value, u.value, ms.value)
         return out
+
+
+def mlmc_run(hx: "Henry", thetas, levels, prob=None, opts=None, alpha: float = 1.0, fields: bool = True):
+    """One multilevel Monte Carlo estimate (paper section 3, eq. A) in a single ragged solve.
+
+    thetas[l]: float64 CUDA tensor [m_l, 13] for level levels[l]; level l > 0 is solved on
+    its own grid and, with the same theta (coupled pair), on the next coarser grid.  All
+    batches go to the library in one call, which merges batches sharing a grid and runs
+    the grids concurrently.  Returns the estimator dict of Henry.mlmc_estimate plus the
+    per-batch solve results.
+    """
+    items, idx = [], []
+    for l, (th, lev) in enumerate(zip(thetas, levels)):
+        items.append((th, level_grid(lev)))
+        f = len(items) - 1
+        c = None
+        if l > 0:
+            items.append((th, level_grid(levels[l - 1])))
+            c = len(items) - 1
+        idx.append((f, c))
+    res = hx.solve_ragged(items, prob, opts, want_c=fields)
+    grids = [level_grid(lev) for lev in levels]
+    gf = [res[f].qoi for f, _ in idx]
+    gc = [None if c is None else res[c].qoi for _, c in idx]
+    cf = [res[f].c_T for f, _ in idx] if fields else None
+    cc = [None if c is None else res[c].c_T for _, c in idx] if fields else None
+    est = hx.mlmc_estimate(grids, gf, gc, cf, cc, alpha)
+    est["results"] = res
+    est["nfailed"] = sum(r.nfailed for r in res)
+    return est
 
 
 def optimal_samples(V, s, eps):

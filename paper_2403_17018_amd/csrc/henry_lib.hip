@@ -15,6 +15,8 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -230,6 +232,24 @@ struct Plan {
   DevBuf sc, lam, ndone, status, stats, part, ctrl;
   size_t lu_stride;
   int mb;
+  int* h_ctrl = nullptr;   // pinned mirror of ctrl
+  // captured BiCGStab iterations: [transposed][first iteration]
+  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int gkey[4] = {0, 0, 0, 0};   // nu_pre, nu_post, precision, valid
+  double grtol = 0.0;
+  void drop_graphs() {
+    for (auto& a : gexec)
+      for (auto& g : a)
+        if (g) {
+          (void)hipGraphExecDestroy(g);
+          g = nullptr;
+        }
+    gkey[3] = 0;
+  }
+  ~Plan() {
+    drop_graphs();
+    if (h_ctrl) (void)hipHostFree(h_ctrl);
+  }
 };
 
 // Optional event timing of kernel classes on the context's stream.  A ring of event
@@ -247,6 +267,7 @@ struct Profiler {
     double ms = 0.0;
   };
   bool on = false;
+  std::mutex mu;
   Cls c[HENRY_PROF_NCLASS];
 
   void drain_one(Cls& k, Slot& sl) {
@@ -300,20 +321,24 @@ struct henry_ctx {
   int* h_ctrl = nullptr;   // pinned
   DevBuf mlmc_tmp;
   DevBuf adj_ck, adj_seg, adj_g;   // adjoint checkpoints, segment states, sensitivities
+  std::vector<hipStream_t> streams; // per-grid streams of ragged solves (default priority)
   Profiler prof;
 };
 
-// Launch `f` and, when profiling, bracket it with events of class `cls`.
+// Launch `f` on stream `st` and, when profiling (and not capturing a graph), bracket
+// it with events of class `cls`.
+static thread_local bool tl_capturing = false;
 template <typename F>
-static void timed(henry_ctx* ctx, int cls, long long units, F&& f) {
-  if (!ctx->prof.on) {
+static void timed(henry_ctx* ctx, hipStream_t st, int cls, long long units, F&& f) {
+  if (!ctx->prof.on || tl_capturing) {
     f();
     return;
   }
+  std::lock_guard<std::mutex> lk(ctx->prof.mu);
   auto& sl = ctx->prof.acquire(cls);
-  HIPCHK(hipEventRecord(sl.a, ctx->stream));
+  HIPCHK(hipEventRecord(sl.a, st));
   f();
-  HIPCHK(hipEventRecord(sl.b, ctx->stream));
+  HIPCHK(hipEventRecord(sl.b, st));
   ctx->prof.c[cls].launches++;
   ctx->prof.c[cls].units += units;
 }
@@ -398,6 +423,7 @@ static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_
   P->stats.alloc((size_t)S * 4 * 8);
   P->part.alloc((size_t)12 * P->m.ncb * S * 8);
   P->ctrl.alloc(64);
+  HIPCHK(hipHostMalloc((void**)&P->h_ctrl, 16 * sizeof(int), hipHostMallocDefault));
   Plan* raw = P.get();
   ctx->plans[key] = std::move(P);
   return raw;
@@ -416,8 +442,8 @@ struct Solver {
   KLModes kl;
   FieldParams fp;
 
-  Solver(henry_ctx* c, const henry_problem& p, const henry_solver_opts& op, Plan& pl, int nsteps)
-      : ctx(c), pr(p), o(op), P(pl), st(c->stream) {
+  Solver(henry_ctx* c, const henry_problem& p, const henry_solver_opts& op, Plan& pl, int nsteps, hipStream_t stream)
+      : ctx(c), pr(p), o(op), P(pl), st(stream) {
     phys = make_phys(pr, P.nx, P.ny, nsteps);
     kl = make_kl(pr);
     fp.phi_mean = pr.phi_mean;
@@ -442,9 +468,9 @@ struct Solver {
 
   void zero_ctrl() { hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, P.ctrl.as<int>(), 16); }
   int read_ctrl(int i) {
-    HIPCHK(hipMemcpyAsync(ctx->h_ctrl, P.ctrl.as<int>(), 16 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(P.h_ctrl, P.ctrl.as<int>(), 16 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    return ctx->h_ctrl[i];
+    return P.h_ctrl[i];
   }
 
   void fields(const double* theta) {
@@ -465,7 +491,7 @@ struct Solver {
   template <typename T>
   void assemble_all() {
     const Map& m = P.m;
-    timed(ctx, HENRY_PROF_ASSEMBLE, (long long)P.N, [&] {
+    timed(ctx, st, HENRY_PROF_ASSEMBLE, (long long)P.N, [&] {
       if (P.prec == 32)
         hipLaunchKernelGGL((k_assemble<true, double, true>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
                            phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
@@ -489,7 +515,7 @@ struct Solver {
     }
     const MGLevel& Cc = *P.lv[P.nlev - 1];
     const size_t lds = (size_t)(P.mb + 1) * (P.mb + 1) * 4 * sizeof(T);
-    timed(ctx, HENRY_PROF_BAND_FACTOR, (long long)Cc.ncell * P.S, [&] {
+    timed(ctx, st, HENRY_PROF_BAND_FACTOR, (long long)Cc.ncell * P.S, [&] {
       hipLaunchKernelGGL((k_band_factor<T>), dim3(P.S), dim3(64), lds, st, P.S, Cc.nx, Cc.ny, level_J<T>(P.nlev - 1),
                          P.LU.as<T>());
     });
@@ -511,7 +537,7 @@ struct Solver {
     if (k == P.nlev - 1) {
       const int CH = band_chunk<T>(L.ncell, P.mb);
       const size_t lds = band_solve_lds<T>(L.ncell, P.mb, CH);
-      timed(ctx, HENRY_PROF_BAND_SOLVE, (long long)L.ncell * P.S, [&] {
+      timed(ctx, st, HENRY_PROF_BAND_SOLVE, (long long)L.ncell * P.S, [&] {
         if (TR)
           hipLaunchKernelGGL((k_band_solve_T<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, CH, P.LU.as<T>(), b,
                              x);
@@ -529,7 +555,7 @@ struct Solver {
       auto f = [&] {
         hipLaunchKernelGGL((k_gs_colour<T, TR>), gg, block_of(m), 0, st, m, L.G, colour, xz, J, b, x);
       };
-      if (k == 0 && !xz) timed(ctx, HENRY_PROF_GS, half_units, f);
+      if (k == 0 && !xz) timed(ctx, st, HENRY_PROF_GS, half_units, f);
       else f();
     };
     for (int sw = 0; sw < o.nu_pre; ++sw) {
@@ -541,14 +567,14 @@ struct Solver {
       hipLaunchKernelGGL((k_residual_restrict<T, TR>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G, 1, J,
                          b, x, C.b.as<T>());
     };
-    if (k == 0) timed(ctx, HENRY_PROF_RESTRICT, (long long)L.ncell * P.S, rr);
+    if (k == 0) timed(ctx, st, HENRY_PROF_RESTRICT, (long long)L.ncell * P.S, rr);
     else rr();
     vcycle<T, TR>(k + 1, C.b.as<T>(), C.x.as<T>());
     auto pc = [&] {
       hipLaunchKernelGGL((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G, C.x.as<T>(),
                          x);
     };
-    if (k == 0) timed(ctx, HENRY_PROF_PROLONG, (long long)L.ncell * P.S, pc);
+    if (k == 0) timed(ctx, st, HENRY_PROF_PROLONG, (long long)L.ncell * P.S, pc);
     else pc();
     for (int sw = 0; sw < o.nu_post; ++sw) {
       gs(0, 0);
@@ -588,11 +614,12 @@ struct Solver {
     hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl);
     if (read_ctrl(0) == 0) return;
     const double rtol2 = o.krylov_rtol * o.krylov_rtol;
-    for (int it = 0; it < o.krylov_maxit; ++it) {
-      hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, it == 0 ? 1 : 0, sc, P.vr.as<double>(),
-                         P.vv.as<double>(), P.vp.as<double>());
+    // one BiCGStab iteration (both preconditioner applications and SpMVs), no host sync
+    auto body = [&](int first) {
+      hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, first, sc, P.vr.as<double>(), P.vv.as<double>(),
+                         P.vp.as<double>());
       precond<T, TR>(P.vp.as<double>(), P.vph.as<double>());
-      timed(ctx, HENRY_PROF_SPMV, (long long)P.N, [&] {
+      timed(ctx, st, HENRY_PROF_SPMV, (long long)P.N, [&] {
         hipLaunchKernelGGL((k_spmv_dot<1, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vph.as<double>(),
                            P.vv.as<double>(), P.vrh.as<double>(), P.part.as<double>());
       });
@@ -600,7 +627,7 @@ struct Solver {
       hipLaunchKernelGGL(k_bicg_s, cg, bl, 0, st, m, P.G.ncell, sc, P.vr.as<double>(), P.vv.as<double>(),
                          P.vs.as<double>());
       precond<T, TR>(P.vs.as<double>(), P.vsh.as<double>());
-      timed(ctx, HENRY_PROF_SPMV, (long long)P.N, [&] {
+      timed(ctx, st, HENRY_PROF_SPMV, (long long)P.N, [&] {
         hipLaunchKernelGGL((k_spmv_dot<2, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vsh.as<double>(),
                            P.vt.as<double>(), P.vs.as<double>(), P.part.as<double>());
       });
@@ -610,6 +637,39 @@ struct Solver {
                          P.part.as<double>());
       zero_ctrl();
       hipLaunchKernelGGL(k_fin_rho, fg, fb, 0, st, m, P.part.as<double>(), sc, rtol2, status, ctrl);
+    };
+    const bool graphs = o.use_graphs && !ctx->prof.on;
+    if (graphs) {
+      const int key[4] = {o.nu_pre, o.nu_post, P.prec, 1};
+      if (std::memcmp(key, P.gkey, sizeof key) != 0 || P.grtol != rtol2) {
+        P.drop_graphs();
+        std::memcpy(P.gkey, key, sizeof key);
+        P.grtol = rtol2;
+      }
+      for (int first = 0; first < 2; ++first) {
+        if (P.gexec[TR][first]) continue;
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        tl_capturing = true;
+        try {
+          body(first);
+        } catch (...) {
+          tl_capturing = false;
+          (void)hipStreamEndCapture(st, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        tl_capturing = false;
+        HIPCHK(hipStreamEndCapture(st, &g));
+        const hipError_t e = hipGraphInstantiate(&P.gexec[TR][first], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+      }
+    }
+    for (int it = 0; it < o.krylov_maxit; ++it) {
+      const int first = it == 0 ? 1 : 0;
+      if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][first], st));
+      else body(first);
       if (read_ctrl(0) == 0) break;
     }
     hipLaunchKernelGGL(k_accum_its, dim3((S + 255) / 256), dim3(256), 0, st, S, sc, P.stats.as<double>());
@@ -820,6 +880,146 @@ static int guarded(henry_ctx* ctx, F&& f) {
 }
 
 // ---------------------------------------------------------------------------
+// ragged batches: merge batches that share a grid, run each grid on its own stream
+// ---------------------------------------------------------------------------
+struct Group {
+  henry_grid grid{};
+  int S = 0;
+  std::vector<int> members, offs;
+  DevBuf theta, c, p, qoi, status, stats;   // merged groups only
+  hipStream_t stream = nullptr;
+  int failed = 0;
+  bool ok = true;
+  HenryError err{0, ""};
+};
+
+static hipStream_t ctx_stream(henry_ctx* ctx, size_t k) {
+  while (ctx->streams.size() <= k) {
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));   // default priority
+    ctx->streams.push_back(s);
+  }
+  return ctx->streams[k];
+}
+
+static int solve_ragged(henry_ctx* ctx, const henry_problem& pr, const henry_solver_opts& o, henry_batch* batches,
+                        int nb) {
+  if (nb == 0) return 0;
+  std::vector<std::unique_ptr<Group>> groups;
+  for (int b = 0; b < nb; ++b) {
+    const henry_grid& g = batches[b].grid;
+    Group* G = nullptr;
+    for (auto& q : groups)
+      if (q->grid.nx == g.nx && q->grid.ny == g.ny && q->grid.nsteps == g.nsteps) G = q.get();
+    if (!G) {
+      groups.push_back(std::make_unique<Group>());
+      G = groups.back().get();
+      G->grid = g;
+    }
+    G->members.push_back(b);
+    G->offs.push_back(G->S);
+    G->S += batches[b].nsamples;
+  }
+  // most expensive first, so the longest dependency chain starts first
+  std::stable_sort(groups.begin(), groups.end(), [](const auto& a, const auto& b) {
+    return (double)a->grid.nx * a->grid.ny * a->grid.nsteps * a->S > (double)b->grid.nx * b->grid.ny * b->grid.nsteps * b->S;
+  });
+  // Work runs on the context's own streams (capturable, unlike the legacy default
+  // stream), ordered after the caller's stream and joined back to it at the end.
+  const bool multi = groups.size() > 1;
+  hipEvent_t start = nullptr;
+  HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(start, ctx->stream));
+  std::vector<Plan*> plans;
+  std::vector<henry_batch> gb(groups.size());
+  for (size_t k = 0; k < groups.size(); ++k) {
+    Group& G = *groups[k];
+    G.stream = ctx_stream(ctx, k);
+    HIPCHK(hipStreamWaitEvent(G.stream, start, 0));
+    plans.push_back(get_plan(ctx, G.grid.nx, G.grid.ny, G.S, o));
+    henry_batch& B = gb[k];
+    B.grid = G.grid;
+    B.nsamples = G.S;
+    if (G.members.size() == 1) {
+      B = batches[G.members[0]];
+      continue;
+    }
+    const size_t N = (size_t)G.grid.nx * G.grid.ny * G.S;
+    G.theta.alloc((size_t)G.S * 13 * 8);
+    for (size_t i = 0; i < G.members.size(); ++i) {
+      const henry_batch& M = batches[G.members[i]];
+      HIPCHK(hipMemcpyAsync(G.theta.as<double>() + (size_t)G.offs[i] * 13, M.theta, (size_t)M.nsamples * 13 * 8,
+                            hipMemcpyDeviceToDevice, G.stream));
+    }
+    G.c.alloc(N * 8);
+    G.p.alloc(N * 8);
+    G.qoi.alloc(G.S * 8);
+    G.status.alloc(G.S * 4);
+    G.stats.alloc((size_t)G.S * 4 * 8);
+    B.theta = G.theta.as<double>();
+    B.c_T = G.c.as<double>();
+    B.p_T = G.p.as<double>();
+    B.qoi = G.qoi.as<double>();
+    B.status = G.status.as<int>();
+    B.stats = G.stats.as<double>();
+  }
+  auto work = [&](size_t k) {
+    Group& G = *groups[k];
+    try {
+      HIPCHK(hipSetDevice(ctx->device));
+      Solver sv(ctx, pr, o, *plans[k], G.grid.nsteps, G.stream);
+      if (o.mg_precision == 32) sv.run<float>(gb[k]);
+      else sv.run<double>(gb[k]);
+      HIPCHK(hipGetLastError());
+      G.failed = sv.count_failed();
+    } catch (const HenryError& e) {
+      G.ok = false;
+      G.err = e;
+    }
+  };
+  if (!multi) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (size_t k = 0; k < groups.size(); ++k) th.emplace_back(work, k);
+    for (auto& t : th) t.join();
+  }
+  int failed = 0;
+  for (auto& gp : groups) {
+    Group& G = *gp;
+    if (!G.ok) throw G.err;
+    failed += G.failed;
+    if (G.members.size() > 1) {
+      const size_t nc = (size_t)G.grid.nx * G.grid.ny;
+      for (size_t i = 0; i < G.members.size(); ++i) {
+        const henry_batch& M = batches[G.members[i]];
+        const size_t off = G.offs[i], Sb = M.nsamples, S = G.S;
+        if (M.c_T)
+          HIPCHK(hipMemcpy2DAsync(M.c_T, Sb * 8, G.c.as<double>() + off, S * 8, Sb * 8, nc, hipMemcpyDeviceToDevice,
+                                  G.stream));
+        if (M.p_T)
+          HIPCHK(hipMemcpy2DAsync(M.p_T, Sb * 8, G.p.as<double>() + off, S * 8, Sb * 8, nc, hipMemcpyDeviceToDevice,
+                                  G.stream));
+        if (M.qoi) HIPCHK(hipMemcpyAsync(M.qoi, G.qoi.as<double>() + off, Sb * 8, hipMemcpyDeviceToDevice, G.stream));
+        if (M.status)
+          HIPCHK(hipMemcpyAsync(M.status, G.status.as<int>() + off, Sb * 4, hipMemcpyDeviceToDevice, G.stream));
+        if (M.stats)
+          HIPCHK(hipMemcpyAsync(M.stats, G.stats.as<double>() + off * 4, Sb * 4 * 8, hipMemcpyDeviceToDevice, G.stream));
+      }
+    }
+    hipEvent_t done = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(done, G.stream));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, done, 0));
+    HIPCHK(hipEventDestroy(done));
+  }
+  // merged buffers are released only after the copies above have run
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipEventDestroy(start));
+  return failed;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -893,6 +1093,10 @@ void henry_ctx_destroy(henry_ctx* c) {
     c->prof.flush();
   } catch (const HenryError&) {
   }
+  for (auto s : c->streams) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
   c->plans.clear();
   if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
   delete c;
@@ -934,17 +1138,7 @@ int henry_solve_batch(henry_ctx* ctx, const henry_problem* prob, const henry_sol
       if (batches[b].nsamples < 1 || !batches[b].theta) fail(HENRY_EINVAL, "batch %d: nsamples < 1 or theta NULL", b);
       if (theta_check(ctx, batches[b].theta, batches[b].nsamples)) fail(HENRY_EINVAL, "batch %d: non-finite theta", b);
     }
-    int failed = 0;
-    for (int b = 0; b < nbatches; ++b) {
-      const henry_batch& B = batches[b];
-      Plan* P = get_plan(ctx, B.grid.nx, B.grid.ny, B.nsamples, o);
-      Solver sv(ctx, *prob, o, *P, B.grid.nsteps);
-      if (o.mg_precision == 32) sv.run<float>(B);
-      else sv.run<double>(B);
-      HIPCHK(hipGetLastError());
-      failed += sv.count_failed();
-    }
-    return failed;
+    return solve_ragged(ctx, *prob, o, batches, nbatches);
   });
 }
 
@@ -962,11 +1156,20 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_problem* prob, const henry_s
     if (checkpoint_every < 1) fail(HENRY_EINVAL, "checkpoint_every must be >= 1");
     if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
     Plan* P = get_plan(ctx, grid.nx, grid.ny, S, o);
-    Solver sv(ctx, *prob, o, *P, grid.nsteps);
+    hipStream_t st = ctx_stream(ctx, 0);
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(st, ev, 0));
+    Solver sv(ctx, *prob, o, *P, grid.nsteps, st);
     if (o.mg_precision == 32) sv.adjoint<float>(theta, grid.nsteps, checkpoint_every, qoi, dqoi_dtheta, status);
     else sv.adjoint<double>(theta, grid.nsteps, checkpoint_every, qoi, dqoi_dtheta, status);
     HIPCHK(hipGetLastError());
-    return sv.count_failed();
+    const int nf = sv.count_failed();
+    HIPCHK(hipEventRecord(ev, st));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ev, 0));
+    HIPCHK(hipEventDestroy(ev));
+    return nf;
   });
 }
 

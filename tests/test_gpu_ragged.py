@@ -1,0 +1,96 @@
+"""Ragged multi-level batching, hipGraph replay and the MLMC driver on the GPU."""
+import numpy as np
+import pytest
+import torch
+
+from henry_inputs import draw_theta
+from tests.oracle_runs import oracle_batch, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hx():
+    import paper_2403_17018_amd as P
+    h = P.Henry(0)
+    yield h
+    h.close()
+
+
+def _cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_ragged_call_matches_separate_calls(hx):
+    """Three batches, two on the same grid (merged inside the library), one on another grid
+    (its own stream): each equals its separate solve to rounding."""
+    import paper_2403_17018_amd as P
+    T = 7500.0
+    prob = P.problem(T=T)
+    a, b, c = draw_theta(31, 24), draw_theta(32, 40), draw_theta(33, 9)
+    ga, gc = P.grid(32, 16, 10), P.grid(64, 32, 20)
+    rr = hx.solve_ragged([(_cu(a), ga), (_cu(c), gc), (_cu(b), ga)], prob, want_p=True)
+    for th, g, r in ((a, ga, rr[0]), (c, gc, rr[1]), (b, ga, rr[2])):
+        s = hx.solve(_cu(th), g, prob, want_p=True)
+        assert r.nfailed == 0 and s.nfailed == 0
+        for x, y in ((r.c_T, s.c_T), (r.p_T, s.p_T)):
+            x, y = x.cpu().numpy(), y.cpu().numpy()
+            assert np.abs(x - y).max() <= 1e-12 * np.abs(y).max()
+        assert np.allclose(r.qoi.cpu().numpy(), s.qoi.cpu().numpy(), rtol=1e-12, atol=0)
+        assert torch.equal(r.stats[:, 0], s.stats[:, 0])
+
+
+def test_graph_replay_is_bitwise_equal_to_eager(hx):
+    """Each BiCGStab iteration replayed from a captured hipGraph, many replays with eager
+    Newton/assembly work in between, against the eager launch sequence."""
+    import paper_2403_17018_amd as P
+    th = _cu(draw_theta(0, 16))
+    for prec in (64, 32):
+        for g in (P.level_grid(0), P.grid(64, 32, 12)):
+            e = hx.solve(th, g, opts=P.solver_opts(mg_precision=prec, use_graphs=0), want_p=True)
+            r = hx.solve(th, g, opts=P.solver_opts(mg_precision=prec, use_graphs=1), want_p=True)
+            assert torch.equal(e.c_T, r.c_T) and torch.equal(e.p_T, r.p_T) and torch.equal(e.stats, r.stats)
+
+
+def test_ragged_with_graphs_matches_oracle(hx):
+    import paper_2403_17018_amd as P
+    T = 6000.0
+    a, b = draw_theta(41, 20), draw_theta(42, 6)
+    ga, gb = P.grid(32, 16, 8), P.grid(64, 32, 16)
+    rr = hx.solve_ragged([(_cu(a), ga), (_cu(b), gb)], P.problem(T=T), P.solver_opts(use_graphs=1, mg_precision=32))
+    for th, g, r in ((a, ga, rr[0]), (b, gb, rr[1])):
+        ref = oracle_batch(th, g.nx, g.ny, g.nsteps, dict(T=T))
+        assert r.nfailed == 0
+        c = r.c_T.permute(2, 0, 1).cpu().numpy()
+        assert rel_inf(c, ref["c"]).max() <= 1e-8
+
+
+def test_mlmc_run_matches_oracle_estimator(hx):
+    """Levels 0..2 with coupled fine/coarse pairs in one ragged call; the estimate equals the
+    oracle's estimator applied to oracle solves of the same samples."""
+    import paper_2403_17018_amd as P
+    from oracle import mlmc as M
+    m = [24, 8, 4]
+    thetas = [draw_theta(3, k, level=l) for l, k in enumerate(m)]
+    est = P.mlmc_run(hx, [_cu(t) for t in thetas], [0, 1, 2], opts=P.solver_opts(use_graphs=1))
+    assert est["nfailed"] == 0
+    gf, gc, cf, cc = [], [], [], []
+    for l, th in enumerate(thetas):
+        nx, ny, ns = 32 << l, 16 << l, 48 << l
+        f = oracle_batch(th, nx, ny, ns)
+        gf.append(f["qoi"])
+        cf.append(f["c"])
+        if l > 0:
+            c = oracle_batch(th, nx // 2, ny // 2, ns // 2)
+            gc.append(c["qoi"])
+            cc.append(c["c"])
+        else:
+            gc.append(None)
+            cc.append(None)
+    ref = M.estimate(gf, gc)
+    assert est["mean"] == pytest.approx(ref["mean"], rel=1e-8)
+    assert np.allclose(est["V"], ref["V"], rtol=1e-6, atol=1e-9 * ref["V"].max())
+    assert est["rmse"] == pytest.approx(ref["rmse"], rel=1e-6)
+    mf, vf = M.field_estimate(cf, cc)
+    assert np.abs(est["mean_field"].cpu().numpy() - mf).max() <= 1e-8
+    assert np.abs(est["var_field"].cpu().numpy() - vf).max() <= 1e-8
