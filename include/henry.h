@@ -101,6 +101,7 @@ typedef struct {
   int krylov_maxit;      /* [60] */
   double c_range_tol;    /* status 4 when c leaves [-tol, 1+tol] [1e-8] */
   int use_graphs;        /* capture each Krylov iteration in a hipGraph and replay it [0] */
+  int red_blocks;        /* target thread blocks of the per-sample reduction kernels [4096] */
 } henry_solver_opts;
 
 /* One batch of S independent samples on one grid (ragged batches: several per call). */
@@ -176,6 +177,16 @@ HENRY_API int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_gri
  * cost = sum m_l s_l.  Host arrays; returns HENRY_OK or HENRY_EINVAL. */
 HENRY_API int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, double eps,
                          long long* m_l, double* cost);
+
+/* Autotuner for one batch shape (ragged-batching support).  Times one Newton iteration
+ * (assembly, coarse factorisation and the full multigrid-preconditioned BiCGStab solve)
+ * from the initial state of the caller's samples for each candidate: coarsest grid
+ * {16x8, 32x16}, smoother sweeps {1+1, 2+2}, reduction blocks {1024, 4096, 16384} and
+ * hipGraphs {off, on}; writes the fastest into *opts (other fields unchanged) and its
+ * time into *best_ms (host, may be NULL).  All candidates converge to the same discrete
+ * solution; only speed differs.  theta: device [S][13]. */
+HENRY_API int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts* opts, henry_grid grid,
+                             int S, const double* theta, double* best_ms);
 
 /* Kernel-class timing on the context's stream (instrumentation for benchmarks).
  * henry_profile(ctx, 1) resets the counters and brackets every later launch of the

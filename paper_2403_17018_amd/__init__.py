@@ -191,6 +191,17 @@ class Henry:
                     var_field=var_f)
 
 
+    def autotune(self, theta, g: henry_grid, prob=None, opts=None):
+        """Fastest solver options for this batch shape (times one Newton iteration per candidate)."""
+        _check_theta(theta, self.device)
+        prob = prob or problem()
+        o = henry_solver_opts()
+        C.memmove(C.byref(o), C.byref(opts or solver_opts()), C.sizeof(o))
+        ms = C.c_double()
+        self._check(self._lib.henry_autotune(self._h, C.byref(prob), C.byref(o), g, theta.shape[0], _ptr(theta),
+                                             C.byref(ms)))
+        return o, ms.value
+
     def profile(self, enable: bool):
         """Start (reset) or stop event timing of kernel classes on this context's stream."""
         self._check(self._lib.henry_profile(self._h, 1 if enable else 0))

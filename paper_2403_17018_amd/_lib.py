@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libhenry.so")
 HENRY_OK, HENRY_EINVAL, HENRY_EDEVICE, HENRY_ENOMEM, HENRY_EUNSUPPORTED = 0, -1, -2, -3, -4
 EXPORTS = ("henry_problem_default", "henry_solver_opts_default", "henry_ctx_create", "henry_ctx_destroy",
            "henry_last_error", "henry_sample_fields", "henry_solve_batch", "henry_adjoint_batch",
-           "mlmc_estimate", "mlmc_optimal_samples", "henry_profile", "henry_profile_read")
+           "mlmc_estimate", "mlmc_optimal_samples", "henry_autotune", "henry_profile", "henry_profile_read")
 PROF_CLASSES = ("assemble", "gs", "spmv", "restrict", "prolong", "band_factor", "band_solve")
 
 
@@ -29,7 +29,7 @@ class henry_solver_opts(C.Structure):
     _fields_ = [("mg_precision", C.c_int), ("coarse_nx", C.c_int), ("coarse_ny", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("newton_tol", C.c_double), ("newton_dc_max", C.c_double),
                 ("newton_maxit", C.c_int), ("krylov_rtol", C.c_double), ("krylov_maxit", C.c_int),
-                ("c_range_tol", C.c_double), ("use_graphs", C.c_int)]
+                ("c_range_tol", C.c_double), ("use_graphs", C.c_int), ("red_blocks", C.c_int)]
 
 
 class henry_batch(C.Structure):
@@ -71,6 +71,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlmc_estimate.restype = i
     lib.mlmc_optimal_samples.argtypes = [i, P(d), P(d), d, P(C.c_longlong), P(d)]
     lib.mlmc_optimal_samples.restype = i
+    lib.henry_autotune.argtypes = [vp, P(henry_problem), P(henry_solver_opts), henry_grid, i, vp, P(d)]
+    lib.henry_autotune.restype = i
     lib.henry_profile.argtypes = [vp, i]
     lib.henry_profile.restype = i
     lib.henry_profile_read.argtypes = [vp, i, P(C.c_longlong), P(C.c_longlong), P(d)]

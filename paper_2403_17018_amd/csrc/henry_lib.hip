@@ -152,17 +152,14 @@ struct DevBuf {
   }
 };
 
-static Map make_map(int S, int ncell) {
+static Map make_map(int S, int ncell, int red_blocks) {
   Map m{};
   m.S = S;
   m.SX = S <= 64 ? S : 64;
   m.CY = std::max(1, 256 / m.SX);
   m.nsb = (S + m.SX - 1) / m.SX;
-  // reduction kernels: CPT cells per thread so that about `target` blocks cover the batch
-  static const int target = [] {
-    const char* e = std::getenv("HENRY_RED_BLOCKS");
-    return e ? std::max(64, std::atoi(e)) : 4096;
-  }();
+  // reduction kernels: CPT cells per thread so that about `red_blocks` blocks cover the batch
+  const int target = red_blocks > 0 ? std::max(64, red_blocks) : 4096;
   const int target_cb = std::max(1, target / m.nsb);
   const int rows = (ncell + m.CY - 1) / m.CY;
   m.CPT = std::max(1, (rows + target_cb - 1) / target_cb);
@@ -317,7 +314,7 @@ struct henry_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  std::map<std::tuple<int, int, int, int, int, int>, std::unique_ptr<Plan>> plans;
+  std::map<std::tuple<int, int, int, int, int, int, int>, std::unique_ptr<Plan>> plans;
   int* h_ctrl = nullptr;   // pinned
   DevBuf mlmc_tmp;
   DevBuf adj_ck, adj_seg, adj_g;   // adjoint checkpoints, segment states, sensitivities
@@ -368,7 +365,7 @@ static void plan_alloc_levels(Plan& P) {
 
 static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_opts& o) {
   const int cnx = std::min(o.coarse_nx, nx), cny = std::min(o.coarse_ny, ny);
-  auto key = std::make_tuple(nx, ny, S, o.mg_precision, cnx, cny);
+  auto key = std::make_tuple(nx, ny, S, o.mg_precision, cnx, cny, o.red_blocks);
   auto it = ctx->plans.find(key);
   if (it != ctx->plans.end()) return it->second.get();
   auto P = std::make_unique<Plan>();
@@ -380,7 +377,7 @@ static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_
   P->cny = cny;
   P->G = Grid2{nx, ny, nx * ny};
   P->N = (size_t)nx * ny * S;
-  P->m = make_map(S, nx * ny);
+  P->m = make_map(S, nx * ny, o.red_blocks);
   // hierarchy: halve while above the coarse size and even
   int gx = nx, gy = ny;
   while (true) {
@@ -721,6 +718,15 @@ struct Solver {
                        P.uin.as<double>(), o.c_range_tol, P.stats.as<double>(), P.status.as<int>());
   }
 
+  // one Newton linear system from the current state (autotuner probe)
+  template <typename T>
+  void probe_iteration() {
+    HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(P.ndone.p, 0, P.S * sizeof(int), st));
+    assemble_all<T>();
+    bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>());
+  }
+
   void qoi(double* out) {
     const Map& m = P.m;
     hipLaunchKernelGGL(k_qoi, grid_red(m), block_of(m), 0, st, m, P.G, phys, P.c.as<double>(), P.part.as<double>());
@@ -848,6 +854,7 @@ static void check_opts(const henry_solver_opts& o) {
   if (o.coarse_nx < 1 || o.coarse_ny < 1) fail(HENRY_EINVAL, "coarse grid must be positive");
   if (!(o.newton_tol > 0) || !(o.krylov_rtol > 0) || !(o.newton_dc_max > 0)) fail(HENRY_EINVAL, "tolerances must be positive");
   if (o.newton_maxit < 1 || o.krylov_maxit < 1) fail(HENRY_EINVAL, "iteration limits must be positive");
+  if (o.red_blocks < 0) fail(HENRY_EINVAL, "red_blocks must be >= 0");
 }
 
 static int theta_check(henry_ctx* ctx, const double* theta, int S) {
@@ -1065,6 +1072,7 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->krylov_maxit = 60;
   o->c_range_tol = 1e-8;
   o->use_graphs = 0;
+  o->red_blocks = 4096;
 }
 
 int henry_ctx_create(henry_ctx** out, int device, void* stream) {
@@ -1111,7 +1119,7 @@ int henry_sample_fields(henry_ctx* ctx, const henry_problem* prob, henry_grid gr
     check_grid(*prob, grid);
     if (S < 1 || !theta) fail(HENRY_EINVAL, "S must be >= 1 and theta non-NULL");
     if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
-    const Map m = make_map(S, grid.nx * grid.ny);
+    const Map m = make_map(S, grid.nx * grid.ny, 0);
     const Grid2 G{grid.nx, grid.ny, grid.nx * grid.ny};
     const Phys P = make_phys(*prob, grid.nx, grid.ny, grid.nsteps);
     const KLModes kl = make_kl(*prob);
@@ -1242,6 +1250,79 @@ int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_grid* grids, 
                          var_field);
       HIPCHK(hipGetLastError());
     }
+    return HENRY_OK;
+  });
+}
+
+int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts* opts, henry_grid grid, int S,
+                   const double* theta, double* best_ms) {
+  return guarded(ctx, [&]() -> int {
+    check_problem(prob);
+    if (!opts) fail(HENRY_EINVAL, "opts is NULL");
+    check_opts(*opts);
+    check_grid(*prob, grid);
+    if (S < 1 || !theta) fail(HENRY_EINVAL, "S < 1 or theta NULL");
+    if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
+    hipStream_t st = ctx_stream(ctx, 0);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    HIPCHK(hipEventCreate(&ev0));
+    HIPCHK(hipEventCreate(&ev1));
+    HIPCHK(hipEventRecord(ev0, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(st, ev0, 0));
+    const bool prof = ctx->prof.on;
+    ctx->prof.on = false;
+    std::vector<henry_solver_opts> cands;
+    const int coarse[2][2] = {{16, 8}, {32, 16}};
+    const int nu[2] = {1, 2};
+    const int rb[3] = {1024, 4096, 16384};
+    for (auto& cg : coarse)
+      for (int v : nu)
+        for (int r : rb)
+          for (int gr = 0; gr < 2; ++gr) {
+            henry_solver_opts c = *opts;
+            c.coarse_nx = cg[0];
+            c.coarse_ny = cg[1];
+            c.nu_pre = c.nu_post = v;
+            c.red_blocks = r;
+            c.use_graphs = gr;
+            cands.push_back(c);
+          }
+    double best = 1e300;
+    henry_solver_opts win = *opts;
+    std::vector<std::tuple<int, int, int, int, int, int, int>> used;
+    for (const auto& c : cands) {
+      Plan* P = get_plan(ctx, grid.nx, grid.ny, S, c);
+      used.emplace_back(grid.nx, grid.ny, S, c.mg_precision, std::min(c.coarse_nx, grid.nx),
+                        std::min(c.coarse_ny, grid.ny), c.red_blocks);
+      Solver sv(ctx, *prob, c, *P, grid.nsteps, st);
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {   // the first repetition absorbs one-time costs
+        sv.init(theta);
+        HIPCHK(hipEventRecord(ev0, st));
+        if (c.mg_precision == 32) sv.probe_iteration<float>();
+        else sv.probe_iteration<double>();
+        HIPCHK(hipEventRecord(ev1, st));
+        HIPCHK(hipEventSynchronize(ev1));
+        HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+      }
+      if (ms < best) {
+        best = ms;
+        win = c;
+      }
+    }
+    // keep only the winner's plan
+    const auto keep = std::make_tuple(grid.nx, grid.ny, S, win.mg_precision, std::min(win.coarse_nx, grid.nx),
+                                      std::min(win.coarse_ny, grid.ny), win.red_blocks);
+    HIPCHK(hipStreamSynchronize(st));
+    for (const auto& k : used)
+      if (k != keep) ctx->plans.erase(k);
+    ctx->prof.on = prof;
+    *opts = win;
+    if (best_ms) *best_ms = best;
+    HIPCHK(hipEventRecord(ev0, st));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ev0, 0));
+    HIPCHK(hipEventDestroy(ev0));
+    HIPCHK(hipEventDestroy(ev1));
     return HENRY_OK;
   });
 }

@@ -94,3 +94,17 @@ def test_mlmc_run_matches_oracle_estimator(hx):
     mf, vf = M.field_estimate(cf, cc)
     assert np.abs(est["mean_field"].cpu().numpy() - mf).max() <= 1e-8
     assert np.abs(est["var_field"].cpu().numpy() - vf).max() <= 1e-8
+
+
+def test_autotune_returns_a_valid_faster_config(hx):
+    """The tuner's choice solves to the same discrete solution as the defaults."""
+    import paper_2403_17018_amd as P
+    th = _cu(draw_theta(51, 48))
+    g = P.grid(64, 32, 6)
+    o, ms = hx.autotune(th, g)
+    assert ms > 0 and o.coarse_nx in (16, 32) and o.nu_pre in (1, 2) and o.red_blocks in (1024, 4096, 16384)
+    a = hx.solve(th, g, opts=o, want_p=True)
+    b = hx.solve(th, g, want_p=True)
+    assert a.nfailed == 0 and b.nfailed == 0
+    ca, cb = a.c_T.cpu().numpy(), b.c_T.cpu().numpy()
+    assert np.abs(ca - cb).max() <= 1e-8 * np.abs(cb).max()
