@@ -97,11 +97,13 @@ typedef struct {
   double newton_tol;     /* converged when |dc|_inf <= tol and |dp|_inf <= tol*rho0*g*Ly [1e-9] */
   double newton_dc_max;  /* each update is scaled by min(1, dc_max/|dc|_inf) [1.0] */
   int newton_maxit;      /* per time step [40] */
-  double krylov_rtol;    /* BiCGStab: |r|_2 <= rtol |r0|_2 per sample [1e-8] */
+  double krylov_rtol;    /* BiCGStab forcing term of the Newton systems: |r|_2 <= rtol |r0|_2 per
+                            sample [1e-2]; Newton's own stopping test fixes the accuracy */
   int krylov_maxit;      /* [60] */
   double c_range_tol;    /* status 4 when c leaves [-tol, 1+tol] [1e-8] */
   int use_graphs;        /* capture each Krylov iteration in a hipGraph and replay it [0] */
   int red_blocks;        /* target thread blocks of the per-sample reduction kernels [4096] */
+  double krylov_rtol_adjoint; /* BiCGStab tolerance of the transposed (adjoint) systems [1e-10] */
 } henry_solver_opts;
 
 /* One batch of S independent samples on one grid (ragged batches: several per call). */

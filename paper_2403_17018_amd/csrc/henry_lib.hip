@@ -232,16 +232,19 @@ struct Plan {
   int* h_ctrl = nullptr;   // pinned mirror of ctrl
   // captured BiCGStab iterations: [transposed][first iteration]
   hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-  int gkey[4] = {0, 0, 0, 0};   // nu_pre, nu_post, precision, valid
-  double grtol = 0.0;
+  int gkey[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // per operator: nu_pre, nu_post, precision, valid
+  double grtol[2] = {0.0, 0.0};
+  void drop_graphs(int tr) {
+    for (auto& g : gexec[tr])
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+    gkey[tr][3] = 0;
+  }
   void drop_graphs() {
-    for (auto& a : gexec)
-      for (auto& g : a)
-        if (g) {
-          (void)hipGraphExecDestroy(g);
-          g = nullptr;
-        }
-    gkey[3] = 0;
+    drop_graphs(0);
+    drop_graphs(1);
   }
   ~Plan() {
     drop_graphs();
@@ -597,7 +600,7 @@ struct Solver {
   // Right-preconditioned BiCGStab, per sample: A x = sign * rhs, x in vx, with A = J
   // (or J^T when TR).  Samples with mask[s] != 0 get a zero right-hand side.
   template <typename T, bool TR = false>
-  void bicgstab(const double* rhs, double sign, const int* mask) {
+  void bicgstab(const double* rhs, double sign, const int* mask, double rtol) {
     const Map& m = P.m;
     const int S = P.S;
     double* sc = P.sc.as<double>();
@@ -610,7 +613,7 @@ struct Solver {
     zero_ctrl();
     hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl);
     if (read_ctrl(0) == 0) return;
-    const double rtol2 = o.krylov_rtol * o.krylov_rtol;
+    const double rtol2 = rtol * rtol;
     // one BiCGStab iteration (both preconditioner applications and SpMVs), no host sync
     auto body = [&](int first) {
       hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, first, sc, P.vr.as<double>(), P.vv.as<double>(),
@@ -638,10 +641,10 @@ struct Solver {
     const bool graphs = o.use_graphs && !ctx->prof.on;
     if (graphs) {
       const int key[4] = {o.nu_pre, o.nu_post, P.prec, 1};
-      if (std::memcmp(key, P.gkey, sizeof key) != 0 || P.grtol != rtol2) {
-        P.drop_graphs();
-        std::memcpy(P.gkey, key, sizeof key);
-        P.grtol = rtol2;
+      if (std::memcmp(key, P.gkey[TR], sizeof key) != 0 || P.grtol[TR] != rtol2) {
+        P.drop_graphs(TR);
+        std::memcpy(P.gkey[TR], key, sizeof key);
+        P.grtol[TR] = rtol2;
       }
       for (int first = 0; first < 2; ++first) {
         if (P.gexec[TR][first]) continue;
@@ -698,7 +701,7 @@ struct Solver {
     int remaining = S;
     for (int it = 0; it < o.newton_maxit && remaining > 0; ++it) {
       assemble_all<T>();
-      bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>());
+      bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>(), o.krylov_rtol);
       hipLaunchKernelGGL(k_delta_max, grid_red(m), bl, 0, st, m, P.G.ncell, P.vx.as<double>(), P.part.as<double>());
       zero_ctrl();
       hipLaunchKernelGGL(k_fin_newton, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), p_ref,
@@ -724,7 +727,7 @@ struct Solver {
     HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemsetAsync(P.ndone.p, 0, P.S * sizeof(int), st));
     assemble_all<T>();
-    bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>());
+    bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>(), o.krylov_rtol);
   }
 
   void qoi(double* out) {
@@ -804,7 +807,7 @@ struct Solver {
         load(un);
         HIPCHK(hipMemcpyAsync(P.c_old.p, um + N, N * 8, hipMemcpyDeviceToDevice, st));
         assemble_all<T>();
-        bicgstab<T, true>(rhs, 1.0, nullptr);   // every sample solves its adjoint system
+        bicgstab<T, true>(rhs, 1.0, nullptr, o.krylov_rtol_adjoint);   // every sample solves its adjoint system
         hipLaunchKernelGGL(k_adj_param, rg, bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
                            P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.vx.as<double>(), gphi, gK,
                            P.part.as<double>());
@@ -852,7 +855,8 @@ static void check_opts(const henry_solver_opts& o) {
   if (o.mg_precision != 32 && o.mg_precision != 64) fail(HENRY_EINVAL, "mg_precision must be 32 or 64");
   if (o.nu_pre < 1 || o.nu_post < 0 || o.nu_pre > 8 || o.nu_post > 8) fail(HENRY_EINVAL, "nu_pre in [1,8], nu_post in [0,8]");
   if (o.coarse_nx < 1 || o.coarse_ny < 1) fail(HENRY_EINVAL, "coarse grid must be positive");
-  if (!(o.newton_tol > 0) || !(o.krylov_rtol > 0) || !(o.newton_dc_max > 0)) fail(HENRY_EINVAL, "tolerances must be positive");
+  if (!(o.newton_tol > 0) || !(o.krylov_rtol > 0) || !(o.newton_dc_max > 0) || !(o.krylov_rtol_adjoint > 0))
+    fail(HENRY_EINVAL, "tolerances must be positive");
   if (o.newton_maxit < 1 || o.krylov_maxit < 1) fail(HENRY_EINVAL, "iteration limits must be positive");
   if (o.red_blocks < 0) fail(HENRY_EINVAL, "red_blocks must be >= 0");
 }
@@ -1068,11 +1072,12 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->newton_tol = 1e-9;
   o->newton_dc_max = 1.0;
   o->newton_maxit = 40;
-  o->krylov_rtol = 1e-8;
+  o->krylov_rtol = 1e-2;
   o->krylov_maxit = 60;
   o->c_range_tol = 1e-8;
   o->use_graphs = 0;
   o->red_blocks = 4096;
+  o->krylov_rtol_adjoint = 1e-10;
 }
 
 int henry_ctx_create(henry_ctx** out, int device, void* stream) {

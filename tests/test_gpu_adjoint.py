@@ -115,3 +115,15 @@ def test_adjoint_level3_full_batch():
     for s in range(4):
         assert np.abs(gr[s] - fd[s]).max() <= 1e-6 * np.abs(fd[s]).max(), (s, gr[s], fd[s])
     h.close()
+
+
+def test_adjoint_with_graphs_equals_eager(hx):
+    """Forward and transposed BiCGStab iterations replayed from hipGraphs (alternating in the
+    reverse sweep) give bitwise the eager gradient."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(23, 8)
+    g = P.grid(64, 32, 8)
+    prob = P.problem(T=6000.0)
+    a = hx.adjoint(_cu(th), g, prob, P.solver_opts(use_graphs=0), checkpoint_every=3)
+    b = hx.adjoint(_cu(th), g, prob, P.solver_opts(use_graphs=1), checkpoint_every=3)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
