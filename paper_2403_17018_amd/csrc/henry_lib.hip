@@ -23,6 +23,7 @@
 
 #include "../../include/henry.h"
 #include "henry_kernels.hpp"
+#include "henry_coarse.hpp"
 #include "henry_mlmc.hpp"
 #include "henry_adjoint.hpp"
 
@@ -551,18 +552,26 @@ struct Solver {
     const dim3 gg = grid_cells(m, L.ny * half);
     // fine-grid smoother passes that read neighbours are timed as one class
     const long long half_units = (long long)L.ny * half * P.S;
-    auto gs = [&](int colour, int xz) {
+    MGLevel& C = *P.lv[k + 1];
+    auto gs = [&](int colour, int mode) {
       auto f = [&] {
-        hipLaunchKernelGGL((k_gs_colour<T, TR>), gg, block_of(m), 0, st, m, L.G, colour, xz, J, b, x);
+        if (mode == 1)
+          hipLaunchKernelGGL((k_gs_colour<T, TR, 1>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
+                             (const T*)nullptr);
+        else if (mode == 2)
+          hipLaunchKernelGGL((k_gs_colour<T, TR, 2>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
+                             (const T*)C.x.as<T>());
+        else
+          hipLaunchKernelGGL((k_gs_colour<T, TR, 0>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
+                             (const T*)nullptr);
       };
-      if (k == 0 && !xz) timed(ctx, st, HENRY_PROF_GS, half_units, f);
+      if (k == 0 && mode == 0) timed(ctx, st, HENRY_PROF_GS, half_units, f);
       else f();
     };
     for (int sw = 0; sw < o.nu_pre; ++sw) {
       gs(0, sw == 0 ? 1 : 0);
       gs(1, 0);
     }
-    MGLevel& C = *P.lv[k + 1];
     auto rr = [&] {
       hipLaunchKernelGGL((k_residual_restrict<T, TR>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G, 1, J,
                          b, x, C.b.as<T>());
@@ -570,13 +579,17 @@ struct Solver {
     if (k == 0) timed(ctx, st, HENRY_PROF_RESTRICT, (long long)L.ncell * P.S, rr);
     else rr();
     vcycle<T, TR>(k + 1, C.b.as<T>(), C.x.as<T>());
-    auto pc = [&] {
+    if (o.nu_post == 0) {
       hipLaunchKernelGGL((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G, C.x.as<T>(),
                          x);
-    };
-    if (k == 0) timed(ctx, st, HENRY_PROF_PROLONG, (long long)L.ncell * P.S, pc);
-    else pc();
-    for (int sw = 0; sw < o.nu_post; ++sw) {
+      return;
+    }
+    // the coarse-grid correction is folded into the first post-smoothing pass
+    auto g2 = [&] { gs(0, 2); };
+    if (k == 0) timed(ctx, st, HENRY_PROF_PROLONG, half_units, g2);
+    else g2();
+    gs(1, 0);
+    for (int sw = 1; sw < o.nu_post; ++sw) {
       gs(0, 0);
       gs(1, 0);
     }
