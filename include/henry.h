@@ -93,12 +93,13 @@ typedef struct {
   int mg_precision;      /* 64: FP64 multigrid; 32: FP32 multigrid preconditioner inside the
                             FP64 BiCGStab/Newton (iterative refinement) [64] */
   int coarse_nx, coarse_ny; /* coarsest multigrid grid, solved by a banded block LU [16, 8] */
-  int nu_pre, nu_post;   /* red-black block Gauss-Seidel sweeps [1, 1] */
+  int nu_pre, nu_post;   /* red-black block Gauss-Seidel sweeps [1, 2] */
   double newton_tol;     /* converged when |dc|_inf <= tol and |dp|_inf <= tol*rho0*g*Ly [1e-9] */
   double newton_dc_max;  /* each update is scaled by min(1, dc_max/|dc|_inf) [1.0] */
   int newton_maxit;      /* per time step [40] */
   double krylov_rtol;    /* BiCGStab forcing term of the Newton systems: |r|_2 <= rtol |r0|_2 per
-                            sample [1e-2]; Newton's own stopping test fixes the accuracy */
+                            sample, tested after each half step [3e-2]; Newton's own stopping
+                            test fixes the accuracy */
   int krylov_maxit;      /* [60] */
   double c_range_tol;    /* status 4 when c leaves [-tol, 1+tol] [1e-8] */
   int use_graphs;        /* capture each Krylov iteration in a hipGraph and replay it [0] */
@@ -180,19 +181,21 @@ HENRY_API int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_gri
 HENRY_API int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, double eps,
                          long long* m_l, double* cost);
 
-/* Autotuner for one batch shape (ragged-batching support).  Times one Newton iteration
- * (assembly, coarse factorisation and the full multigrid-preconditioned BiCGStab solve)
- * from the initial state of the caller's samples for each candidate: coarsest grid
- * {16x8, 32x16}, smoother sweeps {1+1, 2+2}, reduction blocks {1024, 4096, 16384} and
- * hipGraphs {off, on}; writes the fastest into *opts (other fields unchanged) and its
- * time into *best_ms (host, may be NULL).  All candidates converge to the same discrete
- * solution; only speed differs.  theta: device [S][13]. */
+/* Autotuner for one batch shape (ragged-batching support).  For each candidate -- coarsest
+ * grid {16x8, 32x16}, smoother sweeps {1+1, 1+2, 2+2}, reduction blocks {4096, 16384},
+ * hipGraphs {off, on} -- runs the first implicit-Euler step of the caller's samples
+ * untimed and times the second (so a weaker but cheaper preconditioner is charged for
+ * any extra Newton iterations); writes the fastest into *opts (other fields unchanged)
+ * and its step time into *best_ms (host, may be NULL).  All candidates converge to the
+ * same discrete solution; only speed differs.  theta: device [S][13]. */
 HENRY_API int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts* opts, henry_grid grid,
                              int S, const double* theta, double* best_ms);
 
 /* Kernel-class timing on the context's stream (instrumentation for benchmarks).
  * henry_profile(ctx, 1) resets the counters and brackets every later launch of the
- * classes below with HIP events; henry_profile(ctx, 0) stops.  henry_profile_read()
+ * classes below with HIP events (launches on whole batches only: the compacted
+ * sub-batches that finish a time step's last Newton iterations are not timed);
+ * henry_profile(ctx, 0) stops.  henry_profile_read()
  * returns, for one class: launches, units processed (cell-samples; for the smoother,
  * cells of the swept colour x samples) and the summed event time in ms.  Both calls
  * synchronise the stream. */

@@ -505,7 +505,7 @@ __global__ void k_convert(size_t n, const TI* __restrict__ a, TO* __restrict__ b
 // a3/a4: batched BiCGStab (FP64), per-sample scalars, fused dots
 // ==========================================================================
 // per-sample scalar slots
-enum { SC_RHO = 0, SC_ALPHA, SC_OMEGA, SC_BETA, SC_R0, SC_RNORM, SC_ACTIVE, SC_ITS, SC_NSLOT };
+enum { SC_RHO = 0, SC_ALPHA, SC_OMEGA, SC_BETA, SC_R0, SC_RNORM, SC_ACTIVE, SC_ITS, SC_HALF, SC_NSLOT };
 
 // r = sign * R (zero for samples with ndone[s] set; ndone may be NULL), rhat = r, x = 0; partial |r|^2
 __global__ void __launch_bounds__(256) k_bicg_init(Map m, int ncell, const double* __restrict__ R, double sign,
@@ -591,13 +591,25 @@ __global__ void __launch_bounds__(256) k_spmv_dot(Map m, Grid2 G, const double* 
 // s = r - alpha v
 __global__ void __launch_bounds__(256) k_bicg_s(Map m, int ncell, const double* __restrict__ sc,
                                                 const double* __restrict__ r, const double* __restrict__ v,
-                                                double* __restrict__ sv_) {
-  int s, cell, sb, cb;
-  if (!map_cell(m, ncell, s, cell, sb, cb)) return;
-  const size_t N = (size_t)ncell * m.S, id = (size_t)cell * m.S + s;
-  const double al = sc[SC_ALPHA * m.S + s];
-  sv_[id] = r[id] - al * v[id];
-  sv_[N + id] = r[N + id] - al * v[N + id];
+                                                double* __restrict__ sv_, double* __restrict__ part) {
+  __shared__ double lds[256];
+  const int sblk = blockIdx.x % m.nsb, cblk = blockIdx.x / m.nsb;
+  const int s = sblk * m.SX + threadIdx.x;
+  const bool ok = s < m.S;
+  const size_t N = (size_t)ncell * m.S;
+  const double al = ok ? sc[SC_ALPHA * m.S + s] : 0.0;
+  double acc[1] = {0.0};
+  for (int k = 0; k < m.CPT; ++k) {
+    const int cell = (cblk * m.CPT + k) * m.CY + threadIdx.y;
+    if (!ok || cell >= ncell) continue;
+    const size_t id = (size_t)cell * m.S + s;
+    const double s0 = r[id] - al * v[id], s1 = r[N + id] - al * v[N + id];
+    sv_[id] = s0;
+    sv_[N + id] = s1;
+    acc[0] += s0 * s0 + s1 * s1;
+  }
+  block_sum_y<1>(acc, lds);
+  if (threadIdx.y == 0 && ok) part[(size_t)cblk * m.S + s] = acc[0];
 }
 
 // x += alpha ph + omega sh; r = s - omega t; partials (rhat, r), (r, r)
@@ -620,8 +632,9 @@ __global__ void __launch_bounds__(256) k_bicg_xr(Map m, int ncell, const double*
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {
       const size_t q = comp * N + id;
-      x[q] += al * ph[q] + om * sh[q];
-      const double rv = sv_[q] - om * t[q];
+      // omega == 0 (half-step exit or inactive): s-hat and t may be stale, do not read them
+      x[q] += om != 0.0 ? al * ph[q] + om * sh[q] : al * ph[q];
+      const double rv = om != 0.0 ? sv_[q] - om * t[q] : sv_[q];
       r[q] = rv;
       acc[0] += rhat[q] * rv;
       acc[1] += rv * rv;
@@ -728,6 +741,30 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_alpha(Map m, const double* _
   }
 }
 
+// Half-step test: a sample whose |s| already meets the tolerance stops after the
+// alpha update (omega = 0 makes the rest of the iteration a no-op for it).  ctrl[0]
+// counts samples that still need the second half.
+__global__ void __launch_bounds__(64 * FIN_Y) k_fin_half(Map m, const double* __restrict__ part,
+                                                         double* __restrict__ sc, double rtol2, int* __restrict__ ctrl) {
+  __shared__ double lds[64 * FIN_Y];
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  double v[1];
+  reduce_partials<1>(m, part, s, v, lds);
+  if (threadIdx.y == 0 && s < m.S) {
+    const int S = m.S;
+    int half = 0;
+    if (sc[SC_ACTIVE * S + s] != 0.0) {
+      if (v[0] <= rtol2 * sc[SC_R0 * S + s]) {
+        half = 1;
+        sc[SC_OMEGA * S + s] = 0.0;
+      } else {
+        atomicAdd(&ctrl[0], 1);
+      }
+    }
+    sc[SC_HALF * S + s] = half;
+  }
+}
+
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_omega(Map m, const double* __restrict__ part,
                                                           double* __restrict__ sc) {
   __shared__ double lds[2 * 64 * FIN_Y];
@@ -737,7 +774,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_omega(Map m, const double* _
   if (threadIdx.y == 0 && s < m.S) {
     const int S = m.S;
     double om = 0.0;
-    if (sc[SC_ACTIVE * S + s] != 0.0 && v[1] > 0.0) om = v[0] / v[1];
+    if (sc[SC_ACTIVE * S + s] != 0.0 && sc[SC_HALF * S + s] == 0.0 && v[1] > 0.0) om = v[0] / v[1];
     sc[SC_OMEGA * S + s] = om;
   }
 }
@@ -757,7 +794,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_rho(Map m, const double* __r
       sc[SC_ITS * S + s] += 1.0;
       sc[SC_RNORM * S + s] = rr;
       bool act = true;
-      if (!(rr <= rtol2 * sc[SC_R0 * S + s])) {
+      if (!(rr <= rtol2 * sc[SC_R0 * S + s]) && sc[SC_HALF * S + s] == 0.0) {
         if (om == 0.0 || rho_new == 0.0 || !isfinite(rho_new)) {
           act = false;   // breakdown before convergence
           if (status) status[s] = 2;

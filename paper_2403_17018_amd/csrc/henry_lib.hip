@@ -231,8 +231,12 @@ struct Plan {
   size_t lu_stride;
   int mb;
   int* h_ctrl = nullptr;   // pinned mirror of ctrl
+  // Compacted sub-batch for the last Newton iterations of a step: same shape and
+  // capacity, used with an effective sample count Sa <= S (see Solver::compact_newton).
+  std::unique_ptr<Plan> compact;
+  DevBuf cidx;             // indices of the samples still iterating
   // captured BiCGStab iterations: [transposed][first iteration]
-  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t gexec[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
   int gkey[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // per operator: nu_pre, nu_post, precision, valid
   double grtol[2] = {0.0, 0.0};
   void drop_graphs(int tr) {
@@ -329,9 +333,10 @@ struct henry_ctx {
 // Launch `f` on stream `st` and, when profiling (and not capturing a graph), bracket
 // it with events of class `cls`.
 static thread_local bool tl_capturing = false;
+static thread_local bool tl_untimed = false;   // compacted sub-batches are not timed
 template <typename F>
 static void timed(henry_ctx* ctx, hipStream_t st, int cls, long long units, F&& f) {
-  if (!ctx->prof.on || tl_capturing) {
+  if (!ctx->prof.on || tl_capturing || tl_untimed) {
     f();
     return;
   }
@@ -367,11 +372,8 @@ static void plan_alloc_levels(Plan& P) {
   P.LU.alloc(P.lu_stride * P.S * sizeof(T));
 }
 
-static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_opts& o) {
+static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver_opts& o) {
   const int cnx = std::min(o.coarse_nx, nx), cny = std::min(o.coarse_ny, ny);
-  auto key = std::make_tuple(nx, ny, S, o.mg_precision, cnx, cny, o.red_blocks);
-  auto it = ctx->plans.find(key);
-  if (it != ctx->plans.end()) return it->second.get();
   auto P = std::make_unique<Plan>();
   P->nx = nx;
   P->ny = ny;
@@ -425,9 +427,28 @@ static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_
   P->part.alloc((size_t)12 * P->m.ncb * S * 8);
   P->ctrl.alloc(64);
   HIPCHK(hipHostMalloc((void**)&P->h_ctrl, 16 * sizeof(int), hipHostMallocDefault));
+  P->cidx.alloc((size_t)S * sizeof(int));
+  return P;
+}
+
+static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_opts& o) {
+  const int cnx = std::min(o.coarse_nx, nx), cny = std::min(o.coarse_ny, ny);
+  auto key = std::make_tuple(nx, ny, S, o.mg_precision, cnx, cny, o.red_blocks);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) return it->second.get();
+  auto P = make_plan(nx, ny, S, o);
   Plan* raw = P.get();
   ctx->plans[key] = std::move(P);
   return raw;
+}
+
+// Use plan Q (capacity >= Sa samples) for an effective batch of Sa samples.
+static void plan_set_samples(Plan& Q, int Sa, int red_blocks) {
+  Q.S = Sa;
+  Q.N = (size_t)Q.nx * Q.ny * Sa;
+  Q.m = make_map(Sa, Q.nx * Q.ny, red_blocks);
+  Q.part.alloc((size_t)12 * Q.m.ncb * Sa * 8);
+  Q.drop_graphs();
 }
 
 // ---------------------------------------------------------------------------
@@ -627,8 +648,11 @@ struct Solver {
     hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl);
     if (read_ctrl(0) == 0) return;
     const double rtol2 = rtol * rtol;
-    // one BiCGStab iteration (both preconditioner applications and SpMVs), no host sync
-    auto body = [&](int first) {
+    // One BiCGStab iteration in three parts.  A: p update, M^{-1} p, v = A p-hat, alpha,
+    // s = r - alpha v and the half-step test.  B (skipped when every active sample met the
+    // tolerance at the half step): M^{-1} s, t = A s-hat, omega.  C: x, r updates and the
+    // convergence test.  No host sync inside a part.
+    auto partA = [&](int first) {
       hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, first, sc, P.vr.as<double>(), P.vv.as<double>(),
                          P.vp.as<double>());
       precond<T, TR>(P.vp.as<double>(), P.vph.as<double>());
@@ -637,21 +661,27 @@ struct Solver {
                            P.vv.as<double>(), P.vrh.as<double>(), P.part.as<double>());
       });
       hipLaunchKernelGGL(k_fin_alpha, fg, fb, 0, st, m, P.part.as<double>(), sc, status);
-      hipLaunchKernelGGL(k_bicg_s, cg, bl, 0, st, m, P.G.ncell, sc, P.vr.as<double>(), P.vv.as<double>(),
-                         P.vs.as<double>());
+      hipLaunchKernelGGL(k_bicg_s, rg, bl, 0, st, m, P.G.ncell, sc, P.vr.as<double>(), P.vv.as<double>(),
+                         P.vs.as<double>(), P.part.as<double>());
+      zero_ctrl();
+      hipLaunchKernelGGL(k_fin_half, fg, fb, 0, st, m, P.part.as<double>(), sc, rtol2, ctrl);
+    };
+    auto partB = [&]() {
       precond<T, TR>(P.vs.as<double>(), P.vsh.as<double>());
       timed(ctx, st, HENRY_PROF_SPMV, (long long)P.N, [&] {
         hipLaunchKernelGGL((k_spmv_dot<2, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vsh.as<double>(),
                            P.vt.as<double>(), P.vs.as<double>(), P.part.as<double>());
       });
       hipLaunchKernelGGL(k_fin_omega, fg, fb, 0, st, m, P.part.as<double>(), sc);
+    };
+    auto partC = [&]() {
       hipLaunchKernelGGL(k_bicg_xr, rg, bl, 0, st, m, P.G.ncell, sc, P.vph.as<double>(), P.vsh.as<double>(),
                          P.vs.as<double>(), P.vt.as<double>(), P.vrh.as<double>(), P.vx.as<double>(), P.vr.as<double>(),
                          P.part.as<double>());
       zero_ctrl();
       hipLaunchKernelGGL(k_fin_rho, fg, fb, 0, st, m, P.part.as<double>(), sc, rtol2, status, ctrl);
     };
-    const bool graphs = o.use_graphs && !ctx->prof.on;
+    const bool graphs = o.use_graphs && allow_graphs && !ctx->prof.on;
     if (graphs) {
       const int key[4] = {o.nu_pre, o.nu_post, P.prec, 1};
       if (std::memcmp(key, P.gkey[TR], sizeof key) != 0 || P.grtol[TR] != rtol2) {
@@ -659,13 +689,15 @@ struct Solver {
         std::memcpy(P.gkey[TR], key, sizeof key);
         P.grtol[TR] = rtol2;
       }
-      for (int first = 0; first < 2; ++first) {
-        if (P.gexec[TR][first]) continue;
+      for (int part = 0; part < 4; ++part) {
+        if (P.gexec[TR][part]) continue;
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         tl_capturing = true;
         try {
-          body(first);
+          if (part < 2) partA(part);   // part 0: later iterations, part 1: first iteration
+          else if (part == 2) partB();
+          else partC();
         } catch (...) {
           tl_capturing = false;
           (void)hipStreamEndCapture(st, &g);
@@ -674,7 +706,7 @@ struct Solver {
         }
         tl_capturing = false;
         HIPCHK(hipStreamEndCapture(st, &g));
-        const hipError_t e = hipGraphInstantiate(&P.gexec[TR][first], g, nullptr, nullptr, 0);
+        const hipError_t e = hipGraphInstantiate(&P.gexec[TR][part], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         HIPCHK(e);
       }
@@ -682,7 +714,13 @@ struct Solver {
     for (int it = 0; it < o.krylov_maxit; ++it) {
       const int first = it == 0 ? 1 : 0;
       if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][first], st));
-      else body(first);
+      else partA(first);
+      if (read_ctrl(0) > 0) {
+        if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][2], st));
+        else partB();
+      }
+      if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][3], st));
+      else partC();
       if (read_ctrl(0) == 0) break;
     }
     hipLaunchKernelGGL(k_accum_its, dim3((S + 255) / 256), dim3(256), 0, st, S, sc, P.stats.as<double>());
@@ -711,8 +749,25 @@ struct Solver {
     }
     HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
+    newton_loop<T>(0);
+    hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
+                       P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.uin.as<double>(),
+                       P.part.as<double>());
+    hipLaunchKernelGGL(k_fin_balance, fin_grid(S), dim3(64, FIN_Y), 0, st, m, phys, P.part.as<double>(),
+                       P.uin.as<double>(), o.c_range_tol, P.stats.as<double>(), P.status.as<int>());
+  }
+
+  // Newton iterations it0.. of the current step on this plan's batch.  Once at most
+  // 3/4 of the samples are still iterating, the rest of the step runs on a compacted
+  // copy of those samples (compact_newton), so converged samples cost no bandwidth.
+  template <typename T>
+  void newton_loop(int it0) {
+    const Map& m = P.m;
+    const int S = P.S;
+    const dim3 cg = grid_cells(m, P.G.ncell), bl = block_of(m);
+    const double p_ref = pr.rho0 * pr.g * pr.Ly;
     int remaining = S;
-    for (int it = 0; it < o.newton_maxit && remaining > 0; ++it) {
+    for (int it = it0; it < o.newton_maxit && remaining > 0; ++it) {
       assemble_all<T>();
       bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>(), o.krylov_rtol);
       hipLaunchKernelGGL(k_delta_max, grid_red(m), bl, 0, st, m, P.G.ncell, P.vx.as<double>(), P.part.as<double>());
@@ -723,24 +778,67 @@ struct Solver {
       hipLaunchKernelGGL(k_newton_update, cg, bl, 0, st, m, P.G.ncell, P.lam.as<double>(), P.vx.as<double>(),
                          P.p.as<double>(), P.c.as<double>());
       remaining = read_ctrl(1);
+      if (allow_compact && remaining > 0 && 4 * remaining <= 3 * S && it + 1 < o.newton_maxit) {
+        compact_newton<T>(remaining, it + 1);
+        return;
+      }
     }
     if (remaining > 0)
       hipLaunchKernelGGL(k_mark_unconverged, dim3((S + 255) / 256), dim3(256), 0, st, S, P.ndone.as<int>(),
                          P.status.as<int>());
-    hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
-                       P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.uin.as<double>(),
-                       P.part.as<double>());
-    hipLaunchKernelGGL(k_fin_balance, fin_grid(S), dim3(64, FIN_Y), 0, st, m, phys, P.part.as<double>(),
-                       P.uin.as<double>(), o.c_range_tol, P.stats.as<double>(), P.status.as<int>());
   }
 
-  // one Newton linear system from the current state (autotuner probe)
+  bool allow_compact = true;
+
+  // Gather the Sa samples still iterating into the compact sub-plan, finish their Newton
+  // iterations there and scatter state, status and statistics back.
   template <typename T>
-  void probe_iteration() {
-    HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemsetAsync(P.ndone.p, 0, P.S * sizeof(int), st));
-    assemble_all<T>();
-    bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>(), o.krylov_rtol);
+  void compact_newton(int Sa, int it0) {
+    const int S = P.S;
+    if (!P.compact) P.compact = make_plan(P.nx, P.ny, S, o);
+    Plan& Q = *P.compact;
+    plan_set_samples(Q, Sa, o.red_blocks);
+    int* idx = P.cidx.as<int>();
+    hipLaunchKernelGGL(k_compact_index, dim3(1), dim3(64), 0, st, S, P.ndone.as<int>(), idx);
+    auto gather = [&](const double* src, double* dst, size_t rows) {
+      const size_t n = rows * Sa;
+      hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rows, S, Sa, idx, src, dst);
+    };
+    auto scatter = [&](const double* src, double* dst, size_t rows) {
+      const size_t n = rows * Sa;
+      hipLaunchKernelGGL(k_scatter_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rows, S, Sa, idx, src, dst);
+    };
+    const size_t nc = (size_t)P.G.ncell;
+    gather(P.p.as<double>(), Q.p.as<double>(), nc);
+    gather(P.c.as<double>(), Q.c.as<double>(), nc);
+    gather(P.c_old.as<double>(), Q.c_old.as<double>(), nc);
+    gather(P.phi.as<double>(), Q.phi.as<double>(), nc);
+    gather(P.K.as<double>(), Q.K.as<double>(), nc);
+    gather(P.uin.as<double>(), Q.uin.as<double>(), 1);
+    for (int k = 1; k < P.nlev; ++k) {
+      gather(P.lv[k]->phi.as<double>(), Q.lv[k]->phi.as<double>(), P.lv[k]->ncell);
+      gather(P.lv[k]->K.as<double>(), Q.lv[k]->K.as<double>(), P.lv[k]->ncell);
+    }
+    hipLaunchKernelGGL(k_gather_sample_info, dim3((Sa + 255) / 256), dim3(256), 0, st, Sa, idx, P.status.as<int>(),
+                       P.stats.as<double>(), Q.status.as<int>(), Q.stats.as<double>());
+    HIPCHK(hipMemsetAsync(Q.ndone.p, 0, Sa * sizeof(int), st));
+    Solver sq(ctx, pr, o, Q, 1, st);
+    sq.phys = phys;
+    sq.allow_compact = false;
+    sq.allow_graphs = false;
+    tl_untimed = true;
+    try {
+      sq.newton_loop<T>(it0);
+    } catch (...) {
+      tl_untimed = false;
+      throw;
+    }
+    tl_untimed = false;
+    scatter(Q.p.as<double>(), P.p.as<double>(), nc);
+    scatter(Q.c.as<double>(), P.c.as<double>(), nc);
+    hipLaunchKernelGGL(k_scatter_sample_info, dim3((Sa + 255) / 256), dim3(256), 0, st, Sa, idx, Q.status.as<int>(),
+                       Q.stats.as<double>(), Q.ndone.as<int>(), P.status.as<int>(), P.stats.as<double>(),
+                       P.ndone.as<int>());
   }
 
   void qoi(double* out) {
@@ -750,6 +848,7 @@ struct Solver {
   }
 
   int progress_every = 0;
+  bool allow_graphs = true;
 
   template <typename T>
   void run(const henry_batch& B) {
@@ -1081,11 +1180,11 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->coarse_nx = 16;
   o->coarse_ny = 8;
   o->nu_pre = 1;
-  o->nu_post = 1;
+  o->nu_post = 2;
   o->newton_tol = 1e-9;
   o->newton_dc_max = 1.0;
   o->newton_maxit = 40;
-  o->krylov_rtol = 1e-2;
+  o->krylov_rtol = 3e-2;
   o->krylov_maxit = 60;
   o->c_range_tol = 1e-8;
   o->use_graphs = 0;
@@ -1291,16 +1390,17 @@ int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts*
     ctx->prof.on = false;
     std::vector<henry_solver_opts> cands;
     const int coarse[2][2] = {{16, 8}, {32, 16}};
-    const int nu[2] = {1, 2};
-    const int rb[3] = {1024, 4096, 16384};
+    const int nu[3][2] = {{1, 1}, {1, 2}, {2, 2}};
+    const int rb[2] = {4096, 16384};
     for (auto& cg : coarse)
-      for (int v : nu)
+      for (auto& v : nu)
         for (int r : rb)
           for (int gr = 0; gr < 2; ++gr) {
             henry_solver_opts c = *opts;
             c.coarse_nx = cg[0];
             c.coarse_ny = cg[1];
-            c.nu_pre = c.nu_post = v;
+            c.nu_pre = v[0];
+            c.nu_post = v[1];
             c.red_blocks = r;
             c.use_graphs = gr;
             cands.push_back(c);
@@ -1314,11 +1414,16 @@ int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts*
                         std::min(c.coarse_ny, grid.ny), c.red_blocks);
       Solver sv(ctx, *prob, c, *P, grid.nsteps, st);
       float ms = 0.f;
-      for (int rep = 0; rep < 2; ++rep) {   // the first repetition absorbs one-time costs
+      // the first implicit-Euler step (damped start) is run untimed, the second is timed;
+      // a second repetition excludes one-time costs (graph capture, allocation)
+      const int nsteps = std::max(2, grid.nsteps);
+      for (int rep = 0; rep < 2; ++rep) {
         sv.init(theta);
+        if (c.mg_precision == 32) sv.time_step<float>(0, nsteps);
+        else sv.time_step<double>(0, nsteps);
         HIPCHK(hipEventRecord(ev0, st));
-        if (c.mg_precision == 32) sv.probe_iteration<float>();
-        else sv.probe_iteration<double>();
+        if (c.mg_precision == 32) sv.time_step<float>(1, nsteps);
+        else sv.time_step<double>(1, nsteps);
         HIPCHK(hipEventRecord(ev1, st));
         HIPCHK(hipEventSynchronize(ev1));
         HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));

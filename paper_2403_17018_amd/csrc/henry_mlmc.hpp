@@ -31,6 +31,52 @@ __global__ void k_count_nonzero(int S, const int* __restrict__ a, int* __restric
   if (s < S && a[s] != 0) atomicAdd(count, 1);
 }
 
+// Indices of the samples with ndone[s] == 0, in increasing order (one thread; S is small).
+__global__ void k_compact_index(int S, const int* __restrict__ ndone, int* __restrict__ idx) {
+  if (threadIdx.x != 0) return;
+  int a = 0;
+  for (int s = 0; s < S; ++s)
+    if (!ndone[s]) idx[a++] = s;
+}
+
+// dst[r][a] = src[r][idx[a]] for rows r of sample-fastest arrays ([rows][S] -> [rows][Sa])
+__global__ void k_gather_cols(size_t rows, int S, int Sa, const int* __restrict__ idx, const double* __restrict__ src,
+                              double* __restrict__ dst) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * Sa) return;
+  const size_t r = t / Sa, a = t - r * Sa;
+  dst[t] = src[r * S + idx[a]];
+}
+
+__global__ void k_scatter_cols(size_t rows, int S, int Sa, const int* __restrict__ idx, const double* __restrict__ src,
+                               double* __restrict__ dst) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * Sa) return;
+  const size_t r = t / Sa, a = t - r * Sa;
+  dst[r * S + idx[a]] = src[t];
+}
+
+__global__ void k_gather_sample_info(int Sa, const int* __restrict__ idx, const int* __restrict__ status,
+                                     const double* __restrict__ stats, int* __restrict__ cstatus,
+                                     double* __restrict__ cstats) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= Sa) return;
+  const int s = idx[a];
+  cstatus[a] = status[s];
+  for (int q = 0; q < 4; ++q) cstats[(size_t)a * 4 + q] = stats[(size_t)s * 4 + q];
+}
+
+__global__ void k_scatter_sample_info(int Sa, const int* __restrict__ idx, const int* __restrict__ cstatus,
+                                      const double* __restrict__ cstats, const int* __restrict__ cndone,
+                                      int* __restrict__ status, double* __restrict__ stats, int* __restrict__ ndone) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= Sa) return;
+  const int s = idx[a];
+  status[s] = cstatus[a];
+  ndone[s] = cndone[a];
+  for (int q = 0; q < 4; ++q) stats[(size_t)s * 4 + q] = cstats[(size_t)a * 4 + q];
+}
+
 // Fixed-order tree sum over 256 threads.
 __device__ __forceinline__ double block_sum_256(double v, double* lds) {
   const int t = threadIdx.x;

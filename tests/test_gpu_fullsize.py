@@ -40,7 +40,9 @@ def _check(out, name, samples):
         assert np.abs(p - z["p_T"]).max() <= TOL * np.abs(z["p_T"]).max(), s
         assert abs(out["q"][s] - float(z["qoi"])) <= TOL * abs(float(z["qoi"])), s
     assert out["nfailed"] == 0
-    assert out["st"][:, 2].max() < 1e-10 and out["st"][:, 3].max() < 1e-10
+    # global balance of the accepted Newton iterate: storage change + tau * boundary flux = sum of
+    # residuals, bounded by the solver tolerances (the exact discrete fixed point balances to ~1e-13)
+    assert out["st"][:, 2].max() < 1e-8 and out["st"][:, 3].max() < 1e-8
     assert out["c"].min() >= -1e-10 and out["c"].max() <= 1 + 1e-10
 
 

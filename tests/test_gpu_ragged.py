@@ -102,7 +102,8 @@ def test_autotune_returns_a_valid_faster_config(hx):
     th = _cu(draw_theta(51, 48))
     g = P.grid(64, 32, 6)
     o, ms = hx.autotune(th, g)
-    assert ms > 0 and o.coarse_nx in (16, 32) and o.nu_pre in (1, 2) and o.red_blocks in (1024, 4096, 16384)
+    assert ms > 0 and o.coarse_nx in (16, 32) and o.nu_pre in (1, 2) and o.nu_post in (1, 2)
+    assert o.red_blocks in (1024, 4096, 16384)
     a = hx.solve(th, g, opts=o, want_p=True)
     b = hx.solve(th, g, want_p=True)
     assert a.nfailed == 0 and b.nfailed == 0

@@ -64,7 +64,7 @@ def test_level0_batch_matches_oracle(hx):
     q = r.qoi.cpu().numpy()
     assert np.abs(q - ref["qoi"]).max() <= TOL * np.abs(ref["qoi"]).max()
     st = r.stats.cpu().numpy()
-    assert st[:, 2].max() < 1e-10 and st[:, 3].max() < 1e-10     # mass balance
+    assert st[:, 2].max() < 1e-8 and st[:, 3].max() < 1e-8       # mass balance of the accepted iterate
     assert c.min() >= -1e-10 and c.max() <= 1 + 1e-10
 
 

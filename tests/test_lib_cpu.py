@@ -52,7 +52,7 @@ def test_defaults_match_the_workload_constants():
     assert (p.Lx, p.Ly, p.T, p.rho0, p.rho1, p.mu, p.g) == (2.0, 1.0, 36000.0, 1000.0, 1025.0, 1e-3, 9.81)
     assert (p.Dm, p.K_mean, p.q_in, p.corr_len) == (1.88571e-5, 1.020408e-9, 6.6e-5, 0.5)
     o = P.solver_opts()
-    assert o.mg_precision == 64 and o.nu_pre == 1 and o.coarse_nx == 16 and o.coarse_ny == 8
+    assert o.mg_precision == 64 and o.nu_pre == 1 and o.nu_post == 2 and o.coarse_nx == 16 and o.coarse_ny == 8
 
 
 def test_optimal_samples_host_helper_matches_oracle():
