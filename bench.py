@@ -7,7 +7,8 @@ banded LU), mass balance and QoI, then the MLMC estimator over the batch.
 Default workload: MLMC level 3 (256x128 cells, 384 steps, 512 samples, seed 1), FP64.
 The metric is sample-timesteps/s = samples * time steps / wall time.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c1|c4]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c1|c4|c5]
+  c4: MLMC wall time to RMSE for levels 0..4 in one ragged call; c5: discrete adjoint
 """
 import argparse
 import hashlib
@@ -113,12 +114,46 @@ def bench_mlmc(args):
     print(json.dumps(out))
 
 
+def bench_adjoint(args):
+    """Discrete adjoint of the level-3 batch (256 samples, 384 steps, checkpoints every 32):
+    forward with checkpoints, reverse sweep with segment recomputation and transposed solves."""
+    import torch
+    import paper_2403_17018_amd as P
+    w = WORKLOADS["c5_adjoint_level3"]
+    prec = args.precision or 64
+    level, S, seed = w["level"], w["nsamples"], w["seed"]
+    nx, ny, nsteps = level_grid(level)
+    theta = torch.from_numpy(draw_theta(seed, S, level=level)).cuda()
+    hx = P.Henry(0)
+    g = P.grid(nx, ny, nsteps)
+    opts = P.solver_opts(mg_precision=prec)
+    for _ in range(args.warmup):
+        hx.adjoint(theta, g, opts=opts, checkpoint_every=w["checkpoint_every"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        q, grad, st, nf = hx.adjoint(theta, g, opts=opts, checkpoint_every=w["checkpoint_every"])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    out = {
+        "metric": "adjoint sample-timesteps/s", "value": S * nsteps / dt, "unit": "sample-timesteps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == 64 else "f64+f32mg", "data": "synthetic",
+        "config": {"workload": f"c5_adjoint_level3: {nx}x{ny} cells, {nsteps} steps, {S} samples (seed {seed}), "
+                               f"checkpoints every {w['checkpoint_every']} steps, gradient w.r.t. 13 parameters",
+                   "mg_precision": prec, "parallelism": "samples batched on one GPU"},
+        "failed_samples": nf, "mean_abs_grad": float(grad.abs().mean()), "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--graphs", type=int, default=None, help="capture BiCGStab iterations in hipGraphs (c4 default 1)")
     ap.add_argument("--precision", type=int, default=None, help="multigrid precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -129,6 +164,8 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         return bench_mlmc(args)
+    if args.workload == "c5":
+        return bench_adjoint(args)
     name = {"c1": "c1_fp64_level0", "c2": "c2_fp64_level3", "c3": "c3_mixed_level4"}[args.workload]
     w = WORKLOADS[name]
     prec = args.precision or w["mg_precision"]

@@ -105,6 +105,7 @@ typedef struct {
   int use_graphs;        /* capture each Krylov iteration in a hipGraph and replay it [0] */
   int red_blocks;        /* target thread blocks of the per-sample reduction kernels [4096] */
   double krylov_rtol_adjoint; /* BiCGStab tolerance of the transposed (adjoint) systems [1e-10] */
+  int newton_extrapolate;     /* 1: first Newton guess 2u^n - u^{n-1}; 0: u^n [1] */
 } henry_solver_opts;
 
 /* One batch of S independent samples on one grid (ragged batches: several per call). */

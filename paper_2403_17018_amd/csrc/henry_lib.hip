@@ -225,6 +225,7 @@ struct Plan {
   std::vector<std::unique_ptr<MGLevel>> lv;   // lv[0] = fine grid
   int nlev;
   DevBuf phi, K, uin, p, c, c_old, R, J, J32;
+  DevBuf p_prev, c_prev;   // state of the previous step (initial-guess extrapolation)
   DevBuf vx, vr, vrh, vp, vv, vs, vt, vph, vsh;
   DevBuf LU;
   DevBuf sc, lam, ndone, status, stats, part, ctrl;
@@ -413,6 +414,8 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
   P->p.alloc(N * 8);
   P->c.alloc(N * 8);
   P->c_old.alloc(N * 8);
+  P->p_prev.alloc(N * 8);
+  P->c_prev.alloc(N * 8);
   P->R.alloc(2 * N * 8);
   P->J.alloc(20 * N * 8);
   if (o.mg_precision == 32) P->J32.alloc(20 * N * 4);
@@ -749,6 +752,16 @@ struct Solver {
     }
     HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
+    if (o.newton_extrapolate) {
+      // Newton starts from 2 u^n - u^{n-1} (u^0 itself on the first step); the fixed point
+      // of the step does not depend on the guess
+      const size_t n2 = P.N;
+      const dim3 g((unsigned)((n2 + 255) / 256));
+      hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, n == 0 ? 0 : 1, P.p.as<double>(),
+                         P.p_prev.as<double>());
+      hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, n == 0 ? 0 : 1, P.c.as<double>(),
+                         P.c_prev.as<double>());
+    }
     newton_loop<T>(0);
     hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
                        P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.uin.as<double>(),
@@ -874,7 +887,7 @@ struct Solver {
     const int S = P.S;
     const size_t N = P.N, st2 = 2 * N * sizeof(double);
     const int ncp = nsteps / C + 1;
-    ctx->adj_ck.alloc((size_t)ncp * st2);
+    ctx->adj_ck.alloc((size_t)ncp * 2 * st2);   // (p, c) and the previous step's (p, c)
     ctx->adj_seg.alloc((size_t)(C + 1) * st2);
     ctx->adj_g.alloc((2 * N + 2 * N + S) * sizeof(double));
     double* ck = ctx->adj_ck.as<double>();
@@ -891,11 +904,21 @@ struct Solver {
       HIPCHK(hipMemcpyAsync(P.p.p, src, N * 8, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(P.c.p, src + N, N * 8, hipMemcpyDeviceToDevice, st));
     };
+    auto save_ck = [&](double* dst) {
+      save(dst);
+      HIPCHK(hipMemcpyAsync(dst + 2 * N, P.p_prev.p, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(dst + 3 * N, P.c_prev.p, N * 8, hipMemcpyDeviceToDevice, st));
+    };
+    auto load_ck = [&](const double* src) {
+      load(src);
+      HIPCHK(hipMemcpyAsync(P.p_prev.p, src + 2 * N, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(P.c_prev.p, src + 3 * N, N * 8, hipMemcpyDeviceToDevice, st));
+    };
     init(theta);
-    save(ck);
+    save_ck(ck);
     for (int n = 0; n < nsteps; ++n) {
       time_step<T>(n, nsteps);
-      if ((n + 1) % C == 0) save(ck + (size_t)((n + 1) / C) * 2 * N);
+      if ((n + 1) % C == 0) save_ck(ck + (size_t)((n + 1) / C) * 4 * N);
     }
     if (qoi_out) qoi(qoi_out);
     const dim3 cg = grid_cells(m, P.G.ncell), bl = block_of(m), rg = grid_red(m);
@@ -907,7 +930,7 @@ struct Solver {
     const int nseg = (nsteps + C - 1) / C;
     for (int sg = nseg - 1; sg >= 0; --sg) {
       const int n0 = sg * C, n1 = std::min(n0 + C, nsteps);
-      load(ck + (size_t)sg * 2 * N);
+      load_ck(ck + (size_t)sg * 4 * N);
       save(seg);
       for (int n = n0; n < n1; ++n) {
         time_step<T>(n, nsteps);
@@ -1190,6 +1213,7 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->use_graphs = 0;
   o->red_blocks = 4096;
   o->krylov_rtol_adjoint = 1e-10;
+  o->newton_extrapolate = 1;
 }
 
 int henry_ctx_create(henry_ctx** out, int device, void* stream) {
