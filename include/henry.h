@@ -106,6 +106,9 @@ typedef struct {
   int red_blocks;        /* target thread blocks of the per-sample reduction kernels [4096] */
   double krylov_rtol_adjoint; /* BiCGStab tolerance of the transposed (adjoint) systems [1e-10] */
   int newton_extrapolate;     /* 1: first Newton guess 2u^n - u^{n-1}; 0: u^n [1] */
+  double newton_predict;      /* > 0: a sample is also converged, without another linear solve, when
+                                 its predicted update |dc_{k-1}| |R_k| / |R_{k-1}| (after an undamped
+                                 update) is <= newton_predict * newton_tol; 0 disables [1] */
 } henry_solver_opts;
 
 /* One batch of S independent samples on one grid (ragged batches: several per call). */

@@ -30,7 +30,8 @@ class henry_solver_opts(C.Structure):
                 ("nu_post", C.c_int), ("newton_tol", C.c_double), ("newton_dc_max", C.c_double),
                 ("newton_maxit", C.c_int), ("krylov_rtol", C.c_double), ("krylov_maxit", C.c_int),
                 ("c_range_tol", C.c_double), ("use_graphs", C.c_int), ("red_blocks", C.c_int),
-                ("krylov_rtol_adjoint", C.c_double), ("newton_extrapolate", C.c_int)]
+                ("krylov_rtol_adjoint", C.c_double), ("newton_extrapolate", C.c_int),
+                ("newton_predict", C.c_double)]
 
 
 class henry_batch(C.Structure):

@@ -699,8 +699,12 @@ __device__ __forceinline__ void reduce_partials_max(const Map& m, const double* 
 // Finalisation kernels: blockDim = (64, FIN_Y), grid = ceil(S/64).  ctrl[0] counts active samples.
 constexpr int FIN_Y = 16;
 
+// nhist (Newton systems only, else NULL): per sample [size of the last undamped update
+// (0: none), |R|^2 of the previous iterate].  A sample whose predicted next update
+// size * |R_k| / |R_{k-1}| is <= pred_tol is declared converged without solving.
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_init(Map m, const double* __restrict__ part, double* __restrict__ sc,
-                                                  int* __restrict__ ctrl) {
+                                                  int* __restrict__ ctrl, double* __restrict__ nhist,
+                                                  int* __restrict__ ndone, double pred_tol) {
   __shared__ double lds[64 * FIN_Y];
   const int s = blockIdx.x * 64 + threadIdx.x;
   double v[1];
@@ -713,7 +717,16 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_init(Map m, const double* __
     sc[SC_ALPHA * S + s] = 0.0;
     sc[SC_OMEGA * S + s] = 0.0;
     sc[SC_BETA * S + s] = 0.0;
-    const int act = v[0] > 0.0;
+    int act = v[0] > 0.0;
+    if (nhist && act) {
+      const double last = nhist[2 * s], r2prev = nhist[2 * s + 1];
+      if (pred_tol > 0.0 && last > 0.0 && r2prev > 0.0 && last * sqrt(v[0] / r2prev) <= pred_tol) {
+        act = 0;
+        ndone[s] = 1;
+      }
+      nhist[2 * s + 1] = v[0];
+    }
+    if (nhist && !ndone[s]) atomicAdd(&ctrl[1], 1);   // Newton samples still iterating
     sc[SC_ACTIVE * S + s] = act;
     sc[SC_ITS * S + s] = 0.0;
     if (act) atomicAdd(&ctrl[0], 1);
@@ -852,7 +865,8 @@ __global__ void __launch_bounds__(256) k_delta_max(Map m, int ncell, const doubl
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_newton(Map m, const double* __restrict__ part, double p_ref,
                                                            double tol, double dc_max, double* __restrict__ lam,
                                                            int* __restrict__ ndone, int* __restrict__ status,
-                                                           double* __restrict__ stats, int* __restrict__ ctrl) {
+                                                           double* __restrict__ stats, int* __restrict__ ctrl,
+                                                           double* __restrict__ nhist) {
   __shared__ double lds[2 * 64 * FIN_Y];
   const int s = blockIdx.x * 64 + threadIdx.x;
   double v[2];
@@ -872,6 +886,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_newton(Map m, const double* 
   }
   lam[s] = mc > dc_max ? dc_max / mc : 1.0;
   const double size = fmax(mc, mp / p_ref);
+  nhist[2 * s] = mc > dc_max ? 0.0 : size;   // no prediction after a damped update
   if (size <= tol) ndone[s] = 1;
   else atomicAdd(&ctrl[1], 1);
 }

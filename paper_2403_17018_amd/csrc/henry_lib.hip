@@ -229,6 +229,7 @@ struct Plan {
   DevBuf vx, vr, vrh, vp, vv, vs, vt, vph, vsh;
   DevBuf LU;
   DevBuf sc, lam, ndone, status, stats, part, ctrl;
+  DevBuf nhist;            // per sample: last undamped Newton update size, previous |R|^2
   size_t lu_stride;
   int mb;
   int* h_ctrl = nullptr;   // pinned mirror of ctrl
@@ -425,6 +426,7 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
   P->sc.alloc((size_t)SC_NSLOT * S * 8);
   P->lam.alloc(S * 8);
   P->ndone.alloc(S * 4);
+  P->nhist.alloc((size_t)S * 2 * 8);
   P->status.alloc(S * 4);
   P->stats.alloc((size_t)S * 4 * 8);
   P->part.alloc((size_t)12 * P->m.ncb * S * 8);
@@ -635,9 +637,13 @@ struct Solver {
   }
 
   // Right-preconditioned BiCGStab, per sample: A x = sign * rhs, x in vx, with A = J
-  // (or J^T when TR).  Samples with mask[s] != 0 get a zero right-hand side.
+  // (or J^T when TR).  Samples with mask[s] != 0 get a zero right-hand side.  For a
+  // Newton system (newton = true, mask = ndone) the initial residual norms also drive the
+  // predictive convergence test; when that leaves at most `stop_at` samples iterating,
+  // the solve is not started and their count is returned (else -1), so that the caller
+  // can move them to a compacted batch first.
   template <typename T, bool TR = false>
-  void bicgstab(const double* rhs, double sign, const int* mask, double rtol) {
+  int bicgstab(const double* rhs, double sign, int* mask, double rtol, bool newton = false, int stop_at = -1) {
     const Map& m = P.m;
     const int S = P.S;
     double* sc = P.sc.as<double>();
@@ -648,8 +654,10 @@ struct Solver {
     hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, rhs, sign, mask, P.vr.as<double>(), P.vrh.as<double>(),
                        P.vx.as<double>(), P.part.as<double>());
     zero_ctrl();
-    hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl);
-    if (read_ctrl(0) == 0) return;
+    hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl,
+                       newton ? P.nhist.as<double>() : (double*)nullptr, mask, o.newton_tol * o.newton_predict);
+    if (read_ctrl(0) == 0) return -1;
+    if (newton && P.h_ctrl[1] <= stop_at) return P.h_ctrl[1];
     const double rtol2 = rtol * rtol;
     // One BiCGStab iteration in three parts.  A: p update, M^{-1} p, v = A p-hat, alpha,
     // s = r - alpha v and the half-step test.  B (skipped when every active sample met the
@@ -727,6 +735,7 @@ struct Solver {
       if (read_ctrl(0) == 0) break;
     }
     hipLaunchKernelGGL(k_accum_its, dim3((S + 255) / 256), dim3(256), 0, st, S, sc, P.stats.as<double>());
+    return -1;
   }
 
   // fields, coarse coefficients, initial state, cleared status/stats
@@ -752,6 +761,7 @@ struct Solver {
     }
     HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(P.nhist.p, 0, (size_t)S * 2 * sizeof(double), st));
     if (o.newton_extrapolate) {
       // Newton starts from 2 u^n - u^{n-1} (u^0 itself on the first step); the fixed point
       // of the step does not depend on the guess
@@ -782,12 +792,19 @@ struct Solver {
     int remaining = S;
     for (int it = it0; it < o.newton_maxit && remaining > 0; ++it) {
       assemble_all<T>();
-      bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>(), o.krylov_rtol);
+      // predictive stops can leave few samples iterating before the solve: compact first
+      const bool can_compact = allow_compact && o.newton_predict > 0.0 && it + 1 < o.newton_maxit;
+      const int left = bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>(), o.krylov_rtol, true,
+                                          can_compact ? (3 * S) / 4 : -1);
+      if (left >= 0) {
+        if (left > 0) compact_newton<T>(left, it);
+        return;
+      }
       hipLaunchKernelGGL(k_delta_max, grid_red(m), bl, 0, st, m, P.G.ncell, P.vx.as<double>(), P.part.as<double>());
       zero_ctrl();
       hipLaunchKernelGGL(k_fin_newton, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), p_ref,
                          o.newton_tol, o.newton_dc_max, P.lam.as<double>(), P.ndone.as<int>(), P.status.as<int>(),
-                         P.stats.as<double>(), P.ctrl.as<int>());
+                         P.stats.as<double>(), P.ctrl.as<int>(), P.nhist.as<double>());
       hipLaunchKernelGGL(k_newton_update, cg, bl, 0, st, m, P.G.ncell, P.lam.as<double>(), P.vx.as<double>(),
                          P.p.as<double>(), P.c.as<double>());
       remaining = read_ctrl(1);
@@ -833,7 +850,8 @@ struct Solver {
       gather(P.lv[k]->K.as<double>(), Q.lv[k]->K.as<double>(), P.lv[k]->ncell);
     }
     hipLaunchKernelGGL(k_gather_sample_info, dim3((Sa + 255) / 256), dim3(256), 0, st, Sa, idx, P.status.as<int>(),
-                       P.stats.as<double>(), Q.status.as<int>(), Q.stats.as<double>());
+                       P.stats.as<double>(), P.nhist.as<double>(), Q.status.as<int>(), Q.stats.as<double>(),
+                       Q.nhist.as<double>());
     HIPCHK(hipMemsetAsync(Q.ndone.p, 0, Sa * sizeof(int), st));
     Solver sq(ctx, pr, o, Q, 1, st);
     sq.phys = phys;
@@ -850,8 +868,8 @@ struct Solver {
     scatter(Q.p.as<double>(), P.p.as<double>(), nc);
     scatter(Q.c.as<double>(), P.c.as<double>(), nc);
     hipLaunchKernelGGL(k_scatter_sample_info, dim3((Sa + 255) / 256), dim3(256), 0, st, Sa, idx, Q.status.as<int>(),
-                       Q.stats.as<double>(), Q.ndone.as<int>(), P.status.as<int>(), P.stats.as<double>(),
-                       P.ndone.as<int>());
+                       Q.stats.as<double>(), Q.ndone.as<int>(), Q.nhist.as<double>(), P.status.as<int>(),
+                       P.stats.as<double>(), P.ndone.as<int>(), P.nhist.as<double>());
   }
 
   void qoi(double* out) {
@@ -994,6 +1012,7 @@ static void check_opts(const henry_solver_opts& o) {
     fail(HENRY_EINVAL, "tolerances must be positive");
   if (o.newton_maxit < 1 || o.krylov_maxit < 1) fail(HENRY_EINVAL, "iteration limits must be positive");
   if (o.red_blocks < 0) fail(HENRY_EINVAL, "red_blocks must be >= 0");
+  if (!(o.newton_predict >= 0.0 && o.newton_predict <= 1.0)) fail(HENRY_EINVAL, "newton_predict must be in [0, 1]");
 }
 
 static int theta_check(henry_ctx* ctx, const double* theta, int S) {
@@ -1214,6 +1233,7 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->red_blocks = 4096;
   o->krylov_rtol_adjoint = 1e-10;
   o->newton_extrapolate = 1;
+  o->newton_predict = 1.0;
 }
 
 int henry_ctx_create(henry_ctx** out, int device, void* stream) {

@@ -67,24 +67,31 @@ __global__ void k_scatter_cols(size_t rows, int S, int Sa, const int* __restrict
 }
 
 __global__ void k_gather_sample_info(int Sa, const int* __restrict__ idx, const int* __restrict__ status,
-                                     const double* __restrict__ stats, int* __restrict__ cstatus,
-                                     double* __restrict__ cstats) {
+                                     const double* __restrict__ stats, const double* __restrict__ nhist,
+                                     int* __restrict__ cstatus, double* __restrict__ cstats,
+                                     double* __restrict__ cnhist) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= Sa) return;
   const int s = idx[a];
   cstatus[a] = status[s];
   for (int q = 0; q < 4; ++q) cstats[(size_t)a * 4 + q] = stats[(size_t)s * 4 + q];
+  cnhist[2 * a] = nhist[2 * s];
+  cnhist[2 * a + 1] = nhist[2 * s + 1];
 }
 
 __global__ void k_scatter_sample_info(int Sa, const int* __restrict__ idx, const int* __restrict__ cstatus,
                                       const double* __restrict__ cstats, const int* __restrict__ cndone,
-                                      int* __restrict__ status, double* __restrict__ stats, int* __restrict__ ndone) {
+                                      const double* __restrict__ cnhist, int* __restrict__ status,
+                                      double* __restrict__ stats, int* __restrict__ ndone,
+                                      double* __restrict__ nhist) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= Sa) return;
   const int s = idx[a];
   status[s] = cstatus[a];
   ndone[s] = cndone[a];
   for (int q = 0; q < 4; ++q) stats[(size_t)s * 4 + q] = cstats[(size_t)a * 4 + q];
+  nhist[2 * s] = cnhist[2 * a];
+  nhist[2 * s + 1] = cnhist[2 * a + 1];
 }
 
 // Fixed-order tree sum over 256 threads.

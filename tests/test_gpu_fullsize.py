@@ -12,6 +12,11 @@ from henry_inputs import WORKLOADS, draw_theta, level_grid
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 TOL = 1e-8
+# Bound on the per-step mass-balance defect (storage change + tau * boundary flux, over one
+# step's inflow tau rho0 u_in Ly) of an accepted Newton iterate: a c error equal to the Newton
+# tolerance (1e-9) in every cell moves phi rho1 |Omega| 1e-9 of salt, about 1.4e-8 of one
+# step's inflow; the bound allows 7 times that.
+DEFECT = 1e-7
 
 
 def _run(name, prec):
@@ -42,7 +47,7 @@ def _check(out, name, samples):
     assert out["nfailed"] == 0
     # global balance of the accepted Newton iterate: storage change + tau * boundary flux = sum of
     # residuals, bounded by the solver tolerances (the exact discrete fixed point balances to ~1e-13)
-    assert out["st"][:, 2].max() < 1e-8 and out["st"][:, 3].max() < 1e-8
+    assert out["st"][:, 2].max() < DEFECT and out["st"][:, 3].max() < DEFECT
     assert out["c"].min() >= -1e-10 and out["c"].max() <= 1 + 1e-10
 
 
