@@ -109,6 +109,11 @@ typedef struct {
   double newton_predict;      /* > 0: a sample is also converged, without another linear solve, when
                                  its predicted update |dc_{k-1}| |R_k| / |R_{k-1}| (after an undamped
                                  update) is <= newton_predict * newton_tol; 0 disables [1] */
+  double newton_jac_reuse;    /* > 0: after a Newton update whose size (as for newton_tol) is
+                                 <= newton_jac_reuse for every sample still iterating, the next
+                                 iteration keeps the Jacobian, the multigrid hierarchy and the
+                                 coarse factors (a chord step; only R is reassembled).  The first
+                                 iteration of each step always assembles.  0 disables [1e-3] */
 } henry_solver_opts;
 
 /* One batch of S independent samples on one grid (ragged batches: several per call). */

@@ -31,7 +31,8 @@ class henry_solver_opts(C.Structure):
                 ("newton_maxit", C.c_int), ("krylov_rtol", C.c_double), ("krylov_maxit", C.c_int),
                 ("c_range_tol", C.c_double), ("use_graphs", C.c_int), ("red_blocks", C.c_int),
                 ("krylov_rtol_adjoint", C.c_double), ("newton_extrapolate", C.c_int),
-                ("newton_predict", C.c_double)]
+                ("newton_predict", C.c_double),
+                ("newton_jac_reuse", C.c_double)]
 
 
 class henry_batch(C.Structure):

@@ -182,7 +182,7 @@ __device__ __forceinline__ void face_flux(const Phys& P, bool north, double pL, 
 }
 
 // J block order: 0 centre, 1 west, 2 east, 3 south, 4 north.
-template <bool WRITE_R, typename TJ, bool WRITE_J32>
+template <bool WRITE_R, typename TJ, bool WRITE_J32, bool WRITE_J = true>
 __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const double* __restrict__ p,
                                                   const double* __restrict__ c, const double* __restrict__ c_old,
                                                   const double* __restrict__ phi, const double* __restrict__ K,
@@ -282,6 +282,7 @@ __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const 
     R[id] = Rp;
     R[N + id] = Rc;
   }
+  if (!WRITE_J) return;
 #pragma unroll
   for (int e = 0; e < 4; ++e) J[e * N + id] = (TJ)D[e];
 #pragma unroll
@@ -866,7 +867,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_newton(Map m, const double* 
                                                            double tol, double dc_max, double* __restrict__ lam,
                                                            int* __restrict__ ndone, int* __restrict__ status,
                                                            double* __restrict__ stats, int* __restrict__ ctrl,
-                                                           double* __restrict__ nhist) {
+                                                           double* __restrict__ nhist, double jac_reuse) {
   __shared__ double lds[2 * 64 * FIN_Y];
   const int s = blockIdx.x * 64 + threadIdx.x;
   double v[2];
@@ -887,8 +888,12 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_newton(Map m, const double* 
   lam[s] = mc > dc_max ? dc_max / mc : 1.0;
   const double size = fmax(mc, mp / p_ref);
   nhist[2 * s] = mc > dc_max ? 0.0 : size;   // no prediction after a damped update
-  if (size <= tol) ndone[s] = 1;
-  else atomicAdd(&ctrl[1], 1);
+  if (size <= tol) {
+    ndone[s] = 1;
+  } else {
+    atomicAdd(&ctrl[1], 1);
+    if (!(size <= jac_reuse)) atomicAdd(&ctrl[2], 1);   // this sample wants a fresh Jacobian
+  }
 }
 
 __global__ void __launch_bounds__(256) k_newton_update(Map m, int ncell, const double* __restrict__ lam,

@@ -514,6 +514,14 @@ struct Solver {
     }
   }
 
+  // Residual only: the Jacobian hierarchy and the coarse factors of an earlier iterate are kept.
+  void assemble_residual() {
+    const Map& m = P.m;
+    hipLaunchKernelGGL((k_assemble<true, double, false, false>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
+                       phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
+                       P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), (double*)nullptr, (float*)nullptr);
+  }
+
   // fine-grid residual/Jacobian, rediscretised coarse Jacobians, coarse factorisation
   template <typename T>
   void assemble_all() {
@@ -790,8 +798,10 @@ struct Solver {
     const dim3 cg = grid_cells(m, P.G.ncell), bl = block_of(m);
     const double p_ref = pr.rho0 * pr.g * pr.Ly;
     int remaining = S;
+    bool fresh = true;   // the first iteration this plan runs in a step assembles J
     for (int it = it0; it < o.newton_maxit && remaining > 0; ++it) {
-      assemble_all<T>();
+      if (fresh) assemble_all<T>();
+      else assemble_residual();
       // predictive stops can leave few samples iterating before the solve: compact first
       const bool can_compact = allow_compact && o.newton_predict > 0.0 && it + 1 < o.newton_maxit;
       const int left = bicgstab<T, false>(P.R.as<double>(), -1.0, P.ndone.as<int>(), o.krylov_rtol, true,
@@ -804,10 +814,12 @@ struct Solver {
       zero_ctrl();
       hipLaunchKernelGGL(k_fin_newton, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), p_ref,
                          o.newton_tol, o.newton_dc_max, P.lam.as<double>(), P.ndone.as<int>(), P.status.as<int>(),
-                         P.stats.as<double>(), P.ctrl.as<int>(), P.nhist.as<double>());
+                         P.stats.as<double>(), P.ctrl.as<int>(), P.nhist.as<double>(), o.newton_jac_reuse);
       hipLaunchKernelGGL(k_newton_update, cg, bl, 0, st, m, P.G.ncell, P.lam.as<double>(), P.vx.as<double>(),
                          P.p.as<double>(), P.c.as<double>());
       remaining = read_ctrl(1);
+      // chord iteration next (same J) while every iterating sample's update was small
+      fresh = P.h_ctrl[2] > 0;
       if (allow_compact && remaining > 0 && 4 * remaining <= 3 * S && it + 1 < o.newton_maxit) {
         compact_newton<T>(remaining, it + 1);
         return;
@@ -1013,6 +1025,7 @@ static void check_opts(const henry_solver_opts& o) {
   if (o.newton_maxit < 1 || o.krylov_maxit < 1) fail(HENRY_EINVAL, "iteration limits must be positive");
   if (o.red_blocks < 0) fail(HENRY_EINVAL, "red_blocks must be >= 0");
   if (!(o.newton_predict >= 0.0 && o.newton_predict <= 1.0)) fail(HENRY_EINVAL, "newton_predict must be in [0, 1]");
+  if (!(o.newton_jac_reuse >= 0.0)) fail(HENRY_EINVAL, "newton_jac_reuse must be >= 0");
 }
 
 static int theta_check(henry_ctx* ctx, const double* theta, int S) {
@@ -1234,6 +1247,7 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->krylov_rtol_adjoint = 1e-10;
   o->newton_extrapolate = 1;
   o->newton_predict = 1.0;
+  o->newton_jac_reuse = 1e-3;
 }
 
 int henry_ctx_create(henry_ctx** out, int device, void* stream) {
