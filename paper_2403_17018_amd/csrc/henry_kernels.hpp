@@ -369,7 +369,10 @@ __device__ __forceinline__ void prolong_at(const T* __restrict__ e, size_t Nc, i
 // correction x += P e: the neighbours are read as x_Q + (P e)_Q on the fly.  The
 // corrected values of this pass's own colour are never needed (the pass overwrites
 // them) and those of the other colour are only read here (the next pass overwrites
-// them), so the correction is never written back.
+// them), so the correction is never written back.  MODE 3: the second pass of a
+// single pre-smoothing sweep from x = 0: the other colour's x is D^{-1} b there, and is
+// formed on the fly from the neighbours' diagonal blocks and right-hand sides instead of
+// being stored by a first pass (the next value of that colour is computed without it).
 template <typename T, bool TR = false, int MODE = 0>
 __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, Grid2 Gc, int colour, const T* __restrict__ J,
                                                    const T* __restrict__ b, T* __restrict__ x,
@@ -402,6 +405,19 @@ __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, Grid2 Gc, int
     apply_row_f<T, T, TR>(J, xv, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
     r0 -= a0;
     r1 -= a1;
+  } else if (MODE == 3) {
+    auto xv = [&](size_t q, int, T& x0, T& x1) {
+      const T q00 = J[q], q11 = J[3 * N + q];
+      const T q01 = TR ? J[2 * N + q] : J[N + q], q10 = TR ? J[N + q] : J[2 * N + q];
+      const T c0 = b[q], c1 = b[N + q];
+      const T qdet = q00 * q11 - q01 * q10;
+      x0 = (q11 * c0 - q01 * c1) / qdet;
+      x1 = (q00 * c1 - q10 * c0) / qdet;
+    };
+    T a0, a1;
+    apply_row_f<T, T, TR>(J, xv, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
+    r0 -= a0;
+    r1 -= a1;
   }
   const T d00 = J[id], d11 = J[3 * N + id];
   const T d01 = TR ? J[2 * N + id] : J[N + id], d10 = TR ? J[N + id] : J[2 * N + id];
@@ -412,7 +428,9 @@ __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, Grid2 Gc, int
 
 // Fused residual and restriction: b_H(I,J) = sum over the 2x2 children of (b - A x).
 // red_only: the last smoothing pass was the black one, which leaves a zero residual
-// on black cells, so only the two red children are evaluated.
+// on black cells, so only the two red children are evaluated.  red_only == 2: in
+// addition the red cells hold x = D^{-1} b (one pre-smoothing sweep from x = 0, its
+// red half never stored), so their residual is minus the off-diagonal part alone.
 template <typename T, bool TR = false>
 __global__ void __launch_bounds__(256) k_residual_restrict(Map m, Grid2 Gf, Grid2 Gc, int red_only,
                                                            const T* __restrict__ J, const T* __restrict__ b,
@@ -429,9 +447,15 @@ __global__ void __launch_bounds__(256) k_residual_restrict(Map m, Grid2 Gf, Grid
     if (red_only && ((i + j) & 1)) continue;
     const size_t id = ((size_t)j * Gf.nx + i) * S + s;
     T a0, a1;
-    apply_row<T, T, TR>(J, x, Nf, id, i, j, Gf.nx, Gf.ny, S, a0, a1, false);
-    s0 += b[id] - a0;
-    s1 += b[Nf + id] - a1;
+    if (red_only == 2) {
+      apply_row<T, T, TR>(J, x, Nf, id, i, j, Gf.nx, Gf.ny, S, a0, a1, true);
+      s0 -= a0;
+      s1 -= a1;
+    } else {
+      apply_row<T, T, TR>(J, x, Nf, id, i, j, Gf.nx, Gf.ny, S, a0, a1, false);
+      s0 += b[id] - a0;
+      s1 += b[Nf + id] - a1;
+    }
   }
   const size_t idc = (size_t)cc * S + s;
   bH[idc] = s0;

@@ -595,6 +595,9 @@ struct Solver {
         else if (mode == 2)
           hipLaunchKernelGGL((k_gs_colour<T, TR, 2>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
                              (const T*)C.x.as<T>());
+        else if (mode == 3)
+          hipLaunchKernelGGL((k_gs_colour<T, TR, 3>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
+                             (const T*)nullptr);
         else
           hipLaunchKernelGGL((k_gs_colour<T, TR, 0>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
                              (const T*)nullptr);
@@ -602,13 +605,21 @@ struct Solver {
       if (k == 0 && mode == 0) timed(ctx, st, HENRY_PROF_GS, half_units, f);
       else f();
     };
-    for (int sw = 0; sw < o.nu_pre; ++sw) {
-      gs(0, sw == 0 ? 1 : 0);
-      gs(1, 0);
+    // One pre-smoothing sweep followed by post-smoothing: the red half of the sweep is
+    // never stored (its values are D^{-1} b, formed where they are read, and the first
+    // post-smoothing pass recomputes red without them).
+    const bool implicit_red = o.nu_pre == 1 && o.nu_post >= 1;
+    if (implicit_red) {
+      gs(1, 3);
+    } else {
+      for (int sw = 0; sw < o.nu_pre; ++sw) {
+        gs(0, sw == 0 ? 1 : 0);
+        gs(1, 0);
+      }
     }
     auto rr = [&] {
-      hipLaunchKernelGGL((k_residual_restrict<T, TR>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G, 1, J,
-                         b, x, C.b.as<T>());
+      hipLaunchKernelGGL((k_residual_restrict<T, TR>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G,
+                         implicit_red ? 2 : 1, J, b, x, C.b.as<T>());
     };
     if (k == 0) timed(ctx, st, HENRY_PROF_RESTRICT, (long long)L.ncell * P.S, rr);
     else rr();
