@@ -96,7 +96,7 @@ typedef struct {
   int nu_pre, nu_post;   /* red-black block Gauss-Seidel sweeps [1, 2] */
   double newton_tol;     /* converged when |dc|_inf <= tol and |dp|_inf <= tol*rho0*g*Ly [1e-9] */
   double newton_dc_max;  /* each update is scaled by min(1, dc_max/|dc|_inf) [1.0] */
-  int newton_maxit;      /* per time step [40] */
+  int newton_maxit;      /* per time step [100] */
   double krylov_rtol;    /* BiCGStab forcing term of the Newton systems: |r|_2 <= rtol |r0|_2 per
                             sample, tested after each half step [3e-2]; Newton's own stopping
                             test fixes the accuracy */

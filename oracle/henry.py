@@ -272,7 +272,7 @@ def initial_state(prob: Problem, grid: Grid):
 @dataclasses.dataclass
 class SolveOptions:
     newton_tol: float = 1e-9      # |dc|_inf <= tol and |dp|_inf <= tol * rho0 g Ly
-    newton_maxit: int = 40
+    newton_maxit: int = 100
     dc_max: float = 1.0           # per-iteration limit on |dc|_inf (update scaled down)
     stagnate: bool = False        # iterate until the update stops shrinking (FD checks)
 

@@ -1249,7 +1249,7 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->nu_post = 2;
   o->newton_tol = 1e-9;
   o->newton_dc_max = 1.0;
-  o->newton_maxit = 40;
+  o->newton_maxit = 100;
   o->krylov_rtol = 3e-2;
   o->krylov_maxit = 60;
   o->c_range_tol = 1e-8;
