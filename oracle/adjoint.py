@@ -94,7 +94,10 @@ def theta_jacobians(prob, grid, theta):
 
 
 def adjoint_gradient(prob, grid, theta, opts: H.SolveOptions | None = None):
-    """(Q, dQ/dtheta[13]) for one sample via the reverse sweep over stored states."""
+    """(Q, dQ/dtheta[13]) for one sample via the reverse sweep over stored states
+    (KL fields with constant inflow only)."""
+    if prob.field_model != "kl" or prob.recharge_omega != 0.0:
+        raise NotImplementedError("adjoint of the KL model with constant inflow only")
     opts = opts or H.SolveOptions(stagnate=True)
     res = H.solve_sample(prob, grid, theta, opts, keep_states=True)
     phi, K, u_in = H.sample_fields(prob, grid, theta)

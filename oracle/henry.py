@@ -60,6 +60,23 @@ class Problem:
     n_kl_logK: int = 8
     right_c_dirichlet: bool = False
     c_left: float = 0.0
+    field_model: str = "kl"         # "kl": KL fields above; "paper": section 4 porosity and K
+    kappa_kc: float = 2.088415e-8   # Kozeny-Carman scale kappa_KC (Table 1), m^2
+    recharge_omega: float = 0.0     # left inflow u_in (1 + sin(omega t)); 0: constant in time
+
+
+def paper_problem(**kw) -> Problem:
+    """The paper's own stochastic model (section 4).
+
+    Porosity eq. poro_2levels (xi_1 = theta[0], xi_2 = theta[1]), permeability by
+    Kozeny-Carman (eq. e_perm_Kozeny_Carman), recharge eq. e_recharge_of_param:
+    6.6e-2 (1 + 0.5 xi_3)(1 + sin(pi t / 40)) kg/s over the 1 m left face, i.e. the
+    inflow velocity 6.6e-5 (1 + 0.5 xi_3)(1 + sin(pi t / 40)) m/s (xi_3 = theta[12]),
+    and the horizon T = 6016 s of section 4.
+    """
+    d = dict(field_model="paper", q_in_amp=0.5, recharge_omega=np.pi / 40.0, T=6016.0)
+    d.update(kw)
+    return Problem(**d)
 
 
 @dataclasses.dataclass
@@ -90,16 +107,45 @@ def kl_basis(prob: Problem) -> KL2D:
     return _KL_CACHE[key]
 
 
+def paper_porosity(X, Y, xi1, xi2, phi_hat=0.35):
+    """Section 4, eq. poro_2levels: phi = phi_hat C0 C1 C2 with
+    C0 = 1.2 (1 + 0.2 xi_1) below y = -0.8 and 1 above (a second layer),
+    C1 = 1 + 0.15 (xi_2 cos(pi x/2) - xi_2 sin(2 pi y) + xi_1 cos(2 pi x)) (large scales),
+    C2 = 1 + 0.2 (xi_1 sin(64 pi x) + xi_2 sin(32 pi y)) (small scales)."""
+    C0 = np.where(Y < -0.8, 1.2 * (1.0 + 0.2 * xi1), 1.0)
+    C1 = 1.0 + 0.15 * (xi2 * np.cos(np.pi * X / 2.0) - xi2 * np.sin(2.0 * np.pi * Y) + xi1 * np.cos(2.0 * np.pi * X))
+    C2 = 1.0 + 0.2 * (xi1 * np.sin(64.0 * np.pi * X) + xi2 * np.sin(32.0 * np.pi * Y))
+    return phi_hat * C0 * C1 * C2
+
+
+def kozeny_carman(prob: Problem, phi):
+    """eq. e_perm_Kozeny_Carman: K = kappa_KC phi^3 / (1 - phi^2)."""
+    return prob.kappa_kc * phi ** 3 / (1.0 - phi ** 2)
+
+
+def recharge_factor(prob: Problem, t):
+    """Time factor of the left inflow, 1 + sin(omega t) (eq. e_recharge_of_param with
+    omega = pi/40); exactly 1 for the constant-inflow model (omega = 0)."""
+    return 1.0 + np.sin(prob.recharge_omega * t)
+
+
 def sample_fields(prob: Problem, grid: Grid, theta):
     """phi[ny,nx], K[ny,nx], u_in for one theta[13], evaluated at cell centres.
 
-    phi = clip(phi_mean (1 + phi_amp sum_{k<4} sqrt(lam_k) xi_k e_k), phi_min, phi_max)
-    ln K = ln K_mean + logK_amp sum_{k<8} sqrt(lam_k) eta_k e_k
-    u_in = q_in (1 + q_in_amp zeta)
+    KL model:
+      phi = clip(phi_mean (1 + phi_amp sum_{k<4} sqrt(lam_k) xi_k e_k), phi_min, phi_max)
+      ln K = ln K_mean + logK_amp sum_{k<8} sqrt(lam_k) eta_k e_k
+    paper model: phi by eq. poro_2levels, K = kappa_KC phi^3 / (1 - phi^2).
+    Both: u_in = q_in (1 + q_in_amp zeta) (times the recharge time factor per step).
     """
     theta = np.asarray(theta, dtype=np.float64)
-    kl = kl_basis(prob)
     X, Y = cell_centres(prob, grid)
+    if prob.field_model == "paper":
+        phi = paper_porosity(X, Y, theta[0], theta[1], prob.phi_mean)
+        return phi, kozeny_carman(prob, phi), prob.q_in * (1.0 + prob.q_in_amp * theta[12])
+    if prob.field_model != "kl":
+        raise ValueError(prob.field_model)
+    kl = kl_basis(prob)
     E = kl.table(X, Y)
     sl = np.sqrt(kl.lam)
     s_phi = np.zeros_like(X)
@@ -125,6 +171,7 @@ class Discretisation:
     def __init__(self, prob: Problem, grid: Grid, phi, K, u_in, tau=None):
         self.prob, self.grid = prob, grid
         self.phi, self.K, self.u_in = phi, K, u_in
+        self.u_in_t = u_in          # inflow at the time level being solved for
         self.hx, self.hy = grid.h(prob)
         self.tau = prob.T / grid.nsteps if tau is None else tau
         X, Y = cell_centres(prob, grid)
@@ -136,6 +183,10 @@ class Discretisation:
         # face lists: P -> Q (east, then north)
         self.eP, self.eQ = idx[:, :-1].ravel(), idx[:, 1:].ravel()
         self.nP, self.nQ = idx[:-1, :].ravel(), idx[1:, :].ravel()
+
+    def set_time(self, t):
+        """Boundary data of the implicit-Euler step that ends at time t."""
+        self.u_in_t = self.u_in * recharge_factor(self.prob, t)
 
     # -- fluxes -------------------------------------------------------------
     def _face(self, p, c, P, Q, north):
@@ -174,7 +225,7 @@ class Discretisation:
         pr = self.prob
         hx, hy = self.hx, self.hy
         P = self.idx[:, 0]
-        F = -rho(pr, pr.c_left) * self.u_in * hy * np.ones(len(P))
+        F = -rho(pr, pr.c_left) * self.u_in_t * hy * np.ones(len(P))
         G = F * pr.c_left + 2.0 * rho(pr, c[P]) * self.phi.ravel()[P] * pr.Dm * (c[P] - pr.c_left) * hy / hx
         return P, F, G
 
@@ -348,6 +399,7 @@ def solve_sample(prob: Problem, grid: Grid, theta, opts: SolveOptions | None = N
     states = [(p.copy(), c.copy())] if keep_states else None
     for n in range(nsteps if nsteps is not None else grid.nsteps):
         c_old = c.copy()
+        disc.set_time((n + 1) * disc.tau)    # implicit Euler: boundary data at the new time
         p, c, k, conv = newton_step(disc, p, c, c_old, opts)
         its += k
         ok = ok and conv

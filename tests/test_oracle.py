@@ -229,6 +229,87 @@ def test_dirichlet_right_variant_keeps_bounds():
     assert -1e-10 <= r.c_min and r.c_max <= 1 + 1e-10
 
 
+# ------------------------------------------------ the paper's own model (section 4)
+def test_paper_porosity_at_points_where_most_terms_vanish():
+    """eq. poro_2levels at points where all but one or two terms vanish (values by hand):
+    x = 0, 1, 2 put cos(pi x/2) at 1, 0, -1; y = -0.5 and y = -0.25 put sin(2 pi y) at 0 and
+    -1 and sin(32 pi y) at 0; x = 0, 0.5, 1 put sin(64 pi x) at 0; y < -0.8 selects the
+    second layer factor 1.2 (1 + 0.2 xi_1)."""
+    P = lambda x, y, a, b: float(H.paper_porosity(np.array(x), np.array(y), a, b))
+    assert P(0.0, -0.5, 0.0, 1.0) == pytest.approx(0.35 * 1.15, rel=1e-14)    # xi_2 cos(pi x/2)
+    assert P(2.0, -0.5, 0.0, 1.0) == pytest.approx(0.35 * 0.85, rel=1e-14)
+    assert P(1.0, -0.25, 0.0, 1.0) == pytest.approx(0.35 * 1.15, rel=1e-14)   # -xi_2 sin(2 pi y)
+    assert P(1.0, -0.25, 0.0, -1.0) == pytest.approx(0.35 * 0.85, rel=1e-14)
+    assert P(0.0, -0.5, 1.0, 0.0) == pytest.approx(0.35 * 1.15, rel=1e-14)    # xi_1 cos(2 pi x)
+    assert P(0.5, -0.5, 1.0, 0.0) == pytest.approx(0.35 * 0.85, rel=1e-14)
+    assert P(1.0, -0.9, 1.0, 0.0) == pytest.approx(0.35 * 1.44 * 1.15, rel=1e-14)  # layer: 1.2 * 1.2
+    assert P(1.0, -0.9, -1.0, 0.0) == pytest.approx(0.35 * 0.96 * 0.85, rel=1e-14)
+    assert P(1.0, -0.7, 1.0, 0.0) == pytest.approx(0.35 * 1.15, rel=1e-14)
+    # small scales: sin(64 pi x) = 1 at x = 1/128 + k/32, sin(32 pi y) = 1 at y = -63/64
+    x = 0.5 + 1.0 / 128.0   # cos(2 pi x) = -cos(pi/64)
+    assert P(x, -0.5, 1.0, 0.0) == pytest.approx(0.35 * (1.0 - 0.15 * math.cos(math.pi / 64)) * 1.2, rel=1e-14)
+    # y = -33/64: sin(32 pi y) = sin(-16.5 pi) = -1, sin(2 pi y) = sin(pi/32)
+    assert P(1.0, -33.0 / 64.0, 0.0, 1.0) == pytest.approx(0.35 * (1.0 - 0.15 * math.sin(math.pi / 32)) * 0.8, rel=1e-14)
+
+
+def test_paper_fields_theta_zero_two_layers_and_kozeny_carman():
+    """theta = 0: phi = 0.35 above y = -0.8 and 0.42 below; K there is Kozeny-Carman of phi,
+    which at 0.35 is Table 1's K (so kappa_KC and K_hat agree), on every cell-centred grid."""
+    pr = H.paper_problem()
+    t1 = {r[0]: float(r[1]) for r in _table("paper_table1.txt")}
+    assert pr.kappa_kc == t1["kappa_KC"]
+    for lev in (0, 2):
+        g = H.Grid(*level_grid(lev))
+        phi, K, u = H.sample_fields(pr, g, np.zeros(13))
+        _, Y = H.cell_centres(pr, g)
+        np.testing.assert_allclose(phi[Y > -0.8], 0.35, rtol=1e-15)
+        np.testing.assert_allclose(phi[Y < -0.8], 0.42, rtol=1e-15)
+        np.testing.assert_allclose(K[Y > -0.8], t1["K_hat"], rtol=1e-6)
+        np.testing.assert_allclose(K[Y < -0.8], t1["kappa_KC"] * 0.42 ** 3 / (1 - 0.42 ** 2), rtol=1e-6)
+        assert u == pytest.approx(6.6e-5)
+    th = np.zeros(13); th[0], th[1] = 0.7, -0.4
+    g = H.Grid(*level_grid(2))
+    phi2, _, _ = H.sample_fields(pr, g, th)
+    assert 0.11 < phi2.min() and phi2.max() < 0.92     # bounds of C0 C1 C2 for |xi| <= 1
+    # q_in with xi_3: 6.6e-5 (1 + 0.5 xi_3)
+    th[12] = -0.6
+    assert H.sample_fields(pr, g, th)[2] == pytest.approx(6.6e-5 * 0.7, rel=1e-15)
+
+
+def test_recharge_pressure_closed_form_each_step():
+    """Constant density (rho1 = rho0), uniform phi and K (KL model, theta = 0) with the
+    periodic recharge: the flow is incompressible and one-dimensional, so after the step
+    ending at t_n the pressure is exactly p = -rho0 g y + mu u_in(t_n) (Lx - x) / K with
+    u_in(t) = 6.6e-5 (1 + 0.5 zeta)(1 + sin(pi t / 40)) -- boundary data at the new time
+    level (implicit Euler), the two-point flux being exact for a linear profile."""
+    pr = H.Problem(rho1=1000.0, q_in_amp=0.5, recharge_omega=np.pi / 40.0, T=130.0)
+    g = H.Grid(8, 4, 13)
+    th = np.zeros(13); th[12] = 0.4
+    r = H.solve_sample(pr, g, th, keep_states=True)
+    assert r.converged
+    X, Y = H.cell_centres(pr, g)
+    tau = pr.T / g.nsteps
+    for n in range(1, g.nsteps + 1):
+        u = 6.6e-5 * 1.2 * (1.0 + math.sin(math.pi * n * tau / 40.0))
+        p_exact = -1000.0 * 9.81 * Y + 1e-3 * u * (2.0 - X) / 1.020408e-9
+        np.testing.assert_allclose(r.states[n][0], p_exact.ravel(), rtol=1e-12, atol=1e-9 * 1000 * 9.81)
+        assert np.abs(r.states[n][1]).max() == 0.0
+
+
+def test_paper_model_balance_and_bounds_level0():
+    """The paper's model (section 4, T = 6016 s) at level 0: per-step conservation with the
+    time-dependent inflow, c in [0, 1], Newton converged."""
+    pr = H.paper_problem()
+    g = H.Grid(*level_grid(0))
+    th = draw_theta(0, 4)
+    for s in (0, 3):
+        r = H.solve_sample(pr, g, th[s])
+        assert r.converged
+        assert r.max_fluid_defect < 1e-10 and r.max_salt_defect < 1e-10
+        assert -1e-10 <= r.c_min and r.c_max <= 1 + 1e-10
+        assert 0 < r.qoi < 1025.0
+
+
 # ---------------------------------------------------------------- MLMC
 def test_mlmc_single_level_is_sample_mean_and_variance():
     rng = np.random.default_rng(3)
