@@ -80,6 +80,16 @@ typedef struct {
   int right_c_dirichlet;  /* 0: c = 1 carried by inflow on the right side only;
                              1: additionally diffusive Dirichlet c = 1 (paper section 2.1) */
   double c_left;          /* c of the left inflow and its Dirichlet value (0) */
+  int field_model;        /* 0: the KL fields above [0]; 1: the paper's own model (section 4):
+                             phi = phi_mean C0 C1 C2 (eq. poro_2levels) with xi_1 = theta[0],
+                             xi_2 = theta[1]: C0 = 1.2(1 + 0.2 xi_1) for y < -0.8, else 1;
+                             C1 = 1 + 0.15(xi_2 cos(pi x/2) - xi_2 sin(2 pi y) + xi_1 cos(2 pi x));
+                             C2 = 1 + 0.2(xi_1 sin(64 pi x) + xi_2 sin(32 pi y)); K by
+                             Kozeny-Carman (eq. e_perm_Kozeny_Carman); phi_amp, phi_min,
+                             phi_max, K_mean, logK_amp and the KL settings are unused */
+  double kappa_kc;        /* Kozeny-Carman scale: K = kappa_kc phi^3 / (1 - phi^2), m^2 [2.088415e-8] */
+  double recharge_omega;  /* the left inflow of the step ending at t is u_in (1 + sin(recharge_omega t))
+                             (eq. e_recharge_of_param: pi/40 rad/s); 0: constant [0] */
 } henry_problem;
 
 /* One mesh level: nx x ny square cells (h = Lx/nx = Ly/ny), nsteps implicit-Euler
@@ -156,7 +166,8 @@ HENRY_API int henry_solve_batch(henry_ctx* ctx, const henry_problem* prob, const
                       henry_batch* batches, int nbatches);
 
 /* Discrete adjoint of the converged time-stepped solve: dQ/dtheta for
- * Q = salt mass in x > Lx/2 at t = T.  Reverse sweep of transposed, multigrid-
+ * Q = salt mass in x > Lx/2 at t = T (KL fields with constant inflow; field_model 1 or
+ * a non-zero recharge_omega return HENRY_EUNSUPPORTED).  Reverse sweep of transposed, multigrid-
  * preconditioned BiCGStab solves, states recomputed from checkpoints taken every
  * `checkpoint_every` steps.
  *   theta: device [S][13]; qoi: device [S] or NULL; dqoi_dtheta: device [S][13];

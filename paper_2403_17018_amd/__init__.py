@@ -8,6 +8,7 @@ built libhenry.so every call raises.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import dataclasses
 
 import torch
@@ -36,6 +37,15 @@ def problem(**kw) -> henry_problem:
             raise AttributeError(k)
         setattr(p, k, v)
     return p
+
+
+def paper_problem(**kw) -> henry_problem:
+    """The paper's own stochastic model (section 4): two-layer multiscale porosity with
+    xi_1 = theta[0], xi_2 = theta[1], Kozeny-Carman permeability, recharge
+    6.6e-5 (1 + 0.5 xi_3)(1 + sin(pi t/40)) m/s with xi_3 = theta[12], T = 6016 s."""
+    d = dict(field_model=1, q_in_amp=0.5, recharge_omega=math.pi / 40.0, T=6016.0)
+    d.update(kw)
+    return problem(**d)
 
 
 def solver_opts(**kw) -> henry_solver_opts:

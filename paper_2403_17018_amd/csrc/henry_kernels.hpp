@@ -35,6 +35,7 @@ struct Grid2 {
 struct Phys {
   double rho0, drho, rho1, mu, g, Dm, c_left;
   double hx, hy, vol, tau, Ly, Lx;
+  double uin_fac;   // time factor of the left inflow for the step being solved
   int right_dir;
 };
 
@@ -48,8 +49,9 @@ struct KLModes {
 };
 
 struct FieldParams {
-  double phi_mean, phi_amp, phi_min, phi_max, lnK_mean, logK_amp, q_in, q_in_amp;
+  double phi_mean, phi_amp, phi_min, phi_max, lnK_mean, logK_amp, q_in, q_in_amp, kappa_kc;
   int n_phi, n_logK;
+  int model;   // 0: KL fields; 1: the section-4 porosity with Kozeny-Carman permeability
 };
 
 __device__ __forceinline__ bool map_cell(const Map& m, int ncell, int& s, int& cell, int& sblk, int& cblk) {
@@ -118,16 +120,28 @@ __global__ void k_fields(Map m, Grid2 G, Phys P, KLModes kl, FieldParams fp, con
   const double x = (i + 0.5) * P.hx;
   const double y = -P.Ly + (j + 0.5) * P.hy;
   const double* th = theta + (size_t)s * 13;
-  double sp = 0.0, sk = 0.0;
-  for (int k = 0; k < kl.n; ++k) {
-    const double e = kl_1d(kl.wx[k], kl.oddx[k], kl.normx[k], x - kl.xc) *
-                     kl_1d(kl.wy[k], kl.oddy[k], kl.normy[k], y - kl.yc);
-    if (k < fp.n_phi) sp += kl.sqrt_lam[k] * th[k] * e;
-    if (k < fp.n_logK) sk += kl.sqrt_lam[k] * th[4 + k] * e;
-  }
   const size_t id = (size_t)cell * m.S + s;
-  if (phi) phi[id] = fmin(fmax(fp.phi_mean * (1.0 + fp.phi_amp * sp), fp.phi_min), fp.phi_max);
-  if (K) K[id] = exp(fp.lnK_mean + fp.logK_amp * sk);
+  if (fp.model == 1) {
+    // section 4, eq. poro_2levels: a second layer below y = -0.8, large-scale and
+    // small-scale periodic factors; K by Kozeny-Carman (eq. e_perm_Kozeny_Carman)
+    const double xi1 = th[0], xi2 = th[1];
+    const double c0 = y < -0.8 ? 1.2 * (1.0 + 0.2 * xi1) : 1.0;
+    const double c1 = 1.0 + 0.15 * (xi2 * cospi(0.5 * x) - xi2 * sinpi(2.0 * y) + xi1 * cospi(2.0 * x));
+    const double c2 = 1.0 + 0.2 * (xi1 * sinpi(64.0 * x) + xi2 * sinpi(32.0 * y));
+    const double ph = fp.phi_mean * c0 * c1 * c2;
+    if (phi) phi[id] = ph;
+    if (K) K[id] = fp.kappa_kc * ph * ph * ph / (1.0 - ph * ph);
+  } else {
+    double sp = 0.0, sk = 0.0;
+    for (int k = 0; k < kl.n; ++k) {
+      const double e = kl_1d(kl.wx[k], kl.oddx[k], kl.normx[k], x - kl.xc) *
+                       kl_1d(kl.wy[k], kl.oddy[k], kl.normy[k], y - kl.yc);
+      if (k < fp.n_phi) sp += kl.sqrt_lam[k] * th[k] * e;
+      if (k < fp.n_logK) sk += kl.sqrt_lam[k] * th[4 + k] * e;
+    }
+    if (phi) phi[id] = fmin(fmax(fp.phi_mean * (1.0 + fp.phi_amp * sp), fp.phi_min), fp.phi_max);
+    if (K) K[id] = exp(fp.lnK_mean + fp.logK_amp * sk);
+  }
   if (uin && cell == 0) uin[s] = fp.q_in * (1.0 + fp.q_in_amp * th[12]);
 }
 
@@ -251,7 +265,7 @@ __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const 
   const double wb = P.hy / P.hx;
   // left boundary: prescribed inflow at c_left, diffusive Dirichlet c_left
   if (i == 0) {
-    const double F = -(P.rho0 + P.drho * P.c_left) * uin[s] * P.hy;
+    const double F = -(P.rho0 + P.drho * P.c_left) * uin[s] * P.uin_fac * P.hy;
     Rp += F;
     Rc += F * P.c_left + 2.0 * rP * phP * P.Dm * (cP - P.c_left) * wb;
     D[3] += 2.0 * phP * P.Dm * wb * (P.drho * (cP - P.c_left) + rP);
@@ -959,7 +973,7 @@ __global__ void __launch_bounds__(256) k_balance(Map m, Grid2 G, Phys P, const d
     acc[1] += P.vol * ph * (r * cP - ro * co);
     const double wb = P.hy / P.hx;
     if (i == 0) {
-      const double F = -(P.rho0 + P.drho * P.c_left) * uin[s] * P.hy;
+      const double F = -(P.rho0 + P.drho * P.c_left) * uin[s] * P.uin_fac * P.hy;
       acc[2] += P.tau * F;
       acc[3] += P.tau * (F * P.c_left + 2.0 * r * ph * P.Dm * (cP - P.c_left) * wb);
     }

@@ -204,7 +204,25 @@ static Phys make_phys(const henry_problem& pr, int nx, int ny, int nsteps) {
   P.Ly = pr.Ly;
   P.Lx = pr.Lx;
   P.right_dir = pr.right_c_dirichlet;
+  P.uin_fac = 1.0;
   return P;
+}
+
+static FieldParams make_fp(const henry_problem& pr) {
+  FieldParams fp{};
+  fp.phi_mean = pr.phi_mean;
+  fp.phi_amp = pr.phi_amp;
+  fp.phi_min = pr.phi_min;
+  fp.phi_max = pr.phi_max;
+  fp.lnK_mean = std::log(pr.K_mean);
+  fp.logK_amp = pr.logK_amp;
+  fp.q_in = pr.q_in;
+  fp.q_in_amp = pr.q_in_amp;
+  fp.kappa_kc = pr.kappa_kc;
+  fp.n_phi = pr.n_kl_phi;
+  fp.n_logK = pr.n_kl_logK;
+  fp.model = pr.field_model;
+  return fp;
 }
 
 // ---------------------------------------------------------------------------
@@ -473,16 +491,7 @@ struct Solver {
       : ctx(c), pr(p), o(op), P(pl), st(stream) {
     phys = make_phys(pr, P.nx, P.ny, nsteps);
     kl = make_kl(pr);
-    fp.phi_mean = pr.phi_mean;
-    fp.phi_amp = pr.phi_amp;
-    fp.phi_min = pr.phi_min;
-    fp.phi_max = pr.phi_max;
-    fp.lnK_mean = std::log(pr.K_mean);
-    fp.logK_amp = pr.logK_amp;
-    fp.q_in = pr.q_in;
-    fp.q_in_amp = pr.q_in_amp;
-    fp.n_phi = pr.n_kl_phi;
-    fp.n_logK = pr.n_kl_logK;
+    fp = make_fp(pr);
   }
 
   Phys phys_level(int k) const {
@@ -778,6 +787,8 @@ struct Solver {
       std::fprintf(stderr, "[henry] %dx%d S=%d fp%d step %d/%d\n", P.nx, P.ny, S, P.prec, n + 1, nsteps);
       std::fflush(stderr);
     }
+    // implicit Euler: boundary data at the end of the step, t = (n + 1) tau
+    phys.uin_fac = 1.0 + std::sin(pr.recharge_omega * (n + 1) * phys.tau);
     HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
     HIPCHK(hipMemsetAsync(P.nhist.p, 0, (size_t)S * 2 * sizeof(double), st));
@@ -1018,6 +1029,10 @@ static void check_problem(const henry_problem* pr) {
     if (!(std::isfinite(x) && x > 0)) fail(HENRY_EINVAL, "problem constants must be positive and finite");
   if (pr->n_kl_phi < 0 || pr->n_kl_phi > 4 || pr->n_kl_logK < 0 || pr->n_kl_logK > 8)
     fail(HENRY_EINVAL, "n_kl_phi must be in [0,4] and n_kl_logK in [0,8]");
+  if (pr->field_model != 0 && pr->field_model != 1) fail(HENRY_EINVAL, "field_model must be 0 or 1");
+  if (pr->field_model == 1 && !(std::isfinite(pr->kappa_kc) && pr->kappa_kc > 0))
+    fail(HENRY_EINVAL, "kappa_kc must be positive and finite");
+  if (!std::isfinite(pr->recharge_omega)) fail(HENRY_EINVAL, "recharge_omega must be finite");
 }
 
 static void check_grid(const henry_problem& pr, henry_grid g) {
@@ -1237,6 +1252,9 @@ void henry_problem_default(henry_problem* p) {
   p->n_kl_logK = 8;
   p->right_c_dirichlet = 0;
   p->c_left = 0.0;
+  p->field_model = 0;
+  p->kappa_kc = 2.088415e-8;
+  p->recharge_omega = 0.0;
 }
 
 void henry_solver_opts_default(henry_solver_opts* o) {
@@ -1309,8 +1327,7 @@ int henry_sample_fields(henry_ctx* ctx, const henry_problem* prob, henry_grid gr
     const Grid2 G{grid.nx, grid.ny, grid.nx * grid.ny};
     const Phys P = make_phys(*prob, grid.nx, grid.ny, grid.nsteps);
     const KLModes kl = make_kl(*prob);
-    FieldParams fp{prob->phi_mean, prob->phi_amp, prob->phi_min, prob->phi_max, std::log(prob->K_mean),
-                   prob->logK_amp, prob->q_in, prob->q_in_amp, prob->n_kl_phi, prob->n_kl_logK};
+    const FieldParams fp = make_fp(*prob);
     hipLaunchKernelGGL(k_fields, grid_cells(m, G.ncell), block_of(m), 0, ctx->stream, m, G, P, kl, fp, theta, phi, K,
                        q_in);
     HIPCHK(hipGetLastError());
@@ -1348,6 +1365,8 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_problem* prob, const henry_s
     check_grid(*prob, grid);
     if (S < 1 || !theta || !dqoi_dtheta) fail(HENRY_EINVAL, "S < 1, theta or dqoi_dtheta NULL");
     if (checkpoint_every < 1) fail(HENRY_EINVAL, "checkpoint_every must be >= 1");
+    if (prob->field_model != 0 || prob->recharge_omega != 0.0)
+      fail(HENRY_EUNSUPPORTED, "the adjoint covers the KL fields with constant inflow only");
     if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
     Plan* P = get_plan(ctx, grid.nx, grid.ny, S, o);
     hipStream_t st = ctx_stream(ctx, 0);

@@ -4,7 +4,10 @@ The oracle needs minutes per sample at 256x128 and about an hour at 512x256, so
 the GPU parity tests at those sizes compare against these stored results for a
 few sampled realisations instead of re-running the oracle.
 
-usage: python tests/golden/make_golden.py {c2|c3|c5|all} [--procs N]
+"f1" is the paper's own stochastic model (section 4) at level 2 (128x64 cells,
+192 steps over T = 6016 s), seed 5, samples 0 and 1.
+
+usage: python tests/golden/make_golden.py {c2|c3|c5|f1|all} [--procs N]
 """
 import argparse
 import os
@@ -23,7 +26,7 @@ from oracle import henry as H  # noqa: E402
 
 def _forward(args):
     name, level, seed, s = args
-    pr = H.Problem()
+    pr = H.paper_problem() if name == "f1" else H.Problem()
     g = H.Grid(*level_grid(level))
     th = draw_theta(seed, s + 1, level=level)[s]
     t = time.time()
@@ -50,7 +53,7 @@ def _adjoint(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c2", "c3", "c5", "all"])
+    ap.add_argument("which", choices=["c2", "c3", "c5", "f1", "all"])
     ap.add_argument("--procs", type=int, default=3)
     a = ap.parse_args()
     jobs = []
@@ -60,6 +63,8 @@ def main():
     if a.which in ("c5", "all"):
         w = WORKLOADS["c5_adjoint_level3"]
         jobs += [(_adjoint, ("c5", w["level"], w["seed"], 0))]
+    if a.which in ("f1", "all"):
+        jobs += [(_forward, ("f1", 2, 5, s)) for s in (0, 1)]
     if a.which in ("c3", "all"):
         w = WORKLOADS["c3_mixed_level4"]
         jobs += [(_forward, ("c3", w["level"], w["seed"], 0))]

@@ -42,6 +42,20 @@ def oracle_batch(theta, nx, ny, nsteps, prob_kw=None, procs=NPROC):
         return {k: z[k] for k in z.files}
 
 
+def defect_bound(theta, tau, phi_max, q_in_amp=0.1, q_in=6.6e-5, newton_tol=1e-9, margin=5.0):
+    """Largest per-step mass-balance defect allowed for accepted Newton iterates, per sample.
+
+    The GPU reports the defect (storage change + tau * boundary outflux) of each step over
+    one step's inflow tau rho0 u_in Ly.  The exact discrete fixed point balances to rounding;
+    an iterate accepted at Newton tolerance tol may be off by about tol in c in every cell,
+    which moves at most phi_max rho1 |Omega| tol of salt (and rho1 - rho0 times that of
+    fluid).  `margin` covers the predictive stop, whose accepted iterate is only predicted
+    to be within tol.  Returns the bound for every sample of theta [S, 13] (u_in from zeta).
+    """
+    u_in = q_in * (1.0 + q_in_amp * np.asarray(theta)[:, 12])
+    return margin * phi_max * 1025.0 * 2.0 * newton_tol / (tau * 1000.0 * u_in * 1.0)
+
+
 def rel_inf(a, b):
     """Per-sample normwise relative error max|a-b| / max|b| over the leading sample axis."""
     a = np.asarray(a).reshape(a.shape[0], -1)

@@ -1,0 +1,127 @@
+"""GPU parity for the paper's own stochastic model (section 4): two-layer multiscale
+porosity (eq. poro_2levels), Kozeny-Carman permeability (eq. e_perm_Kozeny_Carman) and the
+periodic recharge (eq. e_recharge_of_param), T = 6016 s.  Same tolerance as the KL model:
+per sample max|c_gpu - c_oracle| / max|c_oracle| <= 1e-8, likewise p and the QoI."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from henry_inputs import draw_theta, level_grid
+from tests.oracle_runs import defect_bound, oracle_batch, rel_inf
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-8
+PHI_MAX = 0.92   # bound of eq. poro_2levels for |xi| <= 1 (0.35 * 1.44 * 1.3 * 1.4 below y = -0.8)
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+ORACLE_KW = dict(field_model="paper", q_in_amp=0.5, recharge_omega=math.pi / 40.0, T=6016.0)
+
+
+@pytest.fixture(scope="module")
+def hx():
+    import paper_2403_17018_amd as P
+    h = P.Henry(0)
+    yield h
+    h.close()
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _solve(hx, th, g, **okw):
+    import paper_2403_17018_amd as P
+    r = hx.solve(_cuda(th), g, P.paper_problem(), P.solver_opts(**okw), want_c=True, want_p=True)
+    torch.cuda.synchronize()
+    return r, r.c_T.permute(2, 0, 1).cpu().numpy(), r.p_T.permute(2, 0, 1).cpu().numpy()
+
+
+def test_paper_fields_match_oracle(hx):
+    """Level 2 (the small scales sin(64 pi x), sin(32 pi y) resolved) and level 4."""
+    import paper_2403_17018_amd as P
+    from oracle import henry as H
+    th = draw_theta(5, 19)
+    for lev in (2, 4):
+        g = P.level_grid(lev)
+        phi, K, q = hx.sample_fields(_cuda(th), g, P.paper_problem())
+        phi, K, q = (t.cpu().numpy() for t in (phi, K, q))
+        for s in (0, 7, 18):
+            rphi, rK, ru = H.sample_fields(H.paper_problem(), H.Grid(g.nx, g.ny, g.nsteps), th[s])
+            assert np.abs(phi[..., s] - rphi).max() <= 1e-14
+            assert np.abs(K[..., s] / rK - 1).max() <= 1e-12
+            assert abs(q[s] - ru) <= 1e-18
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_paper_model_matches_oracle(hx, level):
+    """Levels 0 and 1 over the paper's horizon (48 and 96 steps of 6016 s), 8 samples."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(5, 8, level=level)
+    g = P.level_grid(level)
+    for prec in (64, 32):
+        r, c, p = _solve(hx, th, g, mg_precision=prec)
+        ref = oracle_batch(th, g.nx, g.ny, g.nsteps, ORACLE_KW)
+        assert r.nfailed == 0 and ref["conv"].all()
+        assert rel_inf(c, ref["c"]).max() <= TOL, prec
+        assert rel_inf(p, ref["p"]).max() <= TOL, prec
+        q = r.qoi.cpu().numpy()
+        assert np.abs(q - ref["qoi"]).max() <= TOL * np.abs(ref["qoi"]).max()
+        st = r.stats.cpu().numpy()
+        bound = defect_bound(th, 6016.0 / g.nsteps, PHI_MAX, q_in_amp=0.5)
+        assert (st[:, 2] < bound).all() and (st[:, 3] < bound).all()
+        assert c.min() >= -1e-10 and c.max() <= 1 + 1e-10
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "oracle_f1_s0.npz")), reason="oracle result not stored")
+def test_paper_model_level2_batch_against_stored_oracle(hx):
+    """Level 2 (128x64 cells, 192 steps), 64 samples of seed 5 in one batch: samples 0 and 1
+    against the stored oracle results (tests/golden/make_golden.py f1), invariants for all."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(5, 64, level=2)
+    r, c, p = _solve(hx, th, P.level_grid(2))
+    assert r.nfailed == 0
+    q = r.qoi.cpu().numpy()
+    for s in (0, 1):
+        z = np.load(os.path.join(GOLD, f"oracle_f1_s{s}.npz"))
+        assert np.array_equal(z["theta"], th[s])
+        assert np.abs(c[s].ravel() - z["c_T"]).max() <= TOL * np.abs(z["c_T"]).max()
+        assert np.abs(p[s].ravel() - z["p_T"]).max() <= TOL * np.abs(z["p_T"]).max()
+        assert abs(q[s] - float(z["qoi"])) <= TOL * abs(float(z["qoi"]))
+    st = r.stats.cpu().numpy()
+    bound = defect_bound(th, 6016.0 / 192, PHI_MAX, q_in_amp=0.5)
+    assert (st[:, 2] < bound).all() and (st[:, 3] < bound).all()
+    assert c.min() >= -1e-10 and c.max() <= 1 + 1e-10
+
+
+def test_recharge_pressure_closed_form(hx):
+    """Constant density, uniform phi and K (theta = 0) and the periodic recharge: after the
+    last step p = -rho0 g y + mu u_in(T) (Lx - x) / K exactly, u_in(T) = 6.6e-5 (1 + 0.5 zeta)
+    (1 + sin(pi T / 40)), the recharge taken at the end of the step."""
+    import paper_2403_17018_amd as P
+    th = np.zeros((3, 13))
+    th[:, 12] = (0.4, -0.3, 0.9)
+    g = P.grid(32, 16, 13)
+    pr = P.problem(rho1=1000.0, q_in_amp=0.5, recharge_omega=math.pi / 40.0, T=130.0)
+    r = hx.solve(_cuda(th), g, pr, P.solver_opts(), want_c=True, want_p=True)
+    torch.cuda.synchronize()
+    assert r.nfailed == 0
+    p = r.p_T.cpu().numpy()
+    h = 1.0 / 16
+    x = (np.arange(32) + 0.5) * h
+    y = -1.0 + (np.arange(16) + 0.5) * h
+    for s in range(3):
+        u = 6.6e-5 * (1.0 + 0.5 * th[s, 12]) * (1.0 + math.sin(math.pi * 130.0 / 40.0))
+        exact = -1000.0 * 9.81 * y[:, None] + 1e-3 * u * (2.0 - x[None, :]) / 1.020408e-9
+        assert np.abs(p[..., s] - exact).max() <= 1e-9 * 1000.0 * 9.81
+    # no salt enters (outflow everywhere at the right side); inexact Newton iterates may
+    # touch c by less than the Newton tolerance
+    assert np.abs(r.c_T.cpu().numpy()).max() <= 1e-9
+
+
+def test_adjoint_of_paper_model_is_unsupported(hx):
+    import paper_2403_17018_amd as P
+    with pytest.raises(P.HenryError) as e:
+        hx.adjoint(_cuda(draw_theta(5, 2)), P.level_grid(0), P.paper_problem())
+    assert e.value.code == -4

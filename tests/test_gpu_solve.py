@@ -9,15 +9,10 @@ import pytest
 import torch
 
 from henry_inputs import draw_theta, level_grid
-from tests.oracle_runs import oracle_batch, rel_inf
+from tests.oracle_runs import defect_bound, oracle_batch, rel_inf
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-8
-# Bound on the per-step mass-balance defect (storage change + tau * boundary flux, over one
-# step's inflow tau rho0 u_in Ly) of an accepted Newton iterate: a c error equal to the Newton
-# tolerance (1e-9) in every cell moves phi rho1 |Omega| 1e-9 of salt, about 1.4e-8 of one
-# step's inflow; the bound allows 7 times that.
-DEFECT = 1e-7
 
 
 @pytest.fixture(scope="module")
@@ -69,7 +64,8 @@ def test_level0_batch_matches_oracle(hx):
     q = r.qoi.cpu().numpy()
     assert np.abs(q - ref["qoi"]).max() <= TOL * np.abs(ref["qoi"]).max()
     st = r.stats.cpu().numpy()
-    assert st[:, 2].max() < DEFECT and st[:, 3].max() < DEFECT       # mass balance of the accepted iterate
+    bound = defect_bound(th, 36000.0 / g.nsteps, 0.5)               # mass balance of the accepted iterates
+    assert (st[:, 2] < bound).all() and (st[:, 3] < bound).all()
     assert c.min() >= -1e-10 and c.max() <= 1 + 1e-10
 
 

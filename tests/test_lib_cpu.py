@@ -33,17 +33,24 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layout_matches_header(tmp_path):
+    """Size and every field offset of each ABI struct, gcc against the ctypes binding."""
     from paper_2403_17018_amd import _lib
+    structs = {"henry_problem": _lib.henry_problem, "henry_grid": _lib.henry_grid,
+               "henry_solver_opts": _lib.henry_solver_opts, "henry_batch": _lib.henry_batch}
+    exprs, want = [], []
+    for name, cls in structs.items():
+        exprs.append(f"sizeof({name})")
+        want.append(ctypes.sizeof(cls))
+        for f in cls._fields_:
+            exprs.append(f"offsetof({name}, {f[0]})")
+            want.append(getattr(cls, f[0]).offset)
+    body = "".join(f'printf("%zu\\n", (size_t)({x}));' for x in exprs)
     src = tmp_path / "sz.c"
-    src.write_text('#include "henry.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){printf("%zu %zu %zu %zu %zu %zu\\n",'
-                   'sizeof(henry_problem), sizeof(henry_grid), sizeof(henry_solver_opts), sizeof(henry_batch),'
-                   'offsetof(henry_problem, c_left), offsetof(henry_solver_opts, use_graphs));return 0;}\n')
+    src.write_text('#include "henry.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){' + body + 'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
-    v = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
-    assert v == [ctypes.sizeof(_lib.henry_problem), ctypes.sizeof(_lib.henry_grid),
-                 ctypes.sizeof(_lib.henry_solver_opts), ctypes.sizeof(_lib.henry_batch),
-                 _lib.henry_problem.c_left.offset, _lib.henry_solver_opts.use_graphs.offset]
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert dict(zip(exprs, got)) == dict(zip(exprs, want))
 
 
 def test_defaults_match_the_workload_constants():
