@@ -7,8 +7,10 @@ banded LU), mass balance and QoI, then the MLMC estimator over the batch.
 Default workload: MLMC level 3 (256x128 cells, 384 steps, 512 samples, seed 1), FP64.
 The metric is sample-timesteps/s = samples * time steps / wall time.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c1|c4|c5]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c1|c4|c5|qmc] [--model kl|paper]
   c4: MLMC wall time to RMSE for levels 0..4 in one ragged call; c5: discrete adjoint
+  --model paper: the paper's own stochastic model (section 4; T = 6016 s) on the c1-c3 grids
+  qmc: that model over 600 Halton points (section 5) at --level (default 3)
 """
 import argparse
 import hashlib
@@ -27,14 +29,14 @@ from henry_inputs import WORKLOADS, draw_theta, level_grid  # noqa: E402
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # algorithmic bytes per unit of each kernel class (FP64 / FP32 multigrid), see the design doc
 BYTES = {
-    64: dict(gs=208, spmv=208, assemble=216, restrict=196, prolong=216),
-    32: dict(gs=104, spmv=208, assemble=296, restrict=98, prolong=108),
+    64: dict(gs=208, spmv=208, assemble=216, restrict=76, prolong=216),
+    32: dict(gs=104, spmv=208, assemble=296, restrict=38, prolong=108),
 }
 KERNEL_NAME = dict(gs="k_gs_colour", spmv="k_spmv_dot", assemble="k_assemble", restrict="k_residual_restrict",
                    prolong="k_gs_colour (fused prolongation)")
 
 
-def cpu_baseline(level, seed, nsamples_avail, steps_total):
+def cpu_baseline(level, seed, nsamples_avail, steps_total, model="kl"):
     """Oracle on the host cores: `procs` samples of the same workload for the first few steps."""
     procs = min(16, os.cpu_count() or 1)
     nx, ny, _ = level_grid(level)
@@ -46,7 +48,7 @@ from henry_inputs import draw_theta
 from oracle import henry as H
 import multiprocessing as mp
 th = draw_theta({seed}, {min(procs, nsamples_avail)}, level={level})
-pr = H.Problem(); g = H.Grid({nx}, {ny}, {steps_total})
+pr = {"H.paper_problem()" if model == "paper" else "H.Problem()"}; g = H.Grid({nx}, {ny}, {steps_total})
 def one(t):
     return H.solve_sample(pr, g, t, nsteps={nsteps_run}).newton_its
 t0 = time.time()
@@ -148,15 +150,56 @@ def bench_adjoint(args):
     print(json.dumps(out))
 
 
+def bench_qmc(args):
+    """Quasi-Monte Carlo of the paper's own model (section 5: 600 Halton points): one batch
+    at one level, then the single-level estimator (mean and variance of Q and of c at T)."""
+    import torch
+    import paper_2403_17018_amd as P
+    from henry_inputs import qmc_theta
+    level = 3 if args.level is None else args.level
+    prec = args.precision or 64
+    S = 600
+    nx, ny, nsteps = level_grid(level)
+    theta = torch.from_numpy(qmc_theta(S)).cuda()
+    hx = P.Henry(0)
+    opts = P.solver_opts(mg_precision=prec)
+    prob = P.paper_problem()
+    for _ in range(args.warmup):
+        P.mlmc_run(hx, [theta], [level], prob=prob, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        est = P.mlmc_run(hx, [theta], [level], prob=prob, opts=opts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    out = {
+        "metric": "sample-timesteps/s", "value": S * nsteps / dt, "unit": "sample-timesteps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == 64 else "f64+f32mg", "data": "synthetic",
+        "config": {"workload": f"qmc600: the paper's section-4 model, 600 Halton points (bases 2, 3, 5), level {level} "
+                               f"({nx}x{ny} cells, {nsteps} steps, T = 6016 s), single-level estimator",
+                   "mg_precision": prec, "parallelism": "samples batched on one GPU"},
+        "qoi_mean": est["mean"], "qoi_var": est["V"][0],
+        "c_mean_range": [float(est["mean_field"].min()), float(est["mean_field"].max())],
+        "c_var_max": float(est["var_field"].max()), "failed_samples": est["nfailed"],
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "qmc"])
+    ap.add_argument("--level", type=int, default=None, help="level of the qmc workload (default 3)")
     ap.add_argument("--graphs", type=int, default=None, help="capture BiCGStab iterations in hipGraphs (c4 default 1)")
     ap.add_argument("--precision", type=int, default=None, help="multigrid precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--model", default="kl", choices=["kl", "paper"],
+                    help="input model: KL fields (the workloads) or the paper's section-4 model")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -166,13 +209,15 @@ def main():
         return bench_mlmc(args)
     if args.workload == "c5":
         return bench_adjoint(args)
+    if args.workload == "qmc":
+        return bench_qmc(args)
     name = {"c1": "c1_fp64_level0", "c2": "c2_fp64_level3", "c3": "c3_mixed_level4"}[args.workload]
     w = WORKLOADS[name]
     prec = args.precision or w["mg_precision"]
     level, S, seed = w["level"], w["nsamples"], w["seed"]
     nx, ny, nsteps = level_grid(level)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(level, seed, S, nsteps)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(level, seed, S, nsteps, args.model)
 
     import torch
     import paper_2403_17018_amd as P
@@ -181,9 +226,10 @@ def main():
     hx = P.Henry(0)
     g = P.grid(nx, ny, nsteps)
     opts = P.solver_opts(mg_precision=prec)
+    prob = P.paper_problem() if args.model == "paper" else P.problem()
 
     def step():
-        r = hx.solve(theta, g, opts=opts, want_c=True)
+        r = hx.solve(theta, g, prob, opts=opts, want_c=True)
         est = hx.mlmc_estimate([g], [r.qoi], [None], [r.c_T], [None])
         return r, est
 
@@ -221,7 +267,9 @@ def main():
         "dtype": "f64" if prec == 64 else "f64+f32mg",
         "data": "synthetic",
         "config": {"workload": f"{name}: MLMC level {level}, {nx}x{ny} cells, {nsteps} implicit-Euler steps, "
-                               f"{S} samples (seed {seed}), {'FP64' if prec == 64 else 'FP32'} multigrid",
+                               f"{S} samples (seed {seed}), {'FP64' if prec == 64 else 'FP32'} multigrid"
+                               + (", the paper's section-4 porosity/Kozeny-Carman/recharge model, T = 6016 s"
+                                  if args.model == "paper" else ""),
                    "samples": S, "cells": nx * ny, "time_steps": nsteps, "mg_precision": prec,
                    "parallelism": "samples batched on one GPU"},
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAME[cls], "achieved": achieved, "peak": HBM_PEAK_GBS,

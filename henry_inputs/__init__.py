@@ -15,6 +15,9 @@ theta layout per sample (13 values, row-major ``theta[s, k]``):
   k = 0..3   xi_k   ~ U[-1, 1]   porosity KL coefficients
   k = 4..11  eta_k  ~ N(0, 1)    log-permeability KL coefficients
   k = 12     zeta   ~ U[-1, 1]   recharge factor
+The paper's own model (section 4) reads xi_1 = theta[0], xi_2 = theta[1] and
+xi_3 = theta[12] of the same layout; qmc_theta() fills those from the Halton
+sequence for its quasi-Monte Carlo runs (section 5, 600 points).
 """
 from __future__ import annotations
 
@@ -81,6 +84,36 @@ def draw_theta(seed: int, nsamples: int, level: int = 0, first_sample: int = 0) 
     normal = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
     th[:, IDX_ETA] = normal[:, IDX_ETA]
     return np.ascontiguousarray(th)
+
+
+def halton(n: int, bases=(2, 3, 5), start: int = 1) -> np.ndarray:
+    """Points start..start+n-1 of the Halton sequence, [n, len(bases)] in [0, 1).
+
+    Coordinate d of point i is the radical inverse of i in base bases[d]: the base-b
+    digits of i mirrored about the radix point.  Unscrambled; start = 1 skips the origin.
+    """
+    idx = np.arange(start, start + n, dtype=np.int64)
+    out = np.zeros((n, len(bases)))
+    for d, b in enumerate(bases):
+        i = idx.copy()
+        f = 1.0 / b
+        while (i > 0).any():
+            out[:, d] += f * (i % b)
+            i //= b
+            f /= b
+    return out
+
+
+def qmc_theta(n: int, start: int = 1) -> np.ndarray:
+    """theta[n, 13] for the paper's own model (section 4) from the Halton sequence in bases
+    2, 3, 5: xi_1 = theta[0], xi_2 = theta[1], xi_3 = theta[12], each 2u - 1 in [-1, 1);
+    the other components are 0 (unused by that model)."""
+    u = halton(n, (2, 3, 5), start)
+    th = np.zeros((n, N_THETA))
+    th[:, 0] = 2.0 * u[:, 0] - 1.0
+    th[:, 1] = 2.0 * u[:, 1] - 1.0
+    th[:, IDX_ZETA] = 2.0 * u[:, 2] - 1.0
+    return th
 
 
 def level_grid(level: int):

@@ -125,3 +125,22 @@ def test_adjoint_of_paper_model_is_unsupported(hx):
     with pytest.raises(P.HenryError) as e:
         hx.adjoint(_cuda(draw_theta(5, 2)), P.level_grid(0), P.paper_problem())
     assert e.value.code == -4
+
+
+def test_qmc_estimate_matches_oracle(hx):
+    """Quasi-Monte Carlo over Halton points (section 5 uses 600) for the paper's model: one
+    level of the estimator gives the mean and variance of the QoI and of the c field at T.
+    64 points at level 0 against the oracle's solves and estimator."""
+    import paper_2403_17018_amd as P
+    from henry_inputs import qmc_theta
+    from oracle import mlmc as M
+    th = qmc_theta(64)
+    est = P.mlmc_run(hx, [_cuda(th)], [0], prob=P.paper_problem())
+    assert est["nfailed"] == 0
+    ref = oracle_batch(th, 32, 16, 48, ORACLE_KW)
+    r = M.estimate([ref["qoi"]], [None])
+    assert est["mean"] == pytest.approx(r["mean"], rel=TOL)
+    assert est["V"][0] == pytest.approx(r["V"][0], rel=1e-6)
+    mf, vf = M.field_estimate([ref["c"]], [None])
+    assert np.abs(est["mean_field"].cpu().numpy() - mf).max() <= TOL
+    assert np.abs(est["var_field"].cpu().numpy() - vf).max() <= TOL
