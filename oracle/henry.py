@@ -370,6 +370,42 @@ def qoi_salt_mass(prob: Problem, grid: Grid, c):
     return float(np.sum((cc * rho(prob, cc))[m]) * hx * hy)
 
 
+# Time-resolved QoIs of section 5: Q_S (eq. integral_s), Q_FW (eq. integral_fw) and the
+# box integrals Q_1..Q_15 (eq. integral_box) around the points of eq. 12points.
+FW_THRESHOLD = 0.012178
+BOX_POINTS = [(x, y) for y in (-0.95, -0.75, -0.50) for x in (0.90, 1.15, 1.40, 1.65, 1.90)]
+BOX_HALF = 0.1
+N_SERIES = 2 + len(BOX_POINTS)
+
+
+def _interval_overlap(a0, a1, b0, b1):
+    """Length of [a0, a1] intersected with [b0, b1] (0 when disjoint)."""
+    return np.maximum(0.0, np.minimum(a1, b1) - np.maximum(a0, b0))
+
+
+def series_qois(prob: Problem, grid: Grid, c):
+    """[Q_S, Q_FW, Q_1, ..., Q_15] of one state c (flat, row-major [j, i]).
+
+    The cell-wise constant concentration is integrated exactly: Q_S = sum c rho(c) |cell|,
+    Q_FW = sum over cells with c <= 0.012178 of |cell|, Q_i = sum c rho(c) |cell n Delta_i|
+    with Delta_i = [x_i - 0.1, x_i + 0.1] x [y_i - 0.1, y_i + 0.1] (parts outside the
+    domain contribute nothing).
+    """
+    hx, hy = grid.h(prob)
+    cc = c.reshape(grid.ny, grid.nx)
+    m = cc * rho(prob, cc)
+    out = np.empty(N_SERIES)
+    out[0] = m.sum() * hx * hy
+    out[1] = np.count_nonzero(cc <= FW_THRESHOLD) * hx * hy
+    xe = np.arange(grid.nx + 1) * hx                 # cell edges
+    ye = -prob.Ly + np.arange(grid.ny + 1) * hy
+    for b, (bx, by) in enumerate(BOX_POINTS):
+        wx = _interval_overlap(xe[:-1], xe[1:], bx - BOX_HALF, bx + BOX_HALF)   # [nx]
+        wy = _interval_overlap(ye[:-1], ye[1:], by - BOX_HALF, by + BOX_HALF)   # [ny]
+        out[2 + b] = float(wy @ m @ wx)
+    return out
+
+
 @dataclasses.dataclass
 class SampleResult:
     p: np.ndarray
@@ -382,10 +418,11 @@ class SampleResult:
     c_min: float
     c_max: float
     states: list | None = None
+    series: np.ndarray | None = None    # [nsteps, N_SERIES] after every step (series=True)
 
 
 def solve_sample(prob: Problem, grid: Grid, theta, opts: SolveOptions | None = None,
-                 keep_states=False, nsteps=None) -> SampleResult:
+                 keep_states=False, nsteps=None, series=False) -> SampleResult:
     """Full time loop for one sample (plain Newton + sparse direct LU)."""
     opts = opts or SolveOptions()
     phi, K, u_in = sample_fields(prob, grid, theta)
@@ -397,6 +434,7 @@ def solve_sample(prob: Problem, grid: Grid, theta, opts: SolveOptions | None = N
     dmax_f = dmax_s = 0.0
     cmin, cmax = 0.0, 0.0
     states = [(p.copy(), c.copy())] if keep_states else None
+    ser = [] if series else None
     for n in range(nsteps if nsteps is not None else grid.nsteps):
         c_old = c.copy()
         disc.set_time((n + 1) * disc.tau)    # implicit Euler: boundary data at the new time
@@ -413,20 +451,24 @@ def solve_sample(prob: Problem, grid: Grid, theta, opts: SolveOptions | None = N
         cmin, cmax = min(cmin, c.min()), max(cmax, c.max())
         if keep_states:
             states.append((p.copy(), c.copy()))
-    return SampleResult(p, c, qoi_salt_mass(prob, grid, c), its, ok, dmax_f, dmax_s, cmin, cmax, states)
+        if series:
+            ser.append(series_qois(prob, grid, c))
+    return SampleResult(p, c, qoi_salt_mass(prob, grid, c), its, ok, dmax_f, dmax_s, cmin, cmax, states,
+                        np.array(ser) if series else None)
 
 
 def _solve_one(args):
-    prob, grid, th, opts = args
-    r = solve_sample(prob, grid, th, opts)
+    prob, grid, th, opts, series = args
+    r = solve_sample(prob, grid, th, opts, series=series)
     r.states = None
     return r
 
 
-def solve_batch(prob: Problem, grid: Grid, theta, opts: SolveOptions | None = None, processes: int = 1):
+def solve_batch(prob: Problem, grid: Grid, theta, opts: SolveOptions | None = None, processes: int = 1,
+                series: bool = False):
     """Solve every sample of theta[S, 13]; optional process pool (samples are independent)."""
     theta = np.asarray(theta)
-    jobs = [(prob, grid, theta[s], opts) for s in range(theta.shape[0])]
+    jobs = [(prob, grid, theta[s], opts, series) for s in range(theta.shape[0])]
     if processes <= 1:
         return [_solve_one(j) for j in jobs]
     import multiprocessing as mp

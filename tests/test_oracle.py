@@ -310,6 +310,52 @@ def test_paper_model_balance_and_bounds_level0():
         assert 0 < r.qoi < 1025.0
 
 
+# ------------------------------------------------ time-resolved QoIs (section 5)
+def test_series_qois_hand_values():
+    """Q_S, Q_FW, Q_1..Q_15 (eqs. integral_s, integral_fw, integral_box) of simple fields, by
+    hand: the boxes around y = -0.95 stick out below the domain (area 0.2 x 0.15), the others
+    lie inside (0.2 x 0.2); x = 1 is a cell face on every level."""
+    pr = H.Problem()
+    for lev in (0, 2):
+        g = H.Grid(*level_grid(lev))
+        X, _ = H.cell_centres(pr, g)
+        one = np.ones(g.nx * g.ny)
+        np.testing.assert_allclose(H.series_qois(pr, g, one),
+                                   [2050.0, 0.0] + [1025 * 0.03] * 5 + [1025 * 0.04] * 10, rtol=1e-13)
+        np.testing.assert_allclose(H.series_qois(pr, g, 0.5 * one)[:2], [0.5 * 1012.5 * 2.0, 0.0], rtol=1e-13)
+        np.testing.assert_allclose(H.series_qois(pr, g, 0.0 * one), [0.0, 2.0] + [0.0] * 15, atol=1e-13)
+        right = (X > 1.0).astype(float).ravel()       # salt water right of x = 1
+        want = [1025.0, 1.0] + sum(([0.0] + [1025 * a] * 4 for a in (0.03, 0.04, 0.04)), [])
+        np.testing.assert_allclose(H.series_qois(pr, g, right), want, rtol=1e-13, atol=1e-12)
+
+
+def test_series_qois_of_piecewise_constant_field_do_not_depend_on_the_grid():
+    """The exact integral of a field constant on level-0 cells is the same when the field is
+    represented on a finer grid (each coarse cell injected into its children): box overlaps
+    that are partial on level 0 become whole fine cells."""
+    pr = H.Problem()
+    rng = np.random.default_rng(5)
+    c0 = rng.random((16, 32))
+    g0, g2 = H.Grid(*level_grid(0)), H.Grid(*level_grid(2))
+    c2 = np.kron(c0, np.ones((4, 4)))
+    np.testing.assert_allclose(H.series_qois(pr, g0, c0.ravel()), H.series_qois(pr, g2, c2.ravel()), rtol=1e-12)
+
+
+def test_series_follow_the_solve():
+    """The per-step series of a level-0 solve: the last step's salt mass over the whole domain
+    bounds the salt mass in x > 1 (the QoI), all box masses are non-negative and bounded by
+    the whole-domain mass, and the fresh-water area shrinks as the wedge enters."""
+    pr = H.Problem()
+    g = H.Grid(*level_grid(0))
+    r = H.solve_sample(pr, g, draw_theta(0, 1)[0], series=True)
+    s = r.series
+    assert s.shape == (48, H.N_SERIES)
+    assert s[-1, 0] >= r.qoi > 0
+    assert (s[:, 2:] >= -1e-12).all() and (s[:, 2:].sum(axis=1) <= s[:, 0] + 1e-9).all()
+    assert s[-1, 1] < s[0, 1] <= 2.0
+    np.testing.assert_allclose(s[-1], H.series_qois(pr, g, r.c), rtol=0, atol=0)
+
+
 # ---------------------------------------------------------------- MLMC
 def test_mlmc_single_level_is_sample_mean_and_variance():
     rng = np.random.default_rng(3)
