@@ -137,7 +137,17 @@ typedef struct {
   int* status;           /* device [S] henry_sample_status, or NULL */
   double* stats;         /* device [S][4]: Newton iterations, BiCGStab iterations (summed over the
                             run), max relative fluid and salt mass-balance defect; or NULL */
+  double* series;        /* device [nsteps][HENRY_NSERIES][S] or NULL: after every step the
+                            time-resolved QoIs of section 5, integrating the cell-wise constant c
+                            exactly: [0] Q_S = sum c rho(c) |cell| (eq. integral_s, kg/m);
+                            [1] Q_FW = area with c <= 0.012178 (eq. integral_fw, m^2);
+                            [2 + b] salt mass sum c rho(c) |cell n Delta_b| in the square Delta_b
+                            of half-width 0.1 around point b of eq. 12points (eq. integral_box):
+                            x = 0.90, 1.15, 1.40, 1.65, 1.90 for b % 5, y = -0.95, -0.75, -0.50
+                            for b / 5 */
 } henry_batch;
+
+#define HENRY_NSERIES 17
 
 HENRY_API void henry_problem_default(henry_problem* p);
 HENRY_API void henry_solver_opts_default(henry_solver_opts* o);

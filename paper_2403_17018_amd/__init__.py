@@ -16,8 +16,8 @@ import torch
 from . import _lib as L
 from ._lib import henry_batch, henry_grid, henry_problem, henry_solver_opts
 
-__all__ = ["Henry", "HenryError", "problem", "solver_opts", "grid", "level_grid", "optimal_samples", "SolveResult",
-           "mlmc_run"]
+__all__ = ["Henry", "HenryError", "problem", "paper_problem", "solver_opts", "grid", "level_grid", "optimal_samples",
+           "SolveResult", "mlmc_run"]
 
 STATUS = {0: "ok", 1: "newton", 2: "krylov", 3: "nonfinite", 4: "range"}
 
@@ -75,6 +75,7 @@ class SolveResult:
     status: torch.Tensor          # [S] int32
     stats: torch.Tensor           # [S, 4]
     nfailed: int
+    series: torch.Tensor | None = None   # [nsteps, 17, S]: Q_S, Q_FW, Q_1..Q_15 after every step
 
 
 def _ptr(t):
@@ -131,7 +132,7 @@ class Henry:
         return phi, K, q
 
     def solve_ragged(self, items, prob: henry_problem | None = None, opts: henry_solver_opts | None = None,
-                     want_c: bool = True, want_p: bool = False):
+                     want_c: bool = True, want_p: bool = False, want_series: bool = False):
         """items: list of (theta [S,13], henry_grid).  One call; returns a list of SolveResult."""
         prob = prob or problem()
         opts = opts or solver_opts()
@@ -146,9 +147,10 @@ class Henry:
                 p_T=torch.empty((g.ny, g.nx, S), **kw) if want_p else None,
                 qoi=torch.empty((S,), **kw),
                 status=torch.empty((S,), dtype=torch.int32, device=self.device),
-                stats=torch.empty((S, 4), **kw), nfailed=0)
+                stats=torch.empty((S, 4), **kw), nfailed=0,
+                series=torch.empty((g.nsteps, L.NSERIES, S), **kw) if want_series else None)
             arr[b] = henry_batch(g, S, theta.data_ptr(), _ptr(r.c_T), _ptr(r.p_T), _ptr(r.qoi), _ptr(r.status),
-                                 _ptr(r.stats))
+                                 _ptr(r.stats), _ptr(r.series))
             res.append(r)
         rc = self._check(self._lib.henry_solve_batch(self._h, C.byref(prob), C.byref(opts), arr, len(items)))
         for r in res:
@@ -156,8 +158,9 @@ class Henry:
         assert sum(r.nfailed for r in res) == rc
         return res
 
-    def solve(self, theta, g: henry_grid, prob=None, opts=None, want_c=True, want_p=False) -> SolveResult:
-        return self.solve_ragged([(theta, g)], prob, opts, want_c, want_p)[0]
+    def solve(self, theta, g: henry_grid, prob=None, opts=None, want_c=True, want_p=False,
+              want_series=False) -> SolveResult:
+        return self.solve_ragged([(theta, g)], prob, opts, want_c, want_p, want_series)[0]
 
     def adjoint(self, theta, g: henry_grid, prob=None, opts=None, checkpoint_every: int = 32):
         """(qoi [S], dqoi/dtheta [S,13], status [S], nfailed)."""

@@ -38,7 +38,10 @@ class henry_solver_opts(C.Structure):
 
 class henry_batch(C.Structure):
     _fields_ = [("grid", henry_grid), ("nsamples", C.c_int), ("theta", C.c_void_p), ("c_T", C.c_void_p),
-                ("p_T", C.c_void_p), ("qoi", C.c_void_p), ("status", C.c_void_p), ("stats", C.c_void_p)]
+                ("p_T", C.c_void_p), ("qoi", C.c_void_p), ("status", C.c_void_p), ("stats", C.c_void_p),
+                ("series", C.c_void_p)]
+
+NSERIES = 17   # HENRY_NSERIES: Q_S, Q_FW, Q_1..Q_15
 
 
 _lib = None

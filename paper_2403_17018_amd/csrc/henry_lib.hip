@@ -447,7 +447,7 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
   P->nhist.alloc((size_t)S * 2 * 8);
   P->status.alloc(S * 4);
   P->stats.alloc((size_t)S * 4 * 8);
-  P->part.alloc((size_t)12 * P->m.ncb * S * 8);
+  P->part.alloc((size_t)NSERIES * P->m.ncb * S * 8);   // widest reduction: the series
   P->ctrl.alloc(64);
   HIPCHK(hipHostMalloc((void**)&P->h_ctrl, 16 * sizeof(int), hipHostMallocDefault));
   P->cidx.alloc((size_t)S * sizeof(int));
@@ -470,7 +470,7 @@ static void plan_set_samples(Plan& Q, int Sa, int red_blocks) {
   Q.S = Sa;
   Q.N = (size_t)Q.nx * Q.ny * Sa;
   Q.m = make_map(Sa, Q.nx * Q.ny, red_blocks);
-  Q.part.alloc((size_t)12 * Q.m.ncb * Sa * 8);
+  Q.part.alloc((size_t)NSERIES * Q.m.ncb * Sa * 8);
   Q.drop_graphs();
 }
 
@@ -920,8 +920,16 @@ struct Solver {
     const char* pe = std::getenv("HENRY_PROGRESS");
     progress_every = pe ? std::max(1, std::atoi(pe)) : 0;
     init(B.theta);
-    for (int n = 0; n < B.grid.nsteps; ++n) time_step<T>(n, B.grid.nsteps);
     const int S = P.S;
+    for (int n = 0; n < B.grid.nsteps; ++n) {
+      time_step<T>(n, B.grid.nsteps);
+      if (B.series) {
+        hipLaunchKernelGGL(k_series, grid_red(P.m), block_of(P.m), 0, st, P.m, P.G, phys, P.c.as<double>(),
+                           P.part.as<double>());
+        hipLaunchKernelGGL(k_fin_series, fin_grid(S), dim3(64, FIN_Y), 0, st, P.m, P.part.as<double>(),
+                           B.series + (size_t)n * NSERIES * S);
+      }
+    }
     if (B.qoi) qoi(B.qoi);
     if (B.c_T) HIPCHK(hipMemcpyAsync(B.c_T, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
     if (B.p_T) HIPCHK(hipMemcpyAsync(B.p_T, P.p.p, P.N * 8, hipMemcpyDeviceToDevice, st));
@@ -1090,7 +1098,7 @@ struct Group {
   henry_grid grid{};
   int S = 0;
   std::vector<int> members, offs;
-  DevBuf theta, c, p, qoi, status, stats;   // merged groups only
+  DevBuf theta, c, p, qoi, status, stats, series;   // merged groups only
   hipStream_t stream = nullptr;
   int failed = 0;
   bool ok = true;
@@ -1160,6 +1168,10 @@ static int solve_ragged(henry_ctx* ctx, const henry_problem& pr, const henry_sol
     G.qoi.alloc(G.S * 8);
     G.status.alloc(G.S * 4);
     G.stats.alloc((size_t)G.S * 4 * 8);
+    bool want_series = false;
+    for (int b : G.members) want_series = want_series || batches[b].series;
+    if (want_series) G.series.alloc((size_t)G.grid.nsteps * NSERIES * G.S * 8);
+    B.series = want_series ? G.series.as<double>() : nullptr;
     B.theta = G.theta.as<double>();
     B.c_T = G.c.as<double>();
     B.p_T = G.p.as<double>();
@@ -1209,6 +1221,9 @@ static int solve_ragged(henry_ctx* ctx, const henry_problem& pr, const henry_sol
           HIPCHK(hipMemcpyAsync(M.status, G.status.as<int>() + off, Sb * 4, hipMemcpyDeviceToDevice, G.stream));
         if (M.stats)
           HIPCHK(hipMemcpyAsync(M.stats, G.stats.as<double>() + off * 4, Sb * 4 * 8, hipMemcpyDeviceToDevice, G.stream));
+        if (M.series)
+          HIPCHK(hipMemcpy2DAsync(M.series, Sb * 8, G.series.as<double>() + off, S * 8, Sb * 8,
+                                  (size_t)G.grid.nsteps * NSERIES, hipMemcpyDeviceToDevice, G.stream));
       }
     }
     hipEvent_t done = nullptr;

@@ -1,7 +1,10 @@
-// Small control kernels and the MLMC estimator kernels (paper section 3).
+// Small control kernels, the time-resolved QoIs (section 5) and the MLMC estimator kernels
+// (section 3).
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "henry_kernels.hpp"
 
 namespace henry {
 
@@ -92,6 +95,66 @@ __global__ void k_scatter_sample_info(int Sa, const int* __restrict__ idx, const
   for (int q = 0; q < 4; ++q) stats[(size_t)s * 4 + q] = cstats[(size_t)a * 4 + q];
   nhist[2 * s] = cnhist[2 * a];
   nhist[2 * s + 1] = cnhist[2 * a + 1];
+}
+
+// Time-resolved QoIs of the current state (section 5), per-sample partial sums
+// [NSERIES][ncb][S]: 0: Q_S = sum c rho(c) |cell| (eq. integral_s); 1: Q_FW = area of the
+// cells with c <= 0.012178 (eq. integral_fw); 2 + b: sum c rho(c) |cell n Delta_b| with
+// Delta_b the square of half-width 0.1 around point b of eq. 12points (eq. integral_box).
+// The cell-wise constant field is integrated exactly over each box.
+constexpr int NSERIES = 17;
+__global__ void __launch_bounds__(256) k_series(Map m, Grid2 G, Phys P, const double* __restrict__ c,
+                                                double* __restrict__ part) {
+  __shared__ double lds[NSERIES * 256];
+  const int sblk = blockIdx.x % m.nsb, cblk = blockIdx.x / m.nsb;
+  const int s = sblk * m.SX + threadIdx.x;
+  const bool sv = s < m.S;
+  double acc[NSERIES];
+#pragma unroll
+  for (int q = 0; q < NSERIES; ++q) acc[q] = 0.0;
+  for (int kk = 0; kk < m.CPT; ++kk) {
+    const int cell = (cblk * m.CPT + kk) * m.CY + threadIdx.y;
+    if (!sv || cell >= G.ncell) continue;
+    const int j = cell / G.nx, i = cell - j * G.nx;
+    const double cP = c[(size_t)cell * m.S + s];
+    const double mass = cP * (P.rho0 + P.drho * cP);
+    acc[0] += mass * P.vol;
+    acc[1] += cP <= 0.012178 ? P.vol : 0.0;
+    const double x0 = i * P.hx, x1 = (i + 1) * P.hx;
+    const double y0 = -P.Ly + j * P.hy, y1 = -P.Ly + (j + 1) * P.hy;
+#pragma unroll
+    for (int b = 0; b < 15; ++b) {
+      const int col = b % 5, row = b / 5;
+      const double bx = col == 0 ? 0.90 : col == 1 ? 1.15 : col == 2 ? 1.40 : col == 3 ? 1.65 : 1.90;
+      const double by = row == 0 ? -0.95 : row == 1 ? -0.75 : -0.50;
+      const double ox = fmax(0.0, fmin(x1, bx + 0.1) - fmax(x0, bx - 0.1));
+      const double oy = fmax(0.0, fmin(y1, by + 0.1) - fmax(y0, by - 0.1));
+      acc[2 + b] += mass * (oy * ox);
+    }
+  }
+  block_sum_y<NSERIES>(acc, lds);
+  if (threadIdx.y == 0 && sv) {
+#pragma unroll
+    for (int q = 0; q < NSERIES; ++q) part[((size_t)q * m.ncb + cblk) * m.S + s] = acc[q];
+  }
+}
+
+// out[q][s] = sum of the partials (fixed order), q < NSERIES
+__global__ void __launch_bounds__(64 * FIN_Y) k_fin_series(Map m, const double* __restrict__ part,
+                                                           double* __restrict__ out) {
+  __shared__ double lds[4 * 64 * FIN_Y];
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  for (int q0 = 0; q0 < 16; q0 += 4) {
+    double a[4];
+    reduce_partials<4>(m, part + (size_t)q0 * m.ncb * m.S, s, a, lds);
+    if (threadIdx.y == 0 && s < m.S) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[(size_t)(q0 + q) * m.S + s] = a[q];
+    }
+  }
+  double a[1];
+  reduce_partials<1>(m, part + (size_t)16 * m.ncb * m.S, s, a, lds);
+  if (threadIdx.y == 0 && s < m.S) out[(size_t)16 * m.S + s] = a[0];
 }
 
 // Fixed-order tree sum over 256 threads.
