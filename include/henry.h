@@ -206,6 +206,34 @@ HENRY_API int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_gri
                   double* mean, double* var_of_estimator, double* rmse, double* V_l,
                   double* mean_field, double* var_field);
 
+/* MLMC estimate of time-resolved QoIs (section 3 applied at every time point, eq. A) at
+ * the common times t_k = (k + 1) T / r_0, k < r_0 = grids[0].nsteps, where level l's entry is
+ * its step (k + 1) r_l / r_0 - 1 (every r_l a multiple of r_0) and its coarse partner's the
+ * step (k + 1) r_{l-1} / r_0 - 1 of the partner's own series:
+ *   Y_l = s_fine[l] - s_coarse[l] per sample (s_coarse[0] = NULL, i.e. g_{-1} = 0);
+ *   mean = sum_l mean(Y_l), var_of_estimator = sum_l V_l / m_l, V_l unbiased.
+ *   m, grids, s_fine, s_coarse: host [L+1]; s_fine[l]: device [r_l][nq][m_l] (the layout of
+ *   henry_batch.series with nq = HENRY_NSERIES), s_coarse[l]: device [r_{l-1}][nq][m_l];
+ *   mean, var_of_estimator: device [r_0][nq] or NULL; Ymean_l, V_l: device [L+1][r_0][nq]
+ *   or NULL.  A scalar QoI is the case r_l = 1, nq = 1. */
+HENRY_API int mlmc_estimate_series(henry_ctx* ctx, int L, const int* m, const henry_grid* grids, int nq,
+                         const double* const* s_fine, const double* const* s_coarse, double* mean,
+                         double* var_of_estimator, double* Ymean_l, double* V_l);
+
+/* Adaptive MLMC plan (section 3: eqs. num_levels and scaled_m_l_S, here with refinement
+ * factor 2 per level) from pilot statistics on levels 0..Lp (Lp >= 2, host arrays):
+ * |mean Y_l| (Ymean_abs), V_l and the cost per sample s_l.  Least-squares fits in log2 give
+ * |E Y_l| = c1 2^(-alpha l) and V_l = c2 2^(-beta l) over l = 1..Lp and s_l = c3 2^(gamma l)
+ * over l = 0..Lp.  L is the smallest level in [1, max_level] whose bias estimate
+ * c1 2^(-alpha L) / (2^alpha - 1) is <= eps E0 / sqrt(2) (max_level if none), and
+ * m_l = ceil(2 eps^-2 E0^-2 sqrt(V_l/s_l) sum_i sqrt(V_i s_i)) for l <= L, with the pilot V_l
+ * and s_l up to Lp and the fitted models beyond; eps is relative to E0 = |E g_0|.
+ * m_l: host [max_level + 1]; cost: host, model cost sum m_l s_l (may be NULL);
+ * rates: host [6] = alpha, beta, gamma, c1, c2, c3 (may be NULL).
+ * Returns L, or HENRY_EINVAL (also when the fitted alpha is not positive). */
+HENRY_API int mlmc_plan(int Lp, const double* Ymean_abs, const double* V_l, const double* s_l, double eps,
+                        double E0, int max_level, long long* m_l, double* cost, double* rates);
+
 /* eq. M_ell and eq. total_cost_MLMC: m_l = ceil(2 eps^-2 sqrt(V_l/s_l) sum_i sqrt(V_i s_i)),
  * cost = sum m_l s_l.  Host arrays; returns HENRY_OK or HENRY_EINVAL. */
 HENRY_API int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, double eps,

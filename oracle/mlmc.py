@@ -85,3 +85,72 @@ def optimal_samples(V, s, eps):
     m = np.ceil(m_real).astype(np.int64)
     return dict(m=m, m_real=m_real, cost=float(np.sum(m * s)),
                 cost_opt=float(2.0 / eps ** 2 * tot ** 2))
+
+
+def estimate_series(s_fine, s_coarse, alpha: float = 1.0):
+    """Time-resolved QoIs: estimate() at every common time point and QoI.
+
+    s_fine[l]: [m_l, r_l, nq] (level l's series after each of its r_l steps); s_coarse[l]:
+    [m_l, r_{l-1}, nq] on the coarse partner's time grid, None for l = 0.  The common times
+    are t_k = (k + 1) T / r_0: entry (k + 1) r_l / r_0 - 1 of level l's series.
+    Returns dict(mean, var_of_estimator [r_0, nq], Ymean, V [L+1, r_0, nq]).
+    """
+    L = len(s_fine) - 1
+    r0, nq = np.asarray(s_fine[0]).shape[1:]
+    mean = np.zeros((r0, nq)); var = np.zeros((r0, nq))
+    Ym = np.zeros((L + 1, r0, nq)); V = np.zeros((L + 1, r0, nq))
+    for k in range(r0):
+        for q in range(nq):
+            gf, gc = [], []
+            for l in range(L + 1):
+                f = np.asarray(s_fine[l])
+                gf.append(f[:, (k + 1) * (f.shape[1] // r0) - 1, q])
+                if l == 0:
+                    gc.append(None)
+                else:
+                    c = np.asarray(s_coarse[l])
+                    gc.append(c[:, (k + 1) * (c.shape[1] // r0) - 1, q])
+            e = estimate(gf, gc, alpha)
+            mean[k, q], var[k, q] = e["mean"], e["var_of_estimator"]
+            Ym[:, k, q], V[:, k, q] = e["Ymean"], e["V"]
+    return dict(mean=mean, var_of_estimator=var, Ymean=Ym, V=V)
+
+
+def fit_rate(levels, values):
+    """values ~ c 2^(slope l): least-squares line through (l, log2 value); returns (slope, c)."""
+    x = np.asarray(levels, dtype=np.float64)
+    y = np.log2(np.asarray(values, dtype=np.float64))
+    slope, icpt = np.polyfit(x, y, 1)
+    return float(slope), float(2.0 ** icpt)
+
+
+def plan(Ymean_abs, V, s, eps, E0, max_level):
+    """Adaptive MLMC plan from pilot statistics on levels 0..Lp (section 3, eqs. num_levels
+    and scaled_m_l_S; this hierarchy refines by 2 per level, so powers of 2 replace the
+    paper's powers of 4).
+
+    |E Y_l| = c1 2^(-alpha l) and V_l = c2 2^(-beta l) fitted over l = 1..Lp, the cost
+    s_l = c3 2^(gamma l) over l = 0..Lp.  The bias of stopping at level L is the geometric
+    tail sum_{l > L} |E Y_l| = c1 2^(-alpha L) / (2^alpha - 1); L is the smallest level in
+    [1, max_level] where it is at most eps E0 / sqrt(2) (half the mean-square error budget),
+    else max_level.  m_l = ceil(2 eps^-2 E0^-2 sqrt(V_l/s_l) sum_i sqrt(V_i s_i)) (eq.
+    scaled_m_l_S), with the pilot's V_l and s_l for l <= Lp and the fitted laws beyond.
+    """
+    Lp = len(V) - 1
+    sa, c1 = fit_rate(range(1, Lp + 1), Ymean_abs[1:])
+    sb, c2 = fit_rate(range(1, Lp + 1), V[1:])
+    gamma, c3 = fit_rate(range(0, Lp + 1), s)
+    alpha, beta = -sa, -sb
+    if not alpha > 0:
+        raise ValueError("no weak convergence in the pilot")
+    L = max_level
+    for l in range(1, max_level + 1):
+        if c1 * 2.0 ** (-alpha * l) / (2.0 ** alpha - 1.0) <= eps * E0 / math.sqrt(2.0):
+            L = l
+            break
+    Vx = [V[l] if l <= Lp else c2 * 2.0 ** (-beta * l) for l in range(L + 1)]
+    sx = [s[l] if l <= Lp else c3 * 2.0 ** (gamma * l) for l in range(L + 1)]
+    tot = sum(math.sqrt(v * c) for v, c in zip(Vx, sx))
+    m = [int(math.ceil(2.0 / (eps * E0) ** 2 * math.sqrt(v / c) * tot)) for v, c in zip(Vx, sx)]
+    return dict(L=L, m=m, cost=float(sum(mi * c for mi, c in zip(m, sx))), alpha=alpha, beta=beta, gamma=gamma,
+                c1=c1, c2=c2, c3=c3)

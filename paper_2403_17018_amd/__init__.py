@@ -17,7 +17,7 @@ from . import _lib as L
 from ._lib import henry_batch, henry_grid, henry_problem, henry_solver_opts
 
 __all__ = ["Henry", "HenryError", "problem", "paper_problem", "solver_opts", "grid", "level_grid", "optimal_samples",
-           "SolveResult", "mlmc_run"]
+           "SolveResult", "mlmc_run", "mlmc_plan", "mlmc_adaptive"]
 
 STATUS = {0: "ok", 1: "newton", 2: "krylov", 3: "nonfinite", 4: "range"}
 
@@ -204,6 +204,29 @@ class Henry:
                     var_field=var_f)
 
 
+    def mlmc_estimate_series(self, grids, s_fine, s_coarse):
+        """Time-resolved MLMC (device reductions): s_fine[l] [r_l, nq, m_l], s_coarse[l]
+        [r_{l-1}, nq, m_l] (None for l = 0), every r_l a multiple of r_0.  Returns dict of
+        device tensors mean, var_of_estimator [r_0, nq] and Ymean, V [L+1, r_0, nq] at the
+        common times (k + 1) T / r_0."""
+        Lv = len(s_fine) - 1
+        r0, nq = int(s_fine[0].shape[0]), int(s_fine[0].shape[1])
+        for l, t in enumerate(s_fine):
+            if not (t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and t.dim() == 3):
+                raise TypeError("series must be contiguous float64 CUDA tensors [r, nq, m]")
+            if l > 0 and (s_coarse[l] is None or s_coarse[l].shape[1:] != (nq, t.shape[2])):
+                raise ValueError(f"level {l}: coarse series shape")
+        m = (C.c_int * (Lv + 1))(*[int(t.shape[2]) for t in s_fine])
+        ga = (henry_grid * (Lv + 1))(*grids)
+        f = (C.c_void_p * (Lv + 1))(*[t.data_ptr() for t in s_fine])
+        c = (C.c_void_p * (Lv + 1))(*[None if t is None else t.data_ptr() for t in s_coarse])
+        kw = dict(dtype=torch.float64, device=self.device)
+        out = dict(mean=torch.empty((r0, nq), **kw), var_of_estimator=torch.empty((r0, nq), **kw),
+                   Ymean=torch.empty((Lv + 1, r0, nq), **kw), V=torch.empty((Lv + 1, r0, nq), **kw))
+        self._check(self._lib.mlmc_estimate_series(self._h, Lv, m, ga, nq, f, c, _ptr(out["mean"]),
+                                                   _ptr(out["var_of_estimator"]), _ptr(out["Ymean"]), _ptr(out["V"])))
+        return out
+
     def autotune(self, theta, g: henry_grid, prob=None, opts=None):
         """Fastest solver options for this batch shape (times one Newton iteration per candidate)."""
         _check_theta(theta, self.device)
@@ -256,6 +279,67 @@ def mlmc_run(hx: "Henry", thetas, levels, prob=None, opts=None, alpha: float = 1
     est = hx.mlmc_estimate(grids, gf, gc, cf, cc, alpha)
     est["results"] = res
     est["nfailed"] = sum(r.nfailed for r in res)
+    return est
+
+
+def mlmc_plan(Ymean_abs, V, s, eps, E0, max_level):
+    """Adaptive MLMC plan from pilot statistics on levels 0..Lp (mlmc_plan in the C ABI):
+    returns dict(L, m [L+1], cost, alpha, beta, gamma, c1, c2, c3)."""
+    n = len(V)
+    m = (C.c_longlong * (max_level + 1))()
+    cost = C.c_double()
+    rates = (C.c_double * 6)()
+    D = C.c_double * n
+    L_ = L.load().mlmc_plan(n - 1, D(*Ymean_abs), D(*V), D(*s), eps, E0, max_level, m, C.byref(cost), rates)
+    if L_ < 0:
+        raise HenryError(L_, "invalid pilot statistics for mlmc_plan")
+    return dict(L=L_, m=list(m)[:L_ + 1], cost=cost.value, alpha=rates[0], beta=rates[1], gamma=rates[2],
+                c1=rates[3], c2=rates[4], c3=rates[5])
+
+
+def mlmc_adaptive(hx: "Henry", sampler, eps: float, prob=None, opts=None, pilot_levels: int = 3,
+                  pilot_samples: int = 32, max_level: int = 5, alpha_bias: float | None = None):
+    """Adaptive MLMC (section 3): pilot runs, fitted rates, level count and sample sizes, then
+    the production run.
+
+    sampler(level, n, first) -> float64 CUDA tensor [n, 13]: samples first..first+n-1 of the
+    level's independent input stream (the coarse partner reuses them).  The pilot solves
+    levels 0..pilot_levels (each with its coarse partner) one level at a time, so the wall
+    time per sample gives s_l; the per-level mean and variance of Y_l of the QoI (salt mass
+    in x > 1 at T) come from the device estimator.  mlmc_plan picks L and m_l for relative
+    accuracy eps (E0 = |mean g_0| of the pilot); the production run draws fresh samples
+    (first = pilot_samples) for levels 0..L in one ragged call.  The estimate's bias term uses
+    the fitted alpha unless alpha_bias is given.
+    """
+    import time
+    Ym, V, s = [], [], []
+    for lev in range(pilot_levels + 1):
+        th = sampler(lev, pilot_samples, 0)
+        items = [(th, level_grid(lev))] + ([(th, level_grid(lev - 1))] if lev > 0 else [])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = hx.solve_ragged(items, prob, opts, want_c=False)
+        torch.cuda.synchronize()
+        s.append((time.perf_counter() - t0) / pilot_samples)
+        gf = res[0].qoi.view(1, 1, -1)
+        if lev == 0:
+            est = hx.mlmc_estimate_series([henry_grid(1, 1, 1)], [gf], [None])
+        else:
+            gc = res[1].qoi.view(1, 1, -1)
+            est = hx.mlmc_estimate_series([henry_grid(1, 1, 1)] * 2, [gf, gf], [None, gc])
+        Ym.append(abs(float(est["Ymean"][-1, 0, 0])))
+        V.append(float(est["V"][-1, 0, 0]))
+    E0 = Ym[0]
+    plan = mlmc_plan(Ym, V, s, eps, E0, max_level)
+    Lp = plan["L"]
+    thetas = [sampler(l, plan["m"][l], pilot_samples) for l in range(Lp + 1)]
+    t0 = time.perf_counter()
+    est = mlmc_run(hx, thetas, list(range(Lp + 1)), prob, opts,
+                   alpha=plan["alpha"] if alpha_bias is None else alpha_bias, fields=False)
+    torch.cuda.synchronize()
+    est["wall_s"] = time.perf_counter() - t0
+    est["plan"] = plan
+    est["pilot"] = dict(Ymean_abs=Ym, V=V, s=s, E0=E0)
     return est
 
 

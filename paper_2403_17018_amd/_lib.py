@@ -10,7 +10,8 @@ LIB_PATH = os.path.join(HERE, "libhenry.so")
 HENRY_OK, HENRY_EINVAL, HENRY_EDEVICE, HENRY_ENOMEM, HENRY_EUNSUPPORTED = 0, -1, -2, -3, -4
 EXPORTS = ("henry_problem_default", "henry_solver_opts_default", "henry_ctx_create", "henry_ctx_destroy",
            "henry_last_error", "henry_sample_fields", "henry_solve_batch", "henry_adjoint_batch",
-           "mlmc_estimate", "mlmc_optimal_samples", "henry_autotune", "henry_profile", "henry_profile_read")
+           "mlmc_estimate", "mlmc_optimal_samples", "henry_autotune", "henry_profile", "henry_profile_read",
+           "mlmc_estimate_series", "mlmc_plan")
 PROF_CLASSES = ("assemble", "gs", "spmv", "restrict", "prolong", "band_factor", "band_solve")
 
 
@@ -84,5 +85,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.henry_profile.restype = i
     lib.henry_profile_read.argtypes = [vp, i, P(C.c_longlong), P(C.c_longlong), P(d)]
     lib.henry_profile_read.restype = i
+    lib.mlmc_estimate_series.argtypes = [vp, i, P(i), P(henry_grid), i, P(vp), P(vp), vp, vp, vp, vp]
+    lib.mlmc_estimate_series.restype = i
+    lib.mlmc_plan.argtypes = [i, P(d), P(d), P(d), d, d, i, P(C.c_longlong), P(d), P(d)]
+    lib.mlmc_plan.restype = i
     _lib = lib
     return lib

@@ -1474,6 +1474,111 @@ int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_grid* grids, 
   });
 }
 
+int mlmc_estimate_series(henry_ctx* ctx, int L, const int* m, const henry_grid* grids, int nq,
+                         const double* const* s_fine, const double* const* s_coarse, double* mean,
+                         double* var_of_estimator, double* Ymean_l, double* V_l) {
+  return guarded(ctx, [&]() -> int {
+    if (L < 0 || !m || !grids || !s_fine || nq < 1) fail(HENRY_EINVAL, "L, m, grids, s_fine or nq invalid");
+    if (L + 1 > SeriesLevels::MAXL) fail(HENRY_EUNSUPPORTED, "at most %d levels", SeriesLevels::MAXL);
+    SeriesLevels sl{};
+    sl.L = L;
+    sl.nq = nq;
+    sl.r0 = grids[0].nsteps;
+    if (sl.r0 < 1) fail(HENRY_EINVAL, "grids[0].nsteps must be >= 1");
+    for (int l = 0; l <= L; ++l) {
+      if (m[l] < 1 || !s_fine[l]) fail(HENRY_EINVAL, "level %d: m < 1 or s_fine NULL", l);
+      if (grids[l].nsteps % sl.r0) fail(HENRY_EINVAL, "level %d: nsteps is not a multiple of level 0's", l);
+      sl.m[l] = m[l];
+      sl.f[l] = s_fine[l];
+      sl.df[l] = grids[l].nsteps / sl.r0;
+      if (l > 0) {
+        if (!s_coarse || !s_coarse[l]) fail(HENRY_EINVAL, "level %d: s_coarse NULL", l);
+        sl.c[l] = s_coarse[l];
+        sl.dc[l] = grids[l - 1].nsteps / sl.r0;
+      }
+    }
+    hipStream_t st = ctx->stream;
+    const size_t n = (size_t)sl.r0 * nq;
+    DevBuf tmp;
+    double* ym = Ymean_l;
+    double* vv = V_l;
+    if (!ym || !vv) tmp.alloc(2 * (L + 1) * n * sizeof(double));
+    if (!ym) ym = tmp.as<double>();
+    if (!vv) vv = tmp.as<double>() + (L + 1) * n;
+    hipLaunchKernelGGL(k_series_moments, dim3((unsigned)n, (unsigned)(L + 1)), dim3(256), 0, st, sl, ym, vv);
+    hipLaunchKernelGGL(k_series_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sl, ym, vv, mean,
+                       var_of_estimator);
+    HIPCHK(hipGetLastError());
+    if (tmp.p) HIPCHK(hipStreamSynchronize(st));   // tmp is freed on return
+    return HENRY_OK;
+  });
+}
+
+// least-squares fit of log2(v_l) = a + b l over the given levels; returns (b, 2^a)
+static std::pair<double, double> fit_log2(const std::vector<int>& lv, const std::vector<double>& v) {
+  const int n = (int)lv.size();
+  double xm = 0.0, ym = 0.0;
+  for (int i = 0; i < n; ++i) {
+    xm += lv[i];
+    ym += std::log2(v[i]);
+  }
+  xm /= n;
+  ym /= n;
+  double sxy = 0.0, sxx = 0.0;
+  for (int i = 0; i < n; ++i) {
+    sxy += (lv[i] - xm) * (std::log2(v[i]) - ym);
+    sxx += (lv[i] - xm) * (lv[i] - xm);
+  }
+  const double b = sxy / sxx;
+  return {b, std::exp2(ym - b * xm)};
+}
+
+int mlmc_plan(int Lp, const double* Ymean_abs, const double* V_l, const double* s_l, double eps, double E0,
+              int max_level, long long* m_l, double* cost, double* rates) {
+  if (Lp < 2 || !Ymean_abs || !V_l || !s_l || !m_l || !(eps > 0) || !(E0 > 0) || max_level < 1) return HENRY_EINVAL;
+  for (int l = 0; l <= Lp; ++l)
+    if (!(s_l[l] > 0) || !(V_l[l] > 0) || !(Ymean_abs[l] > 0) || !std::isfinite(Ymean_abs[l])) return HENRY_EINVAL;
+  std::vector<int> lv;
+  std::vector<double> ym, vv, ss;
+  for (int l = 1; l <= Lp; ++l) {
+    lv.push_back(l);
+    ym.push_back(Ymean_abs[l]);
+    vv.push_back(V_l[l]);
+  }
+  const auto fa = fit_log2(lv, ym), fb = fit_log2(lv, vv);
+  const double alpha = -fa.first, c1 = fa.second, beta = -fb.first, c2 = fb.second;
+  std::vector<int> lc;
+  for (int l = 0; l <= Lp; ++l) {
+    lc.push_back(l);
+    ss.push_back(s_l[l]);
+  }
+  const auto fg = fit_log2(lc, ss);
+  const double gamma = fg.first, c3 = fg.second;
+  if (!(alpha > 0)) return HENRY_EINVAL;   // no weak convergence: no level count can meet the bias
+  int L = max_level;
+  for (int l = 1; l <= max_level; ++l)
+    if (c1 * std::exp2(-alpha * l) / (std::exp2(alpha) - 1.0) <= eps * E0 / std::sqrt(2.0)) {
+      L = l;
+      break;
+    }
+  std::vector<double> V(L + 1), s(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    V[l] = l <= Lp ? V_l[l] : c2 * std::exp2(-beta * l);
+    s[l] = l <= Lp ? s_l[l] : c3 * std::exp2(gamma * l);
+  }
+  const int rc = mlmc_optimal_samples(L, V.data(), s.data(), eps * E0, m_l, cost);
+  if (rc != HENRY_OK) return rc;
+  if (rates) {
+    rates[0] = alpha;
+    rates[1] = beta;
+    rates[2] = gamma;
+    rates[3] = c1;
+    rates[4] = c2;
+    rates[5] = c3;
+  }
+  return L;
+}
+
 int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts* opts, henry_grid grid, int S,
                    const double* theta, double* best_ms) {
   return guarded(ctx, [&]() -> int {

@@ -207,6 +207,56 @@ __global__ void k_cell_moments(int ncell, int m, const double* __restrict__ f, d
   var[c] = m > 1 ? q / (m - 1) : 0.0;
 }
 
+// Time-resolved MLMC: per level l, common time k and QoI q, mean and unbiased variance over
+// the m_l samples of Y = s_f[l][(k+1) df_l - 1][q][i] - s_c[l][(k+1) dc_l - 1][q][i] (no coarse
+// term on level 0).  Block (k*nq + q, l); out: Ymean, V [L+1][r0][nq].
+struct SeriesLevels {
+  enum { MAXL = 8 };
+  int L, nq, r0;
+  int m[MAXL], df[MAXL], dc[MAXL];
+  const double* f[MAXL];
+  const double* c[MAXL];
+};
+
+__global__ void __launch_bounds__(256) k_series_moments(SeriesLevels sl, double* __restrict__ Ymean,
+                                                        double* __restrict__ V) {
+  __shared__ double lds[256];
+  const int kq = blockIdx.x, l = blockIdx.y;
+  const int k = kq / sl.nq, q = kq - k * sl.nq;
+  const int m = sl.m[l];
+  const double* gf = sl.f[l] + ((size_t)((k + 1) * sl.df[l] - 1) * sl.nq + q) * m;
+  const double* gc = l > 0 ? sl.c[l] + ((size_t)((k + 1) * sl.dc[l] - 1) * sl.nq + q) * m : nullptr;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) a += gf[i] - (gc ? gc[i] : 0.0);
+  const double mean = block_sum_256(a, lds) / m;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const double d = gf[i] - (gc ? gc[i] : 0.0) - mean;
+    v += d * d;
+  }
+  const double ss = block_sum_256(v, lds);
+  if (threadIdx.x == 0) {
+    const size_t o = ((size_t)l * sl.r0 + k) * sl.nq + q;
+    Ymean[o] = mean;
+    V[o] = m > 1 ? ss / (m - 1) : 0.0;
+  }
+}
+
+// mean[k][q] = sum_l Ymean[l][k][q], var_of_estimator[k][q] = sum_l V[l][k][q] / m_l (level order)
+__global__ void k_series_combine(SeriesLevels sl, const double* __restrict__ Ymean, const double* __restrict__ V,
+                                 double* __restrict__ mean, double* __restrict__ var) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = sl.r0 * sl.nq;
+  if (t >= n) return;
+  double mu = 0.0, va = 0.0;
+  for (int l = 0; l <= sl.L; ++l) {
+    mu += Ymean[(size_t)l * n + t];
+    va += V[(size_t)l * n + t] / sl.m[l];
+  }
+  if (mean) mean[t] = mu;
+  if (var) var[t] = va;
+}
+
 struct FieldLevels {
   enum { MAXL = 8 };
   int L;

@@ -62,3 +62,44 @@ def test_series_of_merged_batches_equal_separate_calls(hx):
     a, b = hx.solve_ragged([(th[:5].contiguous(), g), (th[5:].contiguous(), g)], want_series=True)
     whole = hx.solve(th, g, want_series=True)
     assert torch.equal(torch.cat([a.series, b.series], dim=2), whole.series)
+
+
+def test_series_estimator_matches_oracle(hx):
+    """mlmc_estimate_series on random series of three levels (r_l = 4, 8, 16 steps, 3 QoIs)."""
+    import paper_2403_17018_amd as P
+    from oracle import mlmc as M
+    rng = np.random.default_rng(1)
+    m = [33, 10, 5]
+    r = [4, 8, 16]
+    sf = [rng.normal(size=(r[l], 3, m[l])) + 2.0 for l in range(3)]
+    sc = [None] + [sf[l][::2] * 0.0 + rng.normal(size=(r[l - 1], 3, m[l])) + 2.0 for l in (1, 2)]
+    grids = [P.grid(8 << l, 4 << l, r[l]) for l in range(3)]
+    out = hx.mlmc_estimate_series(grids, [_cuda(a) for a in sf], [None] + [_cuda(a) for a in sc[1:]])
+    ref = M.estimate_series([np.moveaxis(a, -1, 0) for a in sf], [None] + [np.moveaxis(a, -1, 0) for a in sc[1:]])
+    for k in ("mean", "var_of_estimator", "Ymean", "V"):
+        np.testing.assert_allclose(out[k].cpu().numpy(), ref[k], rtol=1e-12, atol=1e-14)
+
+
+def test_adaptive_mlmc_plan_and_estimate(hx):
+    """The adaptive driver: its plan is the oracle's plan of the pilot statistics it measured,
+    and its estimate is the oracle's estimator of the production QoIs."""
+    import paper_2403_17018_amd as P
+    from oracle import mlmc as M
+
+    def sampler(level, n, first):
+        return _cuda(draw_theta(11, n, level=level, first_sample=first))
+
+    est = P.mlmc_adaptive(hx, sampler, eps=0.05, pilot_levels=2, pilot_samples=24, max_level=3)
+    assert est["nfailed"] == 0
+    pl, pp = est["plan"], est["pilot"]
+    ref = M.plan(pp["Ymean_abs"], pp["V"], pp["s"], 0.05, pp["E0"], 3)
+    assert pl["L"] == ref["L"] and pl["m"] == ref["m"]
+    res = est["results"]
+    gf, gc, k = [], [], 0
+    for l in range(pl["L"] + 1):
+        gf.append(res[k].qoi.cpu().numpy())
+        gc.append(res[k + 1].qoi.cpu().numpy() if l > 0 else None)
+        k += 2 if l > 0 else 1
+    e = M.estimate(gf, gc, alpha=pl["alpha"])
+    assert est["mean"] == pytest.approx(e["mean"], rel=1e-12)
+    assert est["rmse"] == pytest.approx(e["rmse"], rel=1e-10)

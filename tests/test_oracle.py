@@ -422,6 +422,51 @@ def test_optimal_samples_reproduce_table3_eps_scaling():
 
 
 @pytest.mark.slow
+def test_series_estimate_is_the_scalar_estimator_at_each_common_time():
+    """Level l's entry (k+1) r_l / r_0 - 1 is the common time t_k; a series whose values
+    are the same at every step reproduces the scalar estimate at every time."""
+    rng = np.random.default_rng(2)
+    m = [30, 9, 4]
+    g = [rng.normal(size=k) for k in m]
+    gc = [None] + [g[l] + rng.normal(size=m[l]) * 0.1 for l in (1, 2)]
+    ref = M.estimate(g, gc)
+    r = [3 << l for l in range(3)]
+    sf = [np.repeat(g[l][:, None, None], r[l], axis=1) * np.array([1.0, -2.0]) for l in range(3)]
+    sc = [None] + [np.repeat(gc[l][:, None, None], r[l - 1], axis=1) * np.array([1.0, -2.0]) for l in (1, 2)]
+    e = M.estimate_series(sf, sc)
+    assert e["mean"].shape == (3, 2)
+    np.testing.assert_allclose(e["mean"][:, 0], ref["mean"], rtol=1e-14)
+    np.testing.assert_allclose(e["mean"][:, 1], -2 * ref["mean"], rtol=1e-14)
+    np.testing.assert_allclose(e["var_of_estimator"][:, 1], 4 * ref["var_of_estimator"], rtol=1e-13)
+    # entries off the common times are never read
+    sf[2][:, 0::4, :] = np.nan
+    sf[2][:, 1::4, :] = np.nan
+    sf[2][:, 2::4, :] = np.nan
+    assert np.isfinite(M.estimate_series(sf, sc)["mean"]).all()
+
+
+def test_plan_recovers_exact_rates_and_levels():
+    """Pilot data that follow the power laws exactly: the fit returns the rates; the level
+    count follows the bias rule by hand; m_l is eq. M_ell at accuracy eps E0."""
+    a, b, g = 1.0, 2.0, 3.0
+    lv = np.arange(4)
+    Ym = 1.0 * 2.0 ** (-a * lv)
+    V = 0.5 * 2.0 ** (-b * lv)
+    s = 0.25 * 2.0 ** (g * lv)
+    p = M.plan(Ym, V, s, eps=0.01, E0=10.0, max_level=6)
+    assert p["alpha"] == pytest.approx(a, rel=1e-12) and p["beta"] == pytest.approx(b, rel=1e-12)
+    assert p["gamma"] == pytest.approx(g, rel=1e-12)
+    assert p["c1"] == pytest.approx(1.0, rel=1e-12) and p["c2"] == pytest.approx(0.5, rel=1e-12)
+    # bias 2^-L <= 0.01 * 10 / sqrt(2) = 0.0707: L = 4 (2^-3 = 0.125 is too large)
+    assert p["L"] == 4
+    Vx = 0.5 * 2.0 ** (-b * np.arange(5))
+    sx = 0.25 * 2.0 ** (g * np.arange(5))
+    want = M.optimal_samples(Vx, sx, 0.01 * 10.0)
+    assert p["m"] == list(want["m"])
+    # the bias target cannot be met below max_level
+    assert M.plan(Ym, V, s, eps=1e-6, E0=1.0, max_level=5)["L"] == 5
+
+
 def test_mlmc_agrees_with_plain_mc_on_tiny_levels():
     pr = H.Problem(T=7200.0)
     g0, g1 = H.Grid(8, 4, 6), H.Grid(16, 8, 12)
