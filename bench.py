@@ -29,7 +29,7 @@ from henry_inputs import WORKLOADS, draw_theta, level_grid  # noqa: E402
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # algorithmic bytes per unit of each kernel class (FP64 / FP32 multigrid), see the design doc
 BYTES = {
-    64: dict(gs=208, spmv=208, assemble=216, restrict=76, prolong=216),
+    64: dict(gs=208, spmv=136, assemble=216, restrict=76, prolong=216),
     32: dict(gs=104, spmv=208, assemble=296, restrict=38, prolong=108),
 }
 KERNEL_NAME = dict(gs="k_gs_colour", spmv="k_spmv_dot", assemble="k_assemble", restrict="k_residual_restrict",

@@ -195,7 +195,9 @@ __device__ __forceinline__ void face_flux(const Phys& P, bool north, double pL, 
   o.cup = cup;
 }
 
-// J block order: 0 centre, 1 west, 2 east, 3 south, 4 north.
+// J block order: 0 centre, 1 west, 2 east, 3 south, 4 north.  Each neighbour block is
+// stored as soon as its face is done (zeros for a missing neighbour), so only the centre
+// block and the residual stay live across the faces.
 template <bool WRITE_R, typename TJ, bool WRITE_J32, bool WRITE_J = true>
 __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const double* __restrict__ p,
                                                   const double* __restrict__ c, const double* __restrict__ c_old,
@@ -212,12 +214,16 @@ __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const 
   const double rP = P.rho0 + P.drho * cP;
   double Rp = 0.0, Rc = 0.0;
   double D[4];
-  double NB[4][4];
+  auto put = [&](int slot, double b0, double b1, double b2, double b3) {
+    if (!WRITE_J) return;
+    const double v[4] = {b0, b1, b2, b3};
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+    for (int e = 0; e < 4; ++e) J[(slot * 4 + e) * N + id] = (TJ)v[e];
+    if (WRITE_J32) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) NB[q][e] = 0.0;
-  }
+      for (int e = 0; e < 4; ++e) J32[(slot * 4 + e) * N + id] = (float)v[e];
+    }
+  };
   if (WRITE_R) {
     const double co = c_old[id];
     const double ro = P.rho0 + P.drho * co;
@@ -236,7 +242,9 @@ __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const 
     face_flux(P, false, p[q], c[q], phi[q], K[q], pP, cP, phP, KP, f);
     Rp -= f.F; Rc -= f.G;
     D[0] += f.a; D[1] -= f.bF; D[2] += f.a * f.cup; D[3] -= f.dGH;
-    NB[0][0] = -f.a; NB[0][1] = -f.bF; NB[0][2] = -f.a * f.cup; NB[0][3] = -f.dGL;
+    put(1, -f.a, -f.bF, -f.a * f.cup, -f.dGL);
+  } else {
+    put(1, 0.0, 0.0, 0.0, 0.0);
   }
   // east face: P is the low side
   if (i < G.nx - 1) {
@@ -244,7 +252,9 @@ __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const 
     face_flux(P, false, pP, cP, phP, KP, p[q], c[q], phi[q], K[q], f);
     Rp += f.F; Rc += f.G;
     D[0] += f.a; D[1] += f.bF; D[2] += f.a * f.cup; D[3] += f.dGL;
-    NB[1][0] = -f.a; NB[1][1] = f.bF; NB[1][2] = -f.a * f.cup; NB[1][3] = f.dGH;
+    put(2, -f.a, f.bF, -f.a * f.cup, f.dGH);
+  } else {
+    put(2, 0.0, 0.0, 0.0, 0.0);
   }
   // south face
   if (j > 0) {
@@ -252,7 +262,9 @@ __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const 
     face_flux(P, true, p[q], c[q], phi[q], K[q], pP, cP, phP, KP, f);
     Rp -= f.F; Rc -= f.G;
     D[0] += f.a; D[1] -= f.bF; D[2] += f.a * f.cup; D[3] -= f.dGH;
-    NB[2][0] = -f.a; NB[2][1] = -f.bF; NB[2][2] = -f.a * f.cup; NB[2][3] = -f.dGL;
+    put(3, -f.a, -f.bF, -f.a * f.cup, -f.dGL);
+  } else {
+    put(3, 0.0, 0.0, 0.0, 0.0);
   }
   // north face
   if (j < G.ny - 1) {
@@ -260,7 +272,9 @@ __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const 
     face_flux(P, true, pP, cP, phP, KP, p[q], c[q], phi[q], K[q], f);
     Rp += f.F; Rc += f.G;
     D[0] += f.a; D[1] += f.bF; D[2] += f.a * f.cup; D[3] += f.dGL;
-    NB[3][0] = -f.a; NB[3][1] = f.bF; NB[3][2] = -f.a * f.cup; NB[3][3] = f.dGH;
+    put(4, -f.a, f.bF, -f.a * f.cup, f.dGH);
+  } else {
+    put(4, 0.0, 0.0, 0.0, 0.0);
   }
   const double wb = P.hy / P.hx;
   // left boundary: prescribed inflow at c_left, diffusive Dirichlet c_left
@@ -296,24 +310,9 @@ __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const 
     R[id] = Rp;
     R[N + id] = Rc;
   }
-  if (!WRITE_J) return;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) J[e * N + id] = (TJ)D[e];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) J[((q + 1) * 4 + e) * N + id] = (TJ)NB[q][e];
-  }
-  if (WRITE_J32) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) J32[e * N + id] = (float)D[e];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) J32[((q + 1) * 4 + e) * N + id] = (float)NB[q][e];
-    }
-  }
+  put(0, D[0], D[1], D[2], D[3]);
 }
+
 
 // ==========================================================================
 // a4/a5: block stencil operations (SpMV, red-black block Gauss-Seidel, transfers)
@@ -546,10 +545,10 @@ __global__ void k_convert(size_t n, const TI* __restrict__ a, TO* __restrict__ b
 // per-sample scalar slots
 enum { SC_RHO = 0, SC_ALPHA, SC_OMEGA, SC_BETA, SC_R0, SC_RNORM, SC_ACTIVE, SC_ITS, SC_HALF, SC_NSLOT };
 
-// r = sign * R (zero for samples with ndone[s] set; ndone may be NULL), rhat = r, x = 0; partial |r|^2
+// r = sign * R (zero for samples with ndone[s] set; ndone may be NULL), rhat = r, p = r; partial |r|^2
 __global__ void __launch_bounds__(256) k_bicg_init(Map m, int ncell, const double* __restrict__ R, double sign,
                                                    const int* __restrict__ ndone, double* __restrict__ r,
-                                                   double* __restrict__ rhat, double* __restrict__ x,
+                                                   double* __restrict__ rhat, double* __restrict__ p,
                                                    double* __restrict__ part) {
   __shared__ double lds[256];
   const int sblk = blockIdx.x % m.nsb, cblk = blockIdx.x / m.nsb;
@@ -567,7 +566,7 @@ __global__ void __launch_bounds__(256) k_bicg_init(Map m, int ncell, const doubl
       const double v = R[comp * N + id] * msk;
       r[comp * N + id] = v;
       rhat[comp * N + id] = v;
-      x[comp * N + id] = 0.0;
+      p[comp * N + id] = v;     // first search direction p0 = r0
       acc[0] += v * v;
     }
   }
@@ -591,11 +590,16 @@ __global__ void __launch_bounds__(256) k_bicg_p(Map m, int ncell, int first, con
   }
 }
 
-// y = A x with per-sample partial dot products: NDOT = 1: (d0, y); NDOT = 2: (y, d0), (y, y)
+// y = A x with per-sample partial dot products: NDOT = 1: (d0, y); NDOT = 2: (y, d0), (y, y).
+// yb (or NULL): when x is the output of a V-cycle whose last pass on this grid was the black
+// Gauss-Seidel pass, that pass solved the black rows exactly, (A x)_black = b_black with b the
+// cycle's right-hand side; y takes yb there (equal up to rounding) and only red rows are
+// multiplied out.
 template <int NDOT, bool TR = false>
 __global__ void __launch_bounds__(256) k_spmv_dot(Map m, Grid2 G, const double* __restrict__ J,
                                                   const double* __restrict__ x, double* __restrict__ y,
-                                                  const double* __restrict__ d0, double* __restrict__ part) {
+                                                  const double* __restrict__ d0, double* __restrict__ part,
+                                                  const double* __restrict__ yb) {
   __shared__ double lds[2 * 256];
   const int sblk = blockIdx.x % m.nsb, cblk = blockIdx.x / m.nsb;
   const int s = sblk * m.SX + threadIdx.x;
@@ -610,7 +614,12 @@ __global__ void __launch_bounds__(256) k_spmv_dot(Map m, Grid2 G, const double* 
     const int j = cell / G.nx, i = cell - j * G.nx;
     const size_t id = (size_t)cell * m.S + s;
     double y0, y1;
-    apply_row<double, double, TR>(J, x, N, id, i, j, G.nx, G.ny, m.S, y0, y1, false);
+    if (yb && ((i + j) & 1)) {
+      y0 = yb[id];
+      y1 = yb[N + id];
+    } else {
+      apply_row<double, double, TR>(J, x, N, id, i, j, G.nx, G.ny, m.S, y0, y1, false);
+    }
     y[id] = y0;
     y[N + id] = y1;
     if (NDOT == 1) {
@@ -651,8 +660,9 @@ __global__ void __launch_bounds__(256) k_bicg_s(Map m, int ncell, const double* 
   if (threadIdx.y == 0 && ok) part[(size_t)cblk * m.S + s] = acc[0];
 }
 
-// x += alpha ph + omega sh; r = s - omega t; partials (rhat, r), (r, r)
-__global__ void __launch_bounds__(256) k_bicg_xr(Map m, int ncell, const double* __restrict__ sc,
+// x += alpha ph + omega sh (first iteration: x = alpha ph + omega sh, x0 = 0 is never
+// stored); r = s - omega t; partials (rhat, r), (r, r)
+__global__ void __launch_bounds__(256) k_bicg_xr(Map m, int ncell, int first, const double* __restrict__ sc,
                                                  const double* __restrict__ ph, const double* __restrict__ sh,
                                                  const double* __restrict__ sv_, const double* __restrict__ t,
                                                  const double* __restrict__ rhat, double* __restrict__ x,
@@ -672,7 +682,8 @@ __global__ void __launch_bounds__(256) k_bicg_xr(Map m, int ncell, const double*
     for (int comp = 0; comp < 2; ++comp) {
       const size_t q = comp * N + id;
       // omega == 0 (half-step exit or inactive): s-hat and t may be stale, do not read them
-      x[q] += om != 0.0 ? al * ph[q] + om * sh[q] : al * ph[q];
+      const double dx = om != 0.0 ? al * ph[q] + om * sh[q] : al * ph[q];
+      x[q] = first ? dx : x[q] + dx;
       const double rv = om != 0.0 ? sv_[q] - om * t[q] : sv_[q];
       r[q] = rv;
       acc[0] += rhat[q] * rv;

@@ -256,7 +256,8 @@ struct Plan {
   std::unique_ptr<Plan> compact;
   DevBuf cidx;             // indices of the samples still iterating
   // captured BiCGStab iterations: [transposed][first iteration]
-  hipGraphExec_t gexec[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
+  hipGraphExec_t gexec[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr},
+                                {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int gkey[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // per operator: nu_pre, nu_post, precision, valid
   double grtol[2] = {0.0, 0.0};
   void drop_graphs(int tr) {
@@ -679,12 +680,19 @@ struct Solver {
     int* status = P.status.as<int>();
     const dim3 rg = grid_red(m), bl = block_of(m), cg = grid_cells(m, P.G.ncell);
     const dim3 fg = fin_grid(S), fb(64, FIN_Y);
+    // FP64 cycles ending in a black pass (or the exact coarse solve) leave A M^{-1} b = b on
+    // black rows, so the SpMVs after them multiply out the red rows only
+    const bool black_exact = P.prec == 64 && o.nu_post >= 1;
+    // r = rhat = p = sign * rhs; x0 = 0 is implicit (the first x update overwrites x)
     hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, rhs, sign, mask, P.vr.as<double>(), P.vrh.as<double>(),
-                       P.vx.as<double>(), P.part.as<double>());
+                       P.vp.as<double>(), P.part.as<double>());
     zero_ctrl();
     hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl,
                        newton ? P.nhist.as<double>() : (double*)nullptr, mask, o.newton_tol * o.newton_predict);
-    if (read_ctrl(0) == 0) return -1;
+    if (read_ctrl(0) == 0) {
+      HIPCHK(hipMemsetAsync(P.vx.p, 0, 2 * P.N * sizeof(double), st));   // nothing to solve: x = 0
+      return -1;
+    }
     if (newton && P.h_ctrl[1] <= stop_at) return P.h_ctrl[1];
     const double rtol2 = rtol * rtol;
     // One BiCGStab iteration in three parts.  A: p update, M^{-1} p, v = A p-hat, alpha,
@@ -692,12 +700,14 @@ struct Solver {
     // tolerance at the half step): M^{-1} s, t = A s-hat, omega.  C: x, r updates and the
     // convergence test.  No host sync inside a part.
     auto partA = [&](int first) {
-      hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, first, sc, P.vr.as<double>(), P.vv.as<double>(),
-                         P.vp.as<double>());
+      if (!first)   // p0 = r0 was written by the initialisation
+        hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, 0, sc, P.vr.as<double>(), P.vv.as<double>(),
+                           P.vp.as<double>());
       precond<T, TR>(P.vp.as<double>(), P.vph.as<double>());
       timed(ctx, st, HENRY_PROF_SPMV, (long long)P.N, [&] {
         hipLaunchKernelGGL((k_spmv_dot<1, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vph.as<double>(),
-                           P.vv.as<double>(), P.vrh.as<double>(), P.part.as<double>());
+                           P.vv.as<double>(), P.vrh.as<double>(), P.part.as<double>(),
+                           black_exact ? (const double*)P.vp.as<double>() : nullptr);
       });
       hipLaunchKernelGGL(k_fin_alpha, fg, fb, 0, st, m, P.part.as<double>(), sc, status);
       hipLaunchKernelGGL(k_bicg_s, rg, bl, 0, st, m, P.G.ncell, sc, P.vr.as<double>(), P.vv.as<double>(),
@@ -709,12 +719,13 @@ struct Solver {
       precond<T, TR>(P.vs.as<double>(), P.vsh.as<double>());
       timed(ctx, st, HENRY_PROF_SPMV, (long long)P.N, [&] {
         hipLaunchKernelGGL((k_spmv_dot<2, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vsh.as<double>(),
-                           P.vt.as<double>(), P.vs.as<double>(), P.part.as<double>());
+                           P.vt.as<double>(), P.vs.as<double>(), P.part.as<double>(),
+                           black_exact ? (const double*)P.vs.as<double>() : nullptr);
       });
       hipLaunchKernelGGL(k_fin_omega, fg, fb, 0, st, m, P.part.as<double>(), sc);
     };
-    auto partC = [&]() {
-      hipLaunchKernelGGL(k_bicg_xr, rg, bl, 0, st, m, P.G.ncell, sc, P.vph.as<double>(), P.vsh.as<double>(),
+    auto partC = [&](int first) {
+      hipLaunchKernelGGL(k_bicg_xr, rg, bl, 0, st, m, P.G.ncell, first, sc, P.vph.as<double>(), P.vsh.as<double>(),
                          P.vs.as<double>(), P.vt.as<double>(), P.vrh.as<double>(), P.vx.as<double>(), P.vr.as<double>(),
                          P.part.as<double>());
       zero_ctrl();
@@ -728,15 +739,16 @@ struct Solver {
         std::memcpy(P.gkey[TR], key, sizeof key);
         P.grtol[TR] = rtol2;
       }
-      for (int part = 0; part < 4; ++part) {
+      for (int part = 0; part < 5; ++part) {
         if (P.gexec[TR][part]) continue;
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         tl_capturing = true;
         try {
-          if (part < 2) partA(part);   // part 0: later iterations, part 1: first iteration
+          // parts 0/1: A of later/first iterations, 2: B, 3/4: C of later/first iterations
+          if (part < 2) partA(part);
           else if (part == 2) partB();
-          else partC();
+          else partC(part - 3);
         } catch (...) {
           tl_capturing = false;
           (void)hipStreamEndCapture(st, &g);
@@ -758,8 +770,8 @@ struct Solver {
         if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][2], st));
         else partB();
       }
-      if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][3], st));
-      else partC();
+      if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][3 + first], st));
+      else partC(first);
       if (read_ctrl(0) == 0) break;
     }
     hipLaunchKernelGGL(k_accum_its, dim3((S + 255) / 256), dim3(256), 0, st, S, sc, P.stats.as<double>());
