@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # algorithmic bytes per unit of each kernel class (FP64 / FP32 multigrid), see the design doc
 BYTES = {
     64: dict(gs=208, spmv=136, assemble=216, restrict=76, prolong=216),
-    32: dict(gs=104, spmv=208, assemble=296, restrict=38, prolong=108),
+    32: dict(gs=104, spmv=136, assemble=296, restrict=38, prolong=108),
 }
 KERNEL_NAME = dict(gs="k_gs_colour", spmv="k_spmv_dot", assemble="k_assemble", restrict="k_residual_restrict",
                    prolong="k_gs_colour (fused prolongation)")

@@ -106,9 +106,9 @@ typedef struct {
   int nu_pre, nu_post;   /* red-black block Gauss-Seidel sweeps [1, 2] */
   double newton_tol;     /* converged when |dc|_inf <= tol and |dp|_inf <= tol*rho0*g*Ly [1e-9] */
   double newton_dc_max;  /* each update is scaled by min(1, dc_max/|dc|_inf) [1.0] */
-  int newton_maxit;      /* per time step [100] */
+  int newton_maxit;      /* per time step [200] */
   double krylov_rtol;    /* BiCGStab forcing term of the Newton systems: |r|_2 <= rtol |r0|_2 per
-                            sample, tested after each half step [3e-2]; Newton's own stopping
+                            sample, tested after each half step [5e-2]; Newton's own stopping
                             test fixes the accuracy */
   int krylov_maxit;      /* [60] */
   double c_range_tol;    /* status 4 when c leaves [-tol, 1+tol] [1e-8] */
@@ -124,6 +124,8 @@ typedef struct {
                                  iteration keeps the Jacobian, the multigrid hierarchy and the
                                  coarse factors (a chord step; only R is reassembled).  The first
                                  iteration of each step always assembles.  0 disables [1e-3] */
+  int mg_cycle;               /* 1: V-cycle; 2: W-cycle (two coarse cycles per level above the
+                                 coarsest) [1] */
 } henry_solver_opts;
 
 /* One batch of S independent samples on one grid (ragged batches: several per call). */

@@ -34,7 +34,8 @@ class henry_solver_opts(C.Structure):
                 ("c_range_tol", C.c_double), ("use_graphs", C.c_int), ("red_blocks", C.c_int),
                 ("krylov_rtol_adjoint", C.c_double), ("newton_extrapolate", C.c_int),
                 ("newton_predict", C.c_double),
-                ("newton_jac_reuse", C.c_double)]
+                ("newton_jac_reuse", C.c_double),
+                ("mg_cycle", C.c_int)]
 
 
 class henry_batch(C.Structure):

@@ -593,8 +593,8 @@ __global__ void __launch_bounds__(256) k_bicg_p(Map m, int ncell, int first, con
 // y = A x with per-sample partial dot products: NDOT = 1: (d0, y); NDOT = 2: (y, d0), (y, y).
 // yb (or NULL): when x is the output of a V-cycle whose last pass on this grid was the black
 // Gauss-Seidel pass, that pass solved the black rows exactly, (A x)_black = b_black with b the
-// cycle's right-hand side; y takes yb there (equal up to rounding) and only red rows are
-// multiplied out.
+// cycle's right-hand side; y takes yb there (equal up to rounding, or up to the rounding of
+// the Jacobian for an FP32 cycle) and only red rows are multiplied out.
 template <int NDOT, bool TR = false>
 __global__ void __launch_bounds__(256) k_spmv_dot(Map m, Grid2 G, const double* __restrict__ J,
                                                   const double* __restrict__ x, double* __restrict__ y,

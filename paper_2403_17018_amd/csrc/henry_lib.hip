@@ -258,7 +258,7 @@ struct Plan {
   // captured BiCGStab iterations: [transposed][first iteration]
   hipGraphExec_t gexec[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr},
                                 {nullptr, nullptr, nullptr, nullptr, nullptr}};
-  int gkey[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // per operator: nu_pre, nu_post, precision, valid
+  int gkey[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};   // per operator: nu_pre, nu_post, precision, cycle, valid
   double grtol[2] = {0.0, 0.0};
   void drop_graphs(int tr) {
     for (auto& g : gexec[tr])
@@ -266,7 +266,7 @@ struct Plan {
         (void)hipGraphExecDestroy(g);
         g = nullptr;
       }
-    gkey[tr][3] = 0;
+    gkey[tr][4] = 0;
   }
   void drop_graphs() {
     drop_graphs(0);
@@ -573,10 +573,11 @@ struct Solver {
     return (const T*)P.J.as<double>();
   }
 
-  // One V-cycle x = M^{-1} b on level k (TR: the same cycle built from transposed
-  // operators, a preconditioner for J^T).
+  // One multigrid cycle x = M^{-1} b on level k (TR: the same cycle built from transposed
+  // operators, a preconditioner for J^T): a V-cycle, or a W-cycle (mg_cycle 2: the coarse
+  // problem gets two cycles, the second from the first's result).  zero: x starts at 0.
   template <typename T, bool TR = false>
-  void vcycle(int k, const T* b, T* x) {
+  void vcycle(int k, const T* b, T* x, bool zero = true) {
     const Map& m = P.m;
     MGLevel& L = *P.lv[k];
     if (k == P.nlev - 1) {
@@ -618,12 +619,12 @@ struct Solver {
     // One pre-smoothing sweep followed by post-smoothing: the red half of the sweep is
     // never stored (its values are D^{-1} b, formed where they are read, and the first
     // post-smoothing pass recomputes red without them).
-    const bool implicit_red = o.nu_pre == 1 && o.nu_post >= 1;
+    const bool implicit_red = zero && o.nu_pre == 1 && o.nu_post >= 1;
     if (implicit_red) {
       gs(1, 3);
     } else {
       for (int sw = 0; sw < o.nu_pre; ++sw) {
-        gs(0, sw == 0 ? 1 : 0);
+        gs(0, sw == 0 && zero ? 1 : 0);
         gs(1, 0);
       }
     }
@@ -633,7 +634,8 @@ struct Solver {
     };
     if (k == 0) timed(ctx, st, HENRY_PROF_RESTRICT, (long long)L.ncell * P.S, rr);
     else rr();
-    vcycle<T, TR>(k + 1, C.b.as<T>(), C.x.as<T>());
+    const int visits = k + 2 < P.nlev ? o.mg_cycle : 1;   // the coarsest level is solved exactly
+    for (int v = 0; v < visits; ++v) vcycle<T, TR>(k + 1, C.b.as<T>(), C.x.as<T>(), v == 0);
     if (o.nu_post == 0) {
       hipLaunchKernelGGL((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G, C.x.as<T>(),
                          x);
@@ -680,9 +682,11 @@ struct Solver {
     int* status = P.status.as<int>();
     const dim3 rg = grid_red(m), bl = block_of(m), cg = grid_cells(m, P.G.ncell);
     const dim3 fg = fin_grid(S), fb(64, FIN_Y);
-    // FP64 cycles ending in a black pass (or the exact coarse solve) leave A M^{-1} b = b on
-    // black rows, so the SpMVs after them multiply out the red rows only
-    const bool black_exact = P.prec == 64 && o.nu_post >= 1;
+    // Cycles ending in a black pass (or the exact coarse solve) leave A M^{-1} b = b on black
+    // rows, so the SpMVs after them multiply out the red rows only.  With the FP32 cycle the
+    // identity holds for the FP32 Jacobian: it is off by about 1e-7 relative, far below the
+    // Krylov tolerance, and the Newton residual is always assembled in FP64.
+    const bool black_exact = o.nu_post >= 1;
     // r = rhat = p = sign * rhs; x0 = 0 is implicit (the first x update overwrites x)
     hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, rhs, sign, mask, P.vr.as<double>(), P.vrh.as<double>(),
                        P.vp.as<double>(), P.part.as<double>());
@@ -733,7 +737,7 @@ struct Solver {
     };
     const bool graphs = o.use_graphs && allow_graphs && !ctx->prof.on;
     if (graphs) {
-      const int key[4] = {o.nu_pre, o.nu_post, P.prec, 1};
+      const int key[5] = {o.nu_pre, o.nu_post, P.prec, o.mg_cycle, 1};
       if (std::memcmp(key, P.gkey[TR], sizeof key) != 0 || P.grtol[TR] != rtol2) {
         P.drop_graphs(TR);
         std::memcpy(P.gkey[TR], key, sizeof key);
@@ -1072,6 +1076,7 @@ static void check_opts(const henry_solver_opts& o) {
   if (o.red_blocks < 0) fail(HENRY_EINVAL, "red_blocks must be >= 0");
   if (!(o.newton_predict >= 0.0 && o.newton_predict <= 1.0)) fail(HENRY_EINVAL, "newton_predict must be in [0, 1]");
   if (!(o.newton_jac_reuse >= 0.0)) fail(HENRY_EINVAL, "newton_jac_reuse must be >= 0");
+  if (o.mg_cycle != 1 && o.mg_cycle != 2) fail(HENRY_EINVAL, "mg_cycle must be 1 (V) or 2 (W)");
 }
 
 static int theta_check(henry_ctx* ctx, const double* theta, int S) {
@@ -1294,13 +1299,14 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->nu_post = 2;
   o->newton_tol = 1e-9;
   o->newton_dc_max = 1.0;
-  o->newton_maxit = 100;
-  o->krylov_rtol = 3e-2;
+  o->newton_maxit = 200;
+  o->krylov_rtol = 5e-2;
   o->krylov_maxit = 60;
   o->c_range_tol = 1e-8;
   o->use_graphs = 0;
   o->red_blocks = 4096;
   o->krylov_rtol_adjoint = 1e-10;
+  o->mg_cycle = 1;
   o->newton_extrapolate = 1;
   o->newton_predict = 1.0;
   o->newton_jac_reuse = 1e-3;

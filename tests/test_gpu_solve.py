@@ -80,17 +80,18 @@ def test_level0_fp32_multigrid_matches_oracle(hx):
 
 
 def test_ragged_shape_multigrid_matches_oracle(hx):
-    """37 samples (ragged wavefront tail), 48x24 grid (3 multigrid levels down to 12x6), short horizon."""
+    """37 samples (ragged wavefront tail), 48x24 grid (3 multigrid levels down to 12x6), short horizon;
+    V-cycles in FP64 and FP32 and W-cycles."""
     import paper_2403_17018_amd as P
     th = draw_theta(5, 37)
     g = P.grid(48, 24, 8)
     kw = dict(T=6000.0)
-    for prec in (64, 32):
-        r, c, p = _solve(hx, th, g, kw, mg_precision=prec)
-        ref = oracle_batch(th, g.nx, g.ny, g.nsteps, kw)
+    ref = oracle_batch(th, g.nx, g.ny, g.nsteps, kw)
+    for prec, cycle in ((64, 1), (32, 1), (64, 2)):
+        r, c, p = _solve(hx, th, g, kw, mg_precision=prec, mg_cycle=cycle)
         assert r.nfailed == 0
-        assert rel_inf(c, ref["c"]).max() <= TOL, prec
-        assert rel_inf(p, ref["p"]).max() <= TOL, prec
+        assert rel_inf(c, ref["c"]).max() <= TOL, (prec, cycle)
+        assert rel_inf(p, ref["p"]).max() <= TOL, (prec, cycle)
 
 
 def test_level1_multigrid_dirichlet_variant(hx):
