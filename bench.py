@@ -27,7 +27,9 @@ sys.path.insert(0, ROOT)
 from henry_inputs import WORKLOADS, draw_theta, level_grid  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-# algorithmic bytes per unit of each kernel class (FP64 / FP32 multigrid), see the design doc
+# algorithmic bytes per unit of each kernel class (FP64 / FP32 multigrid): the values each
+# launch must move per cell-sample (per swept cell for the smoother, per fine cell for the
+# restriction), counted from the arrays the kernel reads and writes
 BYTES = {
     64: dict(gs=208, spmv=136, assemble=216, restrict=76, prolong=216),
     32: dict(gs=104, spmv=136, assemble=296, restrict=38, prolong=108),
