@@ -105,7 +105,7 @@ typedef struct {
   int coarse_nx, coarse_ny; /* coarsest multigrid grid, solved by a banded block LU [16, 8] */
   int nu_pre, nu_post;   /* red-black block Gauss-Seidel sweeps [1, 2] */
   double newton_tol;     /* converged when |dc|_inf <= tol and |dp|_inf <= tol*rho0*g*Ly [1e-9] */
-  double newton_dc_max;  /* each update is scaled by min(1, dc_max/|dc|_inf) [1.0] */
+  double newton_dc_max;  /* each update is scaled by min(1, dc_max/|dc|_inf) [2.0] */
   int newton_maxit;      /* per time step [200] */
   double krylov_rtol;    /* BiCGStab forcing term of the Newton systems: |r|_2 <= rtol |r0|_2 per
                             sample, tested after each half step [5e-2]; Newton's own stopping
@@ -114,7 +114,7 @@ typedef struct {
   double c_range_tol;    /* status 4 when c leaves [-tol, 1+tol] [1e-8] */
   int use_graphs;        /* capture each Krylov iteration in a hipGraph and replay it [0] */
   int red_blocks;        /* target thread blocks of the per-sample reduction kernels [4096] */
-  double krylov_rtol_adjoint; /* BiCGStab tolerance of the transposed (adjoint) systems [1e-10] */
+  double krylov_rtol_adjoint; /* BiCGStab tolerance of the transposed (adjoint) systems [1e-8] */
   int newton_extrapolate;     /* 1: first Newton guess 2u^n - u^{n-1}; 0: u^n [1] */
   double newton_predict;      /* > 0: a sample is also converged, without another linear solve, when
                                  its predicted update |dc_{k-1}| |R_k| / |R_{k-1}| (after an undamped

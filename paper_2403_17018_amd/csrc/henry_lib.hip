@@ -1298,14 +1298,14 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->nu_pre = 1;
   o->nu_post = 2;
   o->newton_tol = 1e-9;
-  o->newton_dc_max = 1.0;
+  o->newton_dc_max = 2.0;
   o->newton_maxit = 200;
   o->krylov_rtol = 5e-2;
   o->krylov_maxit = 60;
   o->c_range_tol = 1e-8;
   o->use_graphs = 0;
   o->red_blocks = 4096;
-  o->krylov_rtol_adjoint = 1e-10;
+  o->krylov_rtol_adjoint = 1e-8;
   o->mg_cycle = 1;
   o->newton_extrapolate = 1;
   o->newton_predict = 1.0;
