@@ -102,7 +102,7 @@ typedef struct {
 typedef struct {
   int mg_precision;      /* 64: FP64 multigrid; 32: FP32 multigrid preconditioner inside the
                             FP64 BiCGStab/Newton (iterative refinement) [64] */
-  int coarse_nx, coarse_ny; /* coarsest multigrid grid, solved by a banded block LU [16, 8] */
+  int coarse_nx, coarse_ny; /* coarsest multigrid grid, solved by a banded block LU [8, 4] */
   int nu_pre, nu_post;   /* red-black block Gauss-Seidel sweeps [1, 2] */
   double newton_tol;     /* converged when |dc|_inf <= tol and |dp|_inf <= tol*rho0*g*Ly [1e-9] */
   double newton_dc_max;  /* each update is scaled by min(1, dc_max/|dc|_inf) [2.0] */
@@ -242,7 +242,7 @@ HENRY_API int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, 
                          long long* m_l, double* cost);
 
 /* Autotuner for one batch shape (ragged-batching support).  For each candidate -- coarsest
- * grid {16x8, 32x16}, smoother sweeps {1+1, 1+2, 2+2}, reduction blocks {4096, 16384},
+ * grid {8x4, 16x8}, smoother sweeps {1+1, 1+2, 2+2}, reduction blocks {4096, 16384},
  * hipGraphs {off, on} -- runs the first implicit-Euler step of the caller's samples
  * untimed and times the second (so a weaker but cheaper preconditioner is charged for
  * any extra Newton iterations); writes the fastest into *opts (other fields unchanged)

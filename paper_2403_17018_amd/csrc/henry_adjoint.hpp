@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(256) k_adj_param(Map m, Grid2 G, Phys P, const
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_accum(Map m, const double* __restrict__ part,
                                                           double* __restrict__ out) {
   __shared__ double lds[64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double a[1];
   reduce_partials<1>(m, part, s, a, lds);
   if (threadIdx.y == 0 && s < m.S) out[s] += a[0];
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_theta(Map m, const double* _
                                                           const double* __restrict__ guin, double duin_dzeta,
                                                           double* __restrict__ out) {
   __shared__ double lds[4 * 64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   for (int k0 = 0; k0 < 12; k0 += 4) {
     double a[4];
     reduce_partials<4>(m, part + (size_t)k0 * m.ncb * m.S, s, a, lds);

@@ -746,7 +746,9 @@ __device__ __forceinline__ void reduce_partials_max(const Map& m, const double* 
   for (int q = 0; q < NQ; ++q) out[q] = v[q];
 }
 
-// Finalisation kernels: blockDim = (64, FIN_Y), grid = ceil(S/64).  ctrl[0] counts active samples.
+// Finalisation kernels: 64 * FIN_Y threads per block, blockDim.x samples by blockDim.y
+// threads that share each sample's partial sums (fewer samples per block, more threads per
+// sample for small batches).  ctrl[0] counts active samples.
 constexpr int FIN_Y = 16;
 
 // nhist (Newton systems only, else NULL): per sample [size of the last undamped update
@@ -756,7 +758,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_init(Map m, const double* __
                                                   int* __restrict__ ctrl, double* __restrict__ nhist,
                                                   int* __restrict__ ndone, double pred_tol) {
   __shared__ double lds[64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double v[1];
   reduce_partials<1>(m, part, s, v, lds);
   if (threadIdx.y == 0 && s < m.S) {
@@ -786,7 +788,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_init(Map m, const double* __
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_alpha(Map m, const double* __restrict__ part,
                                                           double* __restrict__ sc, int* __restrict__ status) {
   __shared__ double lds[64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double v[1];
   reduce_partials<1>(m, part, s, v, lds);
   if (threadIdx.y == 0 && s < m.S) {
@@ -810,7 +812,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_alpha(Map m, const double* _
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_half(Map m, const double* __restrict__ part,
                                                          double* __restrict__ sc, double rtol2, int* __restrict__ ctrl) {
   __shared__ double lds[64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double v[1];
   reduce_partials<1>(m, part, s, v, lds);
   if (threadIdx.y == 0 && s < m.S) {
@@ -831,7 +833,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_half(Map m, const double* __
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_omega(Map m, const double* __restrict__ part,
                                                           double* __restrict__ sc) {
   __shared__ double lds[2 * 64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double v[2];
   reduce_partials<2>(m, part, s, v, lds);
   if (threadIdx.y == 0 && s < m.S) {
@@ -846,7 +848,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_rho(Map m, const double* __r
                                                         double* __restrict__ sc, double rtol2, int* __restrict__ status,
                                                         int* __restrict__ ctrl) {
   __shared__ double lds[2 * 64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double v[2];
   reduce_partials<2>(m, part, s, v, lds);
   if (threadIdx.y == 0 && s < m.S) {
@@ -918,7 +920,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_newton(Map m, const double* 
                                                            double* __restrict__ stats, int* __restrict__ ctrl,
                                                            double* __restrict__ nhist, double jac_reuse) {
   __shared__ double lds[2 * 64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double v[2];
   reduce_partials_max<2>(m, part, s, v, lds);
   if (threadIdx.y != 0 || s >= m.S) return;
@@ -1018,7 +1020,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_balance(Map m, Phys P, const
                                                             const double* __restrict__ uin, double c_tol,
                                                             double* __restrict__ stats, int* __restrict__ status) {
   __shared__ double lds[4 * 64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double a[4];
   reduce_partials<4>(m, part, s, a, lds);
   double e[2];
@@ -1057,7 +1059,7 @@ __global__ void __launch_bounds__(256) k_qoi(Map m, Grid2 G, Phys P, const doubl
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_sum(Map m, const double* __restrict__ part, double scale,
                                                         double* __restrict__ out) {
   __shared__ double lds[64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double a[1];
   reduce_partials<1>(m, part, s, a, lds);
   if (threadIdx.y == 0 && s < m.S) out[s] = a[0] * scale;

@@ -174,7 +174,15 @@ static dim3 grid_cells(const Map& m, int ncell) {
 }
 static dim3 grid_red(const Map& m) { return dim3((unsigned)((long long)m.nsb * m.ncb)); }
 static dim3 block_of(const Map& m) { return dim3(m.SX, m.CY); }
-static dim3 fin_grid(int S) { return dim3((S + 63) / 64); }
+// Finalisation launch shape: blockDim.x = min(64, S rounded up to a power of 2) samples,
+// the rest of the 64 * FIN_Y threads split each sample's partial sums.
+static int fin_sx(int S) {
+  int x = 1;
+  while (x < S && x < 64) x <<= 1;
+  return x;
+}
+static dim3 fin_grid(int S) { return dim3((unsigned)((S + fin_sx(S) - 1) / fin_sx(S))); }
+static dim3 fin_block(int S) { return dim3(fin_sx(S), 64 * FIN_Y / fin_sx(S)); }
 
 // LDS of the banded solve: y and x (2n each) plus CH rows of L, CH + mb rows of U, CH Dinv.
 template <typename T>
@@ -681,7 +689,7 @@ struct Solver {
     int* ctrl = P.ctrl.as<int>();
     int* status = P.status.as<int>();
     const dim3 rg = grid_red(m), bl = block_of(m), cg = grid_cells(m, P.G.ncell);
-    const dim3 fg = fin_grid(S), fb(64, FIN_Y);
+    const dim3 fg = fin_grid(S), fb = fin_block(S);
     // Cycles ending in a black pass (or the exact coarse solve) leave A M^{-1} b = b on black
     // rows, so the SpMVs after them multiply out the red rows only.  With the FP32 cycle the
     // identity holds for the FP32 Jacobian: it is off by about 1e-7 relative, far below the
@@ -822,7 +830,7 @@ struct Solver {
     hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
                        P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.uin.as<double>(),
                        P.part.as<double>());
-    hipLaunchKernelGGL(k_fin_balance, fin_grid(S), dim3(64, FIN_Y), 0, st, m, phys, P.part.as<double>(),
+    hipLaunchKernelGGL(k_fin_balance, fin_grid(S), fin_block(S), 0, st, m, phys, P.part.as<double>(),
                        P.uin.as<double>(), o.c_range_tol, P.stats.as<double>(), P.status.as<int>());
   }
 
@@ -850,7 +858,7 @@ struct Solver {
       }
       hipLaunchKernelGGL(k_delta_max, grid_red(m), bl, 0, st, m, P.G.ncell, P.vx.as<double>(), P.part.as<double>());
       zero_ctrl();
-      hipLaunchKernelGGL(k_fin_newton, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), p_ref,
+      hipLaunchKernelGGL(k_fin_newton, fin_grid(S), fin_block(S), 0, st, m, P.part.as<double>(), p_ref,
                          o.newton_tol, o.newton_dc_max, P.lam.as<double>(), P.ndone.as<int>(), P.status.as<int>(),
                          P.stats.as<double>(), P.ctrl.as<int>(), P.nhist.as<double>(), o.newton_jac_reuse);
       hipLaunchKernelGGL(k_newton_update, cg, bl, 0, st, m, P.G.ncell, P.lam.as<double>(), P.vx.as<double>(),
@@ -925,7 +933,7 @@ struct Solver {
   void qoi(double* out) {
     const Map& m = P.m;
     hipLaunchKernelGGL(k_qoi, grid_red(m), block_of(m), 0, st, m, P.G, phys, P.c.as<double>(), P.part.as<double>());
-    hipLaunchKernelGGL(k_fin_sum, fin_grid(P.S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), phys.vol, out);
+    hipLaunchKernelGGL(k_fin_sum, fin_grid(P.S), fin_block(P.S), 0, st, m, P.part.as<double>(), phys.vol, out);
   }
 
   int progress_every = 0;
@@ -942,7 +950,7 @@ struct Solver {
       if (B.series) {
         hipLaunchKernelGGL(k_series, grid_red(P.m), block_of(P.m), 0, st, P.m, P.G, phys, P.c.as<double>(),
                            P.part.as<double>());
-        hipLaunchKernelGGL(k_fin_series, fin_grid(S), dim3(64, FIN_Y), 0, st, P.m, P.part.as<double>(),
+        hipLaunchKernelGGL(k_fin_series, fin_grid(S), fin_block(S), 0, st, P.m, P.part.as<double>(),
                            B.series + (size_t)n * NSERIES * S);
       }
     }
@@ -1022,7 +1030,7 @@ struct Solver {
         hipLaunchKernelGGL(k_adj_param, rg, bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
                            P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.vx.as<double>(), gphi, gK,
                            P.part.as<double>());
-        hipLaunchKernelGGL(k_fin_accum, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), guin);
+        hipLaunchKernelGGL(k_fin_accum, fin_grid(S), fin_block(S), 0, st, m, P.part.as<double>(), guin);
         if (n > 1)
           hipLaunchKernelGGL(k_adj_rhs_prev, cg, bl, 0, st, m, P.G, phys, P.c_old.as<double>(), P.phi.as<double>(),
                              P.vx.as<double>(), rhs);
@@ -1030,7 +1038,7 @@ struct Solver {
     }
     hipLaunchKernelGGL(k_adj_theta, rg, bl, 0, st, m, P.G, phys, kl, fp, theta, P.K.as<double>(), gphi, gK,
                        P.part.as<double>());
-    hipLaunchKernelGGL(k_fin_theta, fin_grid(S), dim3(64, FIN_Y), 0, st, m, P.part.as<double>(), guin,
+    hipLaunchKernelGGL(k_fin_theta, fin_grid(S), fin_block(S), 0, st, m, P.part.as<double>(), guin,
                        pr.q_in * pr.q_in_amp, grad);
     if (status_out) HIPCHK(hipMemcpyAsync(status_out, P.status.p, S * sizeof(int), hipMemcpyDeviceToDevice, st));
   }
@@ -1293,8 +1301,8 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof *o);
   o->mg_precision = 64;
-  o->coarse_nx = 16;
-  o->coarse_ny = 8;
+  o->coarse_nx = 8;
+  o->coarse_ny = 4;
   o->nu_pre = 1;
   o->nu_post = 2;
   o->newton_tol = 1e-9;
@@ -1615,7 +1623,7 @@ int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts*
     const bool prof = ctx->prof.on;
     ctx->prof.on = false;
     std::vector<henry_solver_opts> cands;
-    const int coarse[2][2] = {{16, 8}, {32, 16}};
+    const int coarse[2][2] = {{8, 4}, {16, 8}};
     const int nu[3][2] = {{1, 1}, {1, 2}, {2, 2}};
     const int rb[2] = {4096, 16384};
     for (auto& cg : coarse)

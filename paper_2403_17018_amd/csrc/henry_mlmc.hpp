@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(256) k_series(Map m, Grid2 G, Phys P, const do
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_series(Map m, const double* __restrict__ part,
                                                            double* __restrict__ out) {
   __shared__ double lds[4 * 64 * FIN_Y];
-  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   for (int q0 = 0; q0 < 16; q0 += 4) {
     double a[4];
     reduce_partials<4>(m, part + (size_t)q0 * m.ncb * m.S, s, a, lds);

