@@ -692,9 +692,9 @@ struct Solver {
     const dim3 fg = fin_grid(S), fb = fin_block(S);
     // Cycles ending in a black pass (or the exact coarse solve) leave A M^{-1} b = b on black
     // rows, so the SpMVs after them multiply out the red rows only.  With the FP32 cycle the
-    // identity holds for the FP32 Jacobian: it is off by about 1e-7 relative, far below the
-    // Krylov tolerance, and the Newton residual is always assembled in FP64.
-    const bool black_exact = o.nu_post >= 1;
+    // identity holds for the FP32 Jacobian, i.e. up to about 1e-7 relative: used only when the
+    // tolerance is far above that (the Newton systems; their residual is always FP64).
+    const bool black_exact = o.nu_post >= 1 && (P.prec == 64 || rtol >= 1e-5);
     // r = rhat = p = sign * rhs; x0 = 0 is implicit (the first x update overwrites x)
     hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, rhs, sign, mask, P.vr.as<double>(), P.vrh.as<double>(),
                        P.vp.as<double>(), P.part.as<double>());

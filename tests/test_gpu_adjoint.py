@@ -63,13 +63,16 @@ def _fd(hx, th, g, prob, opts, h=1e-6):
     return (q[:, 0] - q[:, 1]) / (2 * h)
 
 
-@pytest.mark.parametrize("shape", [(32, 16, 12, 9000.0, 5), (48, 24, 10, 7500.0, 4)])
+@pytest.mark.parametrize("shape", [(32, 16, 12, 9000.0, 5, 64), (48, 24, 10, 7500.0, 4, 64),
+                                   (48, 24, 10, 7500.0, 4, 32)])
 def test_adjoint_matches_oracle_and_fd(hx, shape):
+    """Two shapes with FP64 multigrid, one with the FP32 multigrid preconditioner in both
+    the forward and the transposed solves."""
     import paper_2403_17018_amd as P
-    nx, ny, nsteps, T, ck = shape
+    nx, ny, nsteps, T, ck, prec = shape
     th = draw_theta(21, 6, level=1)
     prob = P.problem(T=T)
-    opts = P.solver_opts(**TIGHT)
+    opts = P.solver_opts(mg_precision=prec, **TIGHT)
     g = P.grid(nx, ny, nsteps)
     q, gr, st, nf = hx.adjoint(_cu(th), g, prob, opts, checkpoint_every=ck)
     assert nf == 0
