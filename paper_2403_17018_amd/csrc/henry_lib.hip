@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1113,6 +1114,9 @@ static int guarded(henry_ctx* ctx, F&& f) {
   } catch (const std::bad_alloc&) {
     ctx->err = "host allocation failed";
     return HENRY_ENOMEM;
+  } catch (const std::exception& e) {   // e.g. a host thread that could not start
+    ctx->err = std::string("host runtime error: ") + e.what();
+    return HENRY_EDEVICE;
   }
 }
 

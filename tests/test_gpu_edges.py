@@ -68,3 +68,16 @@ def test_empty_and_invalid_batches(hx):
         hx.solve(th, P.grid(32, 16, 0))        # no time steps
     with pytest.raises(P.HenryError):
         hx.solve(th, P.level_grid(0), P.problem(field_model=2))
+
+
+def test_out_of_memory_is_an_error_not_a_crash(hx):
+    """A batch whose workspace cannot fit in device memory (level 4, two million samples:
+    terabytes per field) is refused with HENRY_ENOMEM; the context stays usable."""
+    import paper_2403_17018_amd as P
+    th = torch.zeros((2_000_000, 13), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.HenryError) as e:
+        hx.solve(th, P.level_grid(4), want_c=False)
+    assert e.value.code == -3
+    del th
+    r = hx.solve(_cuda(draw_theta(0, 2)), P.grid(32, 16, 2), want_c=True)
+    assert r.nfailed == 0
