@@ -115,7 +115,11 @@ typedef struct {
   int use_graphs;        /* capture each Krylov iteration in a hipGraph and replay it [0] */
   int red_blocks;        /* target thread blocks of the per-sample reduction kernels [4096] */
   double krylov_rtol_adjoint; /* BiCGStab tolerance of the transposed (adjoint) systems [1e-8] */
-  int newton_extrapolate;     /* 1: first Newton guess 2u^n - u^{n-1}; 0: u^n [1] */
+  int newton_extrapolate;     /* first Newton guess of a step.  0: u^n.  1: 2u^n - u^{n-1}.
+                                 2: as 1, except under a periodic recharge (recharge_omega != 0),
+                                 where p^n + g (p^n - p^{n-1}) with g the ratio of the next to the
+                                 last change of the inflow factor (bounded to [-3, 3]) and c^n
+                                 [2] */
   double newton_predict;      /* > 0: a sample is also converged, without another linear solve, when
                                  its predicted update |dc_{k-1}| |R_k| / |R_{k-1}| (after an undamped
                                  update) is <= newton_predict * newton_tol; 0 disables [1] */

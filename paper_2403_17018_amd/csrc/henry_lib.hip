@@ -822,10 +822,17 @@ struct Solver {
       // of the step does not depend on the guess
       const size_t n2 = P.N;
       const dim3 g((unsigned)((n2 + 255) / 256));
-      hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, n == 0 ? 0 : 1, P.p.as<double>(),
-                         P.p_prev.as<double>());
-      hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, n == 0 ? 0 : 1, P.c.as<double>(),
-                         P.c_prev.as<double>());
+      double gp = n == 0 ? 0.0 : 1.0, gc = gp;
+      if (n > 0 && o.newton_extrapolate == 2 && pr.recharge_omega != 0.0) {
+        // pressure follows the inflow almost instantly: scale its last increment by the
+        // change of the inflow factor (linear in the forcing), bounded
+        auto f = [&](int k) { return 1.0 + std::sin(pr.recharge_omega * k * phys.tau); };
+        const double d0 = f(n) - f(n - 1), d1 = f(n + 1) - f(n);
+        gp = std::fabs(d0) > 1e-3 ? std::max(-3.0, std::min(3.0, d1 / d0)) : 1.0;
+        gc = 0.0;   // c starts from c^n: its increments do not follow the inflow factor
+      }
+      hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, gp, P.p.as<double>(), P.p_prev.as<double>());
+      hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, gc, P.c.as<double>(), P.c_prev.as<double>());
     }
     newton_loop<T>(0);
     hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
@@ -1085,6 +1092,7 @@ static void check_opts(const henry_solver_opts& o) {
   if (o.red_blocks < 0) fail(HENRY_EINVAL, "red_blocks must be >= 0");
   if (!(o.newton_predict >= 0.0 && o.newton_predict <= 1.0)) fail(HENRY_EINVAL, "newton_predict must be in [0, 1]");
   if (!(o.newton_jac_reuse >= 0.0)) fail(HENRY_EINVAL, "newton_jac_reuse must be >= 0");
+  if (o.newton_extrapolate < 0 || o.newton_extrapolate > 2) fail(HENRY_EINVAL, "newton_extrapolate must be 0, 1 or 2");
   if (o.mg_cycle != 1 && o.mg_cycle != 2) fail(HENRY_EINVAL, "mg_cycle must be 1 (V) or 2 (W)");
 }
 
@@ -1319,7 +1327,7 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->red_blocks = 4096;
   o->krylov_rtol_adjoint = 1e-8;
   o->mg_cycle = 1;
-  o->newton_extrapolate = 1;
+  o->newton_extrapolate = 2;
   o->newton_predict = 1.0;
   o->newton_jac_reuse = 1e-3;
 }

@@ -34,13 +34,13 @@ __global__ void k_count_nonzero(int S, const int* __restrict__ a, int* __restric
   if (s < S && a[s] != 0) atomicAdd(count, 1);
 }
 
-// Initial Newton guess by linear extrapolation in time: mode 1: u <- 2u - u_prev, u_prev <- u
-// (old u); mode 0 (first step): u_prev <- u.
-__global__ void k_extrapolate(size_t n, int mode, double* __restrict__ u, double* __restrict__ u_prev) {
+// Initial Newton guess by extrapolation in time: u <- u + gamma (u - u_prev), u_prev <- u
+// (old u); gamma = 0 (first step) only records u.
+__global__ void k_extrapolate(size_t n, double gamma, double* __restrict__ u, double* __restrict__ u_prev) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const double un = u[t];
-  if (mode) u[t] = 2.0 * un - u_prev[t];
+  if (gamma != 0.0) u[t] = un + gamma * (un - u_prev[t]);
   u_prev[t] = un;
 }
 

@@ -126,6 +126,8 @@ def test_error_paths(hx):
         hx.solve(_gpu_theta(th), P.grid(32, 17, 4))        # non-square cells
     with pytest.raises(P.HenryError):
         hx.solve(_gpu_theta(th), P.level_grid(0), opts=P.solver_opts(mg_precision=16))
+    with pytest.raises(P.HenryError):
+        hx.solve(_gpu_theta(th), P.level_grid(0), opts=P.solver_opts(newton_extrapolate=3))
     # Newton iteration cap: samples are reported, not dropped
     r = hx.solve(_gpu_theta(th), P.level_grid(0), opts=P.solver_opts(newton_maxit=1))
     assert r.nfailed == 4 and (r.status.cpu().numpy() == 1).all()
