@@ -130,6 +130,10 @@ typedef struct {
                                  iteration of each step always assembles.  0 disables [1e-3] */
   int mg_cycle;               /* 1: V-cycle; 2: W-cycle (two coarse cycles per level above the
                                  coarsest) [1] */
+  int adjoint_guess;          /* first guess of each transposed solve of the reverse sweep.
+                                 0: lambda = 0.  1: lambda^{n+1} of the step solved before.
+                                 2: 2 lambda^{n+1} - lambda^{n+2}.  The tolerance
+                                 krylov_rtol_adjoint stays relative to the right-hand side [2] */
 } henry_solver_opts;
 
 /* One batch of S independent samples on one grid (ragged batches: several per call). */

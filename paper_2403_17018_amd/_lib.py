@@ -35,7 +35,8 @@ class henry_solver_opts(C.Structure):
                 ("krylov_rtol_adjoint", C.c_double), ("newton_extrapolate", C.c_int),
                 ("newton_predict", C.c_double),
                 ("newton_jac_reuse", C.c_double),
-                ("mg_cycle", C.c_int)]
+                ("mg_cycle", C.c_int),
+                ("adjoint_guess", C.c_int)]
 
 
 class henry_batch(C.Structure):

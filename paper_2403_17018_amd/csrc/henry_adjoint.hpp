@@ -175,4 +175,11 @@ __global__ void k_zero_f64(size_t n, double* __restrict__ a) {
   if (t < n) a[t] = 0.0;
 }
 
+// out = a x + b y (first guess of a transposed solve from earlier adjoint solutions)
+__global__ void k_axpby(size_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                        double* __restrict__ out) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = a * x[t] + b * y[t];
+}
+
 }  // namespace henry

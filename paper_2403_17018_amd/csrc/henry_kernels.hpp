@@ -546,32 +546,40 @@ __global__ void k_convert(size_t n, const TI* __restrict__ a, TO* __restrict__ b
 enum { SC_RHO = 0, SC_ALPHA, SC_OMEGA, SC_BETA, SC_R0, SC_RNORM, SC_ACTIVE, SC_ITS, SC_HALF, SC_NSLOT };
 
 // r = sign * R (zero for samples with ndone[s] set; ndone may be NULL), rhat = r, p = r; partial |r|^2
+// b = sign * R (0 for samples flagged in ndone); r = rhat = p = b - A x0, where A x0 is
+// given in ax (warm start) or x0 = 0 (ax == nullptr).  Partials |r|^2 and |b|^2.
 __global__ void __launch_bounds__(256) k_bicg_init(Map m, int ncell, const double* __restrict__ R, double sign,
-                                                   const int* __restrict__ ndone, double* __restrict__ r,
-                                                   double* __restrict__ rhat, double* __restrict__ p,
-                                                   double* __restrict__ part) {
-  __shared__ double lds[256];
+                                                   const double* __restrict__ ax, const int* __restrict__ ndone,
+                                                   double* __restrict__ r, double* __restrict__ rhat,
+                                                   double* __restrict__ p, double* __restrict__ part) {
+  __shared__ double lds[2 * 256];
   const int sblk = blockIdx.x % m.nsb, cblk = blockIdx.x / m.nsb;
   const int s = sblk * m.SX + threadIdx.x;
   const bool sv = s < m.S;
   const size_t N = (size_t)ncell * m.S;
-  double acc[1] = {0.0};
-  const double msk = (sv && !(ndone && ndone[s])) ? sign : 0.0;
+  double acc[2] = {0.0, 0.0};
+  const bool act = sv && !(ndone && ndone[s]);
+  const double msk = act ? sign : 0.0;
   for (int k = 0; k < m.CPT; ++k) {
     const int cell = (cblk * m.CPT + k) * m.CY + threadIdx.y;
     if (!sv || cell >= ncell) continue;
     const size_t id = (size_t)cell * m.S + s;
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {
-      const double v = R[comp * N + id] * msk;
+      const double b = R[comp * N + id] * msk;
+      const double v = ax && act ? b - ax[comp * N + id] : b;
       r[comp * N + id] = v;
       rhat[comp * N + id] = v;
       p[comp * N + id] = v;     // first search direction p0 = r0
       acc[0] += v * v;
+      acc[1] += b * b;
     }
   }
-  block_sum_y<1>(acc, lds);
-  if (threadIdx.y == 0 && sv) part[(size_t)cblk * m.S + s] = acc[0];
+  block_sum_y<2>(acc, lds);
+  if (threadIdx.y == 0 && sv) {
+    part[(size_t)cblk * m.S + s] = acc[0];
+    part[((size_t)m.ncb + cblk) * m.S + s] = acc[1];
+  }
 }
 
 // p = r (first) or r + beta (p - omega v)
@@ -756,20 +764,20 @@ constexpr int FIN_Y = 16;
 // size * |R_k| / |R_{k-1}| is <= pred_tol is declared converged without solving.
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_init(Map m, const double* __restrict__ part, double* __restrict__ sc,
                                                   int* __restrict__ ctrl, double* __restrict__ nhist,
-                                                  int* __restrict__ ndone, double pred_tol) {
-  __shared__ double lds[64 * FIN_Y];
+                                                  int* __restrict__ ndone, double pred_tol, double rtol2) {
+  __shared__ double lds[2 * 64 * FIN_Y];
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1];
-  reduce_partials<1>(m, part, s, v, lds);
+  double v[2];
+  reduce_partials<2>(m, part, s, v, lds);
   if (threadIdx.y == 0 && s < m.S) {
     const int S = m.S;
     sc[SC_RHO * S + s] = v[0];          // (rhat, r) = |r|^2 with rhat = r
-    sc[SC_R0 * S + s] = v[0];
+    sc[SC_R0 * S + s] = v[1];           // the tolerance is relative to |b| (= |r0| from x0 = 0)
     sc[SC_RNORM * S + s] = v[0];
     sc[SC_ALPHA * S + s] = 0.0;
     sc[SC_OMEGA * S + s] = 0.0;
     sc[SC_BETA * S + s] = 0.0;
-    int act = v[0] > 0.0;
+    int act = v[0] > 0.0 && v[0] > rtol2 * v[1];
     if (nhist && act) {
       const double last = nhist[2 * s], r2prev = nhist[2 * s + 1];
       if (pred_tol > 0.0 && last > 0.0 && r2prev > 0.0 && last * sqrt(v[0] / r2prev) <= pred_tol) {

@@ -683,7 +683,10 @@ struct Solver {
   // the solve is not started and their count is returned (else -1), so that the caller
   // can move them to a compacted batch first.
   template <typename T, bool TR = false>
-  int bicgstab(const double* rhs, double sign, int* mask, double rtol, bool newton = false, int stop_at = -1) {
+  // warm: start from the x already in vx (r0 = b - A x0); otherwise from x0 = 0.  The
+  // tolerance is relative to |b| either way.
+  int bicgstab(const double* rhs, double sign, int* mask, double rtol, bool newton = false, int stop_at = -1,
+               bool warm = false) {
     const Map& m = P.m;
     const int S = P.S;
     double* sc = P.sc.as<double>();
@@ -696,18 +699,23 @@ struct Solver {
     // identity holds for the FP32 Jacobian, i.e. up to about 1e-7 relative: used only when the
     // tolerance is far above that (the Newton systems; their residual is always FP64).
     const bool black_exact = o.nu_post >= 1 && (P.prec == 64 || rtol >= 1e-5);
-    // r = rhat = p = sign * rhs; x0 = 0 is implicit (the first x update overwrites x)
-    hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, rhs, sign, mask, P.vr.as<double>(), P.vrh.as<double>(),
-                       P.vp.as<double>(), P.part.as<double>());
+    const double rtol2 = rtol * rtol;
+    // r = rhat = p = sign * rhs - A x0; with x0 = 0 it is implicit (the first x update
+    // overwrites x)
+    if (warm)
+      hipLaunchKernelGGL((k_spmv_dot<1, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vx.as<double>(),
+                         P.vv.as<double>(), P.vx.as<double>(), P.part.as<double>(), (const double*)nullptr);
+    hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, rhs, sign, warm ? (const double*)P.vv.as<double>() : nullptr,
+                       mask, P.vr.as<double>(), P.vrh.as<double>(), P.vp.as<double>(), P.part.as<double>());
     zero_ctrl();
     hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl,
-                       newton ? P.nhist.as<double>() : (double*)nullptr, mask, o.newton_tol * o.newton_predict);
+                       newton ? P.nhist.as<double>() : (double*)nullptr, mask, o.newton_tol * o.newton_predict, rtol2);
     if (read_ctrl(0) == 0) {
-      HIPCHK(hipMemsetAsync(P.vx.p, 0, 2 * P.N * sizeof(double), st));   // nothing to solve: x = 0
+      // nothing to solve: x = 0, or x0 already within the tolerance
+      if (!warm) HIPCHK(hipMemsetAsync(P.vx.p, 0, 2 * P.N * sizeof(double), st));
       return -1;
     }
     if (newton && P.h_ctrl[1] <= stop_at) return P.h_ctrl[1];
-    const double rtol2 = rtol * rtol;
     // One BiCGStab iteration in three parts.  A: p update, M^{-1} p, v = A p-hat, alpha,
     // s = r - alpha v and the half-step test.  B (skipped when every active sample met the
     // tolerance at the half step): M^{-1} s, t = A s-hat, omega.  C: x, r updates and the
@@ -777,14 +785,15 @@ struct Solver {
     }
     for (int it = 0; it < o.krylov_maxit; ++it) {
       const int first = it == 0 ? 1 : 0;
+      const int first_x = first && !warm;   // x = update (x0 = 0) rather than x += update
       if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][first], st));
       else partA(first);
       if (read_ctrl(0) > 0) {
         if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][2], st));
         else partB();
       }
-      if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][3 + first], st));
-      else partC(first);
+      if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][3 + first_x], st));
+      else partC(first_x);
       if (read_ctrl(0) == 0) break;
     }
     hipLaunchKernelGGL(k_accum_its, dim3((S + 255) / 256), dim3(256), 0, st, S, sc, P.stats.as<double>());
@@ -981,13 +990,16 @@ struct Solver {
     const int ncp = nsteps / C + 1;
     ctx->adj_ck.alloc((size_t)ncp * 2 * st2);   // (p, c) and the previous step's (p, c)
     ctx->adj_seg.alloc((size_t)(C + 1) * st2);
-    ctx->adj_g.alloc((2 * N + 2 * N + S) * sizeof(double));
+    const int guess = o.adjoint_guess;
+    ctx->adj_g.alloc((2 * N + 2 * N + S + (guess > 0 ? 2 * N : 0) + (guess > 1 ? 2 * N : 0)) * sizeof(double));
     double* ck = ctx->adj_ck.as<double>();
     double* seg = ctx->adj_seg.as<double>();
     double* gphi = ctx->adj_g.as<double>();
     double* gK = gphi + N;
     double* rhs = gK + N;            // 2N
     double* guin = rhs + 2 * N;      // S
+    double* lam1 = guess > 0 ? guin + S : nullptr;          // lambda of the step solved last
+    double* lam2 = guess > 1 ? lam1 + 2 * N : nullptr;      // and of the one before
     auto save = [&](double* dst) {
       HIPCHK(hipMemcpyAsync(dst, P.p.p, N * 8, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(dst + N, P.c.p, N * 8, hipMemcpyDeviceToDevice, st));
@@ -1020,6 +1032,8 @@ struct Solver {
     (void)nz;
     hipLaunchKernelGGL(k_adj_rhs_final, cg, bl, 0, st, m, P.G, phys, P.c.as<double>(), rhs);
     const int nseg = (nsteps + C - 1) / C;
+    const dim3 g2((unsigned)((2 * N + 255) / 256));
+    int solved = 0;   // reverse steps solved so far
     for (int sg = nseg - 1; sg >= 0; --sg) {
       const int n0 = sg * C, n1 = std::min(n0 + C, nsteps);
       load_ck(ck + (size_t)sg * 4 * N);
@@ -1034,7 +1048,17 @@ struct Solver {
         load(un);
         HIPCHK(hipMemcpyAsync(P.c_old.p, um + N, N * 8, hipMemcpyDeviceToDevice, st));
         assemble_all<T>();
-        bicgstab<T, true>(rhs, 1.0, nullptr, o.krylov_rtol_adjoint);   // every sample solves its adjoint system
+        // first guess: lambda of the step after (guess 1) or its linear extrapolation
+        // 2 lambda^{n+1} - lambda^{n+2} (guess 2); the tolerance stays relative to |rhs|
+        const int gmode = std::min(guess, solved);
+        if (gmode == 1)
+          HIPCHK(hipMemcpyAsync(P.vx.p, lam1, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+        else if (gmode == 2)
+          hipLaunchKernelGGL(k_axpby, g2, dim3(256), 0, st, 2 * N, 2.0, lam1, -1.0, lam2, P.vx.as<double>());
+        bicgstab<T, true>(rhs, 1.0, nullptr, o.krylov_rtol_adjoint, false, -1, gmode > 0);   // every sample
+        if (lam2) std::swap(lam1, lam2);
+        if (lam1) HIPCHK(hipMemcpyAsync(lam1, P.vx.p, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+        ++solved;
         hipLaunchKernelGGL(k_adj_param, rg, bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
                            P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.vx.as<double>(), gphi, gK,
                            P.part.as<double>());
@@ -1093,6 +1117,7 @@ static void check_opts(const henry_solver_opts& o) {
   if (!(o.newton_predict >= 0.0 && o.newton_predict <= 1.0)) fail(HENRY_EINVAL, "newton_predict must be in [0, 1]");
   if (!(o.newton_jac_reuse >= 0.0)) fail(HENRY_EINVAL, "newton_jac_reuse must be >= 0");
   if (o.newton_extrapolate < 0 || o.newton_extrapolate > 2) fail(HENRY_EINVAL, "newton_extrapolate must be 0, 1 or 2");
+  if (o.adjoint_guess < 0 || o.adjoint_guess > 2) fail(HENRY_EINVAL, "adjoint_guess must be 0, 1 or 2");
   if (o.mg_cycle != 1 && o.mg_cycle != 2) fail(HENRY_EINVAL, "mg_cycle must be 1 (V) or 2 (W)");
 }
 
@@ -1327,6 +1352,7 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->red_blocks = 4096;
   o->krylov_rtol_adjoint = 1e-8;
   o->mg_cycle = 1;
+  o->adjoint_guess = 2;
   o->newton_extrapolate = 2;
   o->newton_predict = 1.0;
   o->newton_jac_reuse = 1e-3;

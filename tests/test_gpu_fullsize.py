@@ -62,3 +62,67 @@ def test_level3_fp32_multigrid_full_batch():
 def test_level4_fp32_multigrid_full_batch():
     """512x256 cells, 768 steps, 128 samples of seed 2 with the FP32 multigrid preconditioner."""
     _check(_run("c3_mixed_level4", 32), "c3", (0,))
+
+
+def test_mlmc_hierarchy_full_run():
+    """Levels 0..4 with 4096/1024/256/64/16 samples and their coupled coarse partners
+    (seed 3), in one ragged call with hipGraphs, as the benchmark times it.  Sampled
+    realisations of every grid against the oracle (levels 0 and 1 run live, levels 2 and 3
+    stored), every sample against the invariants, and the estimate against the oracle's
+    estimator (eq. A, the variance sum, the bias bound and the fields) on the same QoIs."""
+    import paper_2403_17018_amd as P
+    from oracle import mlmc as M
+    from tests.oracle_runs import oracle_batch
+    w = WORKLOADS["c4_mlmc_levels0to4"]
+    levels, m, seed = w["levels"], w["nsamples"], w["seed"]
+    ths = [draw_theta(seed, k, level=l) for l, k in zip(levels, m)]
+    hx = P.Henry(0)
+    est = P.mlmc_run(hx, [torch.from_numpy(t).cuda() for t in ths], levels, opts=P.solver_opts(use_graphs=1))
+    torch.cuda.synchronize()
+    assert est["nfailed"] == 0
+    res = est["results"]   # level 0 fine; then per level l >= 1: fine, coarse partner
+    fine = [res[0]] + [res[2 * l - 1] for l in range(1, len(levels))]
+    coarse = [None] + [res[2 * l] for l in range(1, len(levels))]
+    host = lambda r: dict(c=r.c_T.permute(2, 0, 1).cpu().numpy(), q=r.qoi.cpu().numpy(), st=r.stats.cpu().numpy())
+    F = [host(r) for r in fine]
+    Cp = [None] + [host(r) for r in coarse[1:]]
+    hx.close()
+
+    def same(c, q, ref_c, ref_q, what):
+        assert np.abs(c.ravel() - ref_c.ravel()).max() <= TOL * np.abs(ref_c).max(), what
+        assert abs(q - ref_q) <= TOL * abs(ref_q), what
+
+    # live oracle: level-0 samples 0 and 4095, level-1 samples 0 and 1023 and the coarse
+    # partner of level-1 sample 0 (its theta on the level-0 grid)
+    r0 = oracle_batch(np.stack([ths[0][0], ths[0][-1], ths[1][0]]), 32, 16, 48)
+    r1 = oracle_batch(np.stack([ths[1][0], ths[1][-1]]), 64, 32, 96)
+    same(F[0]["c"][0], F[0]["q"][0], r0["c"][0], r0["qoi"][0], "level 0, sample 0")
+    same(F[0]["c"][-1], F[0]["q"][-1], r0["c"][1], r0["qoi"][1], "level 0, last sample")
+    same(Cp[1]["c"][0], Cp[1]["q"][0], r0["c"][2], r0["qoi"][2], "level 1 coarse partner, sample 0")
+    same(F[1]["c"][0], F[1]["q"][0], r1["c"][0], r1["qoi"][0], "level 1, sample 0")
+    same(F[1]["c"][-1], F[1]["q"][-1], r1["c"][1], r1["qoi"][1], "level 1, last sample")
+    # stored oracle results (tests/golden/make_golden.py c4)
+    for name, arr in (("c4_l2", F[2]), ("c4_l3", F[3]), ("c4_l4coarse", Cp[4])):
+        f = os.path.join(GOLD, f"oracle_{name}_s0.npz")
+        if not os.path.exists(f):
+            continue
+        z = np.load(f)
+        src = ths[4][0] if name == "c4_l4coarse" else ths[int(name[-1])][0]
+        assert np.array_equal(z["theta"], src)
+        same(arr["c"][0], arr["q"][0], z["c_T"], float(z["qoi"]), name)
+    # invariants of every sample of every grid
+    for l, lev in enumerate(levels):
+        for out, glev in ((F[l], lev), (Cp[l], lev - 1)):
+            if out is None:
+                continue
+            bound = defect_bound(ths[l], 36000.0 / (48 << glev), 0.5)
+            assert (out["st"][:, 2] < bound).all() and (out["st"][:, 3] < bound).all(), (l, glev)
+            assert out["c"].min() >= -1e-10 and out["c"].max() <= 1 + 1e-10, (l, glev)
+    # the estimator on the same QoIs and fields
+    ref = M.estimate([f["q"] for f in F], [None if c is None else c["q"] for c in Cp])
+    assert est["mean"] == pytest.approx(ref["mean"], rel=1e-12)
+    assert np.allclose(est["V"], ref["V"], rtol=1e-9, atol=0.0)
+    assert est["rmse"] == pytest.approx(ref["rmse"], rel=1e-9)
+    mf, vf = M.field_estimate([f["c"] for f in F], [None if c is None else c["c"] for c in Cp])
+    assert np.abs(est["mean_field"].cpu().numpy() - mf).max() <= 1e-11
+    assert np.abs(est["var_field"].cpu().numpy() - vf).max() <= 1e-11
