@@ -130,3 +130,23 @@ def test_adjoint_with_graphs_equals_eager(hx):
     a = hx.adjoint(_cu(th), g, prob, P.solver_opts(use_graphs=0), checkpoint_every=3)
     b = hx.adjoint(_cu(th), g, prob, P.solver_opts(use_graphs=1), checkpoint_every=3)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_adjoint_first_guess_changes_only_the_path(hx):
+    """Transposed solves started from 0, from the later step's adjoint or from its linear
+    extrapolation reach the same gradient when the solves are tight."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(23, 5, level=1)
+    g = P.grid(48, 24, 10)
+    prob = P.problem(T=7500.0)
+    out = []
+    for guess in (0, 1, 2):
+        opts = P.solver_opts(adjoint_guess=guess, krylov_rtol_adjoint=1e-12, **TIGHT)
+        q, gr, st, nf = hx.adjoint(_cu(th), g, prob, opts, checkpoint_every=3)
+        assert nf == 0
+        out.append(gr.cpu().numpy())
+    for gr in out[1:]:
+        for s in range(th.shape[0]):
+            assert np.abs(gr[s] - out[0][s]).max() <= 1e-9 * np.abs(out[0][s]).max(), s
+    with pytest.raises(P.HenryError):
+        hx.adjoint(_cu(th), g, prob, P.solver_opts(adjoint_guess=3))
