@@ -546,12 +546,14 @@ __global__ void k_convert(size_t n, const TI* __restrict__ a, TO* __restrict__ b
 enum { SC_RHO = 0, SC_ALPHA, SC_OMEGA, SC_BETA, SC_R0, SC_RNORM, SC_ACTIVE, SC_ITS, SC_HALF, SC_NSLOT };
 
 // r = sign * R (zero for samples with ndone[s] set; ndone may be NULL), rhat = r, p = r; partial |r|^2
-// b = sign * R (0 for samples flagged in ndone); r = rhat = p = b - A x0, where A x0 is
-// given in ax (warm start) or x0 = 0 (ax == nullptr).  Partials |r|^2 and |b|^2.
+// b = sign * R (0 for samples flagged in ndone); r0 = b - A x0, where A x0 is given in ax
+// (warm start) or x0 = 0 (ax == nullptr).  Writes p = r0 (the first iteration reads r0
+// from p) and, unless rhat is NULL (the caller uses R itself as the shadow residual),
+// rhat = r0.  Partials |r0|^2 and |b|^2.
 __global__ void __launch_bounds__(256) k_bicg_init(Map m, int ncell, const double* __restrict__ R, double sign,
                                                    const double* __restrict__ ax, const int* __restrict__ ndone,
-                                                   double* __restrict__ r, double* __restrict__ rhat,
-                                                   double* __restrict__ p, double* __restrict__ part) {
+                                                   double* __restrict__ rhat, double* __restrict__ p,
+                                                   double* __restrict__ part) {
   __shared__ double lds[2 * 256];
   const int sblk = blockIdx.x % m.nsb, cblk = blockIdx.x / m.nsb;
   const int s = sblk * m.SX + threadIdx.x;
@@ -568,8 +570,7 @@ __global__ void __launch_bounds__(256) k_bicg_init(Map m, int ncell, const doubl
     for (int comp = 0; comp < 2; ++comp) {
       const double b = R[comp * N + id] * msk;
       const double v = ax && act ? b - ax[comp * N + id] : b;
-      r[comp * N + id] = v;
-      rhat[comp * N + id] = v;
+      if (rhat) rhat[comp * N + id] = v;
       p[comp * N + id] = v;     // first search direction p0 = r0
       acc[0] += v * v;
       acc[1] += b * b;
@@ -764,14 +765,15 @@ constexpr int FIN_Y = 16;
 // size * |R_k| / |R_{k-1}| is <= pred_tol is declared converged without solving.
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_init(Map m, const double* __restrict__ part, double* __restrict__ sc,
                                                   int* __restrict__ ctrl, double* __restrict__ nhist,
-                                                  int* __restrict__ ndone, double pred_tol, double rtol2) {
+                                                  int* __restrict__ ndone, double pred_tol, double rtol2,
+                                                  double rhat_sign) {
   __shared__ double lds[2 * 64 * FIN_Y];
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double v[2];
   reduce_partials<2>(m, part, s, v, lds);
   if (threadIdx.y == 0 && s < m.S) {
     const int S = m.S;
-    sc[SC_RHO * S + s] = v[0];          // (rhat, r) = |r|^2 with rhat = r
+    sc[SC_RHO * S + s] = rhat_sign * v[0];   // (rhat, r0) with rhat = rhat_sign r0
     sc[SC_R0 * S + s] = v[1];           // the tolerance is relative to |b| (= |r0| from x0 = 0)
     sc[SC_RNORM * S + s] = v[0];
     sc[SC_ALPHA * S + s] = 0.0;

@@ -700,16 +700,23 @@ struct Solver {
     // tolerance is far above that (the Newton systems; their residual is always FP64).
     const bool black_exact = o.nu_post >= 1 && (P.prec == 64 || rtol >= 1e-5);
     const double rtol2 = rtol * rtol;
-    // r = rhat = p = sign * rhs - A x0; with x0 = 0 it is implicit (the first x update
-    // overwrites x)
+    // Newton systems (the residual buffer, cold start): the shadow residual is R itself,
+    // i.e. sign * r0 (BiCGStab only uses it in ratios of dot products).  Otherwise it is a
+    // stored copy of r0.  The captured graphs hold this pointer, so it is fixed per TR.
+    const bool alias_rhat = !TR;
+    if (alias_rhat && (rhs != P.R.as<double>() || warm || (sign != 1.0 && sign != -1.0)))
+      fail(HENRY_EDEVICE, "internal: untransposed solves take the Newton residual, cold");
+    const double* rh = alias_rhat ? rhs : P.vrh.as<double>();
+    // p = r0 = sign * rhs - A x0 (x0 = 0 is implicit: the first x update overwrites x)
     if (warm)
       hipLaunchKernelGGL((k_spmv_dot<1, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vx.as<double>(),
                          P.vv.as<double>(), P.vx.as<double>(), P.part.as<double>(), (const double*)nullptr);
     hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, rhs, sign, warm ? (const double*)P.vv.as<double>() : nullptr,
-                       mask, P.vr.as<double>(), P.vrh.as<double>(), P.vp.as<double>(), P.part.as<double>());
+                       mask, alias_rhat ? (double*)nullptr : P.vrh.as<double>(), P.vp.as<double>(), P.part.as<double>());
     zero_ctrl();
     hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl,
-                       newton ? P.nhist.as<double>() : (double*)nullptr, mask, o.newton_tol * o.newton_predict, rtol2);
+                       newton ? P.nhist.as<double>() : (double*)nullptr, mask, o.newton_tol * o.newton_predict, rtol2,
+                       alias_rhat ? sign : 1.0);
     if (read_ctrl(0) == 0) {
       // nothing to solve: x = 0, or x0 already within the tolerance
       if (!warm) HIPCHK(hipMemsetAsync(P.vx.p, 0, 2 * P.N * sizeof(double), st));
@@ -727,12 +734,13 @@ struct Solver {
       precond<T, TR>(P.vp.as<double>(), P.vph.as<double>());
       timed(ctx, st, HENRY_PROF_SPMV, (long long)P.N, [&] {
         hipLaunchKernelGGL((k_spmv_dot<1, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vph.as<double>(),
-                           P.vv.as<double>(), P.vrh.as<double>(), P.part.as<double>(),
+                           P.vv.as<double>(), rh, P.part.as<double>(),
                            black_exact ? (const double*)P.vp.as<double>() : nullptr);
       });
       hipLaunchKernelGGL(k_fin_alpha, fg, fb, 0, st, m, P.part.as<double>(), sc, status);
-      hipLaunchKernelGGL(k_bicg_s, rg, bl, 0, st, m, P.G.ncell, sc, P.vr.as<double>(), P.vv.as<double>(),
-                         P.vs.as<double>(), P.part.as<double>());
+      // r0 is held in p (unchanged until the second iteration's p update)
+      hipLaunchKernelGGL(k_bicg_s, rg, bl, 0, st, m, P.G.ncell, sc, first ? P.vp.as<double>() : P.vr.as<double>(),
+                         P.vv.as<double>(), P.vs.as<double>(), P.part.as<double>());
       zero_ctrl();
       hipLaunchKernelGGL(k_fin_half, fg, fb, 0, st, m, P.part.as<double>(), sc, rtol2, ctrl);
     };
@@ -747,7 +755,7 @@ struct Solver {
     };
     auto partC = [&](int first) {
       hipLaunchKernelGGL(k_bicg_xr, rg, bl, 0, st, m, P.G.ncell, first, sc, P.vph.as<double>(), P.vsh.as<double>(),
-                         P.vs.as<double>(), P.vt.as<double>(), P.vrh.as<double>(), P.vx.as<double>(), P.vr.as<double>(),
+                         P.vs.as<double>(), P.vt.as<double>(), rh, P.vx.as<double>(), P.vr.as<double>(),
                          P.part.as<double>());
       zero_ctrl();
       hipLaunchKernelGGL(k_fin_rho, fg, fb, 0, st, m, P.part.as<double>(), sc, rtol2, status, ctrl);
