@@ -186,8 +186,11 @@ HENRY_API int henry_solve_batch(henry_ctx* ctx, const henry_problem* prob, const
                       henry_batch* batches, int nbatches);
 
 /* Discrete adjoint of the converged time-stepped solve: dQ/dtheta for
- * Q = salt mass in x > Lx/2 at t = T (KL fields with constant inflow; field_model 1 or
- * a non-zero recharge_omega return HENRY_EUNSUPPORTED).  Reverse sweep of transposed, multigrid-
+ * Q = salt mass in x > Lx/2 at t = T.  KL fields (field_model 0): xi_1..4, eta_1..8 and
+ * zeta; the paper's model (field_model 1, section 4): xi_1 = theta[0] and xi_2 = theta[1]
+ * through the porosity and the Kozeny-Carman permeability, the other KL slots 0; theta[12]
+ * through the inflow, each step's sensitivity weighted by its recharge factor
+ * 1 + sin(recharge_omega t) at the end of the step.  Reverse sweep of transposed, multigrid-
  * preconditioned BiCGStab solves, states recomputed from checkpoints taken every
  * `checkpoint_every` steps.
  *   theta: device [S][13]; qoi: device [S] or NULL; dqoi_dtheta: device [S][13];

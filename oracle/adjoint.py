@@ -75,7 +75,33 @@ def qoi_gradient_state(prob, grid, c):
 
 
 def theta_jacobians(prob, grid, theta):
-    """d phi / d xi_k [4, cells] (zero where clipped), d K / d eta_k [8, cells], d u_in / d zeta."""
+    """dphi/dtheta [13, cells], dK/dtheta [13, cells], du_in/dzeta (the base inflow).
+
+    KL model: phi depends on xi_1..4 (zero where clipped), K on eta_1..8 through ln K.
+    Paper model (section 4): phi = phi_hat C0 C1 C2 of eq. poro_2levels depends on xi_1 =
+    theta[0] and xi_2 = theta[1] through the product rule, and K = kappa phi^3 / (1 - phi^2)
+    (eq. e_perm_Kozeny_Carman) through phi: dK/dphi = kappa phi^2 (3 - phi^2) / (1 - phi^2)^2.
+    """
+    duin = prob.q_in * prob.q_in_amp
+    if prob.field_model == "paper":
+        X, Y = H.cell_centres(prob, grid)
+        xi1, xi2 = float(theta[0]), float(theta[1])
+        low = Y < -0.8
+        C0 = np.where(low, 1.2 * (1.0 + 0.2 * xi1), 1.0)
+        C1 = 1.0 + 0.15 * (xi2 * np.cos(np.pi * X / 2.0) - xi2 * np.sin(2.0 * np.pi * Y) + xi1 * np.cos(2.0 * np.pi * X))
+        C2 = 1.0 + 0.2 * (xi1 * np.sin(64.0 * np.pi * X) + xi2 * np.sin(32.0 * np.pi * Y))
+        dC0_1 = np.where(low, 1.2 * 0.2, 0.0)
+        dC1_1 = 0.15 * np.cos(2.0 * np.pi * X)
+        dC2_1 = 0.2 * np.sin(64.0 * np.pi * X)
+        dC1_2 = 0.15 * (np.cos(np.pi * X / 2.0) - np.sin(2.0 * np.pi * Y))
+        dC2_2 = 0.2 * np.sin(32.0 * np.pi * Y)
+        ph = prob.phi_mean
+        dphi = np.zeros((13, X.size))
+        dphi[0] = (ph * (dC0_1 * C1 * C2 + C0 * dC1_1 * C2 + C0 * C1 * dC2_1)).ravel()
+        dphi[1] = (ph * (C0 * dC1_2 * C2 + C0 * C1 * dC2_2)).ravel()
+        phi = (ph * C0 * C1 * C2).ravel()
+        dKdphi = prob.kappa_kc * phi ** 2 * (3.0 - phi ** 2) / (1.0 - phi ** 2) ** 2
+        return dphi, dphi * dKdphi, duin
     kl = H.kl_basis(prob)
     X, Y = H.cell_centres(prob, grid)
     E = kl.table(X, Y).reshape(len(kl.lam), -1)
@@ -84,20 +110,23 @@ def theta_jacobians(prob, grid, theta):
     s_phi = sum(sl[k] * theta[k] * E[k] for k in range(prob.n_kl_phi))
     raw = prob.phi_mean * (1.0 + prob.phi_amp * s_phi)
     inside = (raw > prob.phi_min) & (raw < prob.phi_max)
-    dphi = np.stack([np.where(inside, prob.phi_mean * prob.phi_amp * sl[k] * E[k], 0.0)
-                     for k in range(prob.n_kl_phi)])
+    dphi = np.zeros((13, X.size))
+    for k in range(prob.n_kl_phi):
+        dphi[k] = np.where(inside, prob.phi_mean * prob.phi_amp * sl[k] * E[k], 0.0)
     _, K, _ = H.sample_fields(prob, grid, theta)
     Kf = K.ravel()
-    dK = np.stack([prob.logK_amp * sl[k] * E[k] * Kf for k in range(prob.n_kl_logK)])
-    duin = prob.q_in * prob.q_in_amp
+    dK = np.zeros((13, X.size))
+    for k in range(prob.n_kl_logK):
+        dK[4 + k] = prob.logK_amp * sl[k] * E[k] * Kf
     return dphi, dK, duin
 
 
 def adjoint_gradient(prob, grid, theta, opts: H.SolveOptions | None = None):
-    """(Q, dQ/dtheta[13]) for one sample via the reverse sweep over stored states
-    (KL fields with constant inflow only)."""
-    if prob.field_model != "kl" or prob.recharge_omega != 0.0:
-        raise NotImplementedError("adjoint of the KL model with constant inflow only")
+    """(Q, dQ/dtheta[13]) for one sample via the reverse sweep over stored states.
+
+    Under a periodic recharge the inflow of step k is u_in (1 + sin(omega t_k)) at the end
+    of the step, t_k = k tau, so step k's sensitivity to the base inflow carries that factor.
+    """
     opts = opts or H.SolveOptions(stagnate=True)
     res = H.solve_sample(prob, grid, theta, opts, keep_states=True)
     phi, K, u_in = H.sample_fields(prob, grid, theta)
@@ -120,14 +149,12 @@ def adjoint_gradient(prob, grid, theta, opts: H.SolveOptions | None = None):
         lam = spla.splu(J).solve(rhs, trans="T")
         lp, lc = lam[0::2], lam[1::2]
         a, b, u = param_sensitivity_T(disc, p, c, c_old, lp, lc)
-        g_phi += a; g_K += b; g_uin += u
+        g_phi += a; g_K += b; g_uin += u * H.recharge_factor(prob, k * disc.tau)
         # -(dR^k / dc^{k-1})^T lam_k  (storage terms only)
         rhs = np.zeros(2 * n)
         rhs[1::2] = lp * V * phif * dr / disc.tau + lc * V * phif * (prob.rho0 + 2.0 * dr * c_old) / disc.tau
     dphi, dK, duin = theta_jacobians(prob, grid, theta)
-    grad = np.zeros(13)
-    grad[0:prob.n_kl_phi] = dphi @ g_phi
-    grad[4:4 + prob.n_kl_logK] = dK @ g_K
+    grad = dphi @ g_phi + dK @ g_K
     grad[12] = g_uin * duin
     return res.qoi, grad
 

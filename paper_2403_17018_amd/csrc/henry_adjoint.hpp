@@ -37,7 +37,8 @@ __global__ void k_adj_rhs_prev(Map m, Grid2 G, Phys P, const double* __restrict_
 }
 
 // Accumulate g_phi += lam^T dR/dphi, g_K += lam^T dR/dK for one step (gathered per cell),
-// and per-sample partials of lam^T dR/du_in.
+// and per-sample partials of lam^T dR/du_in for the base inflow u_in, which enters the
+// step as u_in * uin_fac (the recharge time factor at the end of the step).
 __global__ void __launch_bounds__(256) k_adj_param(Map m, Grid2 G, Phys P, const double* __restrict__ p,
                                                    const double* __restrict__ c, const double* __restrict__ c_old,
                                                    const double* __restrict__ phi, const double* __restrict__ K,
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(256) k_adj_param(Map m, Grid2 G, Phys P, const
     const double wb = P.hy / P.hx;
     if (i == 0) {
       gph += lc * 2.0 * rP * P.Dm * (cP - P.c_left) * wb;
-      const double dF_duin = -(P.rho0 + P.drho * P.c_left) * P.hy;
+      const double dF_duin = -(P.rho0 + P.drho * P.c_left) * P.uin_fac * P.hy;
       acc[0] += lp * dF_duin + lc * dF_duin * P.c_left;
     }
     if (i == G.nx - 1) {
@@ -115,7 +116,11 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_accum(Map m, const double* _
   if (threadIdx.y == 0 && s < m.S) out[s] += a[0];
 }
 
-// Contract the per-cell sensitivities with dphi/dxi_k and dK/deta_k: partials [12][ncb][S].
+// Contract the per-cell sensitivities with dphi/dtheta_k and dK/dtheta_k: partials [12][ncb][S].
+// KL model: phi depends on xi_1..4 (not where clipped), K on eta_1..8 through ln K.  The
+// paper's model (section 4): phi = phi_hat C0 C1 C2 (eq. poro_2levels) depends on xi_1 =
+// theta[0] and xi_2 = theta[1] (product rule), and K = kappa phi^3 / (1 - phi^2) (eq.
+// e_perm_Kozeny_Carman) on phi, with dK/dphi = kappa phi^2 (3 - phi^2) / (1 - phi^2)^2.
 __global__ void __launch_bounds__(256) k_adj_theta(Map m, Grid2 G, Phys P, KLModes kl, FieldParams fp,
                                                    const double* __restrict__ theta, const double* __restrict__ K,
                                                    const double* __restrict__ gphi, const double* __restrict__ gK,
@@ -134,6 +139,22 @@ __global__ void __launch_bounds__(256) k_adj_theta(Map m, Grid2 G, Phys P, KLMod
     const double x = (i + 0.5) * P.hx, y = -P.Ly + (j + 0.5) * P.hy;
     const size_t id = (size_t)cell * m.S + s;
     const double* th = theta + (size_t)s * 13;
+    if (fp.model == 1) {
+      const double xi1 = th[0], xi2 = th[1];
+      const bool low = y < -0.8;
+      const double c0 = low ? 1.2 * (1.0 + 0.2 * xi1) : 1.0;
+      const double c1 = 1.0 + 0.15 * (xi2 * cospi(0.5 * x) - xi2 * sinpi(2.0 * y) + xi1 * cospi(2.0 * x));
+      const double c2 = 1.0 + 0.2 * (xi1 * sinpi(64.0 * x) + xi2 * sinpi(32.0 * y));
+      const double d0_1 = low ? 1.2 * 0.2 : 0.0;
+      const double d1_1 = 0.15 * cospi(2.0 * x), d2_1 = 0.2 * sinpi(64.0 * x);
+      const double d1_2 = 0.15 * (cospi(0.5 * x) - sinpi(2.0 * y)), d2_2 = 0.2 * sinpi(32.0 * y);
+      const double ph = fp.phi_mean * c0 * c1 * c2, ph2 = ph * ph, om = 1.0 - ph2;
+      const double dKdphi = fp.kappa_kc * ph2 * (3.0 - ph2) / (om * om);
+      const double g = gphi[id] + gK[id] * dKdphi;
+      acc[0] += g * fp.phi_mean * (d0_1 * c1 * c2 + c0 * d1_1 * c2 + c0 * c1 * d2_1);
+      acc[1] += g * fp.phi_mean * (c0 * d1_2 * c2 + c0 * c1 * d2_2);
+      continue;
+    }
     double e[8];
     double sp = 0.0;
     for (int k = 0; k < kl.n; ++k) {

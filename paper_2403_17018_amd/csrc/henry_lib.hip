@@ -1064,6 +1064,8 @@ struct Solver {
         else if (gmode == 2)
           hipLaunchKernelGGL(k_axpby, g2, dim3(256), 0, st, 2 * N, 2.0, lam1, -1.0, lam2, P.vx.as<double>());
         bicgstab<T, true>(rhs, 1.0, nullptr, o.krylov_rtol_adjoint, false, -1, gmode > 0);   // every sample
+        // step n ends at t = n tau: its inflow factor weights the sensitivity to the base inflow
+        phys.uin_fac = 1.0 + std::sin(pr.recharge_omega * n * phys.tau);
         if (lam2) std::swap(lam1, lam2);
         if (lam1) HIPCHK(hipMemcpyAsync(lam1, P.vx.p, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, st));
         ++solved;
@@ -1452,8 +1454,6 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_problem* prob, const henry_s
     check_grid(*prob, grid);
     if (S < 1 || !theta || !dqoi_dtheta) fail(HENRY_EINVAL, "S < 1, theta or dqoi_dtheta NULL");
     if (checkpoint_every < 1) fail(HENRY_EINVAL, "checkpoint_every must be >= 1");
-    if (prob->field_model != 0 || prob->recharge_omega != 0.0)
-      fail(HENRY_EUNSUPPORTED, "the adjoint covers the KL fields with constant inflow only");
     if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
     Plan* P = get_plan(ctx, grid.nx, grid.ny, S, o);
     hipStream_t st = ctx_stream(ctx, 0);

@@ -122,11 +122,61 @@ def test_recharge_pressure_closed_form(hx):
     assert np.abs(r.c_T.cpu().numpy()).max() <= 1e-9
 
 
-def test_adjoint_of_paper_model_is_unsupported(hx):
+def _oracle_adjoint_paper(th, nx, ny, nsteps, T):
+    """Oracle adjoint of the paper's model in a child interpreter (the test process has the GPU open)."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = f"""
+import sys, json, numpy as np
+sys.path.insert(0, {root!r})
+from oracle import henry as H, adjoint as A
+th = np.array(json.loads(sys.argv[1]))
+pr = H.paper_problem(T={T}); g = H.Grid({nx}, {ny}, {nsteps})
+out = [A.adjoint_gradient(pr, g, t) for t in th]
+print(json.dumps([[q, list(gr)] for q, gr in out]))
+"""
+    r = subprocess.run([sys.executable, "-c", code, json.dumps(th.tolist())], capture_output=True, text=True,
+                       check=True)
+    out = json.loads(r.stdout)
+    return np.array([o[0] for o in out]), np.array([o[1] for o in out])
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_adjoint_of_paper_model_matches_oracle_and_fd(hx, prec):
+    """dQ/dxi_1, dQ/dxi_2 (porosity and Kozeny-Carman permeability) and dQ/dxi_3 (the
+    periodic recharge, a different factor every step) on 32x16 cells, 12 steps over
+    T = 1504 s, checkpoints every 5 steps: against the oracle's adjoint and against
+    central differences (h = 1e-6) of batched GPU forward solves; the slots the model
+    does not use are exactly 0."""
     import paper_2403_17018_amd as P
-    with pytest.raises(P.HenryError) as e:
-        hx.adjoint(_cuda(draw_theta(5, 2)), P.level_grid(0), P.paper_problem())
-    assert e.value.code == -4
+    th = draw_theta(24, 5, level=1)
+    T = 6016.0 * 12 / 48
+    prob = P.paper_problem(T=T)
+    g = P.grid(32, 16, 12)
+    tight = dict(newton_tol=1e-13, krylov_rtol=1e-12, krylov_maxit=200, newton_maxit=60, mg_precision=prec)
+    q, gr, st, nf = hx.adjoint(_cuda(th), g, prob, P.solver_opts(**tight), checkpoint_every=5)
+    assert nf == 0
+    q, gr = q.cpu().numpy(), gr.cpu().numpy()
+    qo, go = _oracle_adjoint_paper(th, 32, 16, 12, T)
+    assert np.abs(q - qo).max() <= 1e-10 * np.abs(qo).max()
+    assert np.all(gr[:, 2:12] == 0.0)
+    for s in range(th.shape[0]):
+        assert np.abs(gr[s] - go[s]).max() <= 1e-7 * np.abs(go[s]).max(), (s, gr[s], go[s])
+    # central differences in the three parameters the model uses, one batched solve
+    h = 1e-6
+    comps = (0, 1, 12)
+    pert = np.repeat(th[:, None, None, :], 2, axis=1).repeat(len(comps), axis=2)
+    for a, k in enumerate(comps):
+        pert[:, 0, a, k] += h
+        pert[:, 1, a, k] -= h
+    r = hx.solve(_cuda(pert.reshape(-1, 13)), g, prob, P.solver_opts(**tight), want_c=False)
+    assert r.nfailed == 0
+    qq = r.qoi.cpu().numpy().reshape(th.shape[0], 2, len(comps))
+    fd = (qq[:, 0] - qq[:, 1]) / (2 * h)
+    for s in range(th.shape[0]):
+        assert np.abs(gr[s][list(comps)] - fd[s]).max() <= 1e-6 * np.abs(fd[s]).max(), (s, gr[s], fd[s])
 
 
 def test_qmc_estimate_matches_oracle(hx):

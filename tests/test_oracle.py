@@ -493,6 +493,22 @@ def test_adjoint_matches_central_differences():
     assert np.abs(ga - gf).max() <= 1e-6 * np.abs(gf).max()
 
 
+def test_paper_model_adjoint_matches_central_differences():
+    """The paper's model (section 4): xi_1, xi_2 act through eq. poro_2levels and the
+    Kozeny-Carman permeability, xi_3 through the periodic recharge, whose time factor
+    differs from step to step (dropping it fails the xi_3 component).  The other ten
+    components do not enter the model: their adjoint gradient is exactly zero."""
+    pr = H.paper_problem(T=6016.0 * 12 / 48)
+    g = H.Grid(16, 8, 12)
+    th = draw_theta(8, 3)[2]
+    q, ga = A.adjoint_gradient(pr, g, th)
+    gf = A.fd_gradient(pr, g, th, h=1e-6, comps=(0, 1, 12))
+    for k in (0, 1, 12):
+        assert abs(ga[k] - gf[k]) <= 1e-6 * np.abs(gf).max(), (k, ga[k], gf[k])
+    assert np.all(ga[2:12] == 0.0)
+    assert min(abs(ga[0]), abs(ga[1]), abs(ga[12])) > 1e-3 * np.abs(ga).max()
+
+
 def test_adjoint_taylor_remainder_is_second_order():
     pr = H.Problem()
     g = H.Grid(16, 8, 8)
