@@ -190,12 +190,60 @@ def bench_qmc(args):
     print(json.dumps(out))
 
 
+def bench_adaptive(args):
+    """Adaptive MLMC (sections 3 and 5): pilot solves on levels 0..2 (32 samples each, with
+    coarse partners), fitted rates, the level count and sample sizes for relative accuracy
+    eps, then the production run in one ragged call.  Wall time of the whole driver to its
+    RMSE, with the planned MLMC cost next to plain Monte Carlo's at the same level (Test B4).
+    The paper's model (--model paper) has no decaying level differences on levels 1..3 (its
+    80 s recharge period is aliased by the coarse steps), so its plan is refused there."""
+    import torch
+    import paper_2403_17018_amd as P
+    prec = args.precision or 64
+    eps = args.eps
+    opts = P.solver_opts(mg_precision=prec)
+    prob = P.paper_problem() if args.model == "paper" else P.problem()
+    model = "the paper's section-4 model" if args.model == "paper" else "the KL model (T = 36000 s)"
+    hx = P.Henry(0)
+
+    def sampler(level, n, first):
+        return torch.from_numpy(draw_theta(7, n, level=level, first_sample=first)).cuda()
+
+    def run():
+        return P.mlmc_adaptive(hx, sampler, eps=eps, prob=prob, opts=opts, pilot_levels=2, pilot_samples=32,
+                               max_level=4)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        est = run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    pl = est["plan"]
+    out = {
+        "metric": "MLMC wall time to RMSE (adaptive)", "value": dt, "unit": "s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == 64 else "f64+f32mg", "data": "synthetic",
+        "config": {"workload": f"adaptive MLMC of {model}, relative accuracy {eps}, pilot levels "
+                               f"0..2 x 32 samples (seed 7), at most level 4, production in one ragged call",
+                   "mg_precision": prec, "parallelism": "samples batched on one GPU"},
+        "levels": pl["L"], "m": pl["m"], "rmse": est["rmse"], "mlmc_mean_qoi": est["mean"],
+        "rates": {k: pl[k] for k in ("alpha", "beta", "gamma")},
+        "model_cost_s": pl["cost"], "plain_mc_cost_s": pl["mc_cost"], "production_wall_s": est["wall_s"],
+        "failed_samples": est["nfailed"], "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "qmc"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "qmc", "adaptive"])
+    ap.add_argument("--eps", type=float, default=0.002, help="relative accuracy of the adaptive workload")
     ap.add_argument("--level", type=int, default=None, help="level of the qmc workload (default 3)")
     ap.add_argument("--graphs", type=int, default=None, help="capture BiCGStab iterations in hipGraphs (c4 default 1)")
     ap.add_argument("--precision", type=int, default=None, help="multigrid precision (default: the workload's)")
@@ -213,6 +261,8 @@ def main():
         return bench_adjoint(args)
     if args.workload == "qmc":
         return bench_qmc(args)
+    if args.workload == "adaptive":
+        return bench_adaptive(args)
     name = {"c1": "c1_fp64_level0", "c2": "c2_fp64_level3", "c3": "c3_mixed_level4"}[args.workload]
     w = WORKLOADS[name]
     prec = args.precision or w["mg_precision"]

@@ -242,7 +242,9 @@ HENRY_API int mlmc_estimate_series(henry_ctx* ctx, int L, const int* m, const he
  * m_l = ceil(2 eps^-2 E0^-2 sqrt(V_l/s_l) sum_i sqrt(V_i s_i)) for l <= L, with the pilot V_l
  * and s_l up to Lp and the fitted models beyond; eps is relative to E0 = |E g_0|.
  * m_l: host [max_level + 1]; cost: host, model cost sum m_l s_l (may be NULL);
- * rates: host [6] = alpha, beta, gamma, c1, c2, c3 (may be NULL).
+ * rates: host [7] = alpha, beta, gamma, c1, c2, c3 and the cost of plain Monte Carlo at level
+ * L for the same accuracy, 2 eps^-2 E0^-2 s_L V_0 (section 5, Test B4, with the pilot's
+ * variance of g_0 for that of g_L) (may be NULL).
  * Returns L, or HENRY_EINVAL (also when the fitted alpha is not positive). */
 HENRY_API int mlmc_plan(int Lp, const double* Ymean_abs, const double* V_l, const double* s_l, double eps,
                         double E0, int max_level, long long* m_l, double* cost, double* rates);

@@ -135,6 +135,8 @@ def plan(Ymean_abs, V, s, eps, E0, max_level):
     [1, max_level] where it is at most eps E0 / sqrt(2) (half the mean-square error budget),
     else max_level.  m_l = ceil(2 eps^-2 E0^-2 sqrt(V_l/s_l) sum_i sqrt(V_i s_i)) (eq.
     scaled_m_l_S), with the pilot's V_l and s_l for l <= Lp and the fitted laws beyond.
+    mc_cost = 2 eps^-2 E0^-2 s_L V_0 is the cost of plain Monte Carlo at level L for the same
+    accuracy (section 5, Test B4).
     """
     Lp = len(V) - 1
     sa, c1 = fit_rate(range(1, Lp + 1), Ymean_abs[1:])
@@ -152,5 +154,8 @@ def plan(Ymean_abs, V, s, eps, E0, max_level):
     sx = [s[l] if l <= Lp else c3 * 2.0 ** (gamma * l) for l in range(L + 1)]
     tot = sum(math.sqrt(v * c) for v, c in zip(Vx, sx))
     m = [int(math.ceil(2.0 / (eps * E0) ** 2 * math.sqrt(v / c) * tot)) for v, c in zip(Vx, sx)]
+    # section 5, Test B4: plain Monte Carlo at level L for the same accuracy, with the
+    # pilot's Var g_0 standing in for Var g_L
+    mc_cost = 2.0 / (eps * E0) ** 2 * sx[L] * V[0]
     return dict(L=L, m=m, cost=float(sum(mi * c for mi, c in zip(m, sx))), alpha=alpha, beta=beta, gamma=gamma,
-                c1=c1, c2=c2, c3=c3)
+                c1=c1, c2=c2, c3=c3, mc_cost=float(mc_cost))

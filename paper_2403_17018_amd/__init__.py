@@ -284,17 +284,18 @@ def mlmc_run(hx: "Henry", thetas, levels, prob=None, opts=None, alpha: float = 1
 
 def mlmc_plan(Ymean_abs, V, s, eps, E0, max_level):
     """Adaptive MLMC plan from pilot statistics on levels 0..Lp (mlmc_plan in the C ABI):
-    returns dict(L, m [L+1], cost, alpha, beta, gamma, c1, c2, c3)."""
+    returns dict(L, m [L+1], cost, alpha, beta, gamma, c1, c2, c3, mc_cost); mc_cost is the
+    cost of plain Monte Carlo at level L for the same accuracy (section 5, Test B4)."""
     n = len(V)
     m = (C.c_longlong * (max_level + 1))()
     cost = C.c_double()
-    rates = (C.c_double * 6)()
+    rates = (C.c_double * 7)()
     D = C.c_double * n
     L_ = L.load().mlmc_plan(n - 1, D(*Ymean_abs), D(*V), D(*s), eps, E0, max_level, m, C.byref(cost), rates)
     if L_ < 0:
         raise HenryError(L_, "invalid pilot statistics for mlmc_plan")
     return dict(L=L_, m=list(m)[:L_ + 1], cost=cost.value, alpha=rates[0], beta=rates[1], gamma=rates[2],
-                c1=rates[3], c2=rates[4], c3=rates[5])
+                c1=rates[3], c2=rates[4], c3=rates[5], mc_cost=rates[6])
 
 
 def mlmc_adaptive(hx: "Henry", sampler, eps: float, prob=None, opts=None, pilot_levels: int = 3,

@@ -1647,6 +1647,9 @@ int mlmc_plan(int Lp, const double* Ymean_abs, const double* V_l, const double* 
     rates[3] = c1;
     rates[4] = c2;
     rates[5] = c3;
+    // plain Monte Carlo at level L for the same accuracy (section 5, Test B4): Var g_0 of
+    // the pilot stands in for Var g_L
+    rates[6] = 2.0 / ((eps * E0) * (eps * E0)) * s[L] * V_l[0];
   }
   return L;
 }

@@ -97,5 +97,6 @@ def test_mlmc_plan_host_helper_matches_oracle():
             for k in ("alpha", "beta", "gamma", "c1", "c2", "c3"):
                 assert got[k] == pytest.approx(ref[k], rel=1e-10)
             assert got["cost"] == pytest.approx(ref["cost"], rel=1e-12)
+            assert got["mc_cost"] == pytest.approx(ref["mc_cost"], rel=1e-12)
     with pytest.raises(P.HenryError):
         P.mlmc_plan([1.0, 1.0, 2.0], [1.0, 0.5, 0.25], [1.0, 8.0, 64.0], 0.01, 1.0, 5)   # alpha <= 0

@@ -465,6 +465,14 @@ def test_plan_recovers_exact_rates_and_levels():
     assert p["m"] == list(want["m"])
     # the bias target cannot be met below max_level
     assert M.plan(Ym, V, s, eps=1e-6, E0=1.0, max_level=5)["L"] == 5
+    # Test B4's plain Monte Carlo cost at level L = 4 by hand: 2 (0.01 * 10)^-2 * s_4 * V_0
+    # = 200 * 0.25 * 2^12 * 0.5
+    assert p["mc_cost"] == pytest.approx(200.0 * 0.25 * 4096.0 * 0.5, rel=1e-12)
+    # beta < gamma (as in the paper, beta ~ 1.7 < 3): the MLMC saving over plain MC grows as
+    # the accuracy tightens (section 5 reports factors from about 30 to 3000)
+    ratio = [M.plan(Ym, 0.5 * 2.0 ** (-1.7 * lv), s, eps=e, E0=10.0, max_level=12) for e in (0.03, 0.003, 0.0003)]
+    ratio = [q["mc_cost"] / q["cost"] for q in ratio]
+    assert 1.0 < ratio[0] < ratio[1] < ratio[2] and ratio[2] > 1000.0
 
 
 def test_mlmc_agrees_with_plain_mc_on_tiny_levels():
