@@ -68,12 +68,15 @@ print(time.time() - t0, sum(its))
                       f"so this understates the full-horizon rate"}
 
 
-def pmc_traffic(kernel, prec):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel source is unchanged."""
+def pmc_traffic(kernel, prec, workload, model):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    this workload and model and the kernel source is unchanged."""
     f = os.path.join(ROOT, "profiles", f"pmc_{kernel}_fp{prec}.json")
     if not os.path.exists(f):
         return None
     d = json.load(open(f))
+    if d.get("workload") != workload or d.get("model") != model:
+        return None
     src = open(os.path.join(ROOT, "paper_2403_17018_amd", "csrc", "henry_kernels.hpp"), "rb").read()
     if d.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
         return None
@@ -304,7 +307,7 @@ def main():
     n, units, ms = prof[cls]
     per_launch_bytes = units / n * BYTES[prec][cls]
     achieved = per_launch_bytes / (ms / n * 1e-3) / 1e9
-    traffic = pmc_traffic(KERNEL_NAME[cls], prec)
+    traffic = pmc_traffic(KERNEL_NAME[cls], prec, name, args.model)
     out = {
         "metric": "sample-timesteps/s",
         "value": S * nsteps / dt,
