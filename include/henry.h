@@ -115,11 +115,14 @@ typedef struct {
   int use_graphs;        /* capture each Krylov iteration in a hipGraph and replay it [0] */
   int red_blocks;        /* target thread blocks of the per-sample reduction kernels [4096] */
   double krylov_rtol_adjoint; /* BiCGStab tolerance of the transposed (adjoint) systems [1e-8] */
-  int newton_extrapolate;     /* first Newton guess of a step.  0: u^n.  1: 2u^n - u^{n-1}.
-                                 2: as 1, except under a periodic recharge (recharge_omega != 0),
-                                 where p^n + g (p^n - p^{n-1}) with g the ratio of the next to the
-                                 last change of the inflow factor (bounded to [-3, 3]) and c^n
-                                 [2] */
+  int newton_extrapolate;     /* first Newton guess of a step, from the states of the last steps
+                                 (fewer available on the first steps: lower order).
+                                 0: u^n.  1: 2u^n - u^{n-1}.  2: as 1.  3: quadratic
+                                 3u^n - 3u^{n-1} + u^{n-2}.  4: cubic 4u^n - 6u^{n-1} +
+                                 4u^{n-2} - u^{n-3}.  2..4 under a periodic recharge
+                                 (recharge_omega != 0): p^n + g (p^n - p^{n-1}) with g the
+                                 ratio of the next to the last change of the inflow factor
+                                 (bounded to [-3, 3]) and c^n [4] */
   double newton_predict;      /* > 0: a sample is also converged, without another linear solve, when
                                  its predicted update |dc_{k-1}| |R_k| / |R_{k-1}| (after an undamped
                                  update) is <= newton_predict * newton_tol; 0 disables [1] */

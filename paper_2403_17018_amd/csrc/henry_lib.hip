@@ -253,6 +253,7 @@ struct Plan {
   int nlev;
   DevBuf phi, K, uin, p, c, c_old, R, J, J32;
   DevBuf p_prev, c_prev;   // state of the previous step (initial-guess extrapolation)
+  DevBuf p_prev2, c_prev2, p_prev3, c_prev3;   // and of the ones before (polynomial extrapolation)
   DevBuf vx, vr, vrh, vp, vv, vs, vt, vph, vsh;
   DevBuf LU;
   DevBuf sc, lam, ndone, status, stats, part, ctrl;
@@ -445,6 +446,10 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
   P->c_old.alloc(N * 8);
   P->p_prev.alloc(N * 8);
   P->c_prev.alloc(N * 8);
+  P->p_prev2.alloc(N * 8);
+  P->c_prev2.alloc(N * 8);
+  P->p_prev3.alloc(N * 8);
+  P->c_prev3.alloc(N * 8);
   P->R.alloc(2 * N * 8);
   P->J.alloc(20 * N * 8);
   if (o.mg_precision == 32) P->J32.alloc(20 * N * 4);
@@ -835,12 +840,13 @@ struct Solver {
     HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
     HIPCHK(hipMemsetAsync(P.nhist.p, 0, (size_t)S * 2 * sizeof(double), st));
     if (o.newton_extrapolate) {
-      // Newton starts from 2 u^n - u^{n-1} (u^0 itself on the first step); the fixed point
-      // of the step does not depend on the guess
+      // Newton starts from a polynomial extrapolation of the last steps (u^0 itself on the
+      // first step); the fixed point of the step does not depend on the guess
       const size_t n2 = P.N;
       const dim3 g((unsigned)((n2 + 255) / 256));
       double gp = n == 0 ? 0.0 : 1.0, gc = gp;
-      if (n > 0 && o.newton_extrapolate == 2 && pr.recharge_omega != 0.0) {
+      const bool inflow_rule = o.newton_extrapolate >= 2 && pr.recharge_omega != 0.0;
+      if (n > 0 && inflow_rule) {
         // pressure follows the inflow almost instantly: scale its last increment by the
         // change of the inflow factor (linear in the forcing), bounded
         auto f = [&](int k) { return 1.0 + std::sin(pr.recharge_omega * k * phys.tau); };
@@ -848,8 +854,17 @@ struct Solver {
         gp = std::fabs(d0) > 1e-3 ? std::max(-3.0, std::min(3.0, d1 / d0)) : 1.0;
         gc = 0.0;   // c starts from c^n: its increments do not follow the inflow factor
       }
-      hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, gp, P.p.as<double>(), P.p_prev.as<double>());
-      hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, gc, P.c.as<double>(), P.c_prev.as<double>());
+      if (o.newton_extrapolate >= 3 && !inflow_rule) {
+        const int order = std::min(n, o.newton_extrapolate - 1);
+        const bool h3 = o.newton_extrapolate == 4;
+        hipLaunchKernelGGL(k_extrapolate_poly, g, dim3(256), 0, st, n2, order, P.p.as<double>(), P.p_prev.as<double>(),
+                           P.p_prev2.as<double>(), h3 ? P.p_prev3.as<double>() : nullptr);
+        hipLaunchKernelGGL(k_extrapolate_poly, g, dim3(256), 0, st, n2, order, P.c.as<double>(), P.c_prev.as<double>(),
+                           P.c_prev2.as<double>(), h3 ? P.c_prev3.as<double>() : nullptr);
+      } else {
+        hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, gp, P.p.as<double>(), P.p_prev.as<double>());
+        hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, gc, P.c.as<double>(), P.c_prev.as<double>());
+      }
     }
     newton_loop<T>(0);
     hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
@@ -996,7 +1011,7 @@ struct Solver {
     const int S = P.S;
     const size_t N = P.N, st2 = 2 * N * sizeof(double);
     const int ncp = nsteps / C + 1;
-    ctx->adj_ck.alloc((size_t)ncp * 2 * st2);   // (p, c) and the previous step's (p, c)
+    ctx->adj_ck.alloc((size_t)ncp * 4 * st2);   // (p, c) and the three previous steps' (p, c)
     ctx->adj_seg.alloc((size_t)(C + 1) * st2);
     const int guess = o.adjoint_guess;
     ctx->adj_g.alloc((2 * N + 2 * N + S + (guess > 0 ? 2 * N : 0) + (guess > 1 ? 2 * N : 0)) * sizeof(double));
@@ -1020,17 +1035,25 @@ struct Solver {
       save(dst);
       HIPCHK(hipMemcpyAsync(dst + 2 * N, P.p_prev.p, N * 8, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(dst + 3 * N, P.c_prev.p, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(dst + 4 * N, P.p_prev2.p, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(dst + 5 * N, P.c_prev2.p, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(dst + 6 * N, P.p_prev3.p, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(dst + 7 * N, P.c_prev3.p, N * 8, hipMemcpyDeviceToDevice, st));
     };
     auto load_ck = [&](const double* src) {
       load(src);
       HIPCHK(hipMemcpyAsync(P.p_prev.p, src + 2 * N, N * 8, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(P.c_prev.p, src + 3 * N, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(P.p_prev2.p, src + 4 * N, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(P.c_prev2.p, src + 5 * N, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(P.p_prev3.p, src + 6 * N, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(P.c_prev3.p, src + 7 * N, N * 8, hipMemcpyDeviceToDevice, st));
     };
     init(theta);
     save_ck(ck);
     for (int n = 0; n < nsteps; ++n) {
       time_step<T>(n, nsteps);
-      if ((n + 1) % C == 0) save_ck(ck + (size_t)((n + 1) / C) * 4 * N);
+      if ((n + 1) % C == 0) save_ck(ck + (size_t)((n + 1) / C) * 8 * N);
     }
     if (qoi_out) qoi(qoi_out);
     const dim3 cg = grid_cells(m, P.G.ncell), bl = block_of(m), rg = grid_red(m);
@@ -1044,7 +1067,7 @@ struct Solver {
     int solved = 0;   // reverse steps solved so far
     for (int sg = nseg - 1; sg >= 0; --sg) {
       const int n0 = sg * C, n1 = std::min(n0 + C, nsteps);
-      load_ck(ck + (size_t)sg * 4 * N);
+      load_ck(ck + (size_t)sg * 8 * N);
       save(seg);
       for (int n = n0; n < n1; ++n) {
         time_step<T>(n, nsteps);
@@ -1126,7 +1149,7 @@ static void check_opts(const henry_solver_opts& o) {
   if (o.red_blocks < 0) fail(HENRY_EINVAL, "red_blocks must be >= 0");
   if (!(o.newton_predict >= 0.0 && o.newton_predict <= 1.0)) fail(HENRY_EINVAL, "newton_predict must be in [0, 1]");
   if (!(o.newton_jac_reuse >= 0.0)) fail(HENRY_EINVAL, "newton_jac_reuse must be >= 0");
-  if (o.newton_extrapolate < 0 || o.newton_extrapolate > 2) fail(HENRY_EINVAL, "newton_extrapolate must be 0, 1 or 2");
+  if (o.newton_extrapolate < 0 || o.newton_extrapolate > 4) fail(HENRY_EINVAL, "newton_extrapolate must be 0..4");
   if (o.adjoint_guess < 0 || o.adjoint_guess > 2) fail(HENRY_EINVAL, "adjoint_guess must be 0, 1 or 2");
   if (o.mg_cycle != 1 && o.mg_cycle != 2) fail(HENRY_EINVAL, "mg_cycle must be 1 (V) or 2 (W)");
 }
@@ -1363,7 +1386,7 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->krylov_rtol_adjoint = 1e-8;
   o->mg_cycle = 1;
   o->adjoint_guess = 2;
-  o->newton_extrapolate = 2;
+  o->newton_extrapolate = 4;
   o->newton_predict = 1.0;
   o->newton_jac_reuse = 1e-3;
 }

@@ -44,6 +44,24 @@ __global__ void k_extrapolate(size_t n, double gamma, double* __restrict__ u, do
   u_prev[t] = un;
 }
 
+// Polynomial extrapolation through the last order + 1 steps (order 0: u kept, the first
+// step; 1: 2u - h1; 2: 3u - 3h1 + h2; 3: 4u - 6h1 + 4h2 - h3), h1..h3 the states of the
+// previous steps (h3 may be NULL when order never exceeds 2); the history shifts by one.
+__global__ void k_extrapolate_poly(size_t n, int order, double* __restrict__ u, double* __restrict__ h1,
+                                   double* __restrict__ h2, double* __restrict__ h3) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double un = u[t];
+  const double a = order > 0 ? h1[t] : un;
+  const double b = order > 1 ? h2[t] : a;
+  if (order == 3) u[t] = 4.0 * (un + b) - 6.0 * a - h3[t];
+  else if (order == 2) u[t] = 3.0 * (un - a) + b;
+  else if (order == 1) u[t] = 2.0 * un - a;
+  if (h3) h3[t] = b;
+  h2[t] = a;
+  h1[t] = un;
+}
+
 // Indices of the samples with ndone[s] == 0, in increasing order (one thread; S is small).
 __global__ void k_compact_index(int S, const int* __restrict__ ndone, int* __restrict__ idx) {
   if (threadIdx.x != 0) return;

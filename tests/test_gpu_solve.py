@@ -94,6 +94,24 @@ def test_ragged_shape_multigrid_matches_oracle(hx):
         assert rel_inf(p, ref["p"]).max() <= TOL, (prec, cycle)
 
 
+def test_every_first_guess_reaches_the_oracle_fixed_point(hx):
+    """Level 1 (64x32 cells, 96 steps), 8 samples: Newton started from u^n and from the
+    linear, quadratic and cubic extrapolations of the last steps; the guess changes the
+    iteration path, not the fixed point of each step."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(9, 8, level=1)
+    g = P.level_grid(1)
+    ref = oracle_batch(th, g.nx, g.ny, g.nsteps)
+    its = {}
+    for ext in (0, 1, 3, 4):
+        r, c, p = _solve(hx, th, g, newton_extrapolate=ext)
+        assert r.nfailed == 0, ext
+        assert rel_inf(c, ref["c"]).max() <= TOL, ext
+        assert rel_inf(p, ref["p"]).max() <= TOL, ext
+        its[ext] = r.stats.cpu().numpy()[:, 0].sum()
+    assert its[4] < its[1] < its[0]
+
+
 def test_level1_multigrid_dirichlet_variant(hx):
     import paper_2403_17018_amd as P
     th = draw_theta(6, 8, level=1)
@@ -127,7 +145,7 @@ def test_error_paths(hx):
     with pytest.raises(P.HenryError):
         hx.solve(_gpu_theta(th), P.level_grid(0), opts=P.solver_opts(mg_precision=16))
     with pytest.raises(P.HenryError):
-        hx.solve(_gpu_theta(th), P.level_grid(0), opts=P.solver_opts(newton_extrapolate=3))
+        hx.solve(_gpu_theta(th), P.level_grid(0), opts=P.solver_opts(newton_extrapolate=5))
     # Newton iteration cap: samples are reported, not dropped
     r = hx.solve(_gpu_theta(th), P.level_grid(0), opts=P.solver_opts(newton_maxit=1))
     assert r.nfailed == 4 and (r.status.cpu().numpy() == 1).all()

@@ -60,7 +60,7 @@ def test_defaults_match_the_workload_constants():
     assert (p.Dm, p.K_mean, p.q_in, p.corr_len) == (1.88571e-5, 1.020408e-9, 6.6e-5, 0.5)
     o = P.solver_opts()
     assert o.mg_precision == 64 and o.nu_pre == 1 and o.nu_post == 2 and o.coarse_nx == 8 and o.coarse_ny == 4
-    assert o.newton_tol == 1e-9 and o.krylov_rtol == 5e-2 and o.newton_maxit == 200 and o.newton_extrapolate == 2 and o.newton_predict == 1.0
+    assert o.newton_tol == 1e-9 and o.krylov_rtol == 5e-2 and o.newton_maxit == 200 and o.newton_extrapolate == 4 and o.newton_predict == 1.0
     assert o.newton_jac_reuse == 1e-3 and o.newton_dc_max == 2.0 and o.krylov_rtol_adjoint == 1e-8
     assert o.mg_cycle == 1 and o.adjoint_guess == 2
 
