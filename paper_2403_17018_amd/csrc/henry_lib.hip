@@ -927,7 +927,7 @@ struct Solver {
     Plan& Q = *P.compact;
     plan_set_samples(Q, Sa, o.red_blocks);
     int* idx = P.cidx.as<int>();
-    hipLaunchKernelGGL(k_compact_index, dim3(1), dim3(64), 0, st, S, P.ndone.as<int>(), idx);
+    hipLaunchKernelGGL(k_compact_index, dim3(1), dim3(COMPACT_THREADS), 0, st, S, P.ndone.as<int>(), idx);
     auto gather = [&](const double* src, double* dst, size_t rows) {
       const size_t n = rows * Sa;
       hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rows, S, Sa, idx, src, dst);

@@ -62,12 +62,29 @@ __global__ void k_extrapolate_poly(size_t n, int order, double* __restrict__ u, 
   h1[t] = un;
 }
 
-// Indices of the samples with ndone[s] == 0, in increasing order (one thread; S is small).
-__global__ void k_compact_index(int S, const int* __restrict__ ndone, int* __restrict__ idx) {
-  if (threadIdx.x != 0) return;
-  int a = 0;
-  for (int s = 0; s < S; ++s)
-    if (!ndone[s]) idx[a++] = s;
+// Indices of the samples with ndone[s] == 0, in increasing order.  One block: each thread
+// owns a contiguous range of samples, counts its active ones, and an exclusive scan of the
+// counts (in LDS) gives where its indices start.
+constexpr int COMPACT_THREADS = 1024;
+__global__ void __launch_bounds__(COMPACT_THREADS) k_compact_index(int S, const int* __restrict__ ndone,
+                                                                   int* __restrict__ idx) {
+  __shared__ int cnt[COMPACT_THREADS];
+  const int t = threadIdx.x, T = blockDim.x;
+  const int per = (S + T - 1) / T;
+  const int s0 = min(S, t * per), s1 = min(S, s0 + per);
+  int c = 0;
+  for (int s = s0; s < s1; ++s) c += ndone[s] == 0;
+  cnt[t] = c;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {   // inclusive scan (Hillis-Steele)
+    const int v = t >= off ? cnt[t - off] : 0;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
+  }
+  int a = cnt[t] - c;
+  for (int s = s0; s < s1; ++s)
+    if (ndone[s] == 0) idx[a++] = s;
 }
 
 // dst[r][a] = src[r][idx[a]] for rows r of sample-fastest arrays ([rows][S] -> [rows][Sa])
