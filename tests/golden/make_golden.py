@@ -7,11 +7,13 @@ few sampled realisations instead of re-running the oracle.
 "f1" is the paper's own stochastic model (section 4) at level 2 (128x64 cells,
 192 steps over T = 6016 s), seed 5, samples 0 and 1.
 
+"f1l3" is the paper's model on the benchmark's level-3 input (seed 1, sample 0).
+
 "c4" holds sampled realisations of the full MLMC hierarchy (seed 3): sample 0 of level 2,
 sample 0 of level 3, and the coarse partner of level-4 sample 0 (its theta solved on the
 level-3 grid).
 
-usage: python tests/golden/make_golden.py {c2|c3|c4|c5|f1|all} [--procs N]
+usage: python tests/golden/make_golden.py {c2|c3|c4|c5|f1|f1l3|all} [--procs N]
 """
 import argparse
 import os
@@ -31,7 +33,7 @@ from oracle import henry as H  # noqa: E402
 def _forward(args):
     name, level, seed, s = args[:4]
     theta_level = args[4] if len(args) > 4 else level   # a coupled coarse partner: the finer level's theta
-    pr = H.paper_problem() if name == "f1" else H.Problem()
+    pr = H.paper_problem() if name.startswith("f1") else H.Problem()
     g = H.Grid(*level_grid(level))
     th = draw_theta(seed, s + 1, level=theta_level)[s]
     t = time.time()
@@ -58,7 +60,7 @@ def _adjoint(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "f1", "all"])
+    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "f1", "f1l3", "all"])
     ap.add_argument("--procs", type=int, default=3)
     a = ap.parse_args()
     jobs = []
@@ -74,6 +76,9 @@ def main():
         w = WORKLOADS["c4_mlmc_levels0to4"]
         jobs += [(_forward, ("c4_l2", 2, w["seed"], 0)), (_forward, ("c4_l3", 3, w["seed"], 0)),
                  (_forward, ("c4_l4coarse", 3, w["seed"], 0, 4))]
+    if a.which in ("f1l3", "all"):
+        w = WORKLOADS["c2_fp64_level3"]
+        jobs += [(_forward, ("f1l3", w["level"], w["seed"], 0))]
     if a.which in ("c3", "all"):
         w = WORKLOADS["c3_mixed_level4"]
         jobs += [(_forward, ("c3", w["level"], w["seed"], 0))]

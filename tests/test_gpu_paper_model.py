@@ -97,6 +97,26 @@ def test_paper_model_level2_batch_against_stored_oracle(hx):
     assert c.min() >= -1e-10 and c.max() <= 1 + 1e-10
 
 
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "oracle_f1l3_s0.npz")), reason="oracle result not stored")
+def test_paper_model_benchmark_batch_against_stored_oracle(hx):
+    """The benchmark's paper-model line in its launch configuration: 256x128 cells, 384 steps
+    over T = 6016 s, all 512 samples of seed 1 in one batch.  Sample 0 against the stored
+    oracle result (tests/golden/make_golden.py f1l3), invariants for every sample."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(1, 512, level=3)
+    r, c, p = _solve(hx, th, P.level_grid(3))
+    assert r.nfailed == 0
+    z = np.load(os.path.join(GOLD, "oracle_f1l3_s0.npz"))
+    assert np.array_equal(z["theta"], th[0])
+    assert np.abs(c[0].ravel() - z["c_T"]).max() <= TOL * np.abs(z["c_T"]).max()
+    assert np.abs(p[0].ravel() - z["p_T"]).max() <= TOL * np.abs(z["p_T"]).max()
+    assert abs(float(r.qoi[0]) - float(z["qoi"])) <= TOL * abs(float(z["qoi"]))
+    st = r.stats.cpu().numpy()
+    bound = defect_bound(th, 6016.0 / 384, PHI_MAX, q_in_amp=0.5)
+    assert (st[:, 2] < bound).all() and (st[:, 3] < bound).all()
+    assert c.min() >= -1e-10 and c.max() <= 1 + 1e-10
+
+
 def test_recharge_pressure_closed_form(hx):
     """Constant density, uniform phi and K (theta = 0) and the periodic recharge: after the
     last step p = -rho0 g y + mu u_in(T) (Lx - x) / K exactly, u_in(T) = 6.6e-5 (1 + 0.5 zeta)
