@@ -310,7 +310,9 @@ def mlmc_adaptive(hx: "Henry", sampler, eps: float, prob=None, opts=None, pilot_
     in x > 1 at T) come from the device estimator.  mlmc_plan picks L and m_l for relative
     accuracy eps (E0 = |mean g_0| of the pilot); the production run draws fresh samples
     (first = pilot_samples) for levels 0..L in one ragged call.  The estimate's bias term uses
-    the fitted alpha unless alpha_bias is given.
+    the fitted alpha unless alpha_bias is given.  Raises HenryError (HENRY_EINVAL) when the
+    pilot's |mean Y_l| do not decay (no positive alpha), since no level count can then be
+    derived from the bias rule.
     """
     import time
     Ym, V, s = [], [], []
