@@ -517,6 +517,23 @@ def test_paper_model_adjoint_matches_central_differences():
     assert min(abs(ga[0]), abs(ga[1]), abs(ga[12])) > 1e-3 * np.abs(ga).max()
 
 
+def test_paper_model_adjoint_taylor_remainder_is_second_order():
+    """|Q(theta + e d) - Q(theta) - e g.d| shrinks by 4 when e halves, along a direction in
+    the three parameters of the paper's model."""
+    pr = H.paper_problem(T=6016.0 * 8 / 48)
+    g = H.Grid(16, 8, 8)
+    th = draw_theta(10, 1)[0]
+    q, ga = A.adjoint_gradient(pr, g, th)
+    d = np.zeros(13)
+    d[[0, 1, 12]] = np.random.default_rng(2).normal(size=3)
+    opts = H.SolveOptions(stagnate=True)
+    rem = []
+    for eps in (1e-2, 5e-3, 2.5e-3):
+        qe = H.solve_sample(pr, g, th + eps * d, opts).qoi
+        rem.append(abs(qe - q - eps * ga @ d))
+    assert 3.0 < rem[0] / rem[1] < 5.0 and 3.0 < rem[1] / rem[2] < 5.0
+
+
 def test_adjoint_taylor_remainder_is_second_order():
     pr = H.Problem()
     g = H.Grid(16, 8, 8)
