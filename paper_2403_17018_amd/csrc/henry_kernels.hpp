@@ -328,8 +328,12 @@ __device__ __forceinline__ void apply_row_f(const T* __restrict__ J, XV&& xv, si
   auto acc = [&](int slot, size_t q, size_t xq, int dir) {
     TA x0, x1;
     xv(xq, dir, x0, x1);
-    const TA b0 = (TA)J[(slot * 4 + 0) * N + q], b1 = (TA)J[(slot * 4 + 1) * N + q];
-    const TA b2 = (TA)J[(slot * 4 + 2) * N + q], b3 = (TA)J[(slot * 4 + 3) * N + q];
+    // each Jacobian entry is read once per kernel: non-temporal loads keep the cache for
+    // the neighbours' x, which other threads read again
+    const TA b0 = (TA)__builtin_nontemporal_load(J + (slot * 4 + 0) * N + q);
+    const TA b1 = (TA)__builtin_nontemporal_load(J + (slot * 4 + 1) * N + q);
+    const TA b2 = (TA)__builtin_nontemporal_load(J + (slot * 4 + 2) * N + q);
+    const TA b3 = (TA)__builtin_nontemporal_load(J + (slot * 4 + 3) * N + q);
     if (TR) {
       a0 += b0 * x0 + b2 * x1;
       a1 += b1 * x0 + b3 * x1;
@@ -399,7 +403,7 @@ __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, Grid2 Gc, int
   const int S = m.S;
   const size_t N = (size_t)G.ncell * S;
   const size_t id = ((size_t)j * G.nx + i) * S + s;
-  T r0 = b[id], r1 = b[N + id];
+  T r0 = __builtin_nontemporal_load(b + id), r1 = __builtin_nontemporal_load(b + N + id);
   if (MODE == 0) {
     T a0, a1;
     apply_row<T, T, TR>(J, x, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
@@ -432,8 +436,9 @@ __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, Grid2 Gc, int
     r0 -= a0;
     r1 -= a1;
   }
-  const T d00 = J[id], d11 = J[3 * N + id];
-  const T d01 = TR ? J[2 * N + id] : J[N + id], d10 = TR ? J[N + id] : J[2 * N + id];
+  const T d00 = __builtin_nontemporal_load(J + id), d11 = __builtin_nontemporal_load(J + 3 * N + id);
+  const T j1 = __builtin_nontemporal_load(J + N + id), j2 = __builtin_nontemporal_load(J + 2 * N + id);
+  const T d01 = TR ? j2 : j1, d10 = TR ? j1 : j2;
   const T det = d00 * d11 - d01 * d10;
   x[id] = (d11 * r0 - d01 * r1) / det;
   x[N + id] = (d00 * r1 - d10 * r0) / det;
