@@ -183,7 +183,8 @@ HENRY_API int henry_sample_fields(henry_ctx* ctx, const henry_problem* prob, hen
 
 /* Solve every batch over its full time horizon: c(0) = 0, implicit Euler, Newton with
  * multigrid-preconditioned BiCGStab (section 2.3).  Batches may differ in grid and
- * sample count (ragged MLMC levels); they are solved concurrently.
+ * sample count (ragged MLMC levels); they are solved concurrently.  With the environment
+ * variable HENRY_PROGRESS=k set, every k-th time step is reported on stderr.
  * Returns 0, a hard error, or the total number of samples with non-zero status. */
 HENRY_API int henry_solve_batch(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts,
                       henry_batch* batches, int nbatches);
