@@ -217,11 +217,12 @@ __global__ void __launch_bounds__(256) k_assemble(Map m, Grid2 G, Phys P, const 
   auto put = [&](int slot, double b0, double b1, double b2, double b3) {
     if (!WRITE_J) return;
     const double v[4] = {b0, b1, b2, b3};
+    // written once here and read by later kernels, never from cache: non-temporal stores
 #pragma unroll
-    for (int e = 0; e < 4; ++e) J[(slot * 4 + e) * N + id] = (TJ)v[e];
+    for (int e = 0; e < 4; ++e) __builtin_nontemporal_store((TJ)v[e], J + (slot * 4 + e) * N + id);
     if (WRITE_J32) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) J32[(slot * 4 + e) * N + id] = (float)v[e];
+      for (int e = 0; e < 4; ++e) __builtin_nontemporal_store((float)v[e], J32 + (slot * 4 + e) * N + id);
     }
   };
   if (WRITE_R) {
