@@ -90,6 +90,7 @@ typedef struct {
   double kappa_kc;        /* Kozeny-Carman scale: K = kappa_kc phi^3 / (1 - phi^2), m^2 [2.088415e-8] */
   double recharge_omega;  /* the left inflow of the step ending at t is u_in (1 + sin(recharge_omega t))
                              (eq. e_recharge_of_param: pi/40 rad/s); 0: constant [0] */
+  double qoi_xmin;        /* the QoI is the salt mass in the cells whose centre lies in x > qoi_xmin, m [1.0] */
 } henry_problem;
 
 /* One mesh level: nx x ny square cells (h = Lx/nx = Ly/ny), nsteps implicit-Euler
@@ -146,7 +147,8 @@ typedef struct {
   const double* theta;   /* device [S][13] */
   double* c_T;           /* device [ny][nx][S] concentration at t = T, or NULL */
   double* p_T;           /* device [ny][nx][S] pressure at t = T, or NULL */
-  double* qoi;           /* device [S] salt mass in x > Lx/2 at t = T: sum c rho(c) h^2, or NULL */
+  double* qoi;           /* device [S] salt mass in x > qoi_xmin at t = T: sum c rho(c) h^2 over the
+                            cells whose centre lies there (section 5, eq. integral_s), or NULL */
   int* status;           /* device [S] henry_sample_status, or NULL */
   double* stats;         /* device [S][4]: Newton iterations, BiCGStab iterations (summed over the
                             run), max relative fluid and salt mass-balance defect; or NULL */
@@ -190,7 +192,7 @@ HENRY_API int henry_solve_batch(henry_ctx* ctx, const henry_problem* prob, const
                       henry_batch* batches, int nbatches);
 
 /* Discrete adjoint of the converged time-stepped solve: dQ/dtheta for
- * Q = salt mass in x > Lx/2 at t = T.  KL fields (field_model 0): xi_1..4, eta_1..8 and
+ * Q = salt mass in x > qoi_xmin at t = T.  KL fields (field_model 0): xi_1..4, eta_1..8 and
  * zeta; the paper's model (field_model 1, section 4): xi_1 = theta[0] and xi_2 = theta[1]
  * through the porosity and the Kozeny-Carman permeability, the other KL slots 0; theta[12]
  * through the inflow, each step's sensitivity weighted by its recharge factor

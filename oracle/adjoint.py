@@ -70,7 +70,7 @@ def qoi_gradient_state(prob, grid, c):
     X, _ = H.cell_centres(prob, grid)
     hx, hy = grid.h(prob)
     dr = prob.rho1 - prob.rho0
-    m = (X > 1.0).ravel()
+    m = (X > prob.qoi_xmin).ravel()
     return np.where(m, (prob.rho0 + 2.0 * dr * c) * hx * hy, 0.0)
 
 

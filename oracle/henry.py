@@ -63,6 +63,7 @@ class Problem:
     field_model: str = "kl"         # "kl": KL fields above; "paper": section 4 porosity and K
     kappa_kc: float = 2.088415e-8   # Kozeny-Carman scale kappa_KC (Table 1), m^2
     recharge_omega: float = 0.0     # left inflow u_in (1 + sin(omega t)); 0: constant in time
+    qoi_xmin: float = 1.0           # QoI region: cells whose centre lies in x > qoi_xmin
 
 
 def paper_problem(**kw) -> Problem:
@@ -362,11 +363,12 @@ def newton_step(disc: Discretisation, p, c, c_old, opts: SolveOptions):
 
 
 def qoi_salt_mass(prob: Problem, grid: Grid, c):
-    """Salt mass in x > 1 (the paper's Q_S integrand c rho(c), section 5, restricted to x > 1)."""
+    """Salt mass in x > qoi_xmin = 1 m (the paper's Q_S integrand c rho(c) of section 5,
+    eq. integral_s, over the cells whose centre lies in that part of the domain)."""
     X, _ = cell_centres(prob, grid)
     hx, hy = grid.h(prob)
     cc = c.reshape(grid.ny, grid.nx)
-    m = X > 1.0
+    m = X > prob.qoi_xmin
     return float(np.sum((cc * rho(prob, cc))[m]) * hx * hy)
 
 
@@ -422,12 +424,21 @@ class SampleResult:
 
 
 def solve_sample(prob: Problem, grid: Grid, theta, opts: SolveOptions | None = None,
-                 keep_states=False, nsteps=None, series=False) -> SampleResult:
-    """Full time loop for one sample (plain Newton + sparse direct LU)."""
+                 keep_states=False, nsteps=None, series=False, start=None) -> SampleResult:
+    """Time loop for one sample (plain Newton + sparse direct LU).
+
+    Runs steps n0 .. n0 + nsteps - 1 (all steps by default) from the state (p, c) after
+    step n0; start = (n0, p, c), or None for the initial state (n0 = 0).
+    """
     opts = opts or SolveOptions()
     phi, K, u_in = sample_fields(prob, grid, theta)
     disc = Discretisation(prob, grid, phi, K, u_in)
-    p, c = initial_state(prob, grid)
+    if start is None:
+        n0 = 0
+        p, c = initial_state(prob, grid)
+    else:
+        n0 = int(start[0])
+        p, c = np.array(start[1], dtype=np.float64), np.array(start[2], dtype=np.float64)
     V = disc.hx * disc.hy
     phif = phi.ravel()
     its, ok = 0, True
@@ -435,7 +446,7 @@ def solve_sample(prob: Problem, grid: Grid, theta, opts: SolveOptions | None = N
     cmin, cmax = 0.0, 0.0
     states = [(p.copy(), c.copy())] if keep_states else None
     ser = [] if series else None
-    for n in range(nsteps if nsteps is not None else grid.nsteps):
+    for n in range(n0, n0 + (nsteps if nsteps is not None else grid.nsteps - n0)):
         c_old = c.copy()
         disc.set_time((n + 1) * disc.tau)    # implicit Euler: boundary data at the new time
         p, c, k, conv = newton_step(disc, p, c, c_old, opts)

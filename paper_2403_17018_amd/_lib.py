@@ -20,7 +20,8 @@ class henry_problem(C.Structure):
                                            "phi_min", "phi_max", "K_mean", "logK_amp", "corr_len", "q_in",
                                            "q_in_amp")] + [
         ("n_kl_phi", C.c_int), ("n_kl_logK", C.c_int), ("right_c_dirichlet", C.c_int), ("c_left", C.c_double),
-        ("field_model", C.c_int), ("kappa_kc", C.c_double), ("recharge_omega", C.c_double)]
+        ("field_model", C.c_int), ("kappa_kc", C.c_double), ("recharge_omega", C.c_double),
+        ("qoi_xmin", C.c_double)]
 
 
 class henry_grid(C.Structure):

@@ -20,7 +20,7 @@ __global__ void k_adj_rhs_final(Map m, Grid2 G, Phys P, const double* __restrict
   const int j = cell / G.nx, i = cell - j * G.nx;
   const double cP = c[id];
   rhs[id] = 0.0;
-  rhs[N + id] = ((i + 0.5) * P.hx > 0.5 * P.Lx) ? -(P.rho0 + 2.0 * P.drho * cP) * P.vol : 0.0;
+  rhs[N + id] = ((i + 0.5) * P.hx > P.qoi_xmin) ? -(P.rho0 + 2.0 * P.drho * cP) * P.vol : 0.0;
 }
 
 // rhs for step n-1: -(dR^n/dc^{n-1})^T lam_n, with dR^p/dc_old = -V phi drho / tau and

@@ -36,6 +36,7 @@ struct Phys {
   double rho0, drho, rho1, mu, g, Dm, c_left;
   double hx, hy, vol, tau, Ly, Lx;
   double uin_fac;   // time factor of the left inflow for the step being solved
+  double qoi_xmin;  // QoI region: cells whose centre lies in x > qoi_xmin
   int right_dir;
 };
 
@@ -1051,7 +1052,7 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_balance(Map m, Phys P, const
   if ((!(mn >= -c_tol) || !(mx <= 1.0 + c_tol)) && status[s] == 0) status[s] = 4;
 }
 
-// Q = sum over cells with centre x > Lx/2 of c rho(c) h^2 (partials)
+// Q = sum over cells with centre x > qoi_xmin of c rho(c) h^2 (partials)
 __global__ void __launch_bounds__(256) k_qoi(Map m, Grid2 G, Phys P, const double* __restrict__ c,
                                              double* __restrict__ part) {
   __shared__ double lds[256];
@@ -1063,7 +1064,7 @@ __global__ void __launch_bounds__(256) k_qoi(Map m, Grid2 G, Phys P, const doubl
     const int cell = (cblk * m.CPT + k) * m.CY + threadIdx.y;
     if (!sv || cell >= G.ncell) continue;
     const int j = cell / G.nx, i = cell - j * G.nx;
-    if ((i + 0.5) * P.hx > 0.5 * P.Lx) {
+    if ((i + 0.5) * P.hx > P.qoi_xmin) {
       const double cP = c[(size_t)cell * m.S + s];
       acc[0] += cP * (P.rho0 + P.drho * cP);
     }

@@ -214,6 +214,7 @@ static Phys make_phys(const henry_problem& pr, int nx, int ny, int nsteps) {
   P.Lx = pr.Lx;
   P.right_dir = pr.right_c_dirichlet;
   P.uin_fac = 1.0;
+  P.qoi_xmin = pr.qoi_xmin;
   return P;
 }
 
@@ -1130,6 +1131,7 @@ static void check_problem(const henry_problem* pr) {
   if (pr->field_model == 1 && !(std::isfinite(pr->kappa_kc) && pr->kappa_kc > 0))
     fail(HENRY_EINVAL, "kappa_kc must be positive and finite");
   if (!std::isfinite(pr->recharge_omega)) fail(HENRY_EINVAL, "recharge_omega must be finite");
+  if (!std::isfinite(pr->qoi_xmin)) fail(HENRY_EINVAL, "qoi_xmin must be finite");
 }
 
 static void check_grid(const henry_problem& pr, henry_grid g) {
@@ -1365,6 +1367,7 @@ void henry_problem_default(henry_problem* p) {
   p->field_model = 0;
   p->kappa_kc = 2.088415e-8;
   p->recharge_omega = 0.0;
+  p->qoi_xmin = 1.0;
 }
 
 void henry_solver_opts_default(henry_solver_opts* o) {

@@ -13,7 +13,13 @@ few sampled realisations instead of re-running the oracle.
 sample 0 of level 3, and the coarse partner of level-4 sample 0 (its theta solved on the
 level-3 grid).
 
-usage: python tests/golden/make_golden.py {c2|c3|c4|c5|f1|f1l3|all} [--procs N]
+"span" adds samples of the level-3, level-4 and adjoint workloads chosen to span theta
+(the extreme recharge zeta, the largest and smallest log-permeability and the largest
+porosity contrast over the grid, the last index of the batch).  Two level-3 samples also
+keep the states after steps 1, 96, 192 and 288: the CPU baseline of the benchmark times
+short oracle windows started from them, so that the whole horizon is represented.
+
+usage: python tests/golden/make_golden.py {c2|c3|c4|c5|f1|f1l3|span|all} [--procs N]
 """
 import argparse
 import os
@@ -30,18 +36,32 @@ from oracle import adjoint as A  # noqa: E402
 from oracle import henry as H  # noqa: E402
 
 
+# level-3 steps after which the "span" samples with states keep (p, c)
+STATE_STEPS = (1, 96, 192, 288)
+# samples of the span set: level 3 (seed 1), level 4 (seed 2), adjoint at level 3 (seed 4)
+SPAN_C2 = (68, 313, 342, 502, 478, 511)     # min zeta, max zeta, max / min ln K contrast, max phi contrast, last
+SPAN_C2_STATES = (68, 511)
+SPAN_C3 = (84, 127)                         # min zeta, last
+SPAN_C5 = (108, 255)                        # min zeta, last
+
+
 def _forward(args):
     name, level, seed, s = args[:4]
-    theta_level = args[4] if len(args) > 4 else level   # a coupled coarse partner: the finer level's theta
+    theta_level = args[4] if len(args) > 4 and args[4] is not None else level   # coarse partner: finer level's theta
+    keep = len(args) > 5 and args[5]
     pr = H.paper_problem() if name.startswith("f1") else H.Problem()
     g = H.Grid(*level_grid(level))
     th = draw_theta(seed, s + 1, level=theta_level)[s]
     t = time.time()
-    r = H.solve_sample(pr, g, th)
+    r = H.solve_sample(pr, g, th, keep_states=keep)
     out = os.path.join(HERE, f"oracle_{name}_s{s}.npz")
+    extra = {}
+    if keep:
+        extra = dict(state_steps=np.array(STATE_STEPS), state_p=np.stack([r.states[k][0] for k in STATE_STEPS]),
+                     state_c=np.stack([r.states[k][1] for k in STATE_STEPS]))
     np.savez_compressed(out, theta=th, c_T=r.c, p_T=r.p, qoi=r.qoi, newton_its=r.newton_its,
                         converged=r.converged, max_salt_defect=r.max_salt_defect,
-                        nx=g.nx, ny=g.ny, nsteps=g.nsteps, seconds=time.time() - t)
+                        nx=g.nx, ny=g.ny, nsteps=g.nsteps, seconds=time.time() - t, **extra)
     print(out, r.qoi, r.newton_its, f"{time.time() - t:.0f}s", flush=True)
 
 
@@ -56,11 +76,12 @@ def _adjoint(args):
     np.savez_compressed(out, theta=th, qoi=q, grad=grad, nx=g.nx, ny=g.ny, nsteps=g.nsteps,
                         seconds=time.time() - t)
     print(out, q, grad, f"{time.time() - t:.0f}s", flush=True)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "f1", "f1l3", "all"])
+    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "f1", "f1l3", "span", "all"])
     ap.add_argument("--procs", type=int, default=3)
     a = ap.parse_args()
     jobs = []
@@ -82,6 +103,12 @@ def main():
     if a.which in ("c3", "all"):
         w = WORKLOADS["c3_mixed_level4"]
         jobs += [(_forward, ("c3", w["level"], w["seed"], 0))]
+    if a.which in ("span", "all"):
+        w2, w3, w5 = WORKLOADS["c2_fp64_level3"], WORKLOADS["c3_mixed_level4"], WORKLOADS["c5_adjoint_level3"]
+        # longest first: the level-4 solves take hours
+        jobs += [(_forward, ("c3", w3["level"], w3["seed"], s)) for s in SPAN_C3]
+        jobs += [(_forward, ("c2", w2["level"], w2["seed"], s, None, s in SPAN_C2_STATES)) for s in SPAN_C2]
+        jobs += [(_adjoint, ("c5", w5["level"], w5["seed"], s)) for s in SPAN_C5]
     import multiprocessing as mp
     with mp.get_context("fork").Pool(a.procs) as pool:
         rs = [pool.apply_async(f, (x,)) for f, x in jobs]

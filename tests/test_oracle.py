@@ -546,3 +546,157 @@ def test_adjoint_taylor_remainder_is_second_order():
         qe = H.solve_sample(pr, g, th + eps * d, opts).qoi
         rem.append(abs(qe - q - eps * ga @ d))
     assert 3.0 < rem[0] / rem[1] < 5.0 and 3.0 < rem[1] / rem[2] < 5.0
+
+
+# ---------------------------------------------------------------- pins of single branches
+def test_qoi_salt_mass_hand_values():
+    """Q = sum over the cells whose centre lies in x > 1 of c rho(c) |cell| (section 5, eq. integral_s:
+    the mass of salt is c rho, without porosity).  The part x > 1 of [0,2]x[-1,0] has area 1 m^2."""
+    pr = H.Problem()
+    for lev in (0, 2):
+        g = H.Grid(*level_grid(lev))
+        n = g.nx * g.ny
+        X, _ = H.cell_centres(pr, g)
+        assert H.qoi_salt_mass(pr, g, np.ones(n)) == pytest.approx(1025.0, rel=1e-13)          # c = 1: rho1 * 1 m^2
+        assert H.qoi_salt_mass(pr, g, np.full(n, 0.5)) == pytest.approx(0.5 * 1012.5, rel=1e-13)
+        assert H.qoi_salt_mass(pr, g, (X < 1.0).astype(float).ravel()) == 0.0                  # salt only in x < 1
+        band = ((X > 1.0) & (X < 1.5)).astype(float).ravel()                                   # 1 <= x <= 1.5
+        assert H.qoi_salt_mass(pr, g, band) == pytest.approx(1025.0 * 0.5, rel=1e-13)
+
+
+def _nystrom_modes(L, b, n):
+    """1-D eigenpairs of exp(-|s - t|/b) on an interval of length L by the midpoint-rule Nystrom
+    method (numpy eigh; independent of the closed-form roots): eigenvalues and eigenfunction
+    values at the n midpoints, L2-normalised, sign fixed as the analytic modes fix it (even modes
+    positive at the centre, odd modes positive just right of it).  Returns [(lam, f, parity)]."""
+    h = L / n
+    s = (np.arange(n) + 0.5) * h
+    lam, V = np.linalg.eigh(np.exp(-np.abs(s[:, None] - s[None, :]) / b) * h)
+    out = []
+    for k in np.argsort(lam)[::-1][:12]:
+        f = V[:, k] / np.sqrt(h)
+        even = np.abs(f - f[::-1]).max() < 1e-6 * np.abs(f).max()
+        if f[n // 2] < 0:            # centre value (even) or first value right of the centre (odd)
+            f = -f
+        out.append((lam[k], f, 0 if even else 1))
+    return out
+
+
+def test_kl_fields_single_coefficients_against_nystrom_modes():
+    """theta with one non-zero slot: xi_k = 1 must give phi = 0.35 (1 + 0.2 sqrt(lam_k) e_k), eta_k = 1
+    ln K = ln K_hat + 0.5 sqrt(lam_k) e_k, zeta = 1 the inflow 6.6e-5 * 1.1; lam_k, e_k from an
+    independent Nystrom discretisation of the separable exponential covariance (2-D pairs sorted by
+    lam, descending), at the cell centres of a 1024 x 512 grid (the midpoint nodes).  This pins the
+    slot -> mode map, the sqrt(lam) weights and the two amplitudes."""
+    pr = H.Problem()
+    g = H.Grid(1024, 512, 1)
+    mx = _nystrom_modes(2.0, 0.5, 1024)
+    my = _nystrom_modes(1.0, 0.5, 512)
+    pairs = sorted(((a[0] * c[0], ix, iy) for ix, a in enumerate(mx) for iy, c in enumerate(my)),
+                   key=lambda t: (-t[0], t[1]))[:8]
+    E = [np.outer(my[iy][1], mx[ix][1]) for _, ix, iy in pairs]        # [ny, nx], rows bottom to top
+    lam = np.array([p[0] for p in pairs])
+    assert lam == pytest.approx([0.445499, 0.248790, 0.151538, 0.133054, 0.084627, 0.076935, 0.060876,
+                                 0.048623], rel=3e-4)
+    for k in range(4):
+        th = np.zeros(13)
+        th[k] = 1.0
+        phi, K, u = H.sample_fields(pr, g, th)
+        want = 0.35 * (1.0 + 0.2 * np.sqrt(lam[k]) * E[k])
+        assert np.abs(phi - want).max() <= 2e-4 * np.abs(want - 0.35).max(), k
+        assert np.abs(K / pr.K_mean - 1.0).max() < 1e-15 and u == pr.q_in     # exp(ln K) rounds
+    for k in range(8):
+        th = np.zeros(13)
+        th[4 + k] = 1.0
+        phi, K, u = H.sample_fields(pr, g, th)
+        want = 0.5 * np.sqrt(lam[k]) * E[k]
+        assert np.abs(np.log(K / pr.K_mean) - want).max() <= 2e-4 * np.abs(want).max(), k
+        assert np.all(phi == 0.35) and u == pr.q_in
+    th = np.zeros(13)
+    th[12] = 1.0
+    phi, K, u = H.sample_fields(pr, g, th)
+    assert u == pytest.approx(6.6e-5 * 1.1, rel=1e-15) and np.all(phi == 0.35)
+    # all slots at once: superposition of the single-mode fields
+    th = draw_theta(11, 1)[0]
+    phi, K, u = H.sample_fields(pr, g, th)
+    sp = sum(np.sqrt(lam[k]) * th[k] * E[k] for k in range(4))
+    sk = sum(np.sqrt(lam[k]) * th[4 + k] * E[k] for k in range(8))
+    assert np.abs(phi - 0.35 * (1 + 0.2 * sp)).max() <= 1e-3 * np.abs(0.35 * 0.2 * sp).max()
+    assert np.abs(np.log(K / pr.K_mean) - 0.5 * sk).max() <= 1e-3 * np.abs(0.5 * sk).max()
+
+
+def test_mlmc_bias_and_rmse_on_a_two_level_hand_example():
+    """eqs. A, goal_variance, MSE and the bias estimate |mean Y_L| / (2^alpha - 1), by hand:
+    Y_0 = (1, 2, 3): mean 2, V_0 = 1; Y_1 = (5, 7) - (4, 5) = (1, 2): mean 1.5, V_1 = 0.5.
+    mean = 3.5, Var = 1/3 + 0.5/2 = 7/12; alpha = 1: bias 1.5, rmse = sqrt(7/12 + 2.25);
+    alpha = 2: bias 0.5, rmse = sqrt(7/12 + 0.25)."""
+    e = M.estimate([np.array([1.0, 2.0, 3.0]), np.array([5.0, 7.0])], [None, np.array([4.0, 5.0])], alpha=1.0)
+    assert e["mean"] == pytest.approx(3.5, rel=1e-15)
+    assert e["V"] == pytest.approx([1.0, 0.5], rel=1e-15)
+    assert e["var_of_estimator"] == pytest.approx(7.0 / 12.0, rel=1e-15)
+    assert e["bias"] == pytest.approx(1.5, rel=1e-15)
+    assert e["rmse"] == pytest.approx(math.sqrt(7.0 / 12.0 + 2.25), rel=1e-15)
+    e = M.estimate([np.array([1.0, 2.0, 3.0]), np.array([5.0, 7.0])], [None, np.array([4.0, 5.0])], alpha=2.0)
+    assert e["bias"] == pytest.approx(0.5, rel=1e-15)
+    assert e["rmse"] == pytest.approx(math.sqrt(7.0 / 12.0 + 0.25), rel=1e-15)
+
+
+def test_residual_by_hand_on_a_three_by_two_grid():
+    """Residual of one implicit-Euler step on 3 x 2 unit cells ([0,3]x[-2,0], tau = 100 s), evaluated
+    face by face with scalar arithmetic from the discrete balance laws (section 2.1: fluid and salt
+    mass, Darcy with rho(c) g on vertical faces, D = phi Dm).  The state hits every branch: the left
+    inflow with its Dirichlet diffusion, a right-side inflow cell (rho1 and c = 1 enter) and a
+    right-side outflow cell, upwinding in both directions on east and north faces, gravity on the
+    north faces, harmonic K."""
+    pr = H.Problem(Lx=3.0, Ly=2.0, T=1000.0)
+    g = H.Grid(3, 2, 10)
+    rho0, dr, mu, grav, Dm, tau = 1000.0, 25.0, 1e-3, 9.81, pr.Dm, 100.0
+    phi = np.array([[0.30, 0.35, 0.40], [0.25, 0.30, 0.45]])           # [j, i], j = 0 is the bottom row
+    K = np.array([[1e-9, 2e-9, 1e-9], [3e-9, 1e-9, 2e-9]])
+    u_in = 1.2e-4
+    y = np.array([-1.5, -0.5])
+    pb = -1025.0 * grav * y                                             # right boundary pressure per row
+    c = np.array([[0.1, 0.4, 0.8], [0.2, 0.5, 0.9]])
+    c_old = np.array([[0.0, 0.3, 0.7], [0.1, 0.6, 0.8]])
+    # bottom row: p falls eastward except into the right inflow cell; top row rises at the end
+    p = np.array([[pb[0] + 30.0, pb[0] + 10.0, pb[0] - 20.0],
+                  [pb[1] - 80.0, pb[1] - 60.0, pb[1] + 40.0]])
+    R = np.zeros((2, 2, 3))                                             # [p or c][j][i]
+    rho = lambda v: rho0 + dr * v
+    branches = set()
+    for j in range(2):
+        for i in range(3):
+            R[0, j, i] += phi[j, i] * (rho(c[j, i]) - rho(c_old[j, i])) / tau
+            R[1, j, i] += phi[j, i] * (rho(c[j, i]) * c[j, i] - rho(c_old[j, i]) * c_old[j, i]) / tau
+    faces = [((j, i), (j, i + 1), False) for j in range(2) for i in range(2)] + \
+            [((0, i), (1, i), True) for i in range(3)]
+    for P, Q, north in faces:
+        Kf = 2.0 * K[P] * K[Q] / (K[P] + K[Q])
+        rf = 0.5 * (rho(c[P]) + rho(c[Q]))
+        u = -(Kf / mu) * ((p[Q] - p[P]) / 1.0 + (rf * grav if north else 0.0))
+        F = rf * u * 1.0
+        cup = c[P] if F >= 0 else c[Q]
+        branches.add(("north" if north else "east", F >= 0))
+        G = F * cup - rf * 0.5 * (phi[P] + phi[Q]) * Dm * (c[Q] - c[P])
+        R[0][P] += F; R[0][Q] -= F
+        R[1][P] += G; R[1][Q] -= G
+    for j in range(2):
+        F = -rho0 * u_in * 1.0                                          # c_left = 0: fresh water enters
+        R[0, j, 0] += F
+        R[1, j, 0] += 2.0 * rho(c[j, 0]) * phi[j, 0] * Dm * (c[j, 0] - 0.0) / 1.0
+        u = -(K[j, 2] / mu) * (pb[j] - p[j, 2]) / 0.5
+        if u < 0:                                                       # seawater enters at rho1, c = 1
+            branches.add(("right", "in"))
+            R[0, j, 2] += 1025.0 * u
+            R[1, j, 2] += 1025.0 * u * 1.0
+        else:
+            branches.add(("right", "out"))
+            R[0, j, 2] += rho(c[j, 2]) * u
+            R[1, j, 2] += rho(c[j, 2]) * u * c[j, 2]
+    assert branches >= {("east", True), ("east", False), ("north", True), ("north", False),
+                        ("right", "in"), ("right", "out")}
+    d = H.Discretisation(pr, g, phi, K, u_in)
+    Rp, Rc = d.residual(p.ravel(), c.ravel(), c_old.ravel())
+    scale = np.abs(R).max()
+    assert np.abs(Rp - R[0].ravel()).max() <= 1e-13 * scale
+    assert np.abs(Rc - R[1].ravel()).max() <= 1e-13 * scale
