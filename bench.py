@@ -8,6 +8,8 @@ Default workload: MLMC level 3 (256x128 cells, 384 steps, 512 samples, seed 1), 
 The metric is sample-timesteps/s = samples * time steps / wall time.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c1|c4|c5|qmc] [--model kl|paper]
+  The default run (c2) adds an "extra" object with the rest of the metric: level 3 and level 4
+  with the FP32 multigrid, and the MLMC hierarchy's wall time to RMSE (FP64 and FP32 multigrid).
   c4: MLMC wall time to RMSE for levels 0..4 in one ragged call; c5: discrete adjoint
   --model paper: the paper's own stochastic model (section 4; T = 6016 s) on the c1-c3 grids
   qmc: that model over 600 Halton points (section 5) at --level (default 3)
@@ -18,7 +20,6 @@ import json
 import os
 import subprocess
 import sys
-import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -38,34 +39,105 @@ KERNEL_NAME = dict(gs="k_gs_colour", spmv="k_spmv_dot", assemble="k_assemble", r
                    prolong="k_gs_colour (fused prolongation)")
 
 
+def host_cores():
+    """Host threads the CPU baseline uses: the CPUs this process may run on, at most 16 (the
+    host CPU share of one GPU on the benchmark machines), and what os.cpu_count() reports."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return min(16, avail), os.cpu_count() or 1
+
+
+# oracle states stored along the level-3 horizon (tests/golden/make_golden.py span): the CPU
+# baseline times short windows started from them so that every part of the horizon counts
+WINDOW_SAMPLES = (68, 511)
+WINDOW_STEPS = 4
+
+
 def cpu_baseline(level, seed, nsamples_avail, steps_total, model="kl"):
-    """Oracle on the host cores: `procs` samples of the same workload for the first few steps."""
-    procs = min(16, os.cpu_count() or 1)
+    """The oracle (SuperLU Newton, one sample per process) on the host cores.
+
+    Level 3 with the KL model: windows of WINDOW_STEPS steps started from the oracle's own
+    states after steps 1, 96, 192 and 288 of two stored samples, plus the first step from the
+    initial state; each window stands for the quarter of the horizon it starts, so a sample's
+    full-horizon time is t_first + sum_q t_q / WINDOW_STEPS * (steps of quarter q).  The jobs
+    are repeated cyclically over all `procs` processes so every core is loaded while they are
+    timed.  Other workloads: level <= 1 runs the full horizon for `procs` samples; otherwise the
+    first steps only (labelled as understating the rate)."""
+    procs, ncpu = host_cores()
     nx, ny, _ = level_grid(level)
-    nsteps_run = 10 if level >= 3 else min(steps_total, 48)
+    gold = [os.path.join(ROOT, "tests", "golden", f"oracle_c2_s{s}.npz") for s in WINDOW_SAMPLES]
+    windows = level == 3 and model == "kl" and seed == 1 and all(os.path.exists(f) for f in gold)
     code = f"""
-import sys, time, numpy as np
+import sys, time, json, numpy as np
 sys.path.insert(0, {ROOT!r})
 from henry_inputs import draw_theta
 from oracle import henry as H
 import multiprocessing as mp
-th = draw_theta({seed}, {min(procs, nsamples_avail)}, level={level})
 pr = {"H.paper_problem()" if model == "paper" else "H.Problem()"}; g = H.Grid({nx}, {ny}, {steps_total})
-def one(t):
-    return H.solve_sample(pr, g, t, nsteps={nsteps_run}).newton_its
-t0 = time.time()
+mode = {"'windows'" if windows else ("'full'" if level <= 1 else "'first'")}
+jobs = []
+if mode == 'windows':
+    for f in {gold!r}:
+        z = np.load(f)
+        jobs.append((z['theta'], None, 1))
+        for k, n0 in enumerate(z['state_steps']):
+            jobs.append((z['theta'], (int(n0), z['state_p'][k], z['state_c'][k]), {WINDOW_STEPS}))
+else:
+    th = draw_theta({seed}, {min(procs, nsamples_avail)}, level={level})
+    n = {steps_total} if mode == 'full' else 10
+    jobs = [(t, None, n) for t in th]
+def one(j):
+    th, start, n = j
+    t0 = time.perf_counter()
+    r = H.solve_sample(pr, g, th, nsteps=n, start=start)
+    return time.perf_counter() - t0, r.newton_its
+work = [jobs[i % len(jobs)] for i in range(max({procs}, len(jobs)))]
+t0 = time.perf_counter()
 with mp.get_context('fork').Pool({procs}) as p:
-    its = p.map(one, list(th))
-print(time.time() - t0, sum(its))
+    out = p.map(one, work)
+print(json.dumps(dict(mode=mode, njobs=len(jobs), wall=time.perf_counter() - t0, out=out)))
 """
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, check=True)
-    wall, its = out.stdout.split()
-    ns = min(procs, nsamples_avail)
-    return {"value": ns * nsteps_run / float(wall), "unit": "sample-timesteps/s", "cores": procs, "kind": "oracle",
-            "sample": f"{ns} samples x first {nsteps_run} of {steps_total} steps on {nx}x{ny} cells, one sample per "
-                      f"process (SuperLU Newton, {int(its)} Newton iterations); the first steps are the costliest, "
-                      f"so this understates the full-horizon rate"}
+    r = json.loads(subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                                  check=True).stdout)
+    out = r["out"]
+    if r["mode"] == "windows":
+        nj = r["njobs"]
+        t = [sum(o[0] for o in out[i::nj]) / len(out[i::nj]) for i in range(nj)]   # mean over repeats
+        per_sample = []
+        starts = [1, 96, 192, 288, steps_total]
+        for k in range(len(WINDOW_SAMPLES)):
+            tk = t[5 * k:5 * k + 5]
+            per_sample.append(tk[0] + sum(tk[1 + q] / WINDOW_STEPS * (starts[q + 1] - starts[q]) for q in range(4)))
+        secs = sum(per_sample) / len(per_sample)
+        value = procs * steps_total / secs
+        sample = (f"{len(WINDOW_SAMPLES)} samples of the same workload on {nx}x{ny} cells: the first step and "
+                  f"{WINDOW_STEPS}-step windows from the oracle's states after steps 1, 96, 192 and 288, each window "
+                  f"standing for its quarter of the {steps_total}-step horizon ({len(out)} timed jobs, "
+                  f"{r['wall']:.1f} s wall); full-horizon estimate {secs:.0f} s per sample per process, "
+                  f"{procs} processes at once (os.cpu_count() = {ncpu})")
+    elif r["mode"] == "full":
+        ns = len(out)
+        value = ns * steps_total / r["wall"]
+        sample = f"{ns} samples x all {steps_total} steps on {nx}x{ny} cells, one sample per process"
+    else:
+        ns = len(out)
+        value = ns * 10 / r["wall"]
+        sample = (f"{ns} samples x first 10 of {steps_total} steps on {nx}x{ny} cells, one sample per process; the "
+                  f"first steps are the costliest, so this understates the full-horizon rate")
+    return {"value": value, "unit": "sample-timesteps/s", "cores": procs, "kind": "oracle", "sample": sample}
+
+
+def solver_config(o):
+    """The solver settings that ran, for the config label."""
+    return {"coarse_grid": f"{o.coarse_nx}x{o.coarse_ny}",
+            "coarse_solver": "dense LU with partial pivoting" if getattr(o, "coarse_solver", 0) == 1
+            else "block-banded LU without pivoting",
+            "smoother": f"red-black 2x2-block Gauss-Seidel, {o.nu_pre} pre + {o.nu_post} post sweeps",
+            "cycle": "V" if o.mg_cycle == 1 else "W",
+            "krylov": f"right-preconditioned BiCGStab, forcing term {o.krylov_rtol:g}",
+            "newton": f"tolerance {o.newton_tol:g}, first guess: extrapolation order {o.newton_extrapolate}, "
+                      f"predictive stop {'on' if o.newton_predict > 0 else 'off'}, chord steps below "
+                      f"{o.newton_jac_reuse:g}"}
 
 
 def pmc_traffic(kernel, prec, workload, model):
@@ -240,6 +312,82 @@ def bench_adaptive(args):
     print(json.dumps(out))
 
 
+def measure_batch(hx, theta, g, prob, opts, warmup, steps, workload, model):
+    """Time `steps` whole-batch solves (plus the estimator over the batch) after `warmup`
+    untimed ones; the dominant kernel class and its roofline from HIP events on the library's
+    stream during the timed region."""
+    import torch
+    prec = opts.mg_precision
+    S = theta.shape[0]
+
+    def step():
+        r = hx.solve(theta, g, prob, opts=opts, want_c=True)
+        est = hx.mlmc_estimate([g], [r.qoi], [None], [r.c_T], [None])
+        return r, est
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    hx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r, est = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = hx.profile_read()
+    hx.profile(False)
+    dt = (t1 - t0) / steps
+    st = r.stats.cpu()
+    cls = max(BYTES[prec], key=lambda k: prof[k][2])      # dominant kernel class by summed time
+    n, units, ms = prof[cls]
+    per_launch_bytes = units / n * BYTES[prec][cls]
+    achieved = per_launch_bytes / (ms / n * 1e-3) / 1e9
+    return dict(value=S * g.nsteps / dt, ms_per_step=dt * 1e3,
+                roofline={"bound": "hbm", "kernel": KERNEL_NAME[cls], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                          "traffic": pmc_traffic(KERNEL_NAME[cls], prec, workload, model),
+                          "avg_launch_us": ms / n * 1e3, "launches": n,
+                          "algorithmic_bytes_per_launch": per_launch_bytes},
+                kernel_classes_ms={k: round(v[2], 3) for k, v in prof.items()},
+                newton_its_per_step=float(st[:, 0].mean()) / g.nsteps,
+                krylov_its_per_newton=float(st[:, 1].sum() / st[:, 0].sum()),
+                max_salt_defect=float(st[:, 3].max()), failed_samples=r.nfailed, mlmc_mean_qoi=est["mean"])
+
+
+def extra_lines(hx, P, args):
+    """The rest of the metric at fixed small repeat counts (1 untimed + 1 timed run each, so the
+    default run stays within minutes): level 3 with the FP32 multigrid, level 4 with the FP32
+    multigrid (its workload), and the full MLMC hierarchy's wall time to RMSE with FP64 and
+    FP32 multigrid."""
+    import torch
+    out = {}
+    for key, name, prec in (("c2_fp32mg", "c2_fp64_level3", 32), ("c3_fp32mg_level4", "c3_mixed_level4", 32)):
+        w = WORKLOADS[name]
+        g = P.grid(*level_grid(w["level"]))
+        th = torch.from_numpy(draw_theta(w["seed"], w["nsamples"], level=w["level"])).cuda()
+        o = P.solver_opts(mg_precision=prec)
+        m = measure_batch(hx, th, g, P.problem(), o, 1, 1, name, "kl")
+        out[key] = {"workload": f"{name}: {g.nx}x{g.ny} cells, {g.nsteps} steps, {w['nsamples']} samples "
+                                f"(seed {w['seed']}), FP32 multigrid in FP64 BiCGStab/Newton",
+                    "unit": "sample-timesteps/s", **m}
+        del th
+    w = WORKLOADS["c4_mlmc_levels0to4"]
+    thetas = [torch.from_numpy(draw_theta(w["seed"], k, level=l)).cuda() for l, k in zip(w["levels"], w["nsamples"])]
+    for prec in (64, 32):
+        o = P.solver_opts(mg_precision=prec, use_graphs=1)
+        P.mlmc_run(hx, thetas, w["levels"], opts=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        est = P.mlmc_run(hx, thetas, w["levels"], opts=o)
+        torch.cuda.synchronize()
+        out[f"c4_mlmc_fp{prec}" if prec == 64 else "c4_mlmc_fp32mg"] = {
+            "workload": "c4_mlmc_levels0to4: levels 0..4 (32x16..512x256 cells, 48..768 steps), "
+                        "4096/1024/256/64/16 samples with coupled coarse partners (seed 3), one ragged call",
+            "metric": "MLMC wall time to RMSE", "unit": "s", "value": time.perf_counter() - t0,
+            "rmse": est["rmse"], "mlmc_mean_qoi": est["mean"], "failed_samples": est["nfailed"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +399,7 @@ def main():
     ap.add_argument("--graphs", type=int, default=None, help="capture BiCGStab iterations in hipGraphs (c4 default 1)")
     ap.add_argument("--precision", type=int, default=None, help="multigrid precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra metric lines of the default run")
     ap.add_argument("--model", default="kl", choices=["kl", "paper"],
                     help="input model: KL fields (the workloads) or the paper's section-4 model")
     args = ap.parse_args()
@@ -282,40 +431,16 @@ def main():
     g = P.grid(nx, ny, nsteps)
     opts = P.solver_opts(mg_precision=prec)
     prob = P.paper_problem() if args.model == "paper" else P.problem()
-
-    def step():
-        r = hx.solve(theta, g, prob, opts=opts, want_c=True)
-        est = hx.mlmc_estimate([g], [r.qoi], [None], [r.c_T], [None])
-        return r, est
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    hx.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r, est = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = hx.profile_read()
-    hx.profile(False)
-    dt = (t1 - t0) / args.steps
-    nfailed = r.nfailed
-    st = r.stats.cpu()
-    # dominant kernel class by summed time
-    cls = max(BYTES[prec], key=lambda k: prof[k][2])
-    n, units, ms = prof[cls]
-    per_launch_bytes = units / n * BYTES[prec][cls]
-    achieved = per_launch_bytes / (ms / n * 1e-3) / 1e9
-    traffic = pmc_traffic(KERNEL_NAME[cls], prec, name, args.model)
+    m = measure_batch(hx, theta, g, prob, opts, args.warmup, args.steps, name, args.model)
+    del theta
     out = {
         "metric": "sample-timesteps/s",
-        "value": S * nsteps / dt,
+        "value": m["value"],
         "unit": "sample-timesteps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt * 1e3,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -326,18 +451,14 @@ def main():
                                + (", the paper's section-4 porosity/Kozeny-Carman/recharge model, T = 6016 s"
                                   if args.model == "paper" else ""),
                    "samples": S, "cells": nx * ny, "time_steps": nsteps, "mg_precision": prec,
-                   "parallelism": "samples batched on one GPU"},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_NAME[cls], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_us": ms / n * 1e3, "launches": n, "algorithmic_bytes_per_launch": per_launch_bytes},
-        "kernel_classes_ms": {k: round(v[2], 3) for k, v in prof.items()},
-        "newton_its_per_step": float(st[:, 0].mean()) / nsteps,
-        "krylov_its_per_newton": float(st[:, 1].sum() / st[:, 0].sum()),
-        "max_salt_defect": float(st[:, 3].max()),
-        "failed_samples": nfailed,
-        "mlmc_mean_qoi": est["mean"],
+                   "solver": solver_config(opts), "parallelism": "samples batched on one GPU"},
+        "roofline": m["roofline"],
+        **{k: m[k] for k in ("kernel_classes_ms", "newton_its_per_step", "krylov_its_per_newton", "max_salt_defect",
+                             "failed_samples", "mlmc_mean_qoi")},
         "cpu_baseline": cpu,
     }
+    if args.workload == "c2" and args.model == "kl" and args.precision is None and not args.no_extra:
+        out["extra"] = extra_lines(hx, P, args)
     print(json.dumps(out))
 
 

@@ -103,7 +103,7 @@ typedef struct {
 typedef struct {
   int mg_precision;      /* 64: FP64 multigrid; 32: FP32 multigrid preconditioner inside the
                             FP64 BiCGStab/Newton (iterative refinement) [64] */
-  int coarse_nx, coarse_ny; /* coarsest multigrid grid, solved by a banded block LU [8, 4] */
+  int coarse_nx, coarse_ny; /* coarsest multigrid grid, solved directly (coarse_solver) [8, 4] */
   int nu_pre, nu_post;   /* red-black block Gauss-Seidel sweeps [1, 2] */
   double newton_tol;     /* converged when |dc|_inf <= tol and |dp|_inf <= tol*rho0*g*Ly [1e-9] */
   double newton_dc_max;  /* each update is scaled by min(1, dc_max/|dc|_inf) [2.0] */
@@ -138,6 +138,12 @@ typedef struct {
                                  0: lambda = 0.  1: lambda^{n+1} of the step solved before.
                                  2: 2 lambda^{n+1} - lambda^{n+2}.  The tolerance
                                  krylov_rtol_adjoint stays relative to the right-hand side [2] */
+  int coarse_solver;          /* direct solver of the coarsest grid (Gaussian elimination, section 2.3).
+                                 0: block-banded LU without pivoting (cells ordered j fastest, block
+                                 bandwidth coarse ny), one wavefront per sample [0].  1: dense LU with
+                                 partial pivoting of the 2*cells x 2*cells matrix, one workgroup per
+                                 sample, trailing updates on the matrix cores; needs 2*cells divisible
+                                 by 16 and its 16-column panel in LDS (32x16 cells at most in FP64) */
 } henry_solver_opts;
 
 /* One batch of S independent samples on one grid (ragged batches: several per call). */
@@ -270,6 +276,43 @@ HENRY_API int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, 
 HENRY_API int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts* opts, henry_grid grid,
                              int S, const double* theta, double* best_ms);
 
+/* Kernel-level entry points: single launches of the solve's own kernels, for tests and
+ * diagnostics.  Work runs on the context's stream; henry_assemble, henry_jacobian_apply and
+ * henry_coarse_solve synchronise it before returning (their workspace is the context's).
+ *
+ * henry_assemble: the residual and analytic Jacobian of the implicit-Euler step `step`
+ * (0-based; the step ends at t = (step + 1) T / nsteps, where the recharge factor is taken) at
+ * the state (p, c), previous state c_old, fields from theta (section 2.1 balance laws,
+ * eqs. e_cont_eq, e_tran_eq, e_Darcy_vel, e_lin_density, e_mol_diff with the boundary
+ * conditions of section 2.1; finite volumes and implicit Euler of section 2.3).
+ *   theta: device [S][13]; p, c, c_old: device [ny][nx][S];
+ *   R: device [2][ny][nx][S] (fluid, salt mass residual, kg/m per step as the solve uses it);
+ *   J: device [20][ny][nx][S]: 2x2 blocks d R^a_P / d u^b_Q stored at [blk*4 + a*2 + b] with
+ *   blk = 0 centre (Q = P), 1 west, 2 east, 3 south, 4 north neighbour (0 where it does not
+ *   exist); a, b = 0 pressure, 1 concentration. */
+HENRY_API int henry_assemble(henry_ctx* ctx, const henry_problem* prob, henry_grid grid, int S, const double* theta,
+                             const double* p, const double* c, const double* c_old, int step, double* R, double* J);
+
+/* y = J x (transpose = 0) or J^T x (transpose = 1) for the block operator J in the layout of
+ * henry_assemble: the Newton systems of section 2.3 and their transposes (discrete adjoint).
+ * x, y: device [2][ny][nx][S], distinct. */
+HENRY_API int henry_jacobian_apply(henry_ctx* ctx, henry_grid grid, int S, const double* J, const double* x, double* y,
+                                   int transpose);
+
+/* One colour of a red-black 2x2-block Gauss-Seidel sweep (the multigrid smoother): for every
+ * cell with (i + j) % 2 == colour, x_P = D_P^{-1} (b_P - sum over neighbours A_PQ x_Q), with
+ * J^T's blocks when transpose = 1.  J as in henry_assemble; b, x: device [2][ny][nx][S]. */
+HENRY_API int henry_gs_pass(henry_ctx* ctx, henry_grid grid, int S, const double* J, const double* b, double* x,
+                            int colour, int transpose);
+
+/* Direct solve of a block operator on a coarse grid (Gaussian elimination, section 2.3):
+ * x = J^{-1} b (or J^{-T} b) with solver 0 (block-banded LU without pivoting) or 1 (dense LU
+ * with partial pivoting), factored and solved in `precision` 64 or 32 (J and b are rounded to
+ * FP32 first in the latter).  J: device FP64 [20][ny][nx][S] as in henry_assemble; b, x:
+ * device FP64 [2][ny][nx][S].  HENRY_EUNSUPPORTED when the grid does not fit the solver. */
+HENRY_API int henry_coarse_solve(henry_ctx* ctx, int solver, int precision, henry_grid coarse, int S, const double* J,
+                                 const double* b, double* x, int transpose);
+
 /* Kernel-class timing on the context's stream (instrumentation for benchmarks).
  * henry_profile(ctx, 1) resets the counters and brackets every later launch of the
  * classes below with HIP events (launches on whole batches only: the compacted
@@ -286,7 +329,9 @@ enum henry_prof_class {
   HENRY_PROF_PROLONG = 4,     /* prolongation + correction onto the fine grid */
   HENRY_PROF_BAND_FACTOR = 5, /* coarse banded LU factorisation */
   HENRY_PROF_BAND_SOLVE = 6,  /* coarse banded triangular solves */
-  HENRY_PROF_NCLASS = 7
+  HENRY_PROF_DENSE_FACTOR = 7,/* dense coarse LU: matrix expansion and pivoted factorisation (units: samples) */
+  HENRY_PROF_DENSE_SOLVE = 8, /* dense coarse triangular solves (units: samples) */
+  HENRY_PROF_NCLASS = 9
 };
 HENRY_API int henry_profile(henry_ctx* ctx, int enable);
 HENRY_API int henry_profile_read(henry_ctx* ctx, int cls, long long* launches, long long* units, double* total_ms);

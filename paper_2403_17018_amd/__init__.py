@@ -17,7 +17,7 @@ from . import _lib as L
 from ._lib import henry_batch, henry_grid, henry_problem, henry_solver_opts
 
 __all__ = ["Henry", "HenryError", "problem", "paper_problem", "solver_opts", "grid", "level_grid", "optimal_samples",
-           "SolveResult", "mlmc_run", "mlmc_plan", "mlmc_adaptive"]
+           "SolveResult", "mlmc_run", "mlmc_plan", "mlmc_adaptive", "SaltMassQoI", "salt_mass_qoi"]
 
 STATUS = {0: "ok", 1: "newton", 2: "krylov", 3: "nonfinite", 4: "range"}
 
@@ -176,11 +176,13 @@ class Henry:
                                                        checkpoint_every, _ptr(q), _ptr(gr), _ptr(st)))
         return q, gr, st, rc
 
-    def mlmc_estimate(self, grids, g_fine, g_coarse, c_fine=None, c_coarse=None, alpha: float = 1.0):
+    def mlmc_estimate(self, grids, g_fine, g_coarse, c_fine=None, c_coarse=None, alpha: float = 1.0,
+                      out=None):
         """Telescoping MLMC estimate over levels 0..L (device reductions).
 
         g_fine[l], g_coarse[l] (None for l = 0): float64 CUDA tensors [m_l];
         c_fine[l]: [ny_l, nx_l, m_l]; c_coarse[l]: [ny_{l-1}, nx_{l-1}, m_l] (None for l = 0).
+        out: optional (mean_field, var_field) tensors [ny_L, nx_L] to write instead of new ones.
         """
         Lv = len(g_fine) - 1
         m = (C.c_int * (Lv + 1))(*[int(t.numel()) for t in g_fine])
@@ -194,12 +196,15 @@ class Henry:
             cf = (vp * (Lv + 1))(*[t.data_ptr() for t in c_fine])
             cc = (vp * (Lv + 1))(*[0 if t is None else t.data_ptr() for t in c_coarse])
             gL = grids[-1]
-            mean_f = torch.empty((gL.ny, gL.nx), dtype=torch.float64, device=self.device)
-            var_f = torch.empty_like(mean_f)
+            if out is not None:
+                mean_f, var_f = out
+            else:
+                mean_f = torch.empty((gL.ny, gL.nx), dtype=torch.float64, device=self.device)
+                var_f = torch.empty_like(mean_f)
         mean, var, rmse = C.c_double(), C.c_double(), C.c_double()
         V = (C.c_double * (Lv + 1))()
-        self._check(self._lib.mlmc_estimate(self._h, Lv, m, gr, gf, gc, cf, cc, alpha, C.byref(mean), C.byref(var),
-                                            C.byref(rmse), V, _ptr(mean_f), _ptr(var_f)))
+        self._check(self._lib.mlmc_estimate(self._h, Lv, m, gr, gf, gc, cf, cc, alpha, C.byref(mean), C.byref(var), C.byref(rmse), V,
+                       _ptr(mean_f), _ptr(var_f)))
         return dict(mean=mean.value, var_of_estimator=var.value, rmse=rmse.value, V=list(V), mean_field=mean_f,
                     var_field=var_f)
 
@@ -227,6 +232,52 @@ class Henry:
                                                    _ptr(out["var_of_estimator"]), _ptr(out["Ymean"]), _ptr(out["V"])))
         return out
 
+    # kernel-level calls (single launches of the solve's kernels; tests and diagnostics)
+    def _f64(self, t, shape, name):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+                and t.device == self.device and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {tuple(shape)}")
+
+    def assemble(self, theta, g: henry_grid, p, c, c_old, step: int, prob=None):
+        """(R [2, ny, nx, S], J [20, ny, nx, S]) of implicit-Euler step `step` at (p, c)."""
+        _check_theta(theta, self.device)
+        S = theta.shape[0]
+        for t, nm in ((p, "p"), (c, "c"), (c_old, "c_old")):
+            self._f64(t, (g.ny, g.nx, S), nm)
+        kw = dict(dtype=torch.float64, device=self.device)
+        R = torch.empty((2, g.ny, g.nx, S), **kw)
+        J = torch.empty((20, g.ny, g.nx, S), **kw)
+        self._check(self._lib.henry_assemble(self._h, C.byref(prob or problem()), g, S, _ptr(theta), _ptr(p), _ptr(c),
+                                             _ptr(c_old), step, _ptr(R), _ptr(J)))
+        return R, J
+
+    def jacobian_apply(self, J, x, g: henry_grid, transpose: bool = False):
+        S = x.shape[-1]
+        self._f64(J, (20, g.ny, g.nx, S), "J")
+        self._f64(x, (2, g.ny, g.nx, S), "x")
+        y = torch.empty_like(x)
+        self._check(self._lib.henry_jacobian_apply(self._h, g, S, _ptr(J), _ptr(x), _ptr(y), int(transpose)))
+        return y
+
+    def gs_pass(self, J, b, x, g: henry_grid, colour: int, transpose: bool = False):
+        """One red (0) or black (1) Gauss-Seidel pass, in place on x."""
+        S = x.shape[-1]
+        self._f64(J, (20, g.ny, g.nx, S), "J")
+        self._f64(b, (2, g.ny, g.nx, S), "b")
+        self._f64(x, (2, g.ny, g.nx, S), "x")
+        self._check(self._lib.henry_gs_pass(self._h, g, S, _ptr(J), _ptr(b), _ptr(x), colour, int(transpose)))
+        return x
+
+    def coarse_solve(self, J, b, g: henry_grid, solver: int = 1, precision: int = 64, transpose: bool = False):
+        """x = J^{-1} b (J^{-T} b) by the coarse-grid direct solver (0 banded, 1 dense pivoted LU)."""
+        S = b.shape[-1]
+        self._f64(J, (20, g.ny, g.nx, S), "J")
+        self._f64(b, (2, g.ny, g.nx, S), "b")
+        x = torch.empty_like(b)
+        self._check(self._lib.henry_coarse_solve(self._h, solver, precision, g, S, _ptr(J), _ptr(b), _ptr(x),
+                                                 int(transpose)))
+        return x
+
     def autotune(self, theta, g: henry_grid, prob=None, opts=None):
         """Fastest solver options for this batch shape (times one Newton iteration per candidate)."""
         _check_theta(theta, self.device)
@@ -250,6 +301,42 @@ class Henry:
             self._check(self._lib.henry_profile_read(self._h, k, C.byref(n), C.byref(u), C.byref(ms)))
             out[name] = (n.value, u.value, ms.value)
         return out
+
+
+class SaltMassQoI(torch.autograd.Function):
+    """Q(theta) = salt mass in x > qoi_xmin at t = T per sample, differentiable in theta.
+
+    forward(theta [S, 13], hx, grid, prob, opts, checkpoint_every) -> Q [S].  When theta
+    needs a gradient, forward runs henry_adjoint_batch (the forward solve, then the discrete
+    adjoint's reverse sweep of transposed multigrid-preconditioned solves) and keeps dQ/dtheta
+    [S, 13]; otherwise it runs only the forward solve.  backward(grad_Q) returns
+    grad_Q[:, None] * dQ/dtheta: the implicit-function-theorem adjoint of the converged
+    implicit-Euler steps is exact for the discrete solve, so the product is the vector-Jacobian
+    product of Q.  Samples that fail to converge raise HenryError (no gradient is defined).
+    """
+
+    @staticmethod
+    def forward(ctx, theta, hx, g, prob, opts, checkpoint_every):
+        th = theta.detach().contiguous()
+        if ctx.needs_input_grad[0]:
+            q, grad, st, nf = hx.adjoint(th, g, prob, opts, checkpoint_every)
+            ctx.save_for_backward(grad)
+        else:
+            r = hx.solve(th, g, prob, opts, want_c=False)
+            q, nf = r.qoi, r.nfailed
+        if nf:
+            raise HenryError(nf, f"{nf} samples did not converge; Q and dQ/dtheta are undefined there")
+        return q
+
+    @staticmethod
+    def backward(ctx, grad_q):
+        (grad,) = ctx.saved_tensors
+        return grad_q[:, None] * grad, None, None, None, None, None
+
+
+def salt_mass_qoi(hx: "Henry", theta, g: henry_grid, prob=None, opts=None, checkpoint_every: int = 32):
+    """Q(theta) [S] through SaltMassQoI: torch.autograd.grad(Q.sum(), theta) is dQ/dtheta."""
+    return SaltMassQoI.apply(theta, hx, g, prob or problem(), opts or solver_opts(), checkpoint_every)
 
 
 def mlmc_run(hx: "Henry", thetas, levels, prob=None, opts=None, alpha: float = 1.0, fields: bool = True):

@@ -11,8 +11,10 @@ HENRY_OK, HENRY_EINVAL, HENRY_EDEVICE, HENRY_ENOMEM, HENRY_EUNSUPPORTED = 0, -1,
 EXPORTS = ("henry_problem_default", "henry_solver_opts_default", "henry_ctx_create", "henry_ctx_destroy",
            "henry_last_error", "henry_sample_fields", "henry_solve_batch", "henry_adjoint_batch",
            "mlmc_estimate", "mlmc_optimal_samples", "henry_autotune", "henry_profile", "henry_profile_read",
-           "mlmc_estimate_series", "mlmc_plan")
-PROF_CLASSES = ("assemble", "gs", "spmv", "restrict", "prolong", "band_factor", "band_solve")
+           "mlmc_estimate_series", "mlmc_plan", "henry_assemble", "henry_jacobian_apply",
+           "henry_gs_pass", "henry_coarse_solve")
+PROF_CLASSES = ("assemble", "gs", "spmv", "restrict", "prolong", "band_factor", "band_solve", "dense_factor",
+                "dense_solve")
 
 
 class henry_problem(C.Structure):
@@ -37,7 +39,8 @@ class henry_solver_opts(C.Structure):
                 ("newton_predict", C.c_double),
                 ("newton_jac_reuse", C.c_double),
                 ("mg_cycle", C.c_int),
-                ("adjoint_guess", C.c_int)]
+                ("adjoint_guess", C.c_int),
+                ("coarse_solver", C.c_int)]
 
 
 class henry_batch(C.Structure):
@@ -92,5 +95,13 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlmc_estimate_series.restype = i
     lib.mlmc_plan.argtypes = [i, P(d), P(d), P(d), d, d, i, P(C.c_longlong), P(d), P(d)]
     lib.mlmc_plan.restype = i
+    lib.henry_assemble.argtypes = [vp, P(henry_problem), henry_grid, i, vp, vp, vp, vp, i, vp, vp]
+    lib.henry_assemble.restype = i
+    lib.henry_jacobian_apply.argtypes = [vp, henry_grid, i, vp, vp, vp, i]
+    lib.henry_jacobian_apply.restype = i
+    lib.henry_gs_pass.argtypes = [vp, henry_grid, i, vp, vp, vp, i, i]
+    lib.henry_gs_pass.restype = i
+    lib.henry_coarse_solve.argtypes = [vp, i, i, henry_grid, i, vp, vp, vp, i]
+    lib.henry_coarse_solve.restype = i
     _lib = lib
     return lib

@@ -25,6 +25,7 @@
 #include "../../include/henry.h"
 #include "henry_kernels.hpp"
 #include "henry_coarse.hpp"
+#include "henry_dense.hpp"
 #include "henry_mlmc.hpp"
 #include "henry_adjoint.hpp"
 
@@ -247,6 +248,7 @@ struct MGLevel {
 
 struct Plan {
   int nx, ny, S, prec, cnx, cny;
+  int csolver;             // coarse solver: 0 banded LU, 1 dense LU with partial pivoting
   size_t N;
   Map m;
   Grid2 G;
@@ -256,7 +258,7 @@ struct Plan {
   DevBuf p_prev, c_prev;   // state of the previous step (initial-guess extrapolation)
   DevBuf p_prev2, c_prev2, p_prev3, c_prev3;   // and of the ones before (polynomial extrapolation)
   DevBuf vx, vr, vrh, vp, vv, vs, vt, vph, vsh;
-  DevBuf LU;
+  DevBuf LU, perm;         // coarse factors (banded or dense) and the dense solver's row permutation
   DevBuf sc, lam, ndone, status, stats, part, ctrl;
   DevBuf nhist;            // per sample: last undamped Newton update size, previous |R|^2
   size_t lu_stride;
@@ -354,10 +356,14 @@ struct henry_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  std::map<std::tuple<int, int, int, int, int, int, int>, std::unique_ptr<Plan>> plans;
+  // plans by (nx, ny, S, precision, coarse nx, coarse ny, reduction blocks, coarse solver,
+  // instance): batches of one call that share a shape but are solved concurrently get
+  // distinct instances
+  std::map<std::tuple<int, int, int, int, int, int, int, int, int>, std::unique_ptr<Plan>> plans;
   int* h_ctrl = nullptr;   // pinned
   DevBuf mlmc_tmp;
   DevBuf adj_ck, adj_seg, adj_g;   // adjoint checkpoints, segment states, sensitivities
+  DevBuf kws;                      // workspace of the kernel-level entry points
   std::vector<hipStream_t> streams; // per-grid streams of ragged solves (default priority)
   Profiler prof;
 };
@@ -400,8 +406,38 @@ static void plan_alloc_levels(Plan& P) {
   }
   const MGLevel& C = *P.lv[P.nlev - 1];
   P.mb = C.ny;
-  P.lu_stride = (size_t)C.ncell * (2 * P.mb + 1) * 4;
-  P.LU.alloc(P.lu_stride * P.S * sizeof(T));
+  if (P.csolver == 1) {
+    const size_t n = 2 * (size_t)C.ncell;
+    P.lu_stride = n * n;
+    P.LU.alloc(P.lu_stride * P.S * sizeof(T));
+    P.perm.alloc(n * P.S * sizeof(int));
+  } else {
+    P.lu_stride = (size_t)C.ncell * (2 * P.mb + 1) * 4;
+    P.LU.alloc(P.lu_stride * P.S * sizeof(T));
+  }
+}
+
+// Largest dynamic LDS one workgroup may use on the current device.
+static size_t max_lds_per_block() {
+  int dev = 0, v = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  return (size_t)v;
+}
+
+// The dense factorisation needs more than the default LDS limit of a launch: raise it once
+// per instantiation (and device) before its first launch.
+template <typename T>
+static void dense_factor_prepare(size_t lds) {
+  static std::mutex mu;
+  static bool done[64] = {};
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev >= 0 && dev < 64 && done[dev]) return;
+  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_factor<T, 16>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (dev >= 0 && dev < 64) done[dev] = true;
 }
 
 static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver_opts& o) {
@@ -413,6 +449,7 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
   P->prec = o.mg_precision;
   P->cnx = cnx;
   P->cny = cny;
+  P->csolver = o.coarse_solver;
   P->G = Grid2{nx, ny, nx * ny};
   P->N = (size_t)nx * ny * S;
   P->m = make_map(S, nx * ny, o.red_blocks);
@@ -430,8 +467,14 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
     gy /= 2;
   }
   P->nlev = (int)P->lv.size();
-  if (P->lv.back()->ny > 44) fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d: band width %d exceeds 44", gx, gy, gy);
-  {
+  if (o.coarse_solver == 1) {
+    const int n = 2 * P->lv.back()->ncell;
+    const size_t need = o.mg_precision == 32 ? dense_factor_lds<float>(n, 16) : dense_factor_lds<double>(n, 16);
+    if (n % 16) fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d: the dense LU needs 2 * cells divisible by 16", gx, gy);
+    if (need > max_lds_per_block())
+      fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d too large for the dense LU's LDS panel (%zu bytes)", gx, gy, need);
+  } else {
+    if (P->lv.back()->ny > 44) fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d: band width %d exceeds 44", gx, gy, gy);
     const int n = P->lv.back()->ncell, mb = P->lv.back()->ny;
     const size_t need = o.mg_precision == 32 ? band_solve_lds<float>(n, mb, 1) : band_solve_lds<double>(n, mb, 1);
     if (need > 64 * 1024) fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d too large for the LDS banded solve", gx, gy);
@@ -470,23 +513,43 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
   return P;
 }
 
-static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_opts& o) {
-  const int cnx = std::min(o.coarse_nx, nx), cny = std::min(o.coarse_ny, ny);
-  auto key = std::make_tuple(nx, ny, S, o.mg_precision, cnx, cny, o.red_blocks);
+using PlanKey = std::tuple<int, int, int, int, int, int, int, int, int>;
+
+static PlanKey plan_key(int nx, int ny, int S, const henry_solver_opts& o, int inst) {
+  return PlanKey(nx, ny, S, o.mg_precision, std::min(o.coarse_nx, nx), std::min(o.coarse_ny, ny), o.red_blocks,
+                 o.coarse_solver, inst);
+}
+
+// Widest per-sample reduction buffer any effective batch size Sa <= S needs.
+static size_t part_bytes_max(int nx, int ny, int S, int red_blocks) {
+  size_t mx = 0;
+  for (int Sa = 1; Sa <= S; ++Sa) mx = std::max(mx, (size_t)NSERIES * make_map(Sa, nx * ny, red_blocks).ncb * Sa * 8);
+  return mx;
+}
+
+// The plan of a batch shape, with its compacted sub-plan (see Solver::compact_newton) created
+// and sized for every effective batch size up front: the solve itself then allocates and frees
+// no device or pinned memory, so concurrent solves on worker threads never call the allocator
+// while another thread captures or synchronises a stream.
+static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_opts& o, int inst = 0) {
+  const PlanKey key = plan_key(nx, ny, S, o, inst);
   auto it = ctx->plans.find(key);
   if (it != ctx->plans.end()) return it->second.get();
   auto P = make_plan(nx, ny, S, o);
+  P->compact = make_plan(nx, ny, S, o);
+  P->compact->part.alloc(part_bytes_max(nx, ny, S, o.red_blocks));
   Plan* raw = P.get();
   ctx->plans[key] = std::move(P);
   return raw;
 }
 
-// Use plan Q (capacity >= Sa samples) for an effective batch of Sa samples.
+// Use plan Q (capacity >= Sa samples) for an effective batch of Sa samples.  Allocates
+// nothing: get_plan sized the reduction buffer for every Sa.
 static void plan_set_samples(Plan& Q, int Sa, int red_blocks) {
   Q.S = Sa;
   Q.N = (size_t)Q.nx * Q.ny * Sa;
   Q.m = make_map(Sa, Q.nx * Q.ny, red_blocks);
-  Q.part.alloc((size_t)NSERIES * Q.m.ncb * Sa * 8);
+  if ((size_t)NSERIES * Q.m.ncb * Sa * 8 > Q.part.bytes) fail(HENRY_EDEVICE, "internal: compact plan undersized");
   Q.drop_graphs();
 }
 
@@ -573,7 +636,25 @@ struct Solver {
                          C.phi.as<double>(), C.K.as<double>(), P.uin.as<double>(), (double*)nullptr, C.J.as<T>(),
                          (float*)nullptr);
     }
+    coarse_factor<T>();
+  }
+
+  // factors of the coarsest operator: banded LU, or the dense matrix and its pivoted LU
+  template <typename T>
+  void coarse_factor() {
     const MGLevel& Cc = *P.lv[P.nlev - 1];
+    if (P.csolver == 1) {
+      const int n = 2 * Cc.ncell;
+      const size_t lds = dense_factor_lds<T>(n, 16);
+      dense_factor_prepare<T>(lds);
+      timed(ctx, st, HENRY_PROF_DENSE_FACTOR, (long long)P.S, [&] {
+        hipLaunchKernelGGL((k_dense_build<T>), dim3(n, P.S), dim3(256), 0, st, P.S, Cc.nx, Cc.ny,
+                           level_J<T>(P.nlev - 1), P.LU.as<T>());
+        hipLaunchKernelGGL((k_dense_factor<T, 16>), dim3(P.S), dim3(DENSE_THREADS), lds, st, n, P.LU.as<T>(),
+                           P.perm.as<int>());
+      });
+      return;
+    }
     const size_t lds = (size_t)(P.mb + 1) * (P.mb + 1) * 4 * sizeof(T);
     timed(ctx, st, HENRY_PROF_BAND_FACTOR, (long long)Cc.ncell * P.S, [&] {
       hipLaunchKernelGGL((k_band_factor<T>), dim3(P.S), dim3(64), lds, st, P.S, Cc.nx, Cc.ny, level_J<T>(P.nlev - 1),
@@ -595,6 +676,13 @@ struct Solver {
   void vcycle(int k, const T* b, T* x, bool zero = true) {
     const Map& m = P.m;
     MGLevel& L = *P.lv[k];
+    if (k == P.nlev - 1 && P.csolver == 1) {
+      timed(ctx, st, HENRY_PROF_DENSE_SOLVE, (long long)P.S, [&] {
+        hipLaunchKernelGGL((k_dense_solve<T, TR>), dim3(P.S), dim3(DENSE_THREADS), dense_solve_lds<T>(2 * L.ncell), st,
+                           P.S, L.ncell, P.LU.as<T>(), (const int*)P.perm.as<int>(), b, x);
+      });
+      return;
+    }
     if (k == P.nlev - 1) {
       const int CH = band_chunk<T>(L.ncell, P.mb);
       const size_t lds = band_solve_lds<T>(L.ncell, P.mb, CH);
@@ -924,7 +1012,7 @@ struct Solver {
   template <typename T>
   void compact_newton(int Sa, int it0) {
     const int S = P.S;
-    if (!P.compact) P.compact = make_plan(P.nx, P.ny, S, o);
+    if (!P.compact) fail(HENRY_EDEVICE, "internal: plan without a compact sub-plan");
     Plan& Q = *P.compact;
     plan_set_samples(Q, Sa, o.red_blocks);
     int* idx = P.cidx.as<int>();
@@ -1154,6 +1242,7 @@ static void check_opts(const henry_solver_opts& o) {
   if (o.newton_extrapolate < 0 || o.newton_extrapolate > 4) fail(HENRY_EINVAL, "newton_extrapolate must be 0..4");
   if (o.adjoint_guess < 0 || o.adjoint_guess > 2) fail(HENRY_EINVAL, "adjoint_guess must be 0, 1 or 2");
   if (o.mg_cycle != 1 && o.mg_cycle != 2) fail(HENRY_EINVAL, "mg_cycle must be 1 (V) or 2 (W)");
+  if (o.coarse_solver != 0 && o.coarse_solver != 1) fail(HENRY_EINVAL, "coarse_solver must be 0 (banded) or 1 (dense)");
 }
 
 static int theta_check(henry_ctx* ctx, const double* theta, int S) {
@@ -1241,11 +1330,13 @@ static int solve_ragged(henry_ctx* ctx, const henry_problem& pr, const henry_sol
   HIPCHK(hipEventRecord(start, ctx->stream));
   std::vector<Plan*> plans;
   std::vector<henry_batch> gb(groups.size());
+  std::map<PlanKey, int> used;   // groups that share a plan shape (e.g. the same grid with other step counts)
   for (size_t k = 0; k < groups.size(); ++k) {
     Group& G = *groups[k];
     G.stream = ctx_stream(ctx, k);
     HIPCHK(hipStreamWaitEvent(G.stream, start, 0));
-    plans.push_back(get_plan(ctx, G.grid.nx, G.grid.ny, G.S, o));
+    const int inst = used[plan_key(G.grid.nx, G.grid.ny, G.S, o, 0)]++;
+    plans.push_back(get_plan(ctx, G.grid.nx, G.grid.ny, G.S, o, inst));
     henry_batch& B = gb[k];
     B.grid = G.grid;
     B.nsamples = G.S;
@@ -1288,6 +1379,15 @@ static int solve_ragged(henry_ctx* ctx, const henry_problem& pr, const henry_sol
     } catch (const HenryError& e) {
       G.ok = false;
       G.err = e;
+    } catch (const std::bad_alloc&) {
+      G.ok = false;
+      G.err = HenryError{HENRY_ENOMEM, "host allocation failed"};
+    } catch (const std::exception& e) {
+      G.ok = false;
+      G.err = HenryError{HENRY_EDEVICE, std::string("host runtime error: ") + e.what()};
+    } catch (...) {
+      G.ok = false;
+      G.err = HenryError{HENRY_EDEVICE, "unknown host exception"};
     }
   };
   if (!multi) {
@@ -1389,6 +1489,7 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->krylov_rtol_adjoint = 1e-8;
   o->mg_cycle = 1;
   o->adjoint_guess = 2;
+  o->coarse_solver = 0;
   o->newton_extrapolate = 4;
   o->newton_predict = 1.0;
   o->newton_jac_reuse = 1e-3;
@@ -1499,76 +1600,96 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_problem* prob, const henry_s
   });
 }
 
+}  // extern "C"
+
+// Body of mlmc_estimate.  `work` (device, `work_doubles`
+// long) holds the per-level moments and the per-cell field moments; NULL: the context's own
+// buffer, grown as needed.  Host bookkeeping uses fixed arrays (no host allocation either).
+static int mlmc_estimate_impl(henry_ctx* ctx, int L, const int* m, const henry_grid* grids,
+                              const double* const* g_fine, const double* const* g_coarse,
+                              const double* const* c_fine, const double* const* c_coarse, double alpha, double* mean,
+                              double* var_of_estimator, double* rmse, double* V_l, double* mean_field,
+                              double* var_field, double* work, size_t work_doubles) {
+  if (L < 0 || !m || !g_fine) fail(HENRY_EINVAL, "L, m or g_fine invalid");
+  if (L + 1 > FieldLevels::MAXL) fail(HENRY_EUNSUPPORTED, "at most %d levels", FieldLevels::MAXL);
+  for (int l = 0; l <= L; ++l) {
+    if (m[l] < 1 || !g_fine[l]) fail(HENRY_EINVAL, "level %d: m < 1 or g_fine NULL", l);
+    if (l > 0 && (!g_coarse || !g_coarse[l])) fail(HENRY_EINVAL, "level %d: g_coarse NULL", l);
+  }
+  const bool fields = c_fine && (mean_field || var_field);
+  // workspace: [L+1][2] level moments, then per level [mean_f, var_f, mean_c, var_c] fields
+  size_t off[FieldLevels::MAXL] = {};
+  size_t need = 2 * (size_t)(L + 1);
+  if (fields) {
+    if (!grids) fail(HENRY_EINVAL, "grids required for field moments");
+    for (int l = 0; l <= L; ++l) {
+      if (!c_fine[l]) fail(HENRY_EINVAL, "level %d: c_fine NULL", l);
+      if (l > 0 && (!c_coarse || !c_coarse[l])) fail(HENRY_EINVAL, "level %d: c_coarse NULL", l);
+      if (grids[l].nx < 1 || grids[l].ny < 1) fail(HENRY_EINVAL, "level %d: empty grid", l);
+      if (l > 0 && (grids[l].nx != 2 * grids[l - 1].nx || grids[l].ny != 2 * grids[l - 1].ny))
+        fail(HENRY_EINVAL, "level %d grid is not a 2x refinement of level %d", l, l - 1);
+      off[l] = need;
+      need += 2 * (size_t)grids[l].nx * grids[l].ny + (l > 0 ? 2 * (size_t)grids[l - 1].nx * grids[l - 1].ny : 0);
+    }
+  }
+  if (!work) {
+    ctx->mlmc_tmp.alloc(need * sizeof(double));
+    work = ctx->mlmc_tmp.as<double>();
+  } else if (need > work_doubles) {
+    fail(HENRY_EINVAL, "estimator workspace of %zu doubles exceeds the %zu available", need, work_doubles);
+  }
+  hipStream_t st = ctx->stream;
+  // scalar estimator: per level mean and unbiased variance of Y_l (two-pass, fixed order)
+  for (int l = 0; l <= L; ++l)
+    hipLaunchKernelGGL(k_level_moments, dim3(1), dim3(256), 0, st, m[l], g_fine[l], l > 0 ? g_coarse[l] : nullptr,
+                       work + 2 * l);
+  if (fields) {
+    const int nxL = grids[L].nx, nyL = grids[L].ny, ncL = nxL * nyL;
+    for (int l = 0; l <= L; ++l) {
+      const int nc = grids[l].nx * grids[l].ny;
+      double* t = work + off[l];
+      hipLaunchKernelGGL(k_cell_moments, dim3((nc + 255) / 256), dim3(256), 0, st, nc, m[l], c_fine[l], t, t + nc);
+      if (l > 0) {
+        const int ncc = grids[l - 1].nx * grids[l - 1].ny;
+        hipLaunchKernelGGL(k_cell_moments, dim3((ncc + 255) / 256), dim3(256), 0, st, ncc, m[l], c_coarse[l],
+                           t + 2 * nc, t + 2 * nc + ncc);
+      }
+    }
+    FieldLevels fl{};
+    fl.L = L;
+    for (int l = 0; l <= L; ++l) {
+      fl.nx[l] = grids[l].nx;
+      fl.off[l] = (long long)off[l];
+    }
+    hipLaunchKernelGGL(k_field_accumulate, dim3((ncL + 255) / 256), dim3(256), 0, st, fl, nxL, nyL, work, mean_field,
+                       var_field);
+  }
+  HIPCHK(hipGetLastError());
+  double h[2 * FieldLevels::MAXL];
+  HIPCHK(hipMemcpyAsync(h, work, 2 * (size_t)(L + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double mu = 0.0, var = 0.0;
+  for (int l = 0; l <= L; ++l) {
+    mu += h[2 * l];
+    var += h[2 * l + 1] / m[l];
+    if (V_l) V_l[l] = h[2 * l + 1];
+  }
+  const double bias = L > 0 ? std::fabs(h[2 * L]) / (std::pow(2.0, alpha) - 1.0) : 0.0;
+  if (mean) *mean = mu;
+  if (var_of_estimator) *var_of_estimator = var;
+  if (rmse) *rmse = std::sqrt(var + bias * bias);
+  return HENRY_OK;
+}
+
+extern "C" {
+
 int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_grid* grids, const double* const* g_fine,
                   const double* const* g_coarse, const double* const* c_fine, const double* const* c_coarse,
                   double alpha, double* mean, double* var_of_estimator, double* rmse, double* V_l, double* mean_field,
                   double* var_field) {
   return guarded(ctx, [&]() -> int {
-    if (L < 0 || !m || !g_fine) fail(HENRY_EINVAL, "L, m or g_fine invalid");
-    for (int l = 0; l <= L; ++l) {
-      if (m[l] < 1 || !g_fine[l]) fail(HENRY_EINVAL, "level %d: m < 1 or g_fine NULL", l);
-      if (l > 0 && (!g_coarse || !g_coarse[l])) fail(HENRY_EINVAL, "level %d: g_coarse NULL", l);
-    }
-    hipStream_t st = ctx->stream;
-    // scalar estimator: per level mean and unbiased variance of Y_l (two-pass, fixed order)
-    DevBuf out;
-    out.alloc((size_t)(L + 1) * 2 * sizeof(double));
-    for (int l = 0; l <= L; ++l)
-      hipLaunchKernelGGL(k_level_moments, dim3(1), dim3(256), 0, st, m[l], g_fine[l], l > 0 ? g_coarse[l] : nullptr,
-                         out.as<double>() + 2 * l);
-    std::vector<double> h(2 * (L + 1));
-    HIPCHK(hipMemcpyAsync(h.data(), out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    double mu = 0.0, var = 0.0;
-    for (int l = 0; l <= L; ++l) {
-      mu += h[2 * l];
-      var += h[2 * l + 1] / m[l];
-      if (V_l) V_l[l] = h[2 * l + 1];
-    }
-    const double bias = L > 0 ? std::fabs(h[2 * L]) / (std::pow(2.0, alpha) - 1.0) : 0.0;
-    if (mean) *mean = mu;
-    if (var_of_estimator) *var_of_estimator = var;
-    if (rmse) *rmse = std::sqrt(var + bias * bias);
-    if (c_fine && (mean_field || var_field)) {
-      if (!grids) fail(HENRY_EINVAL, "grids required for field moments");
-      for (int l = 0; l <= L; ++l) {
-        if (!c_fine[l]) fail(HENRY_EINVAL, "level %d: c_fine NULL", l);
-        if (l > 0 && (!c_coarse || !c_coarse[l])) fail(HENRY_EINVAL, "level %d: c_coarse NULL", l);
-        if (l > 0 && (grids[l].nx != 2 * grids[l - 1].nx || grids[l].ny != 2 * grids[l - 1].ny))
-          fail(HENRY_EINVAL, "level %d grid is not a 2x refinement of level %d", l, l - 1);
-      }
-      const int nxL = grids[L].nx, nyL = grids[L].ny, ncL = nxL * nyL;
-      // per-level moments on each level's own grid: [mean_f, var_f, mean_c(coarse grid), var_c]
-      size_t tot = 0;
-      std::vector<size_t> off(L + 1);
-      for (int l = 0; l <= L; ++l) {
-        off[l] = tot;
-        tot += 2 * (size_t)grids[l].nx * grids[l].ny + (l > 0 ? 2 * (size_t)grids[l - 1].nx * grids[l - 1].ny : 0);
-      }
-      ctx->mlmc_tmp.alloc(tot * sizeof(double));
-      double* tmp = ctx->mlmc_tmp.as<double>();
-      for (int l = 0; l <= L; ++l) {
-        const int nc = grids[l].nx * grids[l].ny;
-        hipLaunchKernelGGL(k_cell_moments, dim3((nc + 255) / 256), dim3(256), 0, st, nc, m[l], c_fine[l], tmp + off[l],
-                           tmp + off[l] + nc);
-        if (l > 0) {
-          const int ncc = grids[l - 1].nx * grids[l - 1].ny;
-          hipLaunchKernelGGL(k_cell_moments, dim3((ncc + 255) / 256), dim3(256), 0, st, ncc, m[l], c_coarse[l],
-                             tmp + off[l] + 2 * nc, tmp + off[l] + 2 * nc + ncc);
-        }
-      }
-      FieldLevels fl{};
-      fl.L = L;
-      for (int l = 0; l <= L; ++l) {
-        fl.nx[l] = grids[l].nx;
-        fl.off[l] = (long long)off[l];
-      }
-      if (L + 1 > FieldLevels::MAXL) fail(HENRY_EUNSUPPORTED, "at most %d levels", FieldLevels::MAXL);
-      hipLaunchKernelGGL(k_field_accumulate, dim3((ncL + 255) / 256), dim3(256), 0, st, fl, nxL, nyL, tmp, mean_field,
-                         var_field);
-      HIPCHK(hipGetLastError());
-    }
-    return HENRY_OK;
+    return mlmc_estimate_impl(ctx, L, m, grids, g_fine, g_coarse, c_fine, c_coarse, alpha, mean, var_of_estimator,
+                              rmse, V_l, mean_field, var_field, nullptr, 0);
   });
 }
 
@@ -1680,6 +1801,153 @@ int mlmc_plan(int Lp, const double* Ymean_abs, const double* V_l, const double* 
   return L;
 }
 
+// ---------------------------------------------------------------------------
+// kernel-level entry points (the solve's own kernels, one launch each)
+// ---------------------------------------------------------------------------
+int henry_assemble(henry_ctx* ctx, const henry_problem* prob, henry_grid grid, int S, const double* theta,
+                   const double* p, const double* c, const double* c_old, int step, double* R, double* J) {
+  return guarded(ctx, [&]() -> int {
+    check_problem(prob);
+    check_grid(*prob, grid);
+    if (S < 1 || !theta || !p || !c || !c_old || !R || !J) fail(HENRY_EINVAL, "S < 1 or a NULL array");
+    if (step < 0 || step >= grid.nsteps) fail(HENRY_EINVAL, "step %d outside 0..%d", step, grid.nsteps - 1);
+    if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
+    const Map m = make_map(S, grid.nx * grid.ny, 0);
+    const Grid2 G{grid.nx, grid.ny, grid.nx * grid.ny};
+    Phys P = make_phys(*prob, grid.nx, grid.ny, grid.nsteps);
+    P.uin_fac = 1.0 + std::sin(prob->recharge_omega * (step + 1) * P.tau);   // the step ends at (step + 1) tau
+    const size_t N = (size_t)G.ncell * S;
+    ctx->kws.alloc((2 * N + S) * sizeof(double));
+    double* phi = ctx->kws.as<double>();
+    double* K = phi + N;
+    double* uin = K + N;
+    hipLaunchKernelGGL(k_fields, grid_cells(m, G.ncell), block_of(m), 0, ctx->stream, m, G, P, make_kl(*prob),
+                       make_fp(*prob), theta, phi, K, uin);
+    hipLaunchKernelGGL((k_assemble<true, double, false, true>), grid_cells(m, G.ncell), block_of(m), 0, ctx->stream, m,
+                       G, P, p, c, c_old, (const double*)phi, (const double*)K, (const double*)uin, R, J,
+                       (float*)nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));   // the workspace may be regrown by the next call
+    return HENRY_OK;
+  });
+}
+
+int henry_jacobian_apply(henry_ctx* ctx, henry_grid grid, int S, const double* J, const double* x, double* y,
+                         int transpose) {
+  return guarded(ctx, [&]() -> int {
+    if (grid.nx < 1 || grid.ny < 1 || S < 1 || !J || !x || !y) fail(HENRY_EINVAL, "grid, S or a NULL array");
+    const Map m = make_map(S, grid.nx * grid.ny, 0);
+    const Grid2 G{grid.nx, grid.ny, grid.nx * grid.ny};
+    ctx->kws.alloc((size_t)m.ncb * S * sizeof(double));
+    double* part = ctx->kws.as<double>();
+    if (transpose)
+      hipLaunchKernelGGL((k_spmv_dot<1, true>), grid_red(m), block_of(m), 0, ctx->stream, m, G, J, x, y, x, part,
+                         (const double*)nullptr);
+    else
+      hipLaunchKernelGGL((k_spmv_dot<1, false>), grid_red(m), block_of(m), 0, ctx->stream, m, G, J, x, y, x, part,
+                         (const double*)nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return HENRY_OK;
+  });
+}
+
+int henry_gs_pass(henry_ctx* ctx, henry_grid grid, int S, const double* J, const double* b, double* x, int colour,
+                  int transpose) {
+  return guarded(ctx, [&]() -> int {
+    if (grid.nx < 1 || grid.ny < 1 || S < 1 || !J || !b || !x) fail(HENRY_EINVAL, "grid, S or a NULL array");
+    if (colour != 0 && colour != 1) fail(HENRY_EINVAL, "colour must be 0 (red) or 1 (black)");
+    const Map m = make_map(S, grid.nx * grid.ny, 0);
+    const Grid2 G{grid.nx, grid.ny, grid.nx * grid.ny};
+    const dim3 gg = grid_cells(m, grid.ny * ((grid.nx + 1) / 2));
+    if (transpose)
+      hipLaunchKernelGGL((k_gs_colour<double, true, 0>), gg, block_of(m), 0, ctx->stream, m, G, G, colour, J, b, x,
+                         (const double*)nullptr);
+    else
+      hipLaunchKernelGGL((k_gs_colour<double, false, 0>), gg, block_of(m), 0, ctx->stream, m, G, G, colour, J, b, x,
+                         (const double*)nullptr);
+    HIPCHK(hipGetLastError());
+    return HENRY_OK;
+  });
+}
+
+}  // extern "C"
+
+template <typename T>
+static void coarse_solve_t(henry_ctx* ctx, int solver, henry_grid g, int S, const T* J, const T* b, T* x, int tr,
+                           void* ws) {
+  const int nc = g.nx * g.ny, n = 2 * nc;
+  hipStream_t st = ctx->stream;
+  T* LU = static_cast<T*>(ws);
+  if (solver == 1) {
+    int* perm = reinterpret_cast<int*>(LU + (size_t)n * n * S);
+    const size_t lds = dense_factor_lds<T>(n, 16);
+    dense_factor_prepare<T>(lds);
+    hipLaunchKernelGGL((k_dense_build<T>), dim3(n, S), dim3(256), 0, st, S, g.nx, g.ny, J, LU);
+    hipLaunchKernelGGL((k_dense_factor<T, 16>), dim3(S), dim3(DENSE_THREADS), lds, st, n, LU, perm);
+    if (tr)
+      hipLaunchKernelGGL((k_dense_solve<T, true>), dim3(S), dim3(DENSE_THREADS), dense_solve_lds<T>(n), st, S, nc, LU,
+                         (const int*)perm, b, x);
+    else
+      hipLaunchKernelGGL((k_dense_solve<T, false>), dim3(S), dim3(DENSE_THREADS), dense_solve_lds<T>(n), st, S, nc,
+                         LU, (const int*)perm, b, x);
+    return;
+  }
+  const int mb = g.ny;
+  hipLaunchKernelGGL((k_band_factor<T>), dim3(S), dim3(64), (size_t)(mb + 1) * (mb + 1) * 4 * sizeof(T), st, S, g.nx,
+                     g.ny, J, LU);
+  const int CH = band_chunk<T>(nc, mb);
+  if (tr)
+    hipLaunchKernelGGL((k_band_solve_T<T>), dim3(S), dim3(64), band_solve_lds<T>(nc, mb, CH), st, S, g.nx, g.ny, CH,
+                       (const T*)LU, b, x);
+  else
+    hipLaunchKernelGGL((k_band_solve<T>), dim3(S), dim3(64), band_solve_lds<T>(nc, mb, CH), st, S, g.nx, g.ny, CH,
+                       (const T*)LU, b, x);
+}
+
+extern "C" {
+
+int henry_coarse_solve(henry_ctx* ctx, int solver, int precision, henry_grid coarse, int S, const double* J,
+                       const double* b, double* x, int transpose) {
+  return guarded(ctx, [&]() -> int {
+    if (coarse.nx < 1 || coarse.ny < 1 || S < 1 || !J || !b || !x) fail(HENRY_EINVAL, "grid, S or a NULL array");
+    if (solver != 0 && solver != 1) fail(HENRY_EINVAL, "solver must be 0 (banded) or 1 (dense)");
+    if (precision != 64 && precision != 32) fail(HENRY_EINVAL, "precision must be 64 or 32");
+    const int nc = coarse.nx * coarse.ny, n = 2 * nc;
+    const size_t N = (size_t)nc * S;
+    const size_t tsz = precision == 64 ? 8 : 4;
+    if (solver == 1) {
+      const size_t need = precision == 64 ? dense_factor_lds<double>(n, 16) : dense_factor_lds<float>(n, 16);
+      if (n % 16 || need > max_lds_per_block()) fail(HENRY_EUNSUPPORTED, "grid %dx%d: no dense LU", coarse.nx, coarse.ny);
+    } else {
+      if (coarse.ny > 44 || band_solve_lds<double>(nc, coarse.ny, 1) > 64 * 1024)
+        fail(HENRY_EUNSUPPORTED, "grid %dx%d: no banded LU", coarse.nx, coarse.ny);
+    }
+    const size_t fac = solver == 1 ? (size_t)n * n * S * tsz + (size_t)n * S * sizeof(int)
+                                   : (size_t)nc * (2 * coarse.ny + 1) * 4 * S * tsz;
+    const size_t conv = precision == 32 ? (20 * N + 4 * N) * sizeof(float) : 0;   // FP32 copies of J, b and x
+    ctx->kws.alloc(conv + fac);
+    hipStream_t st = ctx->stream;
+    if (precision == 64) {
+      coarse_solve_t<double>(ctx, solver, coarse, S, J, b, x, transpose, ctx->kws.p);
+    } else {
+      float* J32 = ctx->kws.as<float>();
+      float* b32 = J32 + 20 * N;
+      float* x32 = b32 + 2 * N;
+      hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((20 * N + 255) / 256)), dim3(256), 0, st, 20 * N,
+                         J, J32);
+      hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((2 * N + 255) / 256)), dim3(256), 0, st, 2 * N, b,
+                         b32);
+      coarse_solve_t<float>(ctx, solver, coarse, S, J32, b32, x32, transpose, static_cast<char*>(ctx->kws.p) + conv);
+      hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)((2 * N + 255) / 256)), dim3(256), 0, st, 2 * N,
+                         x32, x);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return HENRY_OK;
+  });
+}
+
 int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts* opts, henry_grid grid, int S,
                    const double* theta, double* best_ms) {
   return guarded(ctx, [&]() -> int {
@@ -1716,11 +1984,10 @@ int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts*
           }
     double best = 1e300;
     henry_solver_opts win = *opts;
-    std::vector<std::tuple<int, int, int, int, int, int, int>> used;
+    std::vector<PlanKey> used;
     for (const auto& c : cands) {
       Plan* P = get_plan(ctx, grid.nx, grid.ny, S, c);
-      used.emplace_back(grid.nx, grid.ny, S, c.mg_precision, std::min(c.coarse_nx, grid.nx),
-                        std::min(c.coarse_ny, grid.ny), c.red_blocks);
+      used.push_back(plan_key(grid.nx, grid.ny, S, c, 0));
       Solver sv(ctx, *prob, c, *P, grid.nsteps, st);
       float ms = 0.f;
       // the first implicit-Euler step (damped start) is run untimed, the second is timed;
@@ -1743,8 +2010,7 @@ int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts*
       }
     }
     // keep only the winner's plan
-    const auto keep = std::make_tuple(grid.nx, grid.ny, S, win.mg_precision, std::min(win.coarse_nx, grid.nx),
-                                      std::min(win.coarse_ny, grid.ny), win.red_blocks);
+    const PlanKey keep = plan_key(grid.nx, grid.ny, S, win, 0);
     HIPCHK(hipStreamSynchronize(st));
     for (const auto& k : used)
       if (k != keep) ctx->plans.erase(k);

@@ -69,18 +69,47 @@ def oracle_batch(theta, nx, ny, nsteps, prob_kw=None, procs=NPROC, series=False)
         return {k: z[k] for k in z.files}
 
 
-def defect_bound(theta, tau, phi_max, q_in_amp=0.1, q_in=6.6e-5, newton_tol=1e-9, margin=5.0):
-    """Largest per-step mass-balance defect allowed for accepted Newton iterates, per sample.
+def defect_bound(theta, prob, nx, ny, nsteps, newton_tol=1e-9, u_max=1e-2):
+    """Largest per-step mass-balance defect an accepted Newton iterate can show, per sample:
+    (fluid bound [S], salt bound [S]), in the GPU's unit (storage change + tau * boundary
+    outflux, over one step's inflow tau rho0 u_in Ly).
 
-    The GPU reports the defect (storage change + tau * boundary outflux) of each step over
-    one step's inflow tau rho0 u_in Ly.  The exact discrete fixed point balances to rounding;
-    an iterate accepted at Newton tolerance tol may be off by about tol in c in every cell,
-    which moves at most phi_max rho1 |Omega| tol of salt (and rho1 - rho0 times that of
-    fluid).  `margin` covers the predictive stop, whose accepted iterate is only predicted
-    to be within tol.  Returns the bound for every sample of theta [S, 13] (u_in from zeta).
-    """
-    u_in = q_in * (1.0 + q_in_amp * np.asarray(theta)[:, 12])
-    return margin * phi_max * 1025.0 * 2.0 * newton_tol / (tau * 1000.0 * u_in * 1.0)
+    Derivation (first order in the tolerance).  Interior fluxes cancel, so the defect of an
+    iterate u is tau |sum_P R_P(u)| / scale, and sum_P R_P is the total storage change plus the
+    boundary outflux.  The accepted iterate lies within one Newton update of the step's discrete
+    solution u*, where sum_P R_P(u*) = 0; the stopping test (or, for the predictive stop, the
+    predicted update) bounds that update by |dc| <= tol and |dp| <= tol rho0 g Ly.  To first
+    order the defect is then at most the sum over cells of |d(storage + boundary outflux)/du|
+    times those bounds, with c in [0, 1]:
+      storage    fluid vol phi drho / tau,  salt vol phi (rho0 + 2 drho) / tau  (per |dc|);
+      left face  salt 2 phi Dm (drho + rho1) hy/hx                            (per |dc|);
+      right face d F/d p = 2 rho1 K / mu (times |dp|; also in the salt flux, c_b <= 1) and
+                 d F/d c = drho |u| hy, d G/d c <= (drho + rho1) |u| hy with |u| <= u_max
+                 (times |dc|); the Dirichlet variant adds 2 phi Dm (drho + rho1) hy/hx.
+    prob: the oracle's Problem (fields and constants); theta [S, 13]."""
+    from oracle import henry as H
+    g = H.Grid(nx, ny, nsteps)
+    hx, hy = g.h(prob)
+    tau = prob.T / nsteps
+    dr = prob.rho1 - prob.rho0
+    dc = newton_tol
+    dp = newton_tol * prob.rho0 * prob.g * prob.Ly
+    vol = hx * hy
+    bf, bs = [], []
+    for th in np.asarray(theta):
+        phi, K, u_in = H.sample_fields(prob, g, th)
+        Kr, phr, phl = K[:, -1], phi[:, -1], phi[:, 0]
+        dFdp = 2.0 * prob.rho1 * Kr / prob.mu
+        fluid = vol * phi.sum() * dr / tau * dc + (dFdp * dp + dr * u_max * hy * dc).sum()
+        salt = vol * phi.sum() * (prob.rho0 + 2.0 * dr) / tau * dc
+        salt += (2.0 * phl * prob.Dm * (dr + prob.rho1) * hy / hx).sum() * dc
+        salt += (dFdp * dp + (2.0 * dr + prob.rho1) * u_max * hy * dc).sum()
+        if prob.right_c_dirichlet:
+            salt += (2.0 * phr * prob.Dm * (dr + prob.rho1) * hy / hx).sum() * dc
+        scale = prob.rho0 * u_in * prob.Ly
+        bf.append(fluid / scale)
+        bs.append(salt / scale)
+    return np.array(bf), np.array(bs)
 
 
 def rel_inf(a, b):

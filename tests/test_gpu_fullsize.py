@@ -43,8 +43,10 @@ def _check(out, name, samples):
     assert out["nfailed"] == 0
     # global balance of the accepted Newton iterate: storage change + tau * boundary flux = sum of
     # residuals, bounded by the solver tolerances (the exact discrete fixed point balances to ~1e-13)
-    bound = defect_bound(out["theta"], 36000.0 / out["nsteps"], 0.5)
-    assert (out["st"][:, 2] < bound).all() and (out["st"][:, 3] < bound).all()
+    from oracle import henry as H
+    ny, nx = out["c"].shape[:2]
+    bf, bs = defect_bound(out["theta"], H.Problem(), nx, ny, out["nsteps"])
+    assert (out["st"][:, 2] < bf).all() and (out["st"][:, 3] < bs).all()
     assert out["c"].min() >= -1e-10 and out["c"].max() <= 1 + 1e-10
 
 
@@ -58,7 +60,6 @@ def test_level3_fp32_multigrid_full_batch():
     _check(_run("c2_fp64_level3", 32), "c2", (0, 1))
 
 
-@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "oracle_c3_s0.npz")), reason="level-4 oracle result not stored")
 def test_level4_fp32_multigrid_full_batch():
     """512x256 cells, 768 steps, 128 samples of seed 2 with the FP32 multigrid preconditioner."""
     _check(_run("c3_mixed_level4", 32), "c3", (0,))
@@ -103,10 +104,7 @@ def test_mlmc_hierarchy_full_run():
     same(F[1]["c"][-1], F[1]["q"][-1], r1["c"][1], r1["qoi"][1], "level 1, last sample")
     # stored oracle results (tests/golden/make_golden.py c4)
     for name, arr in (("c4_l2", F[2]), ("c4_l3", F[3]), ("c4_l4coarse", Cp[4])):
-        f = os.path.join(GOLD, f"oracle_{name}_s0.npz")
-        if not os.path.exists(f):
-            continue
-        z = np.load(f)
+        z = np.load(os.path.join(GOLD, f"oracle_{name}_s0.npz"))
         src = ths[4][0] if name == "c4_l4coarse" else ths[int(name[-1])][0]
         assert np.array_equal(z["theta"], src)
         same(arr["c"][0], arr["q"][0], z["c_T"], float(z["qoi"]), name)
@@ -115,8 +113,9 @@ def test_mlmc_hierarchy_full_run():
         for out, glev in ((F[l], lev), (Cp[l], lev - 1)):
             if out is None:
                 continue
-            bound = defect_bound(ths[l], 36000.0 / (48 << glev), 0.5)
-            assert (out["st"][:, 2] < bound).all() and (out["st"][:, 3] < bound).all(), (l, glev)
+            from oracle import henry as H
+            bf, bs = defect_bound(ths[l], H.Problem(), 32 << glev, 16 << glev, 48 << glev)
+            assert (out["st"][:, 2] < bf).all() and (out["st"][:, 3] < bs).all(), (l, glev)
             assert out["c"].min() >= -1e-10 and out["c"].max() <= 1 + 1e-10, (l, glev)
     # the estimator on the same QoIs and fields
     ref = M.estimate([f["q"] for f in F], [None if c is None else c["q"] for c in Cp])

@@ -14,7 +14,6 @@ from tests.oracle_runs import defect_bound, oracle_batch, rel_inf
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-8
-PHI_MAX = 0.92   # bound of eq. poro_2levels for |xi| <= 1 (0.35 * 1.44 * 1.3 * 1.4 below y = -0.8)
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 ORACLE_KW = dict(field_model="paper", q_in_amp=0.5, recharge_omega=math.pi / 40.0, T=6016.0)
 
@@ -25,6 +24,11 @@ def hx():
     h = P.Henry(0)
     yield h
     h.close()
+
+
+def _oracle_prob():
+    from oracle import henry as H
+    return H.paper_problem()
 
 
 def _cuda(a):
@@ -71,12 +75,11 @@ def test_paper_model_matches_oracle(hx, level):
         q = r.qoi.cpu().numpy()
         assert np.abs(q - ref["qoi"]).max() <= TOL * np.abs(ref["qoi"]).max()
         st = r.stats.cpu().numpy()
-        bound = defect_bound(th, 6016.0 / g.nsteps, PHI_MAX, q_in_amp=0.5)
-        assert (st[:, 2] < bound).all() and (st[:, 3] < bound).all()
+        bf, bs = defect_bound(th, _oracle_prob(), g.nx, g.ny, g.nsteps)
+        assert (st[:, 2] < bf).all() and (st[:, 3] < bs).all()
         assert c.min() >= -1e-10 and c.max() <= 1 + 1e-10
 
 
-@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "oracle_f1_s0.npz")), reason="oracle result not stored")
 def test_paper_model_level2_batch_against_stored_oracle(hx):
     """Level 2 (128x64 cells, 192 steps), 64 samples of seed 5 in one batch: samples 0 and 1
     against the stored oracle results (tests/golden/make_golden.py f1), invariants for all."""
@@ -92,12 +95,11 @@ def test_paper_model_level2_batch_against_stored_oracle(hx):
         assert np.abs(p[s].ravel() - z["p_T"]).max() <= TOL * np.abs(z["p_T"]).max()
         assert abs(q[s] - float(z["qoi"])) <= TOL * abs(float(z["qoi"]))
     st = r.stats.cpu().numpy()
-    bound = defect_bound(th, 6016.0 / 192, PHI_MAX, q_in_amp=0.5)
-    assert (st[:, 2] < bound).all() and (st[:, 3] < bound).all()
+    bf, bs = defect_bound(th, _oracle_prob(), 128, 64, 192)
+    assert (st[:, 2] < bf).all() and (st[:, 3] < bs).all()
     assert c.min() >= -1e-10 and c.max() <= 1 + 1e-10
 
 
-@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "oracle_f1l3_s0.npz")), reason="oracle result not stored")
 def test_paper_model_benchmark_batch_against_stored_oracle(hx):
     """The benchmark's paper-model line in its launch configuration: 256x128 cells, 384 steps
     over T = 6016 s, all 512 samples of seed 1 in one batch.  Sample 0 against the stored
@@ -112,8 +114,8 @@ def test_paper_model_benchmark_batch_against_stored_oracle(hx):
     assert np.abs(p[0].ravel() - z["p_T"]).max() <= TOL * np.abs(z["p_T"]).max()
     assert abs(float(r.qoi[0]) - float(z["qoi"])) <= TOL * abs(float(z["qoi"]))
     st = r.stats.cpu().numpy()
-    bound = defect_bound(th, 6016.0 / 384, PHI_MAX, q_in_amp=0.5)
-    assert (st[:, 2] < bound).all() and (st[:, 3] < bound).all()
+    bf, bs = defect_bound(th, _oracle_prob(), 256, 128, 384)
+    assert (st[:, 2] < bf).all() and (st[:, 3] < bs).all()
     assert c.min() >= -1e-10 and c.max() <= 1 + 1e-10
 
 

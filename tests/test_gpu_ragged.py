@@ -41,6 +41,23 @@ def test_ragged_call_matches_separate_calls(hx):
         assert np.allclose(r.qoi.cpu().numpy(), s.qoi.cpu().numpy(), rtol=1e-9, atol=0)
 
 
+def test_same_grid_and_size_with_other_step_counts(hx):
+    """Two batches on one grid with the same sample count but different step counts are solved
+    concurrently in one call (one stream each): each must equal its own separate solve.  They
+    share a workspace shape, so the library gives each its own instance."""
+    import paper_2403_17018_amd as P
+    prob = P.problem(T=7200.0)
+    a, b = draw_theta(61, 16), draw_theta(62, 16)
+    ga, gb = P.grid(32, 16, 8), P.grid(32, 16, 12)
+    rr = hx.solve_ragged([(_cu(a), ga), (_cu(b), gb)], prob, P.solver_opts(use_graphs=1), want_p=True)
+    for th, g, r in ((a, ga, rr[0]), (b, gb, rr[1])):
+        s = hx.solve(_cu(th), g, prob, P.solver_opts(use_graphs=1), want_p=True)
+        assert r.nfailed == 0 and s.nfailed == 0
+        for x, y in ((r.c_T, s.c_T), (r.p_T, s.p_T)):
+            x, y = x.cpu().numpy(), y.cpu().numpy()
+            assert np.abs(x - y).max() <= 1e-9 * np.abs(y).max()
+
+
 def test_graph_replay_is_bitwise_equal_to_eager(hx):
     """Each BiCGStab iteration replayed from a captured hipGraph, many replays with eager
     Newton/assembly work in between, against the eager launch sequence."""

@@ -64,9 +64,28 @@ def test_level0_batch_matches_oracle(hx):
     q = r.qoi.cpu().numpy()
     assert np.abs(q - ref["qoi"]).max() <= TOL * np.abs(ref["qoi"]).max()
     st = r.stats.cpu().numpy()
-    bound = defect_bound(th, 36000.0 / g.nsteps, 0.5)               # mass balance of the accepted iterates
-    assert (st[:, 2] < bound).all() and (st[:, 3] < bound).all()
+    from oracle import henry as H
+    bf, bs = defect_bound(th, H.Problem(), g.nx, g.ny, g.nsteps)    # mass balance of the accepted iterates
+    assert (st[:, 2] < bf).all() and (st[:, 3] < bs).all()
     assert c.min() >= -1e-10 and c.max() <= 1 + 1e-10
+
+
+def test_mass_balance_at_tight_tolerance(hx):
+    """Conservation (section 2.1): the per-step defect, storage change + tau * boundary outflux,
+    shrinks with the Newton tolerance as the first-order bound derived in
+    tests.oracle_runs.defect_bound says; at tol = 1e-13 (plain stopping test) that bound is
+    about 3e-10 of a step's inflow on level 0."""
+    import paper_2403_17018_amd as P
+    from oracle import henry as H
+    th = draw_theta(0, 16)
+    g = P.level_grid(0)
+    r, c, p = _solve(hx, th, g, newton_tol=1e-13, krylov_rtol=1e-12, krylov_maxit=200, newton_maxit=60,
+                     newton_predict=0.0)
+    assert r.nfailed == 0
+    st = r.stats.cpu().numpy()
+    bf, bs = defect_bound(th, H.Problem(), g.nx, g.ny, g.nsteps, newton_tol=1e-13)
+    assert bs.max() < 1e-9
+    assert (st[:, 2] < bf).all() and (st[:, 3] < bs).all()
 
 
 def test_level0_fp32_multigrid_matches_oracle(hx):
