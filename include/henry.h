@@ -231,6 +231,25 @@ HENRY_API int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_gri
                   double* mean, double* var_of_estimator, double* rmse, double* V_l,
                   double* mean_field, double* var_field);
 
+/* Allocation-free variant of mlmc_estimate, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, outputs, kernels and summation order as mlmc_estimate (results are
+ * bitwise equal).  Its workspace -- 2 (L+1) doubles of level moments plus, with fields,
+ * sum_l 2 (n_l + n_{l-1}) doubles of cell moments (n_l = nx_l ny_l cells, n_{-1} = 0) -- lives
+ * in a file-scope device array of HENRY_NOALLOC_SCRATCH_DOUBLES doubles (8 MiB) that each
+ * device holds until the process ends; its address is recorded when a context is created on
+ * that device.  A larger workspace is refused with HENRY_EINVAL before any work is enqueued
+ * (levels 0..4 of 32x16 .. 512x256 cells need 436 234 doubles).  The call allocates no device
+ * or host memory; like mlmc_estimate it synchronises the context's stream to return the host
+ * scalars.  All calls on one device share the array: calls that overlap on one device (other
+ * contexts or threads) race and must be serialised by the caller. */
+#define HENRY_NOALLOC_SCRATCH_DOUBLES (1 << 20)
+HENRY_API int mlmc_estimate_noalloc(henry_ctx* ctx, int L, const int* m, const henry_grid* grids,
+                                    const double* const* g_fine, const double* const* g_coarse,
+                                    const double* const* c_fine, const double* const* c_coarse, double alpha,
+                                    double* mean, double* var_of_estimator, double* rmse, double* V_l,
+                                    double* mean_field, double* var_field);
+
 /* MLMC estimate of time-resolved QoIs (section 3 applied at every time point, eq. A) at
  * the common times t_k = (k + 1) T / r_0, k < r_0 = grids[0].nsteps, where level l's entry is
  * its step (k + 1) r_l / r_0 - 1 (every r_l a multiple of r_0) and its coarse partner's the

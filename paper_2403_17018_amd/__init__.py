@@ -177,12 +177,13 @@ class Henry:
         return q, gr, st, rc
 
     def mlmc_estimate(self, grids, g_fine, g_coarse, c_fine=None, c_coarse=None, alpha: float = 1.0,
-                      out=None):
+                      noalloc: bool = False, out=None):
         """Telescoping MLMC estimate over levels 0..L (device reductions).
 
         g_fine[l], g_coarse[l] (None for l = 0): float64 CUDA tensors [m_l];
         c_fine[l]: [ny_l, nx_l, m_l]; c_coarse[l]: [ny_{l-1}, nx_{l-1}, m_l] (None for l = 0).
-        out: optional (mean_field, var_field) tensors [ny_L, nx_L] to write instead of new ones.
+        noalloc: call mlmc_estimate_noalloc (the library allocates nothing); out: optional
+        (mean_field, var_field) tensors [ny_L, nx_L] to write instead of new ones.
         """
         Lv = len(g_fine) - 1
         m = (C.c_int * (Lv + 1))(*[int(t.numel()) for t in g_fine])
@@ -203,7 +204,8 @@ class Henry:
                 var_f = torch.empty_like(mean_f)
         mean, var, rmse = C.c_double(), C.c_double(), C.c_double()
         V = (C.c_double * (Lv + 1))()
-        self._check(self._lib.mlmc_estimate(self._h, Lv, m, gr, gf, gc, cf, cc, alpha, C.byref(mean), C.byref(var), C.byref(rmse), V,
+        fn = self._lib.mlmc_estimate_noalloc if noalloc else self._lib.mlmc_estimate
+        self._check(fn(self._h, Lv, m, gr, gf, gc, cf, cc, alpha, C.byref(mean), C.byref(var), C.byref(rmse), V,
                        _ptr(mean_f), _ptr(var_f)))
         return dict(mean=mean.value, var_of_estimator=var.value, rmse=rmse.value, V=list(V), mean_field=mean_f,
                     var_field=var_f)

@@ -11,7 +11,7 @@ HENRY_OK, HENRY_EINVAL, HENRY_EDEVICE, HENRY_ENOMEM, HENRY_EUNSUPPORTED = 0, -1,
 EXPORTS = ("henry_problem_default", "henry_solver_opts_default", "henry_ctx_create", "henry_ctx_destroy",
            "henry_last_error", "henry_sample_fields", "henry_solve_batch", "henry_adjoint_batch",
            "mlmc_estimate", "mlmc_optimal_samples", "henry_autotune", "henry_profile", "henry_profile_read",
-           "mlmc_estimate_series", "mlmc_plan", "henry_assemble", "henry_jacobian_apply",
+           "mlmc_estimate_series", "mlmc_plan", "mlmc_estimate_noalloc", "henry_assemble", "henry_jacobian_apply",
            "henry_gs_pass", "henry_coarse_solve")
 PROF_CLASSES = ("assemble", "gs", "spmv", "restrict", "prolong", "band_factor", "band_solve", "dense_factor",
                 "dense_solve")
@@ -83,6 +83,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlmc_estimate.argtypes = [vp, i, P(i), P(henry_grid), P(vp), P(vp), P(vp), P(vp), d, P(d), P(d), P(d), P(d),
                                   vp, vp]
     lib.mlmc_estimate.restype = i
+    lib.mlmc_estimate_noalloc.argtypes = lib.mlmc_estimate.argtypes
+    lib.mlmc_estimate_noalloc.restype = i
     lib.mlmc_optimal_samples.argtypes = [i, P(d), P(d), d, P(C.c_longlong), P(d)]
     lib.mlmc_optimal_samples.restype = i
     lib.henry_autotune.argtypes = [vp, P(henry_problem), P(henry_solver_opts), henry_grid, i, vp, P(d)]

@@ -368,6 +368,27 @@ struct henry_ctx {
   Profiler prof;
 };
 
+// Workspace of the allocation-free MLMC estimator: a file-scope device array (each device
+// that runs the library holds its own copy until the process ends).  Host code never passes
+// the symbol itself to a kernel or copy: it uses the device address that hipGetSymbolAddress
+// returns for the current device, recorded once per device when a context is created.
+static __device__ __align__(256) double scratch[HENRY_NOALLOC_SCRATCH_DOUBLES];
+static constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch[MAX_DEVICES] = {};
+
+// Record the scratch array's address on `device` (which must be current).
+static hipError_t scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[device] = static_cast<double*>(ptr);
+  return hipSuccess;
+}
+
 // Launch `f` on stream `st` and, when profiling (and not capturing a graph), bracket
 // it with events of class `cls`.
 static thread_local bool tl_capturing = false;
@@ -1505,6 +1526,10 @@ int henry_ctx_create(henry_ctx** out, int device, void* stream) {
   if (!c) return HENRY_ENOMEM;
   c->device = device;
   c->stream = (hipStream_t)stream;
+  if (scratch_init(device) != hipSuccess) {
+    delete c;
+    return HENRY_EDEVICE;
+  }
   if (hipHostMalloc((void**)&c->h_ctrl, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return HENRY_EDEVICE;
@@ -1602,7 +1627,7 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_problem* prob, const henry_s
 
 }  // extern "C"
 
-// Body of mlmc_estimate.  `work` (device, `work_doubles`
+// Shared body of mlmc_estimate and mlmc_estimate_noalloc.  `work` (device, `work_doubles`
 // long) holds the per-level moments and the per-cell field moments; NULL: the context's own
 // buffer, grown as needed.  Host bookkeeping uses fixed arrays (no host allocation either).
 static int mlmc_estimate_impl(henry_ctx* ctx, int L, const int* m, const henry_grid* grids,
@@ -1690,6 +1715,18 @@ int mlmc_estimate(henry_ctx* ctx, int L, const int* m, const henry_grid* grids, 
   return guarded(ctx, [&]() -> int {
     return mlmc_estimate_impl(ctx, L, m, grids, g_fine, g_coarse, c_fine, c_coarse, alpha, mean, var_of_estimator,
                               rmse, V_l, mean_field, var_field, nullptr, 0);
+  });
+}
+
+int mlmc_estimate_noalloc(henry_ctx* ctx, int L, const int* m, const henry_grid* grids, const double* const* g_fine,
+                          const double* const* g_coarse, const double* const* c_fine, const double* const* c_coarse,
+                          double alpha, double* mean, double* var_of_estimator, double* rmse, double* V_l,
+                          double* mean_field, double* var_field) {
+  return guarded(ctx, [&]() -> int {
+    double* ws = (ctx->device >= 0 && ctx->device < MAX_DEVICES) ? g_scratch[ctx->device] : nullptr;
+    if (!ws) fail(HENRY_EDEVICE, "estimator scratch address not recorded for device %d", ctx->device);
+    return mlmc_estimate_impl(ctx, L, m, grids, g_fine, g_coarse, c_fine, c_coarse, alpha, mean, var_of_estimator,
+                              rmse, V_l, mean_field, var_field, ws, (size_t)HENRY_NOALLOC_SCRATCH_DOUBLES);
   });
 }
 
