@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # restriction), counted from the arrays the kernel reads and writes
 BYTES = {
     64: dict(gs=208, spmv=136, assemble=216, restrict=76, prolong=216),
-    32: dict(gs=104, spmv=136, assemble=296, restrict=38, prolong=108),
+    32: dict(gs=104, spmv=96, assemble=136, restrict=38, prolong=108),
 }
 KERNEL_NAME = dict(gs="k_gs_colour", spmv="k_spmv_dot", assemble="k_assemble", restrict="k_residual_restrict",
                    prolong="k_gs_colour (fused prolongation)")
@@ -166,15 +166,20 @@ def bench_mlmc(args):
     levels, m, seed = w["levels"], w["nsamples"], w["seed"]
     thetas = [torch.from_numpy(draw_theta(seed, k, level=l)).cuda() for l, k in zip(levels, m)]
     hx = P.Henry(0)
-    opts = P.solver_opts(mg_precision=prec, use_graphs=graphs)
+    opts = P.solver_opts(mg_precision=prec, use_graphs=graphs, step_graphs=args.step_graphs,
+                         ragged_threads=args.ragged_threads)
     for _ in range(args.warmup):
         P.mlmc_run(hx, thetas, levels, opts=opts)
     torch.cuda.synchronize()
+    n0 = hx.profile_read()["host_sync"]
     t0 = time.perf_counter()
     for _ in range(args.steps):
         est = P.mlmc_run(hx, thetas, levels, opts=opts)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    n1 = hx.profile_read()["host_sync"]
+    # every batch's implicit-Euler steps: each level and each coarse partner
+    nsteps_all = sum((48 << l) + ((48 << (l - 1)) if l > 0 else 0) for l in levels)
     work = sum(k * (48 << l) + (k * (48 << (l - 1)) if l > 0 else 0) for l, k in zip(levels, m))
     out = {
         "metric": "MLMC wall time to RMSE",
@@ -185,7 +190,11 @@ def bench_mlmc(args):
         "dtype": "f64" if prec == 64 else "f64+f32mg", "data": "synthetic",
         "config": {"workload": "c4_mlmc_levels0to4: levels 0..4 (32x16..512x256 cells, 48..768 steps), "
                                "4096/1024/256/64/16 samples with coupled coarse partners (seed 3), one ragged call",
-                   "mg_precision": prec, "hip_graphs": graphs, "parallelism": "one stream per grid on one GPU"},
+                   "mg_precision": prec, "hip_graphs": graphs, "step_graphs": args.step_graphs,
+                   "parallelism": "one stream per grid on one GPU" if not args.ragged_threads
+                   else "grids one after another from one host thread"},
+        "host_syncs_per_batch_step": (n1[0] - n0[0]) / args.steps / nsteps_all,
+        "host_sync_wait_ms": (n1[2] - n0[2]) / args.steps,
         "rmse": est["rmse"], "mlmc_mean_qoi": est["mean"], "var_of_estimator": est["var_of_estimator"],
         "V_l": est["V"], "sample_timesteps_per_s": work / dt, "failed_samples": est["nfailed"],
         "roofline": None, "cpu_baseline": None,
@@ -351,7 +360,8 @@ def measure_batch(hx, theta, g, prob, opts, warmup, steps, workload, model):
                 kernel_classes_ms={k: round(v[2], 3) for k, v in prof.items()},
                 newton_its_per_step=float(st[:, 0].mean()) / g.nsteps,
                 krylov_its_per_newton=float(st[:, 1].sum() / st[:, 0].sum()),
-                max_salt_defect=float(st[:, 3].max()), failed_samples=r.nfailed, mlmc_mean_qoi=est["mean"])
+                max_salt_defect=float(st[:, 3].max()), failed_samples=r.nfailed, mlmc_mean_qoi=est["mean"],
+                _prof=prof)
 
 
 def extra_lines(hx, P, args):
@@ -367,10 +377,32 @@ def extra_lines(hx, P, args):
         th = torch.from_numpy(draw_theta(w["seed"], w["nsamples"], level=w["level"])).cuda()
         o = P.solver_opts(mg_precision=prec)
         m = measure_batch(hx, th, g, P.problem(), o, 1, 1, name, "kl")
+        m.pop("_prof")
         out[key] = {"workload": f"{name}: {g.nx}x{g.ny} cells, {g.nsteps} steps, {w['nsamples']} samples "
                                 f"(seed {w['seed']}), FP32 multigrid in FP64 BiCGStab/Newton",
                     "unit": "sample-timesteps/s", **m}
         del th
+    # the workload as named: multigrid to a 32x16 coarse grid solved by the batched dense LU with
+    # partial pivoting (four grids from 256x128); the factorisation's matrix-core roofline
+    w = WORKLOADS["c2_fp64_level3"]
+    g = P.grid(*level_grid(w["level"]))
+    th = torch.from_numpy(draw_theta(w["seed"], w["nsamples"], level=w["level"])).cuda()
+    o = P.solver_opts(coarse_nx=32, coarse_ny=16, coarse_solver=1)
+    m = measure_batch(hx, th, g, P.problem(), o, 1, 1, "c2_fp64_level3", "kl")
+    prof = m.pop("_prof")
+    nf, uf, msf = prof["dense_factor"]
+    n = 2 * 32 * 16
+    flops = uf / nf * 2.0 * n ** 3 / 3.0                  # per launch: samples x 2n^3/3
+    achieved = flops / (msf / nf * 1e-3) / 1e12
+    out["c2_named_32x16_dense_lu"] = {
+        "workload": f"c2_fp64_level3 with the 32x16 coarsest grid and the batched dense LU with partial pivoting "
+                    f"(n = {n} unknowns per sample), FP64", "unit": "sample-timesteps/s", **m,
+        "solver": solver_config(o),
+        "dense_factor_roofline": {"bound": "mfma", "kernel": "k_dense_factor", "achieved": achieved,
+                                  "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6,
+                                  "avg_launch_us": msf / nf * 1e3, "launches": nf,
+                                  "flops_per_launch": flops}}
+    del th
     w = WORKLOADS["c4_mlmc_levels0to4"]
     thetas = [torch.from_numpy(draw_theta(w["seed"], k, level=l)).cuda() for l, k in zip(w["levels"], w["nsamples"])]
     for prec in (64, 32):
@@ -397,6 +429,8 @@ def main():
     ap.add_argument("--eps", type=float, default=0.002, help="relative accuracy of the adaptive workload")
     ap.add_argument("--level", type=int, default=None, help="level of the qmc workload (default 3)")
     ap.add_argument("--graphs", type=int, default=None, help="capture BiCGStab iterations in hipGraphs (c4 default 1)")
+    ap.add_argument("--step-graphs", type=int, default=0, help="replay each step's first Newton iteration from a graph (c4)")
+    ap.add_argument("--ragged-threads", type=int, default=0, help="c4: 1 runs the grids one after another on one thread")
     ap.add_argument("--precision", type=int, default=None, help="multigrid precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra metric lines of the default run")
@@ -432,6 +466,7 @@ def main():
     opts = P.solver_opts(mg_precision=prec)
     prob = P.paper_problem() if args.model == "paper" else P.problem()
     m = measure_batch(hx, theta, g, prob, opts, args.warmup, args.steps, name, args.model)
+    m.pop("_prof")
     del theta
     out = {
         "metric": "sample-timesteps/s",

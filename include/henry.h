@@ -144,6 +144,22 @@ typedef struct {
                                  partial pivoting of the 2*cells x 2*cells matrix, one workgroup per
                                  sample, trailing updates on the matrix cores; needs 2*cells divisible
                                  by 16 and its 16-column panel in LDS (32x16 cells at most in FP64) */
+  int step_graphs;            /* 1: once a step's kernel arguments are settled (constant inflow, full
+                                 extrapolation history), its first Newton iteration -- the step's
+                                 start, assembly, one BiCGStab iteration with both halves and the
+                                 damped update, every decision taken per sample on the device -- is
+                                 replayed from one captured hipGraph, followed by one host read; only
+                                 samples that still iterate continue as usual.  Changes the iteration
+                                 path, not the discrete solution [1] */
+  int ragged_threads;         /* ragged calls with several grids: 0: one host thread (and stream) per
+                                 grid, run concurrently [0]; 1: the grids one after another from the
+                                 calling thread (for tools that cannot follow several threads) */
+  int sample_block;           /* samples per thread-block row (the kernels' tile): 0: min(S, 64), a
+                                 wavefront reads 64 samples of one cell [0]; 16 or 32: a wavefront
+                                 covers 4 or 2 neighbouring cells of 16 or 32 samples */
+  int fuse_prolong;           /* 1: the coarse-grid correction is prolonged inside the first
+                                 post-smoothing pass and never stored [1]; 0: a separate prolongation
+                                 and correction of every cell, then plain passes */
 } henry_solver_opts;
 
 /* One batch of S independent samples on one grid (ragged batches: several per call). */
@@ -285,13 +301,15 @@ HENRY_API int mlmc_plan(int Lp, const double* Ymean_abs, const double* V_l, cons
 HENRY_API int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, double eps,
                          long long* m_l, double* cost);
 
-/* Autotuner for one batch shape (ragged-batching support).  For each candidate -- coarsest
- * grid {8x4, 16x8}, smoother sweeps {1+1, 1+2, 2+2}, reduction blocks {4096, 16384},
- * hipGraphs {off, on} -- runs the first implicit-Euler step of the caller's samples
- * untimed and times the second (so a weaker but cheaper preconditioner is charged for
- * any extra Newton iterations); writes the fastest into *opts (other fields unchanged)
- * and its step time into *best_ms (host, may be NULL).  All candidates converge to the
- * same discrete solution; only speed differs.  theta: device [S][13]. */
+/* Autotuner for one batch shape (ragged-batching support).  Coordinate descent from *opts:
+ * one setting at a time over its candidates -- coarsest grid {8x4, 16x8}, smoother sweeps
+ * {1+1, 1+2, 2+2}, sample block (tile) {64, 32, 16}, prolongation fusion {on, off},
+ * reduction blocks {4096, 16384}, hipGraphs {off, on} -- keeping the fastest.  Each candidate
+ * runs the first implicit-Euler step of the caller's samples untimed and times the second
+ * (twice; the second timing counts), so a weaker but cheaper preconditioner is charged for any
+ * extra Newton iterations; writes the fastest into *opts (other fields unchanged) and its step
+ * time into *best_ms (host, may be NULL).  All candidates converge to the same discrete
+ * solution; only speed differs.  theta: device [S][13]. */
 HENRY_API int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts* opts, henry_grid grid,
                              int S, const double* theta, double* best_ms);
 
@@ -348,9 +366,12 @@ enum henry_prof_class {
   HENRY_PROF_PROLONG = 4,     /* prolongation + correction onto the fine grid */
   HENRY_PROF_BAND_FACTOR = 5, /* coarse banded LU factorisation */
   HENRY_PROF_BAND_SOLVE = 6,  /* coarse banded triangular solves */
-  HENRY_PROF_DENSE_FACTOR = 7,/* dense coarse LU: matrix expansion and pivoted factorisation (units: samples) */
+  HENRY_PROF_DENSE_FACTOR = 7,/* dense coarse LU: the pivoted factorisation (units: samples) */
   HENRY_PROF_DENSE_SOLVE = 8, /* dense coarse triangular solves (units: samples) */
-  HENRY_PROF_NCLASS = 9
+  HENRY_PROF_HOST_SYNC = 9,   /* the solver's host round trips (control reads): launches = their
+                                 number, units = 0, total_ms = host time spent waiting in them;
+                                 counted whether or not event timing is enabled */
+  HENRY_PROF_NCLASS = 10
 };
 HENRY_API int henry_profile(henry_ctx* ctx, int enable);
 HENRY_API int henry_profile_read(henry_ctx* ctx, int cls, long long* launches, long long* units, double* total_ms);

@@ -14,7 +14,7 @@ EXPORTS = ("henry_problem_default", "henry_solver_opts_default", "henry_ctx_crea
            "mlmc_estimate_series", "mlmc_plan", "mlmc_estimate_noalloc", "henry_assemble", "henry_jacobian_apply",
            "henry_gs_pass", "henry_coarse_solve")
 PROF_CLASSES = ("assemble", "gs", "spmv", "restrict", "prolong", "band_factor", "band_solve", "dense_factor",
-                "dense_solve")
+                "dense_solve", "host_sync")
 
 
 class henry_problem(C.Structure):
@@ -40,7 +40,11 @@ class henry_solver_opts(C.Structure):
                 ("newton_jac_reuse", C.c_double),
                 ("mg_cycle", C.c_int),
                 ("adjoint_guess", C.c_int),
-                ("coarse_solver", C.c_int)]
+                ("coarse_solver", C.c_int),
+                ("step_graphs", C.c_int),
+                ("ragged_threads", C.c_int),
+                ("sample_block", C.c_int),
+                ("fuse_prolong", C.c_int)]
 
 
 class henry_batch(C.Structure):

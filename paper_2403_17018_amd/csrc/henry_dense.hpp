@@ -4,7 +4,7 @@
 // The 2x2-block 5-point coarse Jacobian is expanded into a dense n x n matrix, n = 2 * cells,
 // unknown u = 2 q + component with q = j * nx + i, stored row-major per sample.
 //
-// Factorisation: one workgroup (4 wavefronts) per sample, blocked right-looking LU with
+// Factorisation: one workgroup (16 wavefronts) per sample, blocked right-looking LU with
 // partial pivoting, panel width NB.  Each panel of NB columns is factored in LDS (pivot search
 // by a fixed-order block reduction, so the pivots are run-to-run deterministic); its row
 // interchanges are then applied to every other column (LAPACK form: P A = L U with one
@@ -28,12 +28,18 @@ typedef double mf_d4 __attribute__((ext_vector_type(4)));
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 
 // 16x16x4 matrix-core step acc += a b for one wavefront: lane l supplies a = A[l % 16][l / 16]
-// and b = B[l / 16][l % 16] and holds acc[v] = C[4 (l / 16) + v][l % 16].
+// and b = B[l / 16][l % 16]; it holds acc[v] = C[mfma_row<T>(l, v)][l % 16], where the FP64
+// instruction spreads a lane's four rows 4 apart and the FP32 one keeps them adjacent
+// (both checked on the device).
 __device__ __forceinline__ void mfma16x16x4(double a, double b, mf_d4& acc) {
   acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
 }
 __device__ __forceinline__ void mfma16x16x4(float a, float b, mf_f4& acc) {
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ int mfma_row(int lane, int v) {
+  return sizeof(T) == 8 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
 }
 template <typename T>
 struct MfmaAcc;
@@ -46,8 +52,9 @@ struct MfmaAcc<float> {
   typedef mf_f4 type;
 };
 
-constexpr int DENSE_THREADS = 256;
-constexpr int DENSE_CHUNK = 64;   // trailing-update column chunk (4 MFMA tiles, one per wavefront)
+constexpr int DENSE_THREADS = 1024;  // factorisation workgroup: 16 wavefronts (one workgroup fills a CU's LDS)
+constexpr int DENSE_SOLVE_THREADS = 256;
+constexpr int DENSE_CHUNK = 64;   // trailing-update column chunk: 4 MFMA tiles, each taken by 4 wavefronts
 constexpr int DENSE_DB = 64;      // row block of the triangular solves
 
 // LDS bytes of the factorisation: the panel (n x NB), the U12 chunk (NB x CHUNK), the
@@ -188,21 +195,23 @@ __global__ void __launch_bounds__(DENSE_THREADS) k_dense_factor(int n, T* __rest
         }
       }
       __syncthreads();
-      const int col = cb + 16 * wave;   // this wavefront's 16-column tile
-      if (16 * wave < wdt) {
-        for (int r0 = k0 + NB; r0 < n; r0 += 16) {
+      // wavefront w: 16-column tile w % 4 of the chunk, every fourth 16-row tile from w / 4
+      const int ct = wave & 3, rg = wave >> 2;
+      const int col = cb + 16 * ct;
+      if (16 * ct < wdt) {
+        for (int r0 = k0 + NB + 16 * rg; r0 < n; r0 += 64) {
           acc_t acc;
-          T* Ct = A + (size_t)(r0 + 4 * (lane >> 4)) * n + col + (lane & 15);
+          T* Ct = A + (size_t)r0 * n + col + (lane & 15);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[v] = Ct[(size_t)v * n];
+          for (int v = 0; v < 4; ++v) acc[v] = Ct[(size_t)mfma_row<T>(lane, v) * n];
 #pragma unroll
           for (int kk = 0; kk < NB; kk += 4) {
             const T a = -P[(r0 - k0 + (lane & 15)) * NB + kk + (lane >> 4)];
-            const T b = Uc[(kk + (lane >> 4)) * DENSE_CHUNK + 16 * wave + (lane & 15)];
+            const T b = Uc[(kk + (lane >> 4)) * DENSE_CHUNK + 16 * ct + (lane & 15)];
             mfma16x16x4(a, b, acc);
           }
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Ct[(size_t)v * n] = acc[v];
+          for (int v = 0; v < 4; ++v) Ct[(size_t)mfma_row<T>(lane, v) * n] = acc[v];
         }
       }
       __syncthreads();
@@ -236,7 +245,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 // x = A^{-1} b (TR: x = A^{-T} b) with P A = L U from k_dense_factor, one workgroup per sample.
 // b, x: coarse-grid vectors [component][cell][S] (Nc = cells * S), T precision.
 template <typename T, bool TR>
-__global__ void __launch_bounds__(DENSE_THREADS) k_dense_solve(int S, int nc, const T* __restrict__ LU,
+__global__ void __launch_bounds__(DENSE_SOLVE_THREADS) k_dense_solve(int S, int nc, const T* __restrict__ LU,
                                                                const int* __restrict__ perm, const T* __restrict__ b,
                                                                T* __restrict__ x) {
   extern __shared__ unsigned char smem_raw[];
@@ -249,11 +258,11 @@ __global__ void __launch_bounds__(DENSE_THREADS) k_dense_solve(int S, int nc, co
   const T* A = LU + (size_t)s * n * n;
   const int* pr = perm + (size_t)s * n;
   auto at = [&](int u) { return (size_t)(u & 1) * Nc + (size_t)(u >> 1) * S + s; };
-  for (int i = t; i < n; i += DENSE_THREADS) y[i] = b[at(TR ? i : pr[i])];
+  for (int i = t; i < n; i += DENSE_SOLVE_THREADS) y[i] = b[at(TR ? i : pr[i])];
   __syncthreads();
   const int nblk = (n + DENSE_DB - 1) / DENSE_DB;
   auto load_diag = [&](int r0, int db) {
-    for (int e = t; e < db * db; e += DENSE_THREADS) {
+    for (int e = t; e < db * db; e += DENSE_SOLVE_THREADS) {
       const int i = e / db, k = e - i * db;
       D[i * DENSE_DB + k] = A[(size_t)(r0 + i) * n + r0 + k];
     }
@@ -262,7 +271,7 @@ __global__ void __launch_bounds__(DENSE_THREADS) k_dense_solve(int S, int nc, co
     // L y = P b: rows by blocks, the part left of the block as row dot products
     for (int bk = 0; bk < nblk; ++bk) {
       const int r0 = bk * DENSE_DB, db = min(DENSE_DB, n - r0);
-      for (int i = wave; i < db; i += DENSE_THREADS / 64) {
+      for (int i = wave; i < db; i += DENSE_SOLVE_THREADS / 64) {
         const T* row = A + (size_t)(r0 + i) * n;
         T a = 0;
         for (int k = lane; k < r0; k += 64) a += row[k] * y[k];
@@ -284,7 +293,7 @@ __global__ void __launch_bounds__(DENSE_THREADS) k_dense_solve(int S, int nc, co
     // U x = y: blocks from the bottom, the part right of the block as row dot products
     for (int bk = nblk - 1; bk >= 0; --bk) {
       const int r0 = bk * DENSE_DB, db = min(DENSE_DB, n - r0), r1 = r0 + db;
-      for (int i = wave; i < db; i += DENSE_THREADS / 64) {
+      for (int i = wave; i < db; i += DENSE_SOLVE_THREADS / 64) {
         const T* row = A + (size_t)(r0 + i) * n;
         T a = 0;
         for (int k = r1 + lane; k < n; k += 64) a += row[k] * y[k];
@@ -304,7 +313,7 @@ __global__ void __launch_bounds__(DENSE_THREADS) k_dense_solve(int S, int nc, co
       }
       __syncthreads();
     }
-    for (int i = t; i < n; i += DENSE_THREADS) x[at(i)] = y[i];
+    for (int i = t; i < n; i += DENSE_SOLVE_THREADS) x[at(i)] = y[i];
   } else {
     // U^T z = b: column blocks forward; each finished block updates the later entries with
     // its rows of U (axpy form: contiguous row segments)
@@ -322,7 +331,7 @@ __global__ void __launch_bounds__(DENSE_THREADS) k_dense_solve(int S, int nc, co
         if (lane < db) y[c0 + lane] = v;
       }
       __syncthreads();
-      for (int c = c1 + t; c < n; c += DENSE_THREADS) {
+      for (int c = c1 + t; c < n; c += DENSE_SOLVE_THREADS) {
         T a = 0;
         for (int r = c0; r < c1; ++r) a += A[(size_t)r * n + c] * y[r];
         y[c] -= a;
@@ -343,7 +352,7 @@ __global__ void __launch_bounds__(DENSE_THREADS) k_dense_solve(int S, int nc, co
         if (lane < db) y[c0 + lane] = v;
       }
       __syncthreads();
-      for (int c = t; c < c0; c += DENSE_THREADS) {
+      for (int c = t; c < c0; c += DENSE_SOLVE_THREADS) {
         T a = 0;
         for (int r = c0; r < c1; ++r) a += A[(size_t)r * n + c] * y[r];
         y[c] -= a;
@@ -351,7 +360,7 @@ __global__ void __launch_bounds__(DENSE_THREADS) k_dense_solve(int S, int nc, co
       __syncthreads();
     }
     // x = P^T w
-    for (int i = t; i < n; i += DENSE_THREADS) x[at(pr[i])] = y[i];
+    for (int i = t; i < n; i += DENSE_SOLVE_THREADS) x[at(pr[i])] = y[i];
   }
 }
 

@@ -8,12 +8,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <atomic>
+#include <chrono>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -155,10 +158,14 @@ struct DevBuf {
   }
 };
 
-static Map make_map(int S, int ncell, int red_blocks) {
+// Thread map of a batch: blockDim = (SX, CY) with SX samples (a sample block, at most the
+// batch) by CY = 256/SX cells.  sample_block 0: min(S, 64), i.e. a wavefront covers 64 samples
+// of one cell; 16 or 32: a wavefront covers 2 or 4 neighbouring cells of fewer samples.
+static Map make_map(int S, int ncell, int red_blocks, int sample_block = 0) {
   Map m{};
   m.S = S;
-  m.SX = S <= 64 ? S : 64;
+  const int sb = sample_block > 0 ? sample_block : 64;
+  m.SX = S <= sb ? S : sb;
   m.CY = std::max(1, 256 / m.SX);
   m.nsb = (S + m.SX - 1) / m.SX;
   // reduction kernels: CPT cells per thread so that about `red_blocks` blocks cover the batch
@@ -176,6 +183,9 @@ static dim3 grid_cells(const Map& m, int ncell) {
 }
 static dim3 grid_red(const Map& m) { return dim3((unsigned)((long long)m.nsb * m.ncb)); }
 static dim3 block_of(const Map& m) { return dim3(m.SX, m.CY); }
+// the assembly's tiles: one workgroup per (sample block, ASM_TX x ASM_TY cells)
+static dim3 asm_grid(const Map& m, const Grid2& G) { return dim3((unsigned)((long long)m.nsb * asm_tiles(G.nx, G.ny))); }
+static dim3 asm_block(const Map& m) { return dim3(m.SX, ASM_T); }
 // Finalisation launch shape: blockDim.x = min(64, S rounded up to a power of 2) samples,
 // the rest of the 64 * FIN_Y threads split each sample's partial sums.
 static int fin_sx(int S) {
@@ -273,6 +283,15 @@ struct Plan {
                                 {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int gkey[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};   // per operator: nu_pre, nu_post, precision, cycle, valid
   double grtol[2] = {0.0, 0.0};
+  // captured first Newton iteration of a time step (step_graphs) and what it was captured for
+  hipGraphExec_t step_exec = nullptr;
+  Phys step_phys{};
+  henry_solver_opts step_opts{};
+  int step_order = -1;
+  void drop_step_graph() {
+    if (step_exec) (void)hipGraphExecDestroy(step_exec);
+    step_exec = nullptr;
+  }
   void drop_graphs(int tr) {
     for (auto& g : gexec[tr])
       if (g) {
@@ -284,6 +303,7 @@ struct Plan {
   void drop_graphs() {
     drop_graphs(0);
     drop_graphs(1);
+    drop_step_graph();
   }
   ~Plan() {
     drop_graphs();
@@ -357,13 +377,15 @@ struct henry_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   // plans by (nx, ny, S, precision, coarse nx, coarse ny, reduction blocks, coarse solver,
-  // instance): batches of one call that share a shape but are solved concurrently get
-  // distinct instances
-  std::map<std::tuple<int, int, int, int, int, int, int, int, int>, std::unique_ptr<Plan>> plans;
+  // sample block, instance): batches of one call that share a shape but are solved
+  // concurrently get distinct instances
+  std::map<std::tuple<int, int, int, int, int, int, int, int, int, int>, std::unique_ptr<Plan>> plans;
   int* h_ctrl = nullptr;   // pinned
   DevBuf mlmc_tmp;
   DevBuf adj_ck, adj_seg, adj_g;   // adjoint checkpoints, segment states, sensitivities
   DevBuf kws;                      // workspace of the kernel-level entry points
+  std::atomic<long long> host_syncs{0};   // the solver's host round trips (control reads)
+  std::atomic<long long> host_sync_ns{0}; // and the host time spent waiting in them
   std::vector<hipStream_t> streams; // per-grid streams of ragged solves (default priority)
   Profiler prof;
 };
@@ -415,7 +437,7 @@ static void plan_alloc_levels(Plan& P) {
     const size_t Nk = (size_t)L.ncell * P.S;
     if (k > 0 || P.prec == 32) {
       if (k > 0) L.J.alloc(20 * Nk * sizeof(T));
-      L.x.alloc(2 * Nk * sizeof(T));
+      if (k > 0) L.x.alloc(2 * Nk * sizeof(T));   // the fine cycle writes into the caller's vector
       L.b.alloc(2 * Nk * sizeof(T));
     }
     if (k > 0) {
@@ -438,12 +460,17 @@ static void plan_alloc_levels(Plan& P) {
   }
 }
 
-// Largest dynamic LDS one workgroup may use on the current device.
+// Largest dynamic LDS one workgroup may use on the current device (the opt-in limit, which a
+// launch reaches after hipFuncSetAttribute, when it is the larger).
 static size_t max_lds_per_block() {
-  int dev = 0, v = 0;
+  int dev = 0, v = 0, o = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  return (size_t)v;
+  if (hipDeviceGetAttribute(&o, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    o = 0;
+  }
+  return (size_t)std::max(v, o);
 }
 
 // The dense factorisation needs more than the default LDS limit of a launch: raise it once
@@ -473,7 +500,7 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
   P->csolver = o.coarse_solver;
   P->G = Grid2{nx, ny, nx * ny};
   P->N = (size_t)nx * ny * S;
-  P->m = make_map(S, nx * ny, o.red_blocks);
+  P->m = make_map(S, nx * ny, o.red_blocks, o.sample_block);
   // hierarchy: halve while above the coarse size and even
   int gx = nx, gy = ny;
   while (true) {
@@ -534,17 +561,18 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
   return P;
 }
 
-using PlanKey = std::tuple<int, int, int, int, int, int, int, int, int>;
+using PlanKey = std::tuple<int, int, int, int, int, int, int, int, int, int>;
 
 static PlanKey plan_key(int nx, int ny, int S, const henry_solver_opts& o, int inst) {
   return PlanKey(nx, ny, S, o.mg_precision, std::min(o.coarse_nx, nx), std::min(o.coarse_ny, ny), o.red_blocks,
-                 o.coarse_solver, inst);
+                 o.coarse_solver, o.sample_block, inst);
 }
 
 // Widest per-sample reduction buffer any effective batch size Sa <= S needs.
-static size_t part_bytes_max(int nx, int ny, int S, int red_blocks) {
+static size_t part_bytes_max(int nx, int ny, int S, int red_blocks, int sample_block) {
   size_t mx = 0;
-  for (int Sa = 1; Sa <= S; ++Sa) mx = std::max(mx, (size_t)NSERIES * make_map(Sa, nx * ny, red_blocks).ncb * Sa * 8);
+  for (int Sa = 1; Sa <= S; ++Sa)
+    mx = std::max(mx, (size_t)NSERIES * make_map(Sa, nx * ny, red_blocks, sample_block).ncb * Sa * 8);
   return mx;
 }
 
@@ -558,7 +586,7 @@ static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_
   if (it != ctx->plans.end()) return it->second.get();
   auto P = make_plan(nx, ny, S, o);
   P->compact = make_plan(nx, ny, S, o);
-  P->compact->part.alloc(part_bytes_max(nx, ny, S, o.red_blocks));
+  P->compact->part.alloc(part_bytes_max(nx, ny, S, o.red_blocks, o.sample_block));
   Plan* raw = P.get();
   ctx->plans[key] = std::move(P);
   return raw;
@@ -566,10 +594,10 @@ static Plan* get_plan(henry_ctx* ctx, int nx, int ny, int S, const henry_solver_
 
 // Use plan Q (capacity >= Sa samples) for an effective batch of Sa samples.  Allocates
 // nothing: get_plan sized the reduction buffer for every Sa.
-static void plan_set_samples(Plan& Q, int Sa, int red_blocks) {
+static void plan_set_samples(Plan& Q, int Sa, int red_blocks, int sample_block) {
   Q.S = Sa;
   Q.N = (size_t)Q.nx * Q.ny * Sa;
-  Q.m = make_map(Sa, Q.nx * Q.ny, red_blocks);
+  Q.m = make_map(Sa, Q.nx * Q.ny, red_blocks, sample_block);
   if ((size_t)NSERIES * Q.m.ncb * Sa * 8 > Q.part.bytes) fail(HENRY_EDEVICE, "internal: compact plan undersized");
   Q.drop_graphs();
 }
@@ -604,8 +632,11 @@ struct Solver {
 
   void zero_ctrl() { hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, P.ctrl.as<int>(), 16); }
   int read_ctrl(int i) {
+    const auto t0 = std::chrono::steady_clock::now();
     HIPCHK(hipMemcpyAsync(P.h_ctrl, P.ctrl.as<int>(), 16 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    ctx->host_syncs++;
+    ctx->host_sync_ns += std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
     return P.h_ctrl[i];
   }
 
@@ -626,7 +657,7 @@ struct Solver {
   // Residual only: the Jacobian hierarchy and the coarse factors of an earlier iterate are kept.
   void assemble_residual() {
     const Map& m = P.m;
-    hipLaunchKernelGGL((k_assemble<true, double, false, false>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
+    hipLaunchKernelGGL((k_assemble<true, double, false, false>), asm_grid(m, P.G), asm_block(m), asm_lds(m.SX), st, m, P.G,
                        phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
                        P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), (double*)nullptr, (float*)nullptr);
   }
@@ -636,12 +667,16 @@ struct Solver {
   void assemble_all() {
     const Map& m = P.m;
     timed(ctx, st, HENRY_PROF_ASSEMBLE, (long long)P.N, [&] {
-      if (P.prec == 32)
-        hipLaunchKernelGGL((k_assemble<true, double, true>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
+      if (spmv32())   // only the FP32 Jacobian: the multigrid and the Krylov products read it
+        hipLaunchKernelGGL((k_assemble<true, float, false>), asm_grid(m, P.G), asm_block(m), asm_lds(m.SX), st, m, P.G,
+                           phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
+                           P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J32.as<float>(), (float*)nullptr);
+      else if (P.prec == 32)
+        hipLaunchKernelGGL((k_assemble<true, double, true>), asm_grid(m, P.G), asm_block(m), asm_lds(m.SX), st, m, P.G,
                            phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
                            P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J.as<double>(), P.J32.as<float>());
       else
-        hipLaunchKernelGGL((k_assemble<true, double, false>), grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G,
+        hipLaunchKernelGGL((k_assemble<true, double, false>), asm_grid(m, P.G), asm_block(m), asm_lds(m.SX), st, m, P.G,
                            phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
                            P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J.as<double>(), (float*)nullptr);
     });
@@ -652,7 +687,7 @@ struct Solver {
       const double* fc_ = k == 1 ? P.c.as<double>() : F.c.as<double>();
       hipLaunchKernelGGL(k_restrict_state, grid_cells(m, C.ncell), block_of(m), 0, st, m, F.G, C.G, fp_, fc_,
                          C.p.as<double>(), C.c.as<double>());
-      hipLaunchKernelGGL((k_assemble<false, T, false>), grid_cells(m, C.ncell), block_of(m), 0, st, m, C.G,
+      hipLaunchKernelGGL((k_assemble<false, T, false>), asm_grid(m, C.G), asm_block(m), asm_lds(m.SX), st, m, C.G,
                          phys_level(k), C.p.as<double>(), C.c.as<double>(), (const double*)nullptr,
                          C.phi.as<double>(), C.K.as<double>(), P.uin.as<double>(), (double*)nullptr, C.J.as<T>(),
                          (float*)nullptr);
@@ -668,9 +703,9 @@ struct Solver {
       const int n = 2 * Cc.ncell;
       const size_t lds = dense_factor_lds<T>(n, 16);
       dense_factor_prepare<T>(lds);
+      hipLaunchKernelGGL((k_dense_build<T>), dim3(n, P.S), dim3(256), 0, st, P.S, Cc.nx, Cc.ny,
+                         level_J<T>(P.nlev - 1), P.LU.as<T>());
       timed(ctx, st, HENRY_PROF_DENSE_FACTOR, (long long)P.S, [&] {
-        hipLaunchKernelGGL((k_dense_build<T>), dim3(n, P.S), dim3(256), 0, st, P.S, Cc.nx, Cc.ny,
-                           level_J<T>(P.nlev - 1), P.LU.as<T>());
         hipLaunchKernelGGL((k_dense_factor<T, 16>), dim3(P.S), dim3(DENSE_THREADS), lds, st, n, P.LU.as<T>(),
                            P.perm.as<int>());
       });
@@ -699,7 +734,7 @@ struct Solver {
     MGLevel& L = *P.lv[k];
     if (k == P.nlev - 1 && P.csolver == 1) {
       timed(ctx, st, HENRY_PROF_DENSE_SOLVE, (long long)P.S, [&] {
-        hipLaunchKernelGGL((k_dense_solve<T, TR>), dim3(P.S), dim3(DENSE_THREADS), dense_solve_lds<T>(2 * L.ncell), st,
+        hipLaunchKernelGGL((k_dense_solve<T, TR>), dim3(P.S), dim3(DENSE_SOLVE_THREADS), dense_solve_lds<T>(2 * L.ncell), st,
                            P.S, L.ncell, P.LU.as<T>(), (const int*)P.perm.as<int>(), b, x);
       });
       return;
@@ -760,9 +795,19 @@ struct Solver {
     else rr();
     const int visits = k + 2 < P.nlev ? o.mg_cycle : 1;   // the coarsest level is solved exactly
     for (int v = 0; v < visits; ++v) vcycle<T, TR>(k + 1, C.b.as<T>(), C.x.as<T>(), v == 0);
-    if (o.nu_post == 0) {
-      hipLaunchKernelGGL((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G, C.x.as<T>(),
-                         x);
+    if (o.nu_post == 0 || !o.fuse_prolong) {
+      // separate prolongation and correction of every cell, then plain post-smoothing passes
+      // (the red pass overwrites red x from the black neighbours alone)
+      auto pc = [&] {
+        hipLaunchKernelGGL((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G,
+                           C.x.as<T>(), x);
+      };
+      if (k == 0) timed(ctx, st, HENRY_PROF_PROLONG, (long long)L.ncell * P.S, pc);
+      else pc();
+      for (int sw = 0; sw < o.nu_post; ++sw) {
+        gs(0, 0);
+        gs(1, 0);
+      }
       return;
     }
     // the coarse-grid correction is folded into the first post-smoothing pass
@@ -776,7 +821,9 @@ struct Solver {
     }
   }
 
-  // out = M^{-1} in (FP64 vectors); FP32 mode converts around an FP32 V-cycle
+  // out = M^{-1} in.  FP64 mode: out holds FP64 values.  FP32 mode: the FP64 input is rounded
+  // to FP32 and the FP32 cycle writes its result straight into out's memory as FP32 values,
+  // which the SpMV and the x update read (widening them there is exact, so no FP64 copy).
   template <typename T, bool TR = false>
   void precond(const double* in, double* out) {
     if (P.prec == 32) {
@@ -784,11 +831,113 @@ struct Solver {
       const size_t n = 2 * P.N;
       const dim3 g((unsigned)((n + 255) / 256));
       hipLaunchKernelGGL((k_convert<double, float>), g, dim3(256), 0, st, n, in, L.b.as<float>());
-      vcycle<float, TR>(0, L.b.as<float>(), L.x.as<float>());
-      hipLaunchKernelGGL((k_convert<float, double>), g, dim3(256), 0, st, n, L.x.as<float>(), out);
+      vcycle<float, TR>(0, L.b.as<float>(), reinterpret_cast<float*>(out));
     } else {
       vcycle<double, TR>(0, in, out);
     }
+  }
+
+  // One BiCGStab iteration comes in three parts, each a fixed kernel sequence with no host
+  // decision inside.  A: p update, M^{-1} p, v = A p-hat, alpha, s = r - alpha v and the
+  // half-step test.  B: M^{-1} s, t = A s-hat, omega (a sample that met the tolerance at the
+  // half step keeps omega = 0, so B changes nothing for it).  C: x, r updates and the
+  // convergence test.  rh: shadow residual; black_exact: the SpMV after a cycle multiplies out
+  // red rows only (see bicgstab).
+  template <typename T, bool TR>
+  void kry_partA(int first, const double* rh, bool black_exact, double rtol2) {
+    const Map& m = P.m;
+    double* sc = P.sc.as<double>();
+    const dim3 rg = grid_red(m), bl = block_of(m), cg = grid_cells(m, P.G.ncell);
+    const dim3 fg = fin_grid(P.S), fb = fin_block(P.S);
+    if (!first)   // p0 = r0 was written by the initialisation
+      hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, 0, sc, P.vr.as<double>(), P.vv.as<double>(),
+                         P.vp.as<double>());
+    precond<T, TR>(P.vp.as<double>(), P.vph.as<double>());
+    timed(ctx, st, HENRY_PROF_SPMV, (long long)P.N, [&] {
+      spmv_pre<1, TR>(P.vph.as<double>(), P.vv.as<double>(), rh,
+                      black_exact ? (const double*)P.vp.as<double>() : nullptr);
+    });
+    hipLaunchKernelGGL(k_fin_alpha, fg, fb, 0, st, m, P.part.as<double>(), sc, P.status.as<int>());
+    // r0 is held in p (unchanged until the second iteration's p update)
+    hipLaunchKernelGGL(k_bicg_s, rg, bl, 0, st, m, P.G.ncell, sc, first ? P.vp.as<double>() : P.vr.as<double>(),
+                       P.vv.as<double>(), P.vs.as<double>(), P.part.as<double>());
+    zero_ctrl();
+    hipLaunchKernelGGL(k_fin_half, fg, fb, 0, st, m, P.part.as<double>(), sc, rtol2, P.ctrl.as<int>());
+  }
+
+  template <typename T, bool TR>
+  void kry_partB(bool black_exact) {
+    const Map& m = P.m;
+    precond<T, TR>(P.vs.as<double>(), P.vsh.as<double>());
+    timed(ctx, st, HENRY_PROF_SPMV, (long long)P.N, [&] {
+      spmv_pre<2, TR>(P.vsh.as<double>(), P.vt.as<double>(), P.vs.as<double>(),
+                      black_exact ? (const double*)P.vs.as<double>() : nullptr);
+    });
+    hipLaunchKernelGGL(k_fin_omega, fin_grid(P.S), fin_block(P.S), 0, st, m, P.part.as<double>(), P.sc.as<double>());
+  }
+
+  void kry_partC(int first, const double* rh, double rtol2) {
+    const Map& m = P.m;
+    if (P.prec == 32)
+      hipLaunchKernelGGL(k_bicg_xr<float>, grid_red(m), block_of(m), 0, st, m, P.G.ncell, first, P.sc.as<double>(),
+                         reinterpret_cast<const float*>(P.vph.p), reinterpret_cast<const float*>(P.vsh.p),
+                         P.vs.as<double>(), P.vt.as<double>(), rh, P.vx.as<double>(), P.vr.as<double>(),
+                         P.part.as<double>());
+    else
+      hipLaunchKernelGGL(k_bicg_xr<double>, grid_red(m), block_of(m), 0, st, m, P.G.ncell, first, P.sc.as<double>(),
+                         P.vph.as<double>(), P.vsh.as<double>(), P.vs.as<double>(), P.vt.as<double>(), rh,
+                         P.vx.as<double>(), P.vr.as<double>(), P.part.as<double>());
+    zero_ctrl();
+    hipLaunchKernelGGL(k_fin_rho, fin_grid(P.S), fin_block(P.S), 0, st, m, P.part.as<double>(), P.sc.as<double>(),
+                       rtol2, P.status.as<int>(), P.ctrl.as<int>());
+  }
+
+  // Start of a solve: r0 = sign * rhs (- A x0 when warm), p0 = r0, per-sample norms, the
+  // active flags and, for Newton systems, the predictive convergence test (ctrl[0]: active
+  // samples, ctrl[1]: Newton samples still iterating).
+  template <bool TR>
+  void kry_init(const double* rhs, double sign, int* mask, bool warm, bool newton, double rtol2, bool alias_rhat) {
+    const Map& m = P.m;
+    const dim3 rg = grid_red(m), bl = block_of(m);
+    if (warm) spmv<1, TR, double>(P.vx.as<double>(), P.vv.as<double>(), P.vx.as<double>(), nullptr);
+    hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, rhs, sign, warm ? (const double*)P.vv.as<double>() : nullptr,
+                       mask, alias_rhat ? (double*)nullptr : P.vrh.as<double>(), P.vp.as<double>(), P.part.as<double>());
+    zero_ctrl();
+    hipLaunchKernelGGL(k_fin_init, fin_grid(P.S), fin_block(P.S), 0, st, m, P.part.as<double>(), P.sc.as<double>(),
+                       P.ctrl.as<int>(), newton ? P.nhist.as<double>() : (double*)nullptr, mask,
+                       o.newton_tol * o.newton_predict, rtol2, alias_rhat ? sign : 1.0);
+  }
+
+  // Cycles ending in a black pass (or the exact coarse solve) leave A M^{-1} b = b on black
+  // rows, so the SpMVs after them multiply out the red rows only.  With the FP32 cycle the
+  // identity holds for the FP32 Jacobian, i.e. up to about 1e-7 relative: used only when the
+  // tolerance is far above that (the Newton systems; their residual is always FP64).
+  bool black_exact(double rtol) const { return o.nu_post >= 1 && (P.prec == 64 || rtol >= 1e-5); }
+
+  // The forward solves of the FP32-multigrid path keep only the FP32 Jacobian: the Newton
+  // systems need the operator only to the forcing term (5e-2 relative), far above FP32
+  // rounding, while Newton's residual stays FP64, so the fixed point is that of the FP64
+  // equations.  The adjoint's transposed solves (tolerance 1e-8) use the FP64 Jacobian.
+  bool fwd_fp32_jacobian = true;
+  bool spmv32() const { return P.prec == 32 && fwd_fp32_jacobian; }
+
+  // y = J x (J^T x) with per-sample dots (k_spmv_dot) on the fine grid, in the Jacobian's
+  // storage precision for these solves; x in precision TX
+  template <int NDOT, bool TR, typename TX>
+  void spmv(const TX* x, double* y, const double* d0, const double* yb) {
+    const Map& m = P.m;
+    if (spmv32())
+      hipLaunchKernelGGL((k_spmv_dot<NDOT, TR, float, TX>), grid_red(m), block_of(m), 0, st, m, P.G,
+                         (const float*)P.J32.as<float>(), x, y, d0, P.part.as<double>(), yb);
+    else
+      hipLaunchKernelGGL((k_spmv_dot<NDOT, TR, double, TX>), grid_red(m), block_of(m), 0, st, m, P.G,
+                         (const double*)P.J.as<double>(), x, y, d0, P.part.as<double>(), yb);
+  }
+  // y = J M^{-1}-output: the preconditioned vector is FP32 in the FP32-multigrid path
+  template <int NDOT, bool TR>
+  void spmv_pre(const double* xbuf, double* y, const double* d0, const double* yb) {
+    if (P.prec == 32) spmv<NDOT, TR, float>(reinterpret_cast<const float*>(xbuf), y, d0, yb);
+    else spmv<NDOT, TR, double>(xbuf, y, d0, yb);
   }
 
   // Right-preconditioned BiCGStab, per sample: A x = sign * rhs, x in vx, with A = J
@@ -797,23 +946,13 @@ struct Solver {
   // predictive convergence test; when that leaves at most `stop_at` samples iterating,
   // the solve is not started and their count is returned (else -1), so that the caller
   // can move them to a compacted batch first.
-  template <typename T, bool TR = false>
   // warm: start from the x already in vx (r0 = b - A x0); otherwise from x0 = 0.  The
   // tolerance is relative to |b| either way.
+  template <typename T, bool TR = false>
   int bicgstab(const double* rhs, double sign, int* mask, double rtol, bool newton = false, int stop_at = -1,
                bool warm = false) {
-    const Map& m = P.m;
     const int S = P.S;
-    double* sc = P.sc.as<double>();
-    int* ctrl = P.ctrl.as<int>();
-    int* status = P.status.as<int>();
-    const dim3 rg = grid_red(m), bl = block_of(m), cg = grid_cells(m, P.G.ncell);
-    const dim3 fg = fin_grid(S), fb = fin_block(S);
-    // Cycles ending in a black pass (or the exact coarse solve) leave A M^{-1} b = b on black
-    // rows, so the SpMVs after them multiply out the red rows only.  With the FP32 cycle the
-    // identity holds for the FP32 Jacobian, i.e. up to about 1e-7 relative: used only when the
-    // tolerance is far above that (the Newton systems; their residual is always FP64).
-    const bool black_exact = o.nu_post >= 1 && (P.prec == 64 || rtol >= 1e-5);
+    const bool bx = black_exact(rtol);
     const double rtol2 = rtol * rtol;
     // Newton systems (the residual buffer, cold start): the shadow residual is R itself,
     // i.e. sign * r0 (BiCGStab only uses it in ratios of dot products).  Otherwise it is a
@@ -822,59 +961,13 @@ struct Solver {
     if (alias_rhat && (rhs != P.R.as<double>() || warm || (sign != 1.0 && sign != -1.0)))
       fail(HENRY_EDEVICE, "internal: untransposed solves take the Newton residual, cold");
     const double* rh = alias_rhat ? rhs : P.vrh.as<double>();
-    // p = r0 = sign * rhs - A x0 (x0 = 0 is implicit: the first x update overwrites x)
-    if (warm)
-      hipLaunchKernelGGL((k_spmv_dot<1, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vx.as<double>(),
-                         P.vv.as<double>(), P.vx.as<double>(), P.part.as<double>(), (const double*)nullptr);
-    hipLaunchKernelGGL(k_bicg_init, rg, bl, 0, st, m, P.G.ncell, rhs, sign, warm ? (const double*)P.vv.as<double>() : nullptr,
-                       mask, alias_rhat ? (double*)nullptr : P.vrh.as<double>(), P.vp.as<double>(), P.part.as<double>());
-    zero_ctrl();
-    hipLaunchKernelGGL(k_fin_init, fg, fb, 0, st, m, P.part.as<double>(), sc, ctrl,
-                       newton ? P.nhist.as<double>() : (double*)nullptr, mask, o.newton_tol * o.newton_predict, rtol2,
-                       alias_rhat ? sign : 1.0);
+    kry_init<TR>(rhs, sign, mask, warm, newton, rtol2, alias_rhat);
     if (read_ctrl(0) == 0) {
       // nothing to solve: x = 0, or x0 already within the tolerance
       if (!warm) HIPCHK(hipMemsetAsync(P.vx.p, 0, 2 * P.N * sizeof(double), st));
       return -1;
     }
     if (newton && P.h_ctrl[1] <= stop_at) return P.h_ctrl[1];
-    // One BiCGStab iteration in three parts.  A: p update, M^{-1} p, v = A p-hat, alpha,
-    // s = r - alpha v and the half-step test.  B (skipped when every active sample met the
-    // tolerance at the half step): M^{-1} s, t = A s-hat, omega.  C: x, r updates and the
-    // convergence test.  No host sync inside a part.
-    auto partA = [&](int first) {
-      if (!first)   // p0 = r0 was written by the initialisation
-        hipLaunchKernelGGL(k_bicg_p, cg, bl, 0, st, m, P.G.ncell, 0, sc, P.vr.as<double>(), P.vv.as<double>(),
-                           P.vp.as<double>());
-      precond<T, TR>(P.vp.as<double>(), P.vph.as<double>());
-      timed(ctx, st, HENRY_PROF_SPMV, (long long)P.N, [&] {
-        hipLaunchKernelGGL((k_spmv_dot<1, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vph.as<double>(),
-                           P.vv.as<double>(), rh, P.part.as<double>(),
-                           black_exact ? (const double*)P.vp.as<double>() : nullptr);
-      });
-      hipLaunchKernelGGL(k_fin_alpha, fg, fb, 0, st, m, P.part.as<double>(), sc, status);
-      // r0 is held in p (unchanged until the second iteration's p update)
-      hipLaunchKernelGGL(k_bicg_s, rg, bl, 0, st, m, P.G.ncell, sc, first ? P.vp.as<double>() : P.vr.as<double>(),
-                         P.vv.as<double>(), P.vs.as<double>(), P.part.as<double>());
-      zero_ctrl();
-      hipLaunchKernelGGL(k_fin_half, fg, fb, 0, st, m, P.part.as<double>(), sc, rtol2, ctrl);
-    };
-    auto partB = [&]() {
-      precond<T, TR>(P.vs.as<double>(), P.vsh.as<double>());
-      timed(ctx, st, HENRY_PROF_SPMV, (long long)P.N, [&] {
-        hipLaunchKernelGGL((k_spmv_dot<2, TR>), rg, bl, 0, st, m, P.G, P.J.as<double>(), P.vsh.as<double>(),
-                           P.vt.as<double>(), P.vs.as<double>(), P.part.as<double>(),
-                           black_exact ? (const double*)P.vs.as<double>() : nullptr);
-      });
-      hipLaunchKernelGGL(k_fin_omega, fg, fb, 0, st, m, P.part.as<double>(), sc);
-    };
-    auto partC = [&](int first) {
-      hipLaunchKernelGGL(k_bicg_xr, rg, bl, 0, st, m, P.G.ncell, first, sc, P.vph.as<double>(), P.vsh.as<double>(),
-                         P.vs.as<double>(), P.vt.as<double>(), rh, P.vx.as<double>(), P.vr.as<double>(),
-                         P.part.as<double>());
-      zero_ctrl();
-      hipLaunchKernelGGL(k_fin_rho, fg, fb, 0, st, m, P.part.as<double>(), sc, rtol2, status, ctrl);
-    };
     const bool graphs = o.use_graphs && allow_graphs && !ctx->prof.on;
     if (graphs) {
       const int key[5] = {o.nu_pre, o.nu_post, P.prec, o.mg_cycle, 1};
@@ -885,42 +978,52 @@ struct Solver {
       }
       for (int part = 0; part < 5; ++part) {
         if (P.gexec[TR][part]) continue;
-        hipGraph_t g = nullptr;
-        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        tl_capturing = true;
-        try {
-          // parts 0/1: A of later/first iterations, 2: B, 3/4: C of later/first iterations
-          if (part < 2) partA(part);
-          else if (part == 2) partB();
-          else partC(part - 3);
-        } catch (...) {
-          tl_capturing = false;
-          (void)hipStreamEndCapture(st, &g);
-          if (g) (void)hipGraphDestroy(g);
-          throw;
-        }
-        tl_capturing = false;
-        HIPCHK(hipStreamEndCapture(st, &g));
-        const hipError_t e = hipGraphInstantiate(&P.gexec[TR][part], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        HIPCHK(e);
+        // parts 0/1: A of later/first iterations, 2: B, 3/4: C of later/first iterations
+        P.gexec[TR][part] = capture([&] {
+          if (part < 2) kry_partA<T, TR>(part, rh, bx, rtol2);
+          else if (part == 2) kry_partB<T, TR>(bx);
+          else kry_partC(part - 3, rh, rtol2);
+        });
       }
     }
     for (int it = 0; it < o.krylov_maxit; ++it) {
       const int first = it == 0 ? 1 : 0;
       const int first_x = first && !warm;   // x = update (x0 = 0) rather than x += update
       if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][first], st));
-      else partA(first);
+      else kry_partA<T, TR>(first, rh, bx, rtol2);
       if (read_ctrl(0) > 0) {
         if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][2], st));
-        else partB();
+        else kry_partB<T, TR>(bx);
       }
       if (graphs) HIPCHK(hipGraphLaunch(P.gexec[TR][3 + first_x], st));
-      else partC(first_x);
+      else kry_partC(first_x, rh, rtol2);
       if (read_ctrl(0) == 0) break;
     }
-    hipLaunchKernelGGL(k_accum_its, dim3((S + 255) / 256), dim3(256), 0, st, S, sc, P.stats.as<double>());
+    hipLaunchKernelGGL(k_accum_its, dim3((S + 255) / 256), dim3(256), 0, st, S, P.sc.as<double>(), P.stats.as<double>());
     return -1;
+  }
+
+  // Capture the launches `f` makes on this solver's stream as an instantiated graph.
+  template <typename F>
+  hipGraphExec_t capture(F&& f) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    tl_capturing = true;
+    try {
+      f();
+    } catch (...) {
+      tl_capturing = false;
+      (void)hipStreamEndCapture(st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    tl_capturing = false;
+    HIPCHK(hipStreamEndCapture(st, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    return ex;
   }
 
   // fields, coarse coefficients, initial state, cleared status/stats
@@ -933,50 +1036,145 @@ struct Solver {
     HIPCHK(hipMemsetAsync(P.stats.p, 0, (size_t)P.S * 4 * sizeof(double), st));
   }
 
+  // Extrapolation order of the first Newton guess at step n (-1: the inflow-aware rule of a
+  // periodic recharge); constant once enough history exists.
+  int guess_order(int n) const {
+    if (!o.newton_extrapolate) return 0;
+    if (o.newton_extrapolate >= 2 && pr.recharge_omega != 0.0) return -1;
+    if (o.newton_extrapolate >= 3) return std::min(n, o.newton_extrapolate - 1);
+    return n == 0 ? 0 : 1;
+  }
+
+  // Start of step n: c_old = c, Newton flags cleared, first guess extrapolated.  Inside a
+  // captured graph the flags are cleared by a fill kernel, not a memset node.
+  void step_prologue(int n, bool in_graph) {
+    const int S = P.S;
+    HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
+    if (in_graph) {
+      hipLaunchKernelGGL(k_zero_i32, dim3((S + 255) / 256), dim3(256), 0, st, (size_t)S, P.ndone.as<int>());
+      hipLaunchKernelGGL(k_zero_f64, dim3((2 * S + 255) / 256), dim3(256), 0, st, (size_t)2 * S, P.nhist.as<double>());
+    } else {
+      HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
+      HIPCHK(hipMemsetAsync(P.nhist.p, 0, (size_t)S * 2 * sizeof(double), st));
+    }
+    if (!o.newton_extrapolate) return;
+    // Newton starts from a polynomial extrapolation of the last steps (u^0 itself on the
+    // first step); the fixed point of the step does not depend on the guess
+    const size_t n2 = P.N;
+    const dim3 g((unsigned)((n2 + 255) / 256));
+    const int order = guess_order(n);
+    if (order >= 0 && o.newton_extrapolate >= 3) {
+      const bool h3 = o.newton_extrapolate == 4;
+      hipLaunchKernelGGL(k_extrapolate_poly, g, dim3(256), 0, st, n2, order, P.p.as<double>(), P.p_prev.as<double>(),
+                         P.p_prev2.as<double>(), h3 ? P.p_prev3.as<double>() : nullptr);
+      hipLaunchKernelGGL(k_extrapolate_poly, g, dim3(256), 0, st, n2, order, P.c.as<double>(), P.c_prev.as<double>(),
+                         P.c_prev2.as<double>(), h3 ? P.c_prev3.as<double>() : nullptr);
+      return;
+    }
+    double gp = n == 0 ? 0.0 : 1.0, gc = gp;
+    if (n > 0 && order < 0) {
+      // pressure follows the inflow almost instantly: scale its last increment by the
+      // change of the inflow factor (linear in the forcing), bounded
+      auto f = [&](int k) { return 1.0 + std::sin(pr.recharge_omega * k * phys.tau); };
+      const double d0 = f(n) - f(n - 1), d1 = f(n + 1) - f(n);
+      gp = std::fabs(d0) > 1e-3 ? std::max(-3.0, std::min(3.0, d1 / d0)) : 1.0;
+      gc = 0.0;   // c starts from c^n: its increments do not follow the inflow factor
+    }
+    hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, gp, P.p.as<double>(), P.p_prev.as<double>());
+    hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, gc, P.c.as<double>(), P.c_prev.as<double>());
+  }
+
+  // Newton update from vx: per-sample damping, convergence flags and statistics (ctrl[1]:
+  // samples still iterating, ctrl[2]: samples that want a fresh Jacobian), then u += lam dx.
+  void newton_update() {
+    const Map& m = P.m;
+    const int S = P.S;
+    hipLaunchKernelGGL(k_delta_max, grid_red(m), block_of(m), 0, st, m, P.G.ncell, P.vx.as<double>(),
+                       P.part.as<double>());
+    zero_ctrl();
+    hipLaunchKernelGGL(k_fin_newton, fin_grid(S), fin_block(S), 0, st, m, P.part.as<double>(),
+                       pr.rho0 * pr.g * pr.Ly, o.newton_tol, o.newton_dc_max, P.lam.as<double>(), P.ndone.as<int>(),
+                       P.status.as<int>(), P.stats.as<double>(), P.ctrl.as<int>(), P.nhist.as<double>(),
+                       o.newton_jac_reuse);
+    hipLaunchKernelGGL(k_newton_update, grid_cells(m, P.G.ncell), block_of(m), 0, st, m, P.G.ncell,
+                       P.lam.as<double>(), P.vx.as<double>(), P.p.as<double>(), P.c.as<double>());
+  }
+
+  // The first Newton iteration of a step as a fixed kernel sequence with every decision on
+  // the device: full assembly, exactly one BiCGStab iteration with both halves (per-sample
+  // active flags and omega = 0 after a half-step exit mask the samples that are done), the
+  // damped update and the convergence flags.  No prediction can stop a sample before its
+  // first solve (the history was cleared), so nothing needs compacting before it.
+  template <typename T>
+  void newton_first_fixed() {
+    assemble_all<T>();
+    const double rtol2 = o.krylov_rtol * o.krylov_rtol;
+    const bool bx = black_exact(o.krylov_rtol);
+    const double* rh = P.R.as<double>();
+    kry_init<false>(rh, -1.0, P.ndone.as<int>(), false, true, rtol2, true);
+    kry_partA<T, false>(1, rh, bx, rtol2);
+    kry_partB<T, false>(bx);
+    kry_partC(1, rh, rtol2);
+    hipLaunchKernelGGL(k_accum_its, dim3((P.S + 255) / 256), dim3(256), 0, st, P.S, P.sc.as<double>(),
+                       P.stats.as<double>());
+    newton_update();
+  }
+
+  static bool same_phys(const Phys& a, const Phys& b) {
+    return a.rho0 == b.rho0 && a.drho == b.drho && a.rho1 == b.rho1 && a.mu == b.mu && a.g == b.g && a.Dm == b.Dm &&
+           a.c_left == b.c_left && a.hx == b.hx && a.hy == b.hy && a.vol == b.vol && a.tau == b.tau && a.Ly == b.Ly &&
+           a.Lx == b.Lx && a.uin_fac == b.uin_fac && a.qoi_xmin == b.qoi_xmin && a.right_dir == b.right_dir;
+  }
+
+  // Replay (capturing first when the plan has none for these settings) the step graph:
+  // prologue + newton_first_fixed.  Returns after the launch; nothing is read back.
+  template <typename T>
+  void launch_step_graph(int n) {
+    const int order = guess_order(n);
+    if (!P.step_exec || !same_phys(P.step_phys, phys) || std::memcmp(&P.step_opts, &o, sizeof o) != 0 ||
+        P.step_order != order) {
+      P.drop_step_graph();
+      P.step_exec = capture([&] {
+        step_prologue(n, true);
+        newton_first_fixed<T>();
+      });
+      P.step_phys = phys;
+      P.step_opts = o;
+      P.step_order = order;
+    }
+    HIPCHK(hipGraphLaunch(P.step_exec, st));
+  }
+
   // one implicit-Euler step n -> n+1: damped Newton with multigrid-preconditioned BiCGStab
   template <typename T>
   void time_step(int n, int nsteps) {
     const Map& m = P.m;
     const int S = P.S;
-    const dim3 cg = grid_cells(m, P.G.ncell), bl = block_of(m);
-    const double p_ref = pr.rho0 * pr.g * pr.Ly;
+    const dim3 bl = block_of(m);
     if (progress_every && (n % progress_every == 0 || n == nsteps - 1)) {
       std::fprintf(stderr, "[henry] %dx%d S=%d fp%d step %d/%d\n", P.nx, P.ny, S, P.prec, n + 1, nsteps);
       std::fflush(stderr);
     }
     // implicit Euler: boundary data at the end of the step, t = (n + 1) tau
     phys.uin_fac = 1.0 + std::sin(pr.recharge_omega * (n + 1) * phys.tau);
-    HIPCHK(hipMemcpyAsync(P.c_old.p, P.c.p, P.N * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemsetAsync(P.ndone.p, 0, S * sizeof(int), st));
-    HIPCHK(hipMemsetAsync(P.nhist.p, 0, (size_t)S * 2 * sizeof(double), st));
-    if (o.newton_extrapolate) {
-      // Newton starts from a polynomial extrapolation of the last steps (u^0 itself on the
-      // first step); the fixed point of the step does not depend on the guess
-      const size_t n2 = P.N;
-      const dim3 g((unsigned)((n2 + 255) / 256));
-      double gp = n == 0 ? 0.0 : 1.0, gc = gp;
-      const bool inflow_rule = o.newton_extrapolate >= 2 && pr.recharge_omega != 0.0;
-      if (n > 0 && inflow_rule) {
-        // pressure follows the inflow almost instantly: scale its last increment by the
-        // change of the inflow factor (linear in the forcing), bounded
-        auto f = [&](int k) { return 1.0 + std::sin(pr.recharge_omega * k * phys.tau); };
-        const double d0 = f(n) - f(n - 1), d1 = f(n + 1) - f(n);
-        gp = std::fabs(d0) > 1e-3 ? std::max(-3.0, std::min(3.0, d1 / d0)) : 1.0;
-        gc = 0.0;   // c starts from c^n: its increments do not follow the inflow factor
+    // The whole first Newton iteration replayed as one graph, with one host read after it, once
+    // the step's kernel arguments no longer change: constant inflow and a settled extrapolation
+    // order (the first steps have less history).
+    const int order = guess_order(n);
+    const bool settled = order >= 0 && order == guess_order(n + 1);
+    if (o.step_graphs && allow_graphs && !ctx->prof.on && pr.recharge_omega == 0.0 && settled &&
+        o.newton_maxit > 1) {
+      launch_step_graph<T>(n);
+      const int remaining = read_ctrl(1);
+      const bool fresh = P.h_ctrl[2] > 0;
+      if (remaining > 0) {
+        if (allow_compact && 4 * remaining <= 3 * S) compact_newton<T>(remaining, 1);
+        else newton_loop<T>(1, fresh);
       }
-      if (o.newton_extrapolate >= 3 && !inflow_rule) {
-        const int order = std::min(n, o.newton_extrapolate - 1);
-        const bool h3 = o.newton_extrapolate == 4;
-        hipLaunchKernelGGL(k_extrapolate_poly, g, dim3(256), 0, st, n2, order, P.p.as<double>(), P.p_prev.as<double>(),
-                           P.p_prev2.as<double>(), h3 ? P.p_prev3.as<double>() : nullptr);
-        hipLaunchKernelGGL(k_extrapolate_poly, g, dim3(256), 0, st, n2, order, P.c.as<double>(), P.c_prev.as<double>(),
-                           P.c_prev2.as<double>(), h3 ? P.c_prev3.as<double>() : nullptr);
-      } else {
-        hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, gp, P.p.as<double>(), P.p_prev.as<double>());
-        hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, n2, gc, P.c.as<double>(), P.c_prev.as<double>());
-      }
+    } else {
+      step_prologue(n, false);
+      newton_loop<T>(0);
     }
-    newton_loop<T>(0);
     hipLaunchKernelGGL(k_balance, grid_red(m), bl, 0, st, m, P.G, phys, P.p.as<double>(), P.c.as<double>(),
                        P.c_old.as<double>(), P.phi.as<double>(), P.K.as<double>(), P.uin.as<double>(),
                        P.part.as<double>());
@@ -987,14 +1185,13 @@ struct Solver {
   // Newton iterations it0.. of the current step on this plan's batch.  Once at most
   // 3/4 of the samples are still iterating, the rest of the step runs on a compacted
   // copy of those samples (compact_newton), so converged samples cost no bandwidth.
+  // fresh0: the first of these iterations assembles J (else it keeps the Jacobian of the
+  // previous iteration: a chord step).
   template <typename T>
-  void newton_loop(int it0) {
-    const Map& m = P.m;
+  void newton_loop(int it0, bool fresh0 = true) {
     const int S = P.S;
-    const dim3 cg = grid_cells(m, P.G.ncell), bl = block_of(m);
-    const double p_ref = pr.rho0 * pr.g * pr.Ly;
     int remaining = S;
-    bool fresh = true;   // the first iteration this plan runs in a step assembles J
+    bool fresh = fresh0;
     for (int it = it0; it < o.newton_maxit && remaining > 0; ++it) {
       if (fresh) assemble_all<T>();
       else assemble_residual();
@@ -1006,13 +1203,7 @@ struct Solver {
         if (left > 0) compact_newton<T>(left, it);
         return;
       }
-      hipLaunchKernelGGL(k_delta_max, grid_red(m), bl, 0, st, m, P.G.ncell, P.vx.as<double>(), P.part.as<double>());
-      zero_ctrl();
-      hipLaunchKernelGGL(k_fin_newton, fin_grid(S), fin_block(S), 0, st, m, P.part.as<double>(), p_ref,
-                         o.newton_tol, o.newton_dc_max, P.lam.as<double>(), P.ndone.as<int>(), P.status.as<int>(),
-                         P.stats.as<double>(), P.ctrl.as<int>(), P.nhist.as<double>(), o.newton_jac_reuse);
-      hipLaunchKernelGGL(k_newton_update, cg, bl, 0, st, m, P.G.ncell, P.lam.as<double>(), P.vx.as<double>(),
-                         P.p.as<double>(), P.c.as<double>());
+      newton_update();
       remaining = read_ctrl(1);
       // chord iteration next (same J) while every iterating sample's update was small
       fresh = P.h_ctrl[2] > 0;
@@ -1035,7 +1226,7 @@ struct Solver {
     const int S = P.S;
     if (!P.compact) fail(HENRY_EDEVICE, "internal: plan without a compact sub-plan");
     Plan& Q = *P.compact;
-    plan_set_samples(Q, Sa, o.red_blocks);
+    plan_set_samples(Q, Sa, o.red_blocks, o.sample_block);
     int* idx = P.cidx.as<int>();
     hipLaunchKernelGGL(k_compact_index, dim3(1), dim3(COMPACT_THREADS), 0, st, S, P.ndone.as<int>(), idx);
     auto gather = [&](const double* src, double* dst, size_t rows) {
@@ -1065,6 +1256,7 @@ struct Solver {
     sq.phys = phys;
     sq.allow_compact = false;
     sq.allow_graphs = false;
+    sq.fwd_fp32_jacobian = fwd_fp32_jacobian;
     tl_untimed = true;
     try {
       sq.newton_loop<T>(it0);
@@ -1115,6 +1307,7 @@ struct Solver {
   // recomputes each segment and solves J_n^T lam_n = rhs_n step by step.
   template <typename T>
   void adjoint(const double* theta, int nsteps, int C, double* qoi_out, double* grad, int* status_out) {
+    fwd_fp32_jacobian = false;   // forward, recomputed and transposed solves all use the FP64 Jacobian
     const char* pe = std::getenv("HENRY_PROGRESS");
     progress_every = pe ? std::max(1, std::atoi(pe)) : 0;
     const Map& m = P.m;
@@ -1264,6 +1457,11 @@ static void check_opts(const henry_solver_opts& o) {
   if (o.adjoint_guess < 0 || o.adjoint_guess > 2) fail(HENRY_EINVAL, "adjoint_guess must be 0, 1 or 2");
   if (o.mg_cycle != 1 && o.mg_cycle != 2) fail(HENRY_EINVAL, "mg_cycle must be 1 (V) or 2 (W)");
   if (o.coarse_solver != 0 && o.coarse_solver != 1) fail(HENRY_EINVAL, "coarse_solver must be 0 (banded) or 1 (dense)");
+  if (o.step_graphs != 0 && o.step_graphs != 1) fail(HENRY_EINVAL, "step_graphs must be 0 or 1");
+  if (o.ragged_threads != 0 && o.ragged_threads != 1) fail(HENRY_EINVAL, "ragged_threads must be 0 or 1");
+  if (o.sample_block != 0 && o.sample_block != 16 && o.sample_block != 32 && o.sample_block != 64)
+    fail(HENRY_EINVAL, "sample_block must be 0, 16, 32 or 64");
+  if (o.fuse_prolong != 0 && o.fuse_prolong != 1) fail(HENRY_EINVAL, "fuse_prolong must be 0 or 1");
 }
 
 static int theta_check(henry_ctx* ctx, const double* theta, int S) {
@@ -1411,8 +1609,8 @@ static int solve_ragged(henry_ctx* ctx, const henry_problem& pr, const henry_sol
       G.err = HenryError{HENRY_EDEVICE, "unknown host exception"};
     }
   };
-  if (!multi) {
-    work(0);
+  if (!multi || o.ragged_threads == 1) {
+    for (size_t k = 0; k < groups.size(); ++k) work(k);
   } else {
     std::vector<std::thread> th;
     for (size_t k = 0; k < groups.size(); ++k) th.emplace_back(work, k);
@@ -1511,6 +1709,10 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->mg_cycle = 1;
   o->adjoint_guess = 2;
   o->coarse_solver = 0;
+  o->step_graphs = 1;
+  o->ragged_threads = 0;
+  o->sample_block = 0;
+  o->fuse_prolong = 1;
   o->newton_extrapolate = 4;
   o->newton_predict = 1.0;
   o->newton_jac_reuse = 1e-3;
@@ -1860,7 +2062,7 @@ int henry_assemble(henry_ctx* ctx, const henry_problem* prob, henry_grid grid, i
     double* uin = K + N;
     hipLaunchKernelGGL(k_fields, grid_cells(m, G.ncell), block_of(m), 0, ctx->stream, m, G, P, make_kl(*prob),
                        make_fp(*prob), theta, phi, K, uin);
-    hipLaunchKernelGGL((k_assemble<true, double, false, true>), grid_cells(m, G.ncell), block_of(m), 0, ctx->stream, m,
+    hipLaunchKernelGGL((k_assemble<true, double, false, true>), asm_grid(m, G), asm_block(m), asm_lds(m.SX), ctx->stream, m,
                        G, P, p, c, c_old, (const double*)phi, (const double*)K, (const double*)uin, R, J,
                        (float*)nullptr);
     HIPCHK(hipGetLastError());
@@ -1923,10 +2125,10 @@ static void coarse_solve_t(henry_ctx* ctx, int solver, henry_grid g, int S, cons
     hipLaunchKernelGGL((k_dense_build<T>), dim3(n, S), dim3(256), 0, st, S, g.nx, g.ny, J, LU);
     hipLaunchKernelGGL((k_dense_factor<T, 16>), dim3(S), dim3(DENSE_THREADS), lds, st, n, LU, perm);
     if (tr)
-      hipLaunchKernelGGL((k_dense_solve<T, true>), dim3(S), dim3(DENSE_THREADS), dense_solve_lds<T>(n), st, S, nc, LU,
+      hipLaunchKernelGGL((k_dense_solve<T, true>), dim3(S), dim3(DENSE_SOLVE_THREADS), dense_solve_lds<T>(n), st, S, nc, LU,
                          (const int*)perm, b, x);
     else
-      hipLaunchKernelGGL((k_dense_solve<T, false>), dim3(S), dim3(DENSE_THREADS), dense_solve_lds<T>(n), st, S, nc,
+      hipLaunchKernelGGL((k_dense_solve<T, false>), dim3(S), dim3(DENSE_SOLVE_THREADS), dense_solve_lds<T>(n), st, S, nc,
                          LU, (const int*)perm, b, x);
     return;
   }
@@ -2002,34 +2204,16 @@ int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts*
     HIPCHK(hipStreamWaitEvent(st, ev0, 0));
     const bool prof = ctx->prof.on;
     ctx->prof.on = false;
-    std::vector<henry_solver_opts> cands;
-    const int coarse[2][2] = {{8, 4}, {16, 8}};
-    const int nu[3][2] = {{1, 1}, {1, 2}, {2, 2}};
-    const int rb[2] = {4096, 16384};
-    for (auto& cg : coarse)
-      for (auto& v : nu)
-        for (int r : rb)
-          for (int gr = 0; gr < 2; ++gr) {
-            henry_solver_opts c = *opts;
-            c.coarse_nx = cg[0];
-            c.coarse_ny = cg[1];
-            c.nu_pre = v[0];
-            c.nu_post = v[1];
-            c.red_blocks = r;
-            c.use_graphs = gr;
-            cands.push_back(c);
-          }
-    double best = 1e300;
-    henry_solver_opts win = *opts;
     std::vector<PlanKey> used;
-    for (const auto& c : cands) {
+    // time of one implicit-Euler step of the caller's batch: the first step (damped start) and
+    // a repetition run untimed, so one-time costs (allocation, graph capture) are excluded and
+    // a weaker but cheaper preconditioner is charged for its extra Newton iterations
+    const int nsteps = std::max(4, grid.nsteps);
+    auto time_of = [&](const henry_solver_opts& c) -> double {
       Plan* P = get_plan(ctx, grid.nx, grid.ny, S, c);
       used.push_back(plan_key(grid.nx, grid.ny, S, c, 0));
-      Solver sv(ctx, *prob, c, *P, grid.nsteps, st);
+      Solver sv(ctx, *prob, c, *P, nsteps, st);
       float ms = 0.f;
-      // the first implicit-Euler step (damped start) is run untimed, the second is timed;
-      // a second repetition excludes one-time costs (graph capture, allocation)
-      const int nsteps = std::max(2, grid.nsteps);
       for (int rep = 0; rep < 2; ++rep) {
         sv.init(theta);
         if (c.mg_precision == 32) sv.time_step<float>(0, nsteps);
@@ -2041,11 +2225,33 @@ int henry_autotune(henry_ctx* ctx, const henry_problem* prob, henry_solver_opts*
         HIPCHK(hipEventSynchronize(ev1));
         HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
       }
-      if (ms < best) {
-        best = ms;
-        win = c;
+      return ms;
+    };
+    // coordinate descent from the caller's options: one setting at a time over its candidates,
+    // keeping the fastest (coarsest grid, smoother sweeps, thread map, prolongation fusion,
+    // reduction blocks, hipGraphs)
+    henry_solver_opts win = *opts;
+    double best = time_of(win);
+    auto sweep = [&](auto apply, const std::vector<std::array<int, 2>>& vals) {
+      for (const auto& v : vals) {
+        henry_solver_opts c = win;
+        apply(c, v);
+        if (std::memcmp(&c, &win, sizeof c) == 0) continue;
+        const double t = time_of(c);
+        if (t < best) {
+          best = t;
+          win = c;
+        }
       }
-    }
+    };
+    sweep([](henry_solver_opts& c, std::array<int, 2> v) { c.coarse_nx = v[0]; c.coarse_ny = v[1]; },
+          {{8, 4}, {16, 8}});
+    sweep([](henry_solver_opts& c, std::array<int, 2> v) { c.nu_pre = v[0]; c.nu_post = v[1]; },
+          {{1, 1}, {1, 2}, {2, 2}});
+    sweep([](henry_solver_opts& c, std::array<int, 2> v) { c.sample_block = v[0]; }, {{0, 0}, {32, 0}, {16, 0}});
+    sweep([](henry_solver_opts& c, std::array<int, 2> v) { c.fuse_prolong = v[0]; }, {{1, 0}, {0, 0}});
+    sweep([](henry_solver_opts& c, std::array<int, 2> v) { c.red_blocks = v[0]; }, {{4096, 0}, {16384, 0}});
+    sweep([](henry_solver_opts& c, std::array<int, 2> v) { c.use_graphs = v[0]; }, {{0, 0}, {1, 0}});
     // keep only the winner's plan
     const PlanKey keep = plan_key(grid.nx, grid.ny, S, win, 0);
     HIPCHK(hipStreamSynchronize(st));
@@ -2068,6 +2274,8 @@ int henry_profile(henry_ctx* ctx, int enable) {
     if (enable) {
       ctx->prof.reset();
       ctx->prof.on = true;
+      ctx->host_syncs = 0;
+      ctx->host_sync_ns = 0;
     } else {
       ctx->prof.on = false;
     }
@@ -2079,6 +2287,12 @@ int henry_profile_read(henry_ctx* ctx, int cls, long long* launches, long long* 
   return guarded(ctx, [&]() -> int {
     if (cls < 0 || cls >= HENRY_PROF_NCLASS) fail(HENRY_EINVAL, "profile class %d", cls);
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (cls == HENRY_PROF_HOST_SYNC) {
+      if (launches) *launches = ctx->host_syncs.load();
+      if (units) *units = 0;
+      if (total_ms) *total_ms = ctx->host_sync_ns.load() * 1e-6;
+      return HENRY_OK;
+    }
     auto& k = ctx->prof.c[cls];
     // drain completed pairs without dropping the class's accumulated totals
     const size_t n = k.ring.size();

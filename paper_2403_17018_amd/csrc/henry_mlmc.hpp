@@ -13,6 +13,11 @@ __global__ void k_zero_int(int* __restrict__ a, int n) {
   if (t < n) a[t] = 0;
 }
 
+__global__ void k_zero_i32(size_t n, int* __restrict__ a) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) a[t] = 0;
+}
+
 __global__ void k_check_finite(size_t n, const double* __restrict__ a, int* __restrict__ flag) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n && !isfinite(a[t])) atomicOr(flag, 1);

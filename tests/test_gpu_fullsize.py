@@ -13,15 +13,20 @@ from tests.oracle_runs import defect_bound
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 TOL = 1e-8
+# stored level-3 samples (tests/golden/make_golden.py c2, span): the first two, the extreme
+# recharge zeta (68 min, 313 max), the largest and smallest log-permeability contrast (342, 502),
+# the largest porosity contrast (478) and the last index of the batch (511)
+C2_SAMPLES = (0, 1, 68, 313, 342, 478, 502, 511)
 
 
-def _run(name, prec):
+def _run(name, prec, **okw):
     import paper_2403_17018_amd as P
     w = WORKLOADS[name]
     th = draw_theta(w["seed"], w["nsamples"], level=w["level"])
     hx = P.Henry(0)
     g = P.grid(*level_grid(w["level"]))
-    r = hx.solve(torch.from_numpy(th).cuda(), g, opts=P.solver_opts(mg_precision=prec), want_c=True, want_p=True)
+    r = hx.solve(torch.from_numpy(th).cuda(), g, opts=P.solver_opts(mg_precision=prec, **okw), want_c=True,
+                 want_p=True)
     torch.cuda.synchronize()
     out = dict(c=r.c_T.cpu().numpy(), p=r.p_T.cpu().numpy(), q=r.qoi.cpu().numpy(), st=r.stats.cpu().numpy(),
                nfailed=r.nfailed, theta=th, nsteps=g.nsteps)
@@ -52,12 +57,18 @@ def _check(out, name, samples):
 
 def test_level3_fp64_full_batch():
     """256x128 cells, 384 steps, all 512 samples of seed 1 in one batch (the benchmark workload)."""
-    _check(_run("c2_fp64_level3", 64), "c2", (0, 1))
+    _check(_run("c2_fp64_level3", 64), "c2", C2_SAMPLES)
+
+
+def test_level3_named_configuration_32x16_dense_lu():
+    """The workload as named: multigrid down to a 32x16 coarsest grid (4 grids from 256x128)
+    solved by the batched dense LU with partial pivoting, all 512 samples in one batch."""
+    _check(_run("c2_fp64_level3", 64, coarse_nx=32, coarse_ny=16, coarse_solver=1), "c2", C2_SAMPLES)
 
 
 def test_level3_fp32_multigrid_full_batch():
     """Same workload with the FP32 multigrid preconditioner inside FP64 BiCGStab/Newton."""
-    _check(_run("c2_fp64_level3", 32), "c2", (0, 1))
+    _check(_run("c2_fp64_level3", 32), "c2", C2_SAMPLES)
 
 
 def test_level4_fp32_multigrid_full_batch():

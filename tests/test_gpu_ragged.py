@@ -127,3 +127,50 @@ def test_autotune_returns_a_valid_faster_config(hx):
     assert a.nfailed == 0 and b.nfailed == 0
     ca, cb = a.c_T.cpu().numpy(), b.c_T.cpu().numpy()
     assert np.abs(ca - cb).max() <= 1e-8 * np.abs(cb).max()
+
+
+def _host_syncs(hx):
+    return hx.profile_read()["host_sync"][0]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_step_graphs_match_oracle_and_eager_series(hx, prec):
+    """Steps whose first Newton iteration is replayed from one captured graph (device-side
+    control, one host read per step): c and p at T against the oracle (1e-8), and the salt
+    masses after every step against the eager solve, so each of the replays -- with eager
+    continuation iterations, balance kernels and host reads between them -- is checked; the
+    replayed path needs fewer host round trips."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(0, 16)
+    g = P.level_grid(0)
+    ref = oracle_batch(th, g.nx, g.ny, g.nsteps)
+    out = {}
+    for sg in (0, 1):
+        n0 = _host_syncs(hx)
+        r = hx.solve(_cu(th), g, opts=P.solver_opts(mg_precision=prec, step_graphs=sg), want_p=True,
+                     want_series=True)
+        torch.cuda.synchronize()
+        out[sg] = (r, _host_syncs(hx) - n0)
+        assert r.nfailed == 0
+        c = r.c_T.permute(2, 0, 1).cpu().numpy()
+        p = r.p_T.permute(2, 0, 1).cpu().numpy()
+        assert rel_inf(c, ref["c"]).max() <= 1e-8 and rel_inf(p, ref["p"]).max() <= 1e-8, sg
+    se, sg_ = out[0][0].series.cpu().numpy(), out[1][0].series.cpu().numpy()   # [nsteps, 17, S]
+    mass = [0] + list(range(2, 17))                                               # Q_S and the box masses
+    for k in range(g.nsteps):
+        a, b = se[k, mass], sg_[k, mass]
+        assert np.abs(a - b).max() <= 1e-8 * np.abs(a).max(), k
+    assert out[1][1] < out[0][1], (out[1][1], out[0][1])
+
+
+def test_ragged_threads_sequential_equals_concurrent(hx):
+    """The grids of a ragged call run from the calling thread one after another give bitwise
+    the results of one host thread per grid."""
+    import paper_2403_17018_amd as P
+    prob = P.problem(T=6000.0)
+    a, b = draw_theta(63, 12), draw_theta(64, 5)
+    items = [(_cu(a), P.grid(32, 16, 8)), (_cu(b), P.grid(64, 32, 16))]
+    r0 = hx.solve_ragged(items, prob, P.solver_opts(ragged_threads=0), want_p=True)
+    r1 = hx.solve_ragged(items, prob, P.solver_opts(ragged_threads=1), want_p=True)
+    for x, y in zip(r0, r1):
+        assert torch.equal(x.c_T, y.c_T) and torch.equal(x.p_T, y.p_T) and torch.equal(x.stats, y.stats)

@@ -113,6 +113,24 @@ def test_ragged_shape_multigrid_matches_oracle(hx):
         assert rel_inf(p, ref["p"]).max() <= TOL, (prec, cycle)
 
 
+def test_tile_shapes_and_unfused_prolongation_match_oracle(hx):
+    """The autotuner's other kernel schedules on the ragged shape (37 samples, 48x24): sample
+    blocks of 32 and 16 (a wavefront covers 2 or 4 neighbouring cells; 37 samples leave ragged
+    sample blocks) and the prolongation as its own kernel instead of folded into the first
+    post-smoothing pass, FP64 and FP32 multigrid, with and without step graphs."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(5, 37)
+    g = P.grid(48, 24, 8)
+    kw = dict(T=6000.0)
+    ref = oracle_batch(th, g.nx, g.ny, g.nsteps, kw)
+    for okw in (dict(sample_block=32), dict(sample_block=16, mg_precision=32), dict(fuse_prolong=0),
+                dict(fuse_prolong=0, mg_precision=32, step_graphs=0), dict(sample_block=16, fuse_prolong=0)):
+        r, c, p = _solve(hx, th, g, kw, **okw)
+        assert r.nfailed == 0, okw
+        assert rel_inf(c, ref["c"]).max() <= TOL, okw
+        assert rel_inf(p, ref["p"]).max() <= TOL, okw
+
+
 def test_every_first_guess_reaches_the_oracle_fixed_point(hx):
     """Level 1 (64x32 cells, 96 steps), 8 samples: Newton started from u^n and from the
     linear, quadratic and cubic extrapolations of the last steps; the guess changes the

@@ -63,6 +63,8 @@ def test_defaults_match_the_workload_constants():
     assert o.newton_tol == 1e-9 and o.krylov_rtol == 5e-2 and o.newton_maxit == 200 and o.newton_extrapolate == 4 and o.newton_predict == 1.0
     assert o.newton_jac_reuse == 1e-3 and o.newton_dc_max == 2.0 and o.krylov_rtol_adjoint == 1e-8
     assert o.mg_cycle == 1 and o.adjoint_guess == 2
+    assert o.coarse_solver == 0 and o.step_graphs == 1 and o.ragged_threads == 0
+    assert p.qoi_xmin == 1.0
 
 
 def test_optimal_samples_host_helper_matches_oracle():
