@@ -27,14 +27,10 @@ sys.path.insert(0, ROOT)
 
 from henry_inputs import WORKLOADS, draw_theta, level_grid  # noqa: E402
 
-HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-# algorithmic bytes per unit of each kernel class (FP64 / FP32 multigrid): the values each
-# launch must move per cell-sample (per swept cell for the smoother, per fine cell for the
-# restriction), counted from the arrays the kernel reads and writes
-BYTES = {
-    64: dict(gs=208, spmv=136, assemble=216, restrict=76, prolong=216),
-    32: dict(gs=104, spmv=96, assemble=136, restrict=38, prolong=108),
-}
+# HBM peak and the algorithmic bytes per unit of each kernel class (FP64 / FP32 multigrid)
+from paper_2403_17018_amd.metrics import BYTES_PER_UNIT as BYTES, HBM_PEAK_GBS, MetricsLog, batch_record  # noqa: E402
+
+METRICS = None   # MetricsLog of --metrics: one JSON line per measured batch
 KERNEL_NAME = dict(gs="k_gs_colour", spmv="k_spmv_dot", assemble="k_assemble", restrict="k_residual_restrict",
                    prolong="k_gs_colour (fused prolongation)")
 
@@ -130,8 +126,9 @@ print(json.dumps(dict(mode=mode, njobs=len(jobs), wall=time.perf_counter() - t0,
 def solver_config(o):
     """The solver settings that ran, for the config label."""
     return {"coarse_grid": f"{o.coarse_nx}x{o.coarse_ny}",
-            "coarse_solver": "dense LU with partial pivoting" if getattr(o, "coarse_solver", 0) == 1
-            else "block-banded LU without pivoting",
+            "coarse_solver": {1: "dense LU with partial pivoting",
+                              2: "LU with partial pivoting in band storage (the dense elimination's pivots)"}.get(
+                getattr(o, "coarse_solver", 0), "block-banded LU without pivoting"),
             "smoother": f"red-black 2x2-block Gauss-Seidel, {o.nu_pre} pre + {o.nu_post} post sweeps",
             "cycle": "V" if o.mg_cycle == 1 else "W",
             "krylov": f"right-preconditioned BiCGStab, forcing term {o.krylov_rtol:g}",
@@ -178,6 +175,16 @@ def bench_mlmc(args):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     n1 = hx.profile_read()["host_sync"]
+    if METRICS is not None:
+        k = 0
+        for l, lev in enumerate(levels):
+            g = P.level_grid(lev)
+            METRICS.write(batch_record(f"c4 level {lev}", g, est["results"][k], mg_precision=prec, call_seconds=dt))
+            k += 1
+            if l > 0:
+                METRICS.write(batch_record(f"c4 level {lev} coarse partner", P.level_grid(levels[l - 1]),
+                                           est["results"][k], mg_precision=prec, call_seconds=dt))
+                k += 1
     # every batch's implicit-Euler steps: each level and each coarse partner
     nsteps_all = sum((48 << l) + ((48 << (l - 1)) if l > 0 else 0) for l in levels)
     work = sum(k * (48 << l) + (k * (48 << (l - 1)) if l > 0 else 0) for l, k in zip(levels, m))
@@ -346,6 +353,9 @@ def measure_batch(hx, theta, g, prob, opts, warmup, steps, workload, model):
     prof = hx.profile_read()
     hx.profile(False)
     dt = (t1 - t0) / steps
+    if METRICS is not None:
+        METRICS.write(batch_record(workload, g, r, seconds=dt, prof=prof, mg_precision=prec, timed_runs=steps,
+                                   coarse=f"{opts.coarse_nx}x{opts.coarse_ny}", coarse_solver=opts.coarse_solver))
     st = r.stats.cpu()
     cls = max(BYTES[prec], key=lambda k: prof[k][2])      # dominant kernel class by summed time
     n, units, ms = prof[cls]
@@ -402,6 +412,17 @@ def extra_lines(hx, P, args):
                                   "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6,
                                   "avg_launch_us": msf / nf * 1e3, "launches": nf,
                                   "flops_per_launch": flops}}
+    # the same named configuration with the elimination in band storage: the dense LU's pivots
+    # and factors, without its work on the zeros outside the band
+    o = P.solver_opts(coarse_nx=32, coarse_ny=16, coarse_solver=2)
+    m = measure_batch(hx, th, g, P.problem(), o, 1, 1, "c2_fp64_level3", "kl")
+    prof = m.pop("_prof")
+    out["c2_named_32x16_pivoted_band_lu"] = {
+        "workload": f"c2_fp64_level3 with the 32x16 coarsest grid and Gaussian elimination with partial pivoting "
+                    f"in band storage (n = {n}, 2 x 33 diagonals, pivots as the dense LU's), FP64",
+        "unit": "sample-timesteps/s", **m, "solver": solver_config(o),
+        "coarse_ms": {"factor": prof["band_factor"][2], "factor_launches": prof["band_factor"][0],
+                      "solve": prof["band_solve"][2], "solve_launches": prof["band_solve"][0]}}
     del th
     w = WORKLOADS["c4_mlmc_levels0to4"]
     thetas = [torch.from_numpy(draw_theta(w["seed"], k, level=l)).cuda() for l, k in zip(w["levels"], w["nsamples"])]
@@ -436,7 +457,13 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the extra metric lines of the default run")
     ap.add_argument("--model", default="kl", choices=["kl", "paper"],
                     help="input model: KL fields (the workloads) or the paper's section-4 model")
+    ap.add_argument("--metrics", default=None, metavar="FILE",
+                    help="append one JSON line per measured batch (iteration histograms, kernel classes, "
+                         "throughput, mass balance) to FILE")
     args = ap.parse_args()
+    global METRICS
+    if args.metrics:
+        METRICS = MetricsLog(args.metrics)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(samples would shard across GPUs with one all-reduce of the MLMC sums)", file=sys.stderr)

@@ -112,7 +112,8 @@ typedef struct {
                             sample, tested after each half step [5e-2]; Newton's own stopping
                             test fixes the accuracy */
   int krylov_maxit;      /* [60] */
-  double c_range_tol;    /* status 4 when c leaves [-tol, 1+tol] [1e-8] */
+  double c_range_tol;    /* status 4 when c leaves [-tol, 1+tol] after a step; a flag only, the
+                            sample goes on (a negative tol narrows the range) [1e-8] */
   int use_graphs;        /* capture each Krylov iteration in a hipGraph and replay it [0] */
   int red_blocks;        /* target thread blocks of the per-sample reduction kernels [4096] */
   double krylov_rtol_adjoint; /* BiCGStab tolerance of the transposed (adjoint) systems [1e-8] */
@@ -143,7 +144,11 @@ typedef struct {
                                  bandwidth coarse ny), one wavefront per sample [0].  1: dense LU with
                                  partial pivoting of the 2*cells x 2*cells matrix, one workgroup per
                                  sample, trailing updates on the matrix cores; needs 2*cells divisible
-                                 by 16 and its 16-column panel in LDS (32x16 cells at most in FP64) */
+                                 by 16 and its 16-column panel in LDS (32x16 cells at most in FP64).
+                                 2: the same elimination with partial pivoting in band storage (cells
+                                 ordered i-major: kl = ku = 2 coarse_ny + 1 scalar diagonals; the
+                                 dense LU's pivots and factors without its work on the zeros outside
+                                 the band), one workgroup per sample; needs coarse_ny <= 31 */
   int step_graphs;            /* 1: once a step's kernel arguments are settled (constant inflow, full
                                  extrapolation history), its first Newton iteration -- the step's
                                  start, assembly, one BiCGStab iteration with both halves and the
@@ -160,6 +165,11 @@ typedef struct {
   int fuse_prolong;           /* 1: the coarse-grid correction is prolonged inside the first
                                  post-smoothing pass and never stored [1]; 0: a separate prolongation
                                  and correction of every cell, then plain passes */
+  double krylov_breakdown;    /* near-breakdown guard of BiCGStab: a sample stops with status 2 when
+                                 |(r-hat, A M^-1 p)| <= krylov_breakdown * |rho|, i.e. when the step
+                                 length |alpha| would reach 1 / krylov_breakdown; the exact zeros
+                                 (rho, omega or (r-hat, A M^-1 p) vanishing, or a non-finite value)
+                                 stop it whatever the value.  >= 0 [0] */
 } henry_solver_opts;
 
 /* One batch of S independent samples on one grid (ragged batches: several per call). */
@@ -343,8 +353,9 @@ HENRY_API int henry_gs_pass(henry_ctx* ctx, henry_grid grid, int S, const double
                             int colour, int transpose);
 
 /* Direct solve of a block operator on a coarse grid (Gaussian elimination, section 2.3):
- * x = J^{-1} b (or J^{-T} b) with solver 0 (block-banded LU without pivoting) or 1 (dense LU
- * with partial pivoting), factored and solved in `precision` 64 or 32 (J and b are rounded to
+ * x = J^{-1} b (or J^{-T} b) with solver 0 (block-banded LU without pivoting), 1 (dense LU
+ * with partial pivoting) or 2 (LU with partial pivoting in band storage), factored and solved
+ * in `precision` 64 or 32 (J and b are rounded to
  * FP32 first in the latter).  J: device FP64 [20][ny][nx][S] as in henry_assemble; b, x:
  * device FP64 [2][ny][nx][S].  HENRY_EUNSUPPORTED when the grid does not fit the solver. */
 HENRY_API int henry_coarse_solve(henry_ctx* ctx, int solver, int precision, henry_grid coarse, int S, const double* J,

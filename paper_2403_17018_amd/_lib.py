@@ -44,7 +44,8 @@ class henry_solver_opts(C.Structure):
                 ("step_graphs", C.c_int),
                 ("ragged_threads", C.c_int),
                 ("sample_block", C.c_int),
-                ("fuse_prolong", C.c_int)]
+                ("fuse_prolong", C.c_int),
+                ("krylov_breakdown", C.c_double)]
 
 
 class henry_batch(C.Structure):

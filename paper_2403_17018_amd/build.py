@@ -23,12 +23,14 @@ FLAGS = [
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+# roctx ranges per solve, grid and time step (rocprofiler-sdk's marker library)
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def build(verbose: bool = False) -> str:
     src = os.path.join(CSRC, "henry_lib.hip")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, src]
+    cmd = [HIPCC, *FLAGS, "-o", tmp, src, *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -866,7 +866,8 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_init(Map m, const double* __
 }
 
 __global__ void __launch_bounds__(64 * FIN_Y) k_fin_alpha(Map m, const double* __restrict__ part,
-                                                          double* __restrict__ sc, int* __restrict__ status) {
+                                                          double* __restrict__ sc, double breakdown,
+                                                          int* __restrict__ status) {
   __shared__ double lds[64 * FIN_Y];
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double v[1];
@@ -875,10 +876,11 @@ __global__ void __launch_bounds__(64 * FIN_Y) k_fin_alpha(Map m, const double* _
     const int S = m.S;
     double al = 0.0;
     if (sc[SC_ACTIVE * S + s] != 0.0) {
-      if (v[0] != 0.0 && isfinite(v[0])) {
-        al = sc[SC_RHO * S + s] / v[0];
+      const double rho = sc[SC_RHO * S + s];
+      if (v[0] != 0.0 && isfinite(v[0]) && !(fabs(v[0]) <= breakdown * fabs(rho))) {
+        al = rho / v[0];
       } else {
-        sc[SC_ACTIVE * S + s] = 0.0;   // breakdown: (rhat, A p) = 0
+        sc[SC_ACTIVE * S + s] = 0.0;   // (near) breakdown: (rhat, A p) = 0 or |alpha| >= 1/breakdown
         if (status) status[s] = 2;
       }
     }

@@ -25,14 +25,34 @@
 #include <tuple>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/henry.h"
 #include "henry_kernels.hpp"
 #include "henry_coarse.hpp"
 #include "henry_dense.hpp"
+#include "henry_gbsv.hpp"
 #include "henry_mlmc.hpp"
 #include "henry_adjoint.hpp"
 
 using namespace henry;
+
+// A roctx range for the lifetime of the object (rocprofv3 --marker-trace shows them): one per
+// solve call, per grid of a ragged call, per forward time step and per reverse adjoint step.
+// Ranges nest per host thread; without a tool attached the calls return at once.
+struct Range {
+  explicit Range(const char* fmt, ...) {
+    char b[112];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(b, sizeof b, fmt, ap);
+    va_end(ap);
+    roctxRangePushA(b);
+  }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 // ---------------------------------------------------------------------------
 // errors
@@ -258,7 +278,8 @@ struct MGLevel {
 
 struct Plan {
   int nx, ny, S, prec, cnx, cny;
-  int csolver;             // coarse solver: 0 banded LU, 1 dense LU with partial pivoting
+  int csolver;             // coarse solver: 0 banded LU, 1 dense LU with partial pivoting, 2 band LU with
+                           // partial pivoting
   size_t N;
   Map m;
   Grid2 G;
@@ -454,6 +475,10 @@ static void plan_alloc_levels(Plan& P) {
     P.lu_stride = n * n;
     P.LU.alloc(P.lu_stride * P.S * sizeof(T));
     P.perm.alloc(n * P.S * sizeof(int));
+  } else if (P.csolver == 2) {
+    P.lu_stride = gb_stride(C.nx, C.ny);
+    P.LU.alloc(P.lu_stride * P.S * sizeof(T));
+    P.perm.alloc(2 * (size_t)C.ncell * P.S * sizeof(int));
   } else {
     P.lu_stride = (size_t)C.ncell * (2 * P.mb + 1) * 4;
     P.LU.alloc(P.lu_stride * P.S * sizeof(T));
@@ -486,6 +511,16 @@ static void dense_factor_prepare(size_t lds) {
   HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_factor<T, 16>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (dev >= 0 && dev < 64) done[dev] = true;
+}
+
+// Band LU with partial pivoting: the pivot search covers kl + 1 rows in one wavefront, and the
+// factor window and the solve's staging must fit the default LDS limit of a launch.
+static void check_gb_size(int nxc, int nyc, int prec) {
+  const size_t f = prec == 32 ? gb_factor_lds<float>(nyc) : gb_factor_lds<double>(nyc);
+  const size_t sv = prec == 32 ? gb_solve_lds<float>(nxc, nyc) : gb_solve_lds<double>(nxc, nyc);
+  if (gb_kl(nyc) + 1 > 64 || f > 64 * 1024 || sv > 64 * 1024)
+    fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d too large for the pivoted band LU (2 ny + 2 <= 64 rows, LDS)", nxc,
+         nyc);
 }
 
 static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver_opts& o) {
@@ -521,6 +556,8 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
     if (n % 16) fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d: the dense LU needs 2 * cells divisible by 16", gx, gy);
     if (need > max_lds_per_block())
       fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d too large for the dense LU's LDS panel (%zu bytes)", gx, gy, need);
+  } else if (o.coarse_solver == 2) {
+    check_gb_size(gx, gy, o.mg_precision);
   } else {
     if (P->lv.back()->ny > 44) fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d: band width %d exceeds 44", gx, gy, gy);
     const int n = P->lv.back()->ncell, mb = P->lv.back()->ny;
@@ -711,6 +748,13 @@ struct Solver {
       });
       return;
     }
+    if (P.csolver == 2) {
+      timed(ctx, st, HENRY_PROF_BAND_FACTOR, (long long)Cc.ncell * P.S, [&] {
+        hipLaunchKernelGGL((k_gb_factor<T>), dim3(P.S), dim3(GB_THREADS), gb_factor_lds<T>(Cc.ny), st, P.S, Cc.nx,
+                           Cc.ny, level_J<T>(P.nlev - 1), P.LU.as<T>(), P.perm.as<int>());
+      });
+      return;
+    }
     const size_t lds = (size_t)(P.mb + 1) * (P.mb + 1) * 4 * sizeof(T);
     timed(ctx, st, HENRY_PROF_BAND_FACTOR, (long long)Cc.ncell * P.S, [&] {
       hipLaunchKernelGGL((k_band_factor<T>), dim3(P.S), dim3(64), lds, st, P.S, Cc.nx, Cc.ny, level_J<T>(P.nlev - 1),
@@ -736,6 +780,13 @@ struct Solver {
       timed(ctx, st, HENRY_PROF_DENSE_SOLVE, (long long)P.S, [&] {
         hipLaunchKernelGGL((k_dense_solve<T, TR>), dim3(P.S), dim3(DENSE_SOLVE_THREADS), dense_solve_lds<T>(2 * L.ncell), st,
                            P.S, L.ncell, P.LU.as<T>(), (const int*)P.perm.as<int>(), b, x);
+      });
+      return;
+    }
+    if (k == P.nlev - 1 && P.csolver == 2) {
+      timed(ctx, st, HENRY_PROF_BAND_SOLVE, (long long)L.ncell * P.S, [&] {
+        hipLaunchKernelGGL((k_gb_solve<T, TR>), dim3(P.S), dim3(64), gb_solve_lds<T>(L.nx, L.ny), st, P.S, L.nx, L.ny,
+                           (const T*)P.LU.as<T>(), (const int*)P.perm.as<int>(), b, x);
       });
       return;
     }
@@ -857,7 +908,8 @@ struct Solver {
       spmv_pre<1, TR>(P.vph.as<double>(), P.vv.as<double>(), rh,
                       black_exact ? (const double*)P.vp.as<double>() : nullptr);
     });
-    hipLaunchKernelGGL(k_fin_alpha, fg, fb, 0, st, m, P.part.as<double>(), sc, P.status.as<int>());
+    hipLaunchKernelGGL(k_fin_alpha, fg, fb, 0, st, m, P.part.as<double>(), sc, o.krylov_breakdown,
+                       P.status.as<int>());
     // r0 is held in p (unchanged until the second iteration's p update)
     hipLaunchKernelGGL(k_bicg_s, rg, bl, 0, st, m, P.G.ncell, sc, first ? P.vp.as<double>() : P.vr.as<double>(),
                        P.vv.as<double>(), P.vs.as<double>(), P.part.as<double>());
@@ -1151,6 +1203,7 @@ struct Solver {
     const Map& m = P.m;
     const int S = P.S;
     const dim3 bl = block_of(m);
+    const Range range("henry step %d/%d %dx%d S=%d fp%d", n + 1, nsteps, P.nx, P.ny, S, P.prec);
     if (progress_every && (n % progress_every == 0 || n == nsteps - 1)) {
       std::fprintf(stderr, "[henry] %dx%d S=%d fp%d step %d/%d\n", P.nx, P.ny, S, P.prec, n + 1, nsteps);
       std::fflush(stderr);
@@ -1377,6 +1430,7 @@ struct Solver {
         save(seg + (size_t)(n + 1 - n0) * 2 * N);
       }
       for (int n = n1; n > n0; --n) {
+        const Range range("henry adjoint step %d/%d %dx%d S=%d", n, nsteps, P.nx, P.ny, S);
         const double* un = seg + (size_t)(n - n0) * 2 * N;
         const double* um = seg + (size_t)(n - 1 - n0) * 2 * N;
         load(un);
@@ -1456,12 +1510,15 @@ static void check_opts(const henry_solver_opts& o) {
   if (o.newton_extrapolate < 0 || o.newton_extrapolate > 4) fail(HENRY_EINVAL, "newton_extrapolate must be 0..4");
   if (o.adjoint_guess < 0 || o.adjoint_guess > 2) fail(HENRY_EINVAL, "adjoint_guess must be 0, 1 or 2");
   if (o.mg_cycle != 1 && o.mg_cycle != 2) fail(HENRY_EINVAL, "mg_cycle must be 1 (V) or 2 (W)");
-  if (o.coarse_solver != 0 && o.coarse_solver != 1) fail(HENRY_EINVAL, "coarse_solver must be 0 (banded) or 1 (dense)");
+  if (o.coarse_solver < 0 || o.coarse_solver > 2)
+    fail(HENRY_EINVAL, "coarse_solver must be 0 (banded), 1 (dense) or 2 (pivoted band)");
   if (o.step_graphs != 0 && o.step_graphs != 1) fail(HENRY_EINVAL, "step_graphs must be 0 or 1");
   if (o.ragged_threads != 0 && o.ragged_threads != 1) fail(HENRY_EINVAL, "ragged_threads must be 0 or 1");
   if (o.sample_block != 0 && o.sample_block != 16 && o.sample_block != 32 && o.sample_block != 64)
     fail(HENRY_EINVAL, "sample_block must be 0, 16, 32 or 64");
   if (o.fuse_prolong != 0 && o.fuse_prolong != 1) fail(HENRY_EINVAL, "fuse_prolong must be 0 or 1");
+  if (!(o.krylov_breakdown >= 0.0) || !std::isfinite(o.krylov_breakdown))
+    fail(HENRY_EINVAL, "krylov_breakdown must be finite and >= 0");
 }
 
 static int theta_check(henry_ctx* ctx, const double* theta, int S) {
@@ -1588,6 +1645,7 @@ static int solve_ragged(henry_ctx* ctx, const henry_problem& pr, const henry_sol
   }
   auto work = [&](size_t k) {
     Group& G = *groups[k];
+    const Range range("henry grid %dx%d S=%d steps=%d", G.grid.nx, G.grid.ny, G.S, G.grid.nsteps);
     try {
       HIPCHK(hipSetDevice(ctx->device));
       Solver sv(ctx, pr, o, *plans[k], G.grid.nsteps, G.stream);
@@ -1713,6 +1771,7 @@ void henry_solver_opts_default(henry_solver_opts* o) {
   o->ragged_threads = 0;
   o->sample_block = 0;
   o->fuse_prolong = 1;
+  o->krylov_breakdown = 0.0;
   o->newton_extrapolate = 4;
   o->newton_predict = 1.0;
   o->newton_jac_reuse = 1e-3;
@@ -1792,6 +1851,7 @@ int henry_solve_batch(henry_ctx* ctx, const henry_problem* prob, const henry_sol
       if (batches[b].nsamples < 1 || !batches[b].theta) fail(HENRY_EINVAL, "batch %d: nsamples < 1 or theta NULL", b);
       if (theta_check(ctx, batches[b].theta, batches[b].nsamples)) fail(HENRY_EINVAL, "batch %d: non-finite theta", b);
     }
+    const Range range("henry_solve_batch %d batches", nbatches);
     return solve_ragged(ctx, *prob, o, batches, nbatches);
   });
 }
@@ -1810,6 +1870,7 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_problem* prob, const henry_s
     if (checkpoint_every < 1) fail(HENRY_EINVAL, "checkpoint_every must be >= 1");
     if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
     Plan* P = get_plan(ctx, grid.nx, grid.ny, S, o);
+    const Range range("henry_adjoint_batch %dx%d S=%d steps=%d", grid.nx, grid.ny, S, grid.nsteps);
     hipStream_t st = ctx_stream(ctx, 0);
     hipEvent_t ev = nullptr;
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -2132,6 +2193,18 @@ static void coarse_solve_t(henry_ctx* ctx, int solver, henry_grid g, int S, cons
                          LU, (const int*)perm, b, x);
     return;
   }
+  if (solver == 2) {
+    int* piv = reinterpret_cast<int*>(LU + gb_stride(g.nx, g.ny) * S);
+    hipLaunchKernelGGL((k_gb_factor<T>), dim3(S), dim3(GB_THREADS), gb_factor_lds<T>(g.ny), st, S, g.nx, g.ny, J, LU,
+                       piv);
+    if (tr)
+      hipLaunchKernelGGL((k_gb_solve<T, true>), dim3(S), dim3(64), gb_solve_lds<T>(g.nx, g.ny), st, S, g.nx, g.ny,
+                         (const T*)LU, (const int*)piv, b, x);
+    else
+      hipLaunchKernelGGL((k_gb_solve<T, false>), dim3(S), dim3(64), gb_solve_lds<T>(g.nx, g.ny), st, S, g.nx, g.ny,
+                         (const T*)LU, (const int*)piv, b, x);
+    return;
+  }
   const int mb = g.ny;
   hipLaunchKernelGGL((k_band_factor<T>), dim3(S), dim3(64), (size_t)(mb + 1) * (mb + 1) * 4 * sizeof(T), st, S, g.nx,
                      g.ny, J, LU);
@@ -2150,7 +2223,7 @@ int henry_coarse_solve(henry_ctx* ctx, int solver, int precision, henry_grid coa
                        const double* b, double* x, int transpose) {
   return guarded(ctx, [&]() -> int {
     if (coarse.nx < 1 || coarse.ny < 1 || S < 1 || !J || !b || !x) fail(HENRY_EINVAL, "grid, S or a NULL array");
-    if (solver != 0 && solver != 1) fail(HENRY_EINVAL, "solver must be 0 (banded) or 1 (dense)");
+    if (solver < 0 || solver > 2) fail(HENRY_EINVAL, "solver must be 0 (banded), 1 (dense) or 2 (pivoted band)");
     if (precision != 64 && precision != 32) fail(HENRY_EINVAL, "precision must be 64 or 32");
     const int nc = coarse.nx * coarse.ny, n = 2 * nc;
     const size_t N = (size_t)nc * S;
@@ -2158,12 +2231,15 @@ int henry_coarse_solve(henry_ctx* ctx, int solver, int precision, henry_grid coa
     if (solver == 1) {
       const size_t need = precision == 64 ? dense_factor_lds<double>(n, 16) : dense_factor_lds<float>(n, 16);
       if (n % 16 || need > max_lds_per_block()) fail(HENRY_EUNSUPPORTED, "grid %dx%d: no dense LU", coarse.nx, coarse.ny);
+    } else if (solver == 2) {
+      check_gb_size(coarse.nx, coarse.ny, precision);
     } else {
       if (coarse.ny > 44 || band_solve_lds<double>(nc, coarse.ny, 1) > 64 * 1024)
         fail(HENRY_EUNSUPPORTED, "grid %dx%d: no banded LU", coarse.nx, coarse.ny);
     }
-    const size_t fac = solver == 1 ? (size_t)n * n * S * tsz + (size_t)n * S * sizeof(int)
-                                   : (size_t)nc * (2 * coarse.ny + 1) * 4 * S * tsz;
+    const size_t fac = solver == 1   ? (size_t)n * n * S * tsz + (size_t)n * S * sizeof(int)
+                       : solver == 2 ? gb_stride(coarse.nx, coarse.ny) * S * tsz + (size_t)n * S * sizeof(int)
+                                     : (size_t)nc * (2 * coarse.ny + 1) * 4 * S * tsz;
     const size_t conv = precision == 32 ? (20 * N + 4 * N) * sizeof(float) : 0;   // FP32 copies of J, b and x
     ctx->kws.alloc(conv + fac);
     hipStream_t st = ctx->stream;

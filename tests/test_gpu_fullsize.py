@@ -66,6 +66,12 @@ def test_level3_named_configuration_32x16_dense_lu():
     _check(_run("c2_fp64_level3", 64, coarse_nx=32, coarse_ny=16, coarse_solver=1), "c2", C2_SAMPLES)
 
 
+def test_level3_named_configuration_32x16_pivoted_band_lu():
+    """The same 32x16 coarsest grid solved by Gaussian elimination with partial pivoting in band
+    storage (the dense elimination's pivots and factors, without its O(n^3) work)."""
+    _check(_run("c2_fp64_level3", 64, coarse_nx=32, coarse_ny=16, coarse_solver=2), "c2", C2_SAMPLES)
+
+
 def test_level3_fp32_multigrid_full_batch():
     """Same workload with the FP32 multigrid preconditioner inside FP64 BiCGStab/Newton."""
     _check(_run("c2_fp64_level3", 32), "c2", C2_SAMPLES)

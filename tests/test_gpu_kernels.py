@@ -228,7 +228,7 @@ def test_coarse_solvers_against_numpy(hx, kind):
     for nx, ny in ((8, 4), (16, 8), (32, 16)):
         J, b = _coarse_case(rng, nx, ny, S, kind)
         g = P.grid(nx, ny, 1)
-        for solver in ((0, 1) if kind == "jacobian" else (1,)):
+        for solver in ((0, 1, 2) if kind == "jacobian" else (1, 2)):
             if solver == 0 and ny > 16:
                 continue
             for prec in (64, 32):
@@ -251,15 +251,16 @@ def test_coarse_solvers_against_numpy(hx, kind):
 
 
 def test_named_configuration_32x16_dense_lu_matches_oracle(hx):
-    """The 32x16 coarsest grid with the dense pivoted LU (FP64 and FP32 multigrid) and with the
-    banded LU, on a level-2 batch (128x64 cells: 3 grids) against the oracle."""
+    """The 32x16 coarsest grid with the dense pivoted LU and the pivoted band LU (FP64 and FP32
+    multigrid each) and with the banded LU, on a level-2 batch (128x64 cells: 3 grids) against
+    the oracle."""
     import paper_2403_17018_amd as P
     th = draw_theta(75, 6, level=2)
     g = P.grid(128, 64, 30)
     T = 36000.0 * 30 / 192
     prob = P.problem(T=T)
     ref = oracle_batch(th, 128, 64, 30, dict(T=T))
-    for solver, prec in ((1, 64), (1, 32), (0, 64)):
+    for solver, prec in ((1, 64), (1, 32), (2, 64), (2, 32), (0, 64)):
         o = P.solver_opts(coarse_nx=32, coarse_ny=16, coarse_solver=solver, mg_precision=prec)
         r = hx.solve(_cu(th), g, prob, o, want_c=True, want_p=True)
         assert r.nfailed == 0
@@ -270,15 +271,16 @@ def test_named_configuration_32x16_dense_lu_matches_oracle(hx):
 
 
 def test_adjoint_with_dense_coarse_lu(hx):
-    """The transposed dense solve inside the adjoint's transposed multigrid (64x32 cells, coarse
-    32x16): the gradient equals the one with the banded coarse solver to the solve tolerance."""
+    """The transposed dense and pivoted band solves inside the adjoint's transposed multigrid
+    (64x32 cells, coarse 32x16): the gradient equals the one with the banded coarse solver to
+    the solve tolerance."""
     import paper_2403_17018_amd as P
     th = draw_theta(76, 4, level=1)
     g = P.grid(64, 32, 8)
     prob = P.problem(T=6000.0)
     tight = dict(newton_tol=1e-13, krylov_rtol=1e-12, krylov_maxit=200, newton_maxit=60, krylov_rtol_adjoint=1e-12)
     out = []
-    for solver, prec in ((0, 64), (1, 64), (1, 32)):
+    for solver, prec in ((0, 64), (1, 64), (1, 32), (2, 64), (2, 32)):
         o = P.solver_opts(coarse_nx=32, coarse_ny=16, coarse_solver=solver, mg_precision=prec, **tight)
         q, gr, st, nf = hx.adjoint(_cu(th), g, prob, o, checkpoint_every=3)
         assert nf == 0

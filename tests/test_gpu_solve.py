@@ -192,6 +192,30 @@ def test_error_paths(hx):
     assert np.array_equal(c[0], c[1]) and np.array_equal(c[0], c[2])
 
 
+def test_forced_krylov_breakdown_and_range_statuses(hx):
+    """Statuses 2 and 4 forced from the host: every sample is reported, none dropped, and the
+    range check (a flag only) leaves the solution bit for bit unchanged."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(3, 6)
+    g = P.level_grid(0)
+    r0, c0, p0 = _solve(hx, th, g)
+    assert r0.nfailed == 0 and (r0.status.cpu().numpy() == 0).all()
+    # no state keeps c inside [0.25, 0.75]: fresh water (c = 0) stays at the inland boundary
+    r4, c4, p4 = _solve(hx, th, g, c_range_tol=-0.25)
+    assert r4.nfailed == 6 and (r4.status.cpu().numpy() == 4).all()
+    assert np.array_equal(c4, c0) and np.array_equal(p4, p0)
+    assert np.array_equal(r4.qoi.cpu().numpy(), r0.qoi.cpu().numpy())
+    # a guard that no finite step length passes: every first BiCGStab iteration breaks down
+    r2, c2, _ = _solve(hx, th, g, krylov_breakdown=1e300, newton_maxit=3)
+    assert r2.nfailed == 6 and (r2.status.cpu().numpy() == 2).all()
+    assert np.isfinite(c2).all()
+    # the default guard (0) and a tiny one leave converging solves alone
+    r5, c5, _ = _solve(hx, th, g, krylov_breakdown=1e-12)
+    assert r5.nfailed == 0 and np.array_equal(c5, c0)
+    with pytest.raises(P.HenryError):
+        _solve(hx, th, g, krylov_breakdown=-1.0)
+
+
 def test_mlmc_estimate_matches_oracle(hx):
     import paper_2403_17018_amd as P
     from oracle import mlmc as M

@@ -64,6 +64,7 @@ def test_defaults_match_the_workload_constants():
     assert o.newton_jac_reuse == 1e-3 and o.newton_dc_max == 2.0 and o.krylov_rtol_adjoint == 1e-8
     assert o.mg_cycle == 1 and o.adjoint_guess == 2
     assert o.coarse_solver == 0 and o.step_graphs == 1 and o.ragged_threads == 0
+    assert o.sample_block == 0 and o.fuse_prolong == 1 and o.krylov_breakdown == 0.0
     assert p.qoi_xmin == 1.0
 
 
