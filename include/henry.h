@@ -148,7 +148,7 @@ typedef struct {
                                  2: the same elimination with partial pivoting in band storage (cells
                                  ordered i-major: kl = ku = 2 coarse_ny + 1 scalar diagonals; the
                                  dense LU's pivots and factors without its work on the zeros outside
-                                 the band), one workgroup per sample; needs coarse_ny <= 31 */
+                                 the band), one workgroup per sample; needs coarse_ny <= 19 */
   int step_graphs;            /* 1: once a step's kernel arguments are settled (constant inflow, full
                                  extrapolation history), its first Newton iteration -- the step's
                                  start, assembly, one BiCGStab iteration with both halves and the

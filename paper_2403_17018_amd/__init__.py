@@ -271,7 +271,8 @@ class Henry:
         return x
 
     def coarse_solve(self, J, b, g: henry_grid, solver: int = 1, precision: int = 64, transpose: bool = False):
-        """x = J^{-1} b (J^{-T} b) by the coarse-grid direct solver (0 banded, 1 dense pivoted LU)."""
+        """x = J^{-1} b (J^{-T} b) by the coarse-grid direct solver (0 banded, 1 dense pivoted LU, 2 pivoted
+        band LU)."""
         S = b.shape[-1]
         self._f64(J, (20, g.ny, g.nx, S), "J")
         self._f64(b, (2, g.ny, g.nx, S), "b")

@@ -37,7 +37,7 @@ __device__ __forceinline__ void band_orig(const T* __restrict__ J, size_t N, int
 template <typename T>
 __global__ void __launch_bounds__(64) k_band_factor(int S, int nxc, int nyc, const T* __restrict__ J,
                                                     T* __restrict__ LU) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* W = reinterpret_cast<T*>(smem_raw);
   const int s = blockIdx.x;
   const int lane = threadIdx.x;
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(64) k_band_factor(int S, int nxc, int nyc, con
 template <typename T>
 __global__ void __launch_bounds__(64) k_band_solve(int S, int nxc, int nyc, int CH, const T* __restrict__ LU,
                                                    const T* __restrict__ b, T* __restrict__ x) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int s = blockIdx.x;
   const int lane = threadIdx.x;
   const int n = nxc * nyc, mb = nyc;
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(64) k_band_solve(int S, int nxc, int nyc, int 
 template <typename T>
 __global__ void __launch_bounds__(64) k_band_solve_T(int S, int nxc, int nyc, int CH, const T* __restrict__ LU,
                                                      const T* __restrict__ b, T* __restrict__ x) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int s = blockIdx.x;
   const int lane = threadIdx.x;
   const int n = nxc * nyc, mb = nyc;

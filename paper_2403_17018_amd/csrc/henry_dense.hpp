@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(256) k_dense_build(int S, int nxc, int nyc, co
 // trailing update works on whole 16 x 16 matrix-core tiles).
 template <typename T, int NB>
 __global__ void __launch_bounds__(DENSE_THREADS) k_dense_factor(int n, T* __restrict__ LU, int* __restrict__ perm) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* P = reinterpret_cast<T*>(smem_raw);                 // panel [n - k0][NB]
   T* Uc = P + (size_t)n * NB;                            // U12 chunk [NB][DENSE_CHUNK]
   T* rv = Uc + NB * DENSE_CHUNK;                         // pivot search values [DENSE_THREADS]
@@ -248,7 +248,7 @@ template <typename T, bool TR>
 __global__ void __launch_bounds__(DENSE_SOLVE_THREADS) k_dense_solve(int S, int nc, const T* __restrict__ LU,
                                                                const int* __restrict__ perm, const T* __restrict__ b,
                                                                T* __restrict__ x) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = 2 * nc;
   T* y = reinterpret_cast<T*>(smem_raw);   // [n]
   T* D = y + n;                            // diagonal block [DENSE_DB][DENSE_DB]

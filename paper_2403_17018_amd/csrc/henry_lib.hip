@@ -518,8 +518,8 @@ static void dense_factor_prepare(size_t lds) {
 static void check_gb_size(int nxc, int nyc, int prec) {
   const size_t f = prec == 32 ? gb_factor_lds<float>(nyc) : gb_factor_lds<double>(nyc);
   const size_t sv = prec == 32 ? gb_solve_lds<float>(nxc, nyc) : gb_solve_lds<double>(nxc, nyc);
-  if (gb_kl(nyc) + 1 > 64 || f > 64 * 1024 || sv > 64 * 1024)
-    fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d too large for the pivoted band LU (2 ny + 2 <= 64 rows, LDS)", nxc,
+  if (gb_kl(nyc) + 1 > 64 || gb_kl(nyc) * 2 * gb_kl(nyc) > GB_THREADS * GB_UPD || f > 64 * 1024 || sv > 64 * 1024)
+    fail(HENRY_EUNSUPPORTED, "coarsest grid %dx%d too large for the pivoted band LU (ny <= 19 and the LDS limit)", nxc,
          nyc);
 }
 
