@@ -438,6 +438,29 @@ def extra_lines(hx, P, args):
                         "4096/1024/256/64/16 samples with coupled coarse partners (seed 3), one ragged call",
             "metric": "MLMC wall time to RMSE", "unit": "s", "value": time.perf_counter() - t0,
             "rmse": est["rmse"], "mlmc_mean_qoi": est["mean"], "failed_samples": est["nfailed"]}
+    # the paper's own discretisation (vertex-centred finite volumes, section 2.3) on level 1 of
+    # its Table 2 (64 x 32 elements, 2145 vertices, 376 steps of 16 s) with its own model
+    g = P.vc_level_grid(1)
+    S = 128
+    th = torch.from_numpy(draw_theta(5, S)).cuda()
+    o = P.solver_opts(krylov_maxit=1000)
+    hx.vc_solve(th, P.grid(g.nx, g.ny, 4), P.paper_problem(T=6016.0 * 4 / g.nsteps), o, want_c=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = hx.vc_solve(th, g, P.paper_problem(), o, want_c=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = r.stats.cpu()
+    if METRICS is not None:
+        METRICS.write(batch_record("f3_vc_level1_paper", g, r, seconds=dt))
+    out["f3_vc_level1_paper"] = {
+        "workload": "the paper's vertex-centred discretisation, level 1 of Table 2: 64x32 elements (2145 vertices), "
+                    "376 steps of 16 s, 128 samples (seed 5) of the section-4 model; BiCGStab with symmetric "
+                    "four-colour block Gauss-Seidel preconditioning",
+        "unit": "sample-timesteps/s", "value": S * g.nsteps / dt, "ms_per_step": dt * 1e3,
+        "newton_its_per_step": float(st[:, 0].mean()) / g.nsteps,
+        "krylov_its_per_newton": float(st[:, 1].sum() / st[:, 0].sum()), "failed_samples": r.nfailed,
+        "mean_qoi": float(r.qoi.mean())}
     return out
 
 

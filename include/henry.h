@@ -361,6 +361,37 @@ HENRY_API int henry_gs_pass(henry_ctx* ctx, henry_grid grid, int S, const double
 HENRY_API int henry_coarse_solve(henry_ctx* ctx, int solver, int precision, henry_grid coarse, int S, const double* J,
                                  const double* b, double* x, int transpose);
 
+/* The paper's own discretisation (section 2.3): vertex-centred finite volumes on a grid of
+ * grid.nx x grid.ny rectangular elements (grid.nsteps implicit-Euler steps over prob->T), with
+ * p and c at the (nx + 1)(ny + 1) vertices, each vertex's box made of its quarter-elements,
+ * fluxes through the box faces inside each element evaluated at the face midpoints with the
+ * bilinear gradients of p and c and the interpolated density (eqs. e_cont_eq, e_tran_eq,
+ * e_Darcy_vel, e_lin_density), partial upwind for the convective salt flux (the upwind fraction
+ * w = max(0, 1 - 2 D_f / |F|) of each face, D_f = rho phi D_m |face| / h: central where the
+ * face Peclet number is at most 2), and the boundary data of section 2.1: Dirichlet
+ * p = -rho1 g y, c = 1 at the vertices on x = Lx, Dirichlet c = c_left and the inflow mass flux
+ * rho(c_left) u_in on x = 0, closed top and bottom.  phi and K are constant per element (the
+ * fields of henry_sample_fields at element centres).  Vectors are [ny+1][nx+1][S]; vertex
+ * (i, j) sits at x = i Lx/nx, y = -Ly + j Ly/ny.  Any element aspect ratio is allowed.
+ *
+ * henry_vc_solve: the whole run per sample from c = 0 (c = 1 on x = Lx), damped Newton as in
+ * henry_solve_batch (newton_tol, newton_dc_max, newton_maxit), each Newton system solved by
+ * right-preconditioned BiCGStab (krylov_rtol, krylov_maxit) with nu_pre + nu_post symmetric
+ * four-colour block Gauss-Seidel sweeps as the preconditioner.
+ *   theta: device [S][13]; c_T, p_T: device [ny+1][nx+1][S] or NULL; qoi: device [S] salt mass
+ *   sum c rho(c) |box n {x > qoi_xmin}| or NULL; status: device [S] (1 Newton, 2 Krylov
+ *   breakdown, 3 non-finite) or NULL; stats: device [S][2] Newton and BiCGStab iterations or NULL.
+ *   Returns the number of samples with a non-zero status, or a negative error.
+ * henry_vc_assemble: residual R [2][ny+1][nx+1][S] and Jacobian J [36][ny+1][nx+1][S] of step
+ *   `step` at (p, c) with previous state c_old; J holds the 2x2 blocks d R^a_v / d u^k_q for the
+ *   3 x 3 vertices q = v + (di, dj) around v at [((dj+1) * 3 + di+1) * 4 + a * 2 + k] (0 where q
+ *   does not exist).  A Dirichlet unknown's row is u - u_D.  Synchronises the stream. */
+HENRY_API int henry_vc_solve(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts, henry_grid grid,
+                             int S, const double* theta, double* c_T, double* p_T, double* qoi, int* status,
+                             double* stats);
+HENRY_API int henry_vc_assemble(henry_ctx* ctx, const henry_problem* prob, henry_grid grid, int S, const double* theta,
+                                const double* p, const double* c, const double* c_old, int step, double* R, double* J);
+
 /* Kernel-class timing on the context's stream (instrumentation for benchmarks).
  * henry_profile(ctx, 1) resets the counters and brackets every later launch of the
  * classes below with HIP events (launches on whole batches only: the compacted

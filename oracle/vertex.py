@@ -36,7 +36,8 @@ scheme to its references, so this file states the reading it implements:
 * Hierarchy of Table 2: level l has 16 4^l x 8 4^l elements, (16 4^l + 1)(8 4^l + 1)
   vertices and 94 4^l steps of 64 / 4^l s (T = 6016 s).
 
-The Newton matrix is the residual's Jacobian by central differences, all vertices of one
+The Newton matrix is the residual's Jacobian by central differences (steps 1e-5 in c and
+1e-7 rho0 g Ly in p), all vertices of one
 colour (i mod 3, j mod 3) perturbed at once (a residual row depends only on the 3 x 3
 vertices around it), solved by SuperLU; the Jacobian affects only the convergence of
 Newton's method, not its fixed point.
@@ -183,7 +184,12 @@ class VCDiscretisation:
         colour = ((iv % 3) + 3 * (jv % 3)).ravel()
         # neighbourhood of every vertex: itself and the (up to) 8 vertices around it
         rows, cols, vals = [], [], []
-        steps = (pr.rho0 * pr.g * pr.Ly * 1e-7, 1e-7)
+        # the residual is linear in p and at most quadratic in c (apart from the upwind fraction),
+        # so central differences are exact up to rounding.  In c a step of 1e-5 keeps the
+        # rounding of the hydrostatic term (~rho g Ly) small against the change it measures; in
+        # p a step of 1e-7 rho0 g Ly moves a face flux by ~1e-5 of itself, so it seldom carries
+        # a face across the upwind fraction's kink |F| = 2 D_f.
+        steps = (pr.rho0 * pr.g * pr.Ly * 1e-7, 1e-5)
         for comp in range(2):
             for col in range(9):
                 vs = np.nonzero(colour == col)[0]

@@ -17,7 +17,7 @@ from . import _lib as L
 from ._lib import henry_batch, henry_grid, henry_problem, henry_solver_opts
 
 __all__ = ["Henry", "HenryError", "problem", "paper_problem", "solver_opts", "grid", "level_grid", "optimal_samples",
-           "SolveResult", "mlmc_run", "mlmc_plan", "mlmc_adaptive", "SaltMassQoI", "salt_mass_qoi"]
+           "SolveResult", "mlmc_run", "mlmc_plan", "mlmc_adaptive", "SaltMassQoI", "salt_mass_qoi", "vc_level_grid"]
 
 STATUS = {0: "ok", 1: "newton", 2: "krylov", 3: "nonfinite", 4: "range"}
 
@@ -60,6 +60,12 @@ def solver_opts(**kw) -> henry_solver_opts:
 
 def grid(nx: int, ny: int, nsteps: int) -> henry_grid:
     return henry_grid(nx, ny, nsteps)
+
+
+def vc_level_grid(level: int) -> henry_grid:
+    """Level l of the paper's Table 2 for the vertex-centred discretisation: 16*4^l x 8*4^l
+    elements ((16*4^l + 1)(8*4^l + 1) vertices), 94*4^l implicit-Euler steps."""
+    return henry_grid(16 * 4 ** level, 8 * 4 ** level, 94 * 4 ** level)
 
 
 def level_grid(level: int) -> henry_grid:
@@ -251,6 +257,36 @@ class Henry:
         J = torch.empty((20, g.ny, g.nx, S), **kw)
         self._check(self._lib.henry_assemble(self._h, C.byref(prob or problem()), g, S, _ptr(theta), _ptr(p), _ptr(c),
                                              _ptr(c_old), step, _ptr(R), _ptr(J)))
+        return R, J
+
+    def vc_solve(self, theta, g: henry_grid, prob=None, opts=None, want_c=True, want_p=False):
+        """The paper's vertex-centred discretisation on g.nx x g.ny elements (henry_vc_solve):
+        SolveResult with c_T, p_T [ny+1, nx+1, S] at the vertices and stats [S, 2] (Newton,
+        BiCGStab iterations)."""
+        _check_theta(theta, self.device)
+        S = theta.shape[0]
+        kw = dict(dtype=torch.float64, device=self.device)
+        r = SolveResult(c_T=torch.empty((g.ny + 1, g.nx + 1, S), **kw) if want_c else None,
+                        p_T=torch.empty((g.ny + 1, g.nx + 1, S), **kw) if want_p else None,
+                        qoi=torch.empty((S,), **kw), status=torch.zeros((S,), dtype=torch.int32, device=self.device),
+                        stats=torch.zeros((S, 2), **kw), nfailed=0)
+        rc = self._lib.henry_vc_solve(self._h, C.byref(prob or problem()), C.byref(opts or solver_opts()), g, S,
+                                      _ptr(theta), _ptr(r.c_T), _ptr(r.p_T), _ptr(r.qoi), _ptr(r.status), _ptr(r.stats))
+        self._check(rc)
+        r.nfailed = rc
+        return r
+
+    def vc_assemble(self, theta, g: henry_grid, p, c, c_old, step: int, prob=None):
+        """(R [2, ny+1, nx+1, S], J [36, ny+1, nx+1, S]) of the vertex-centred step `step`."""
+        _check_theta(theta, self.device)
+        S = theta.shape[0]
+        for t, nm in ((p, "p"), (c, "c"), (c_old, "c_old")):
+            self._f64(t, (g.ny + 1, g.nx + 1, S), nm)
+        kw = dict(dtype=torch.float64, device=self.device)
+        R = torch.empty((2, g.ny + 1, g.nx + 1, S), **kw)
+        J = torch.empty((36, g.ny + 1, g.nx + 1, S), **kw)
+        self._check(self._lib.henry_vc_assemble(self._h, C.byref(prob or problem()), g, S, _ptr(theta), _ptr(p),
+                                                _ptr(c), _ptr(c_old), step, _ptr(R), _ptr(J)))
         return R, J
 
     def jacobian_apply(self, J, x, g: henry_grid, transpose: bool = False):

@@ -34,6 +34,7 @@
 #include "henry_gbsv.hpp"
 #include "henry_mlmc.hpp"
 #include "henry_adjoint.hpp"
+#include "henry_vc.hpp"
 
 using namespace henry;
 
@@ -2403,6 +2404,230 @@ int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, double eps
   }
   if (cost) *cost = c;
   return HENRY_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The paper's vertex-centred discretisation (section 2.3): batched time loop with damped
+// Newton and right-preconditioned BiCGStab, the preconditioner symmetric four-colour block
+// Gauss-Seidel sweeps from zero (the same arithmetic for every sample; per-sample decisions
+// on the device, one host read per Krylov iteration and per Newton iteration).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct VCSolver {
+  henry_ctx* ctx;
+  const henry_problem& pr;
+  const henry_solver_opts& o;
+  int nx, ny, nsteps, S, nv, ne;
+  hipStream_t st;
+  Map m, me;
+  Grid2 E;
+  Phys P;
+  size_t NV;
+  DevBuf phi, K, uin, p, c, c_old, R, J, x, r, rh, pv, ph, v, sv, sh, t, part, sc, ctrl, status;
+  int* h_ctrl = nullptr;
+
+  VCSolver(henry_ctx* c_, const henry_problem& pr_, const henry_solver_opts& o_, henry_grid g, int S_)
+      : ctx(c_), pr(pr_), o(o_), nx(g.nx), ny(g.ny), nsteps(g.nsteps), S(S_) {
+    st = ctx->stream;
+    nv = (nx + 1) * (ny + 1);
+    ne = nx * ny;
+    m = make_map(S, nv, o.red_blocks);
+    me = make_map(S, ne, 0);
+    E = Grid2{nx, ny, ne};
+    P = make_phys(pr, nx, ny, nsteps);
+    NV = (size_t)nv * S;
+    phi.alloc((size_t)ne * S * 8);
+    K.alloc((size_t)ne * S * 8);
+    uin.alloc((size_t)S * 8);
+    for (DevBuf* b : {&p, &c, &c_old}) b->alloc(NV * 8);
+    for (DevBuf* b : {&R, &x, &r, &rh, &pv, &ph, &v, &sv, &sh, &t}) b->alloc(2 * NV * 8);
+    J.alloc(36 * NV * 8);
+    part.alloc((size_t)3 * m.ncb * S * 8);
+    sc.alloc((size_t)VC_NSC * S * 8);
+    ctrl.alloc(sizeof(int));
+    status.alloc((size_t)S * sizeof(int));
+    HIPCHK(hipHostMalloc((void**)&h_ctrl, sizeof(int), hipHostMallocDefault));
+  }
+  ~VCSolver() {
+    if (h_ctrl) (void)hipHostFree(h_ctrl);
+  }
+
+  void fields(const double* theta) {
+    hipLaunchKernelGGL(k_fields, grid_cells(me, ne), block_of(me), 0, st, me, E, P, make_kl(pr), make_fp(pr), theta,
+                       phi.as<double>(), K.as<double>(), uin.as<double>());
+  }
+  void assemble(bool with_j, const double* pp, const double* cc, const double* co, double* RR, double* JJ) {
+    if (with_j)
+      hipLaunchKernelGGL((k_vc_assemble<true>), grid_cells(m, nv), block_of(m), 0, st, m, E, P,
+                         (const double*)phi.as<double>(), (const double*)K.as<double>(),
+                         (const double*)uin.as<double>(), pp, cc, co, RR, JJ);
+    else
+      hipLaunchKernelGGL((k_vc_assemble<false>), grid_cells(m, nv), block_of(m), 0, st, m, E, P,
+                         (const double*)phi.as<double>(), (const double*)K.as<double>(),
+                         (const double*)uin.as<double>(), pp, cc, co, RR, JJ);
+  }
+  int read_ctrl() {
+    HIPCHK(hipMemcpyAsync(h_ctrl, ctrl.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return *h_ctrl;
+  }
+  void zero_ctrl() { hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, (size_t)1, ctrl.as<int>()); }
+  template <int NQ>
+  void dots(VCPairs ab) {
+    hipLaunchKernelGGL((k_vc_dots<NQ>), grid_red(m), block_of(m), 0, st, m, nv, ab, part.as<double>());
+  }
+  dim3 g2() const { return dim3((unsigned)((2 * NV + 255) / 256)); }
+  // x = M^{-1} b: symmetric four-colour sweeps from zero
+  void precond(const double* b, double* xo) {
+    hipLaunchKernelGGL(k_zero_f64, g2(), dim3(256), 0, st, 2 * NV, xo);
+    const int sweeps = std::max(1, o.nu_pre + o.nu_post);
+    for (int k = 0; k < sweeps; ++k) {
+      for (int col = 0; col < 4; ++col)
+        hipLaunchKernelGGL(k_vc_gs, grid_cells(m, nv), block_of(m), 0, st, m, E, col, (const double*)J.as<double>(), b,
+                           xo);
+      for (int col = 3; col >= 0; --col)
+        hipLaunchKernelGGL(k_vc_gs, grid_cells(m, nv), block_of(m), 0, st, m, E, col, (const double*)J.as<double>(), b,
+                           xo);
+    }
+  }
+  void spmv(const double* xi, double* yo) {
+    hipLaunchKernelGGL(k_vc_spmv, grid_cells(m, nv), block_of(m), 0, st, m, E, (const double*)J.as<double>(), xi, yo);
+  }
+  // J x = -R (masked by the Newton flags); returns the iterations run
+  int bicgstab() {
+    double* scp = sc.as<double>();
+    const dim3 fg = fin_grid(S), fb = fin_block(S);
+    const double rtol2 = o.krylov_rtol * o.krylov_rtol;
+    hipLaunchKernelGGL(k_vc_rhs, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp, (const double*)R.as<double>(),
+                       x.as<double>(), r.as<double>(), pv.as<double>(), rh.as<double>());
+    dots<1>(VCPairs{{r.as<double>(), nullptr, nullptr}, {r.as<double>(), nullptr, nullptr}});
+    zero_ctrl();
+    hipLaunchKernelGGL(k_vc_bicg_start, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, ctrl.as<int>());
+    if (read_ctrl() == 0) return 0;
+    int it = 0;
+    for (; it < o.krylov_maxit; ++it) {
+      precond(pv.as<double>(), ph.as<double>());
+      spmv(ph.as<double>(), v.as<double>());
+      dots<1>(VCPairs{{rh.as<double>(), nullptr, nullptr}, {v.as<double>(), nullptr, nullptr}});
+      hipLaunchKernelGGL(k_vc_bicg_alpha, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, status.as<int>());
+      hipLaunchKernelGGL(k_vc_axpy_s, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp,
+                         (const double*)r.as<double>(), (const double*)v.as<double>(), sv.as<double>());
+      precond(sv.as<double>(), sh.as<double>());
+      spmv(sh.as<double>(), t.as<double>());
+      dots<3>(VCPairs{{sv.as<double>(), t.as<double>(), t.as<double>()}, {sv.as<double>(), sv.as<double>(), t.as<double>()}});
+      hipLaunchKernelGGL(k_vc_bicg_omega, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, rtol2);
+      hipLaunchKernelGGL(k_vc_update_xr, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp,
+                         (const double*)ph.as<double>(), (const double*)sh.as<double>(), (const double*)sv.as<double>(),
+                         (const double*)t.as<double>(), x.as<double>(), r.as<double>());
+      dots<2>(VCPairs{{rh.as<double>(), r.as<double>(), nullptr}, {r.as<double>(), r.as<double>(), nullptr}});
+      zero_ctrl();
+      hipLaunchKernelGGL(k_vc_bicg_beta, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, rtol2,
+                         status.as<int>(), ctrl.as<int>());
+      hipLaunchKernelGGL(k_vc_update_p, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp,
+                         (const double*)r.as<double>(), (const double*)v.as<double>(), pv.as<double>());
+      if (read_ctrl() == 0) {
+        ++it;
+        break;
+      }
+    }
+    return it;
+  }
+  void run(const double* theta, double* c_T, double* p_T, double* qoi, int* status_out, double* stats) {
+    fields(theta);
+    hipLaunchKernelGGL(k_vc_init, grid_cells(m, nv), block_of(m), 0, st, m, E, P, p.as<double>(), c.as<double>());
+    HIPCHK(hipMemsetAsync(sc.p, 0, (size_t)VC_NSC * S * 8, st));
+    HIPCHK(hipMemsetAsync(status.p, 0, (size_t)S * sizeof(int), st));
+    double* scp = sc.as<double>();
+    const double p_ref = pr.rho0 * pr.g * pr.Ly;
+    const dim3 fg = fin_grid(S), fb = fin_block(S);
+    for (int n = 0; n < nsteps; ++n) {
+      const Range range("henry vc step %d/%d %dx%d S=%d", n + 1, nsteps, nx, ny, S);
+      P.uin_fac = 1.0 + std::sin(pr.recharge_omega * (n + 1) * P.tau);
+      HIPCHK(hipMemcpyAsync(c_old.p, c.p, NV * 8, hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(k_vc_step_start, fg, fb, 0, st, S, (const int*)status.as<int>(), scp);
+      bool done = false;
+      for (int it = 0; it < o.newton_maxit && !done; ++it) {
+        assemble(true, p.as<double>(), c.as<double>(), c_old.as<double>(), R.as<double>(), J.as<double>());
+        bicgstab();
+        hipLaunchKernelGGL(k_vc_absmax, grid_red(m), block_of(m), 0, st, m, nv, (const double*)x.as<double>(),
+                           part.as<double>());
+        zero_ctrl();
+        hipLaunchKernelGGL(k_vc_newton_fin, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, o.newton_tol, p_ref,
+                           o.newton_dc_max, status.as<int>(), ctrl.as<int>());
+        hipLaunchKernelGGL(k_vc_newton_update, dim3((unsigned)((NV + 255) / 256)), dim3(256), 0, st, NV, S,
+                           (const double*)scp, (const double*)x.as<double>(), p.as<double>(), c.as<double>());
+        done = read_ctrl() == 0;
+      }
+      hipLaunchKernelGGL(k_vc_step_end, fg, fb, 0, st, S, status.as<int>(), (const double*)scp);
+    }
+    if (qoi) {
+      hipLaunchKernelGGL(k_vc_qoi, grid_red(m), block_of(m), 0, st, m, E, P, (const double*)c.as<double>(),
+                         part.as<double>());
+      hipLaunchKernelGGL(k_fin_sum, fg, fb, 0, st, m, (const double*)part.as<double>(), 1.0, qoi);
+    }
+    if (c_T) HIPCHK(hipMemcpyAsync(c_T, c.p, NV * 8, hipMemcpyDeviceToDevice, st));
+    if (p_T) HIPCHK(hipMemcpyAsync(p_T, p.p, NV * 8, hipMemcpyDeviceToDevice, st));
+    if (status_out) HIPCHK(hipMemcpyAsync(status_out, status.p, (size_t)S * sizeof(int), hipMemcpyDeviceToDevice, st));
+    if (stats)
+      hipLaunchKernelGGL(k_vc_stats, fg, fb, 0, st, S, (const double*)scp, stats);
+  }
+};
+
+static void check_vc_grid(const henry_problem& pr, henry_grid g) {
+  if (g.nx < 2 || g.ny < 2 || g.nsteps < 1) fail(HENRY_EINVAL, "grid %dx%d, %d steps is invalid", g.nx, g.ny, g.nsteps);
+  if ((long long)(g.nx + 1) * (g.ny + 1) > (1LL << 24)) fail(HENRY_EINVAL, "grid too large");
+  (void)pr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int henry_vc_assemble(henry_ctx* ctx, const henry_problem* prob, henry_grid grid, int S, const double* theta,
+                      const double* p, const double* c, const double* c_old, int step, double* R, double* J) {
+  return guarded(ctx, [&]() -> int {
+    check_problem(prob);
+    check_vc_grid(*prob, grid);
+    if (S < 1 || !theta || !p || !c || !c_old || !R || !J) fail(HENRY_EINVAL, "S < 1 or a NULL array");
+    if (step < 0 || step >= grid.nsteps) fail(HENRY_EINVAL, "step %d outside 0..%d", step, grid.nsteps - 1);
+    if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
+    henry_solver_opts o;
+    henry_solver_opts_default(&o);
+    VCSolver sv(ctx, *prob, o, grid, S);
+    sv.P.uin_fac = 1.0 + std::sin(prob->recharge_omega * (step + 1) * sv.P.tau);
+    sv.fields(theta);
+    sv.assemble(true, p, c, c_old, R, J);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return HENRY_OK;
+  });
+}
+
+int henry_vc_solve(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts, henry_grid grid, int S,
+                   const double* theta, double* c_T, double* p_T, double* qoi, int* status, double* stats) {
+  return guarded(ctx, [&]() -> int {
+    check_problem(prob);
+    henry_solver_opts o;
+    if (opts) o = *opts;
+    else henry_solver_opts_default(&o);
+    check_opts(o);
+    check_vc_grid(*prob, grid);
+    if (S < 1 || !theta) fail(HENRY_EINVAL, "S < 1 or theta NULL");
+    if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
+    const Range range("henry_vc_solve %dx%d S=%d steps=%d", grid.nx, grid.ny, S, grid.nsteps);
+    VCSolver sv(ctx, *prob, o, grid, S);
+    sv.run(theta, c_T, p_T, qoi, status, stats);
+    HIPCHK(hipGetLastError());
+    int nf = 0;
+    std::vector<int> hs(S);
+    HIPCHK(hipMemcpyAsync(hs.data(), sv.status.p, (size_t)S * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int s = 0; s < S; ++s) nf += hs[s] != 0;
+    return nf;
+  });
 }
 
 }  // extern "C"

@@ -1,0 +1,556 @@
+// The paper's vertex-centred finite-volume discretisation (section 2.3): unknowns at the vertices
+// of the element grid, boxes around vertices, fluxes through the four box faces inside each
+// element, partial upwind for the convective salt flux.  Batched over samples: vectors are
+// [component][vertex][S] with vertex v = j (nx + 1) + i, the Jacobian is [36][vertex][S] of
+// 2x2 blocks for the 3 x 3 vertices around v, block b = (dj + 1) * 3 + (di + 1) (4 = centre),
+// entry [b * 4 + a * 2 + k] = d R^a_v / d u^k_{v + (di, dj)} (a, k: 0 pressure, 1 concentration).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace henry {
+
+constexpr int VC_BLK = 9;
+enum { VC_RHO = 0, VC_ALPHA, VC_OMEGA, VC_R0, VC_ACTIVE, VC_ITS, VC_NEWTON, VC_DONE, VC_NSC };
+
+// Element faces: face f separates local vertices a -> b (0 = (i, j), 1 = (i+1, j),
+// 2 = (i+1, j+1), 3 = (i, j+1)), is crossed along +x (axis 0) or +y (axis 1), and has its
+// integration point at local (s, t).
+__device__ __forceinline__ void vc_face_geom(int f, int& a, int& b, int& axis, double& s, double& t) {
+  switch (f) {
+    case 0: a = 0; b = 1; axis = 0; s = 0.5; t = 0.25; break;
+    case 1: a = 1; b = 2; axis = 1; s = 0.75; t = 0.5; break;
+    case 2: a = 3; b = 2; axis = 0; s = 0.5; t = 0.75; break;
+    default: a = 0; b = 3; axis = 1; s = 0.25; t = 0.5; break;
+  }
+}
+
+// Fluid and salt mass flux a -> b through face f of one element and their derivatives with
+// respect to p_k, c_k of the element's four vertices (the upwind fraction w included).
+__device__ __forceinline__ void vc_face(int f, const double (&pk)[4], const double (&ck)[4], double Ke, double phie,
+                                        const Phys& P, double& F, double& G, double (&dFp)[4], double (&dFc)[4],
+                                        double (&dGp)[4], double (&dGc)[4]) {
+  int a, b, axis;
+  double s, t;
+  vc_face_geom(f, a, b, axis, s, t);
+  const double N[4] = {(1 - s) * (1 - t), s * (1 - t), s * t, (1 - s) * t};
+  double dN[4];
+  if (axis == 0) {
+    dN[0] = -(1 - t) / P.hx; dN[1] = (1 - t) / P.hx; dN[2] = t / P.hx; dN[3] = -t / P.hx;
+  } else {
+    dN[0] = -(1 - s) / P.hy; dN[1] = -s / P.hy; dN[2] = s / P.hy; dN[3] = (1 - s) / P.hy;
+  }
+  const double L = axis == 0 ? 0.5 * P.hy : 0.5 * P.hx;
+  const double h = axis == 0 ? P.hx : P.hy;
+  double r = 0.0, gp = 0.0, gc = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r += N[k] * (P.rho0 + P.drho * ck[k]);
+    gp += pk[k] * dN[k];
+    gc += ck[k] * dN[k];
+  }
+  const double kk = Ke / P.mu;
+  const double qn = -kk * (gp + (axis == 1 ? r * P.g : 0.0));
+  F = r * qn * L;
+  const double Df = r * phie * P.Dm * L / h;
+  const double aF = fabs(F);
+  double w = 0.0;
+  if (aF > 0.0) w = fmax(0.0, 1.0 - 2.0 * Df / aF);
+  const bool upa = F >= 0.0;
+  const int up = upa ? a : b;
+  const double cup = ck[up], cm = 0.5 * (ck[a] + ck[b]);
+  const double cconv = cm + w * (cup - cm);
+  G = F * cconv - r * phie * P.Dm * gc * L;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    dFp[k] = r * L * (-kk * dN[k]);
+    dFc[k] = L * (N[k] * P.drho * qn + r * (axis == 1 ? -kk * P.g * N[k] * P.drho : 0.0));
+    double dwp = 0.0, dwc = 0.0;
+    if (w > 0.0) {
+      const double sg = F > 0.0 ? 1.0 : -1.0;
+      const double dDf = N[k] * P.drho * phie * P.Dm * L / h;
+      dwp = 2.0 * Df * sg * dFp[k] / (F * F);
+      dwc = -2.0 * dDf / aF + 2.0 * Df * sg * dFc[k] / (F * F);
+    }
+    const double dcc_c = ((k == a || k == b) ? 0.5 * (1.0 - w) : 0.0) + (k == up ? w : 0.0) + (cup - cm) * dwc;
+    const double dcc_p = (cup - cm) * dwp;
+    const double dGd_c = phie * P.Dm * L * (N[k] * P.drho * gc + r * dN[k]);
+    dGp[k] = dFp[k] * cconv + F * dcc_p;
+    dGc[k] = dFc[k] * cconv + F * dcc_c - dGd_c;
+  }
+}
+
+// Residual (and Jacobian) of one implicit-Euler step at every vertex: a thread per (vertex,
+// sample) gathers the two faces of each element around its vertex that bound its box.
+// E: the element grid; phi, K: [element][S]; uin: [S] (times P.uin_fac).
+template <bool WRITE_J>
+__global__ void __launch_bounds__(256) k_vc_assemble(Map m, Grid2 E, Phys P, const double* __restrict__ phi,
+                                                     const double* __restrict__ K, const double* __restrict__ uin,
+                                                     const double* __restrict__ p, const double* __restrict__ c,
+                                                     const double* __restrict__ c_old, double* __restrict__ R,
+                                                     double* __restrict__ J) {
+  const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
+  int s, v, sb, cb;
+  if (!map_cell(m, nv, s, v, sb, cb)) return;
+  const int S = m.S;
+  const size_t NV = (size_t)nv * S;
+  const int j = v / nvx, i = v - j * nvx;
+  const size_t id = (size_t)v * S + s;
+  const double y = -P.Ly + j * P.hy;
+  double Jb[36];
+#pragma unroll
+  for (int q = 0; q < 36; ++q) Jb[q] = 0.0;
+  double Rp = 0.0, Rc = 0.0;
+  if (i == E.nx) {   // seaside: p = -rho1 g y, c = 1
+    Rp = p[id] + P.rho1 * P.g * y;
+    Rc = c[id] - 1.0;
+    Jb[16] = 1.0;
+    Jb[19] = 1.0;
+  } else {
+    double pn[3][3], cn[3][3];
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const int qi = i + di, qj = j + dj;
+        const bool in = qi >= 0 && qi < nvx && qj >= 0 && qj < nvy;
+        const size_t q = ((size_t)(in ? qj : j) * nvx + (in ? qi : i)) * S + s;
+        pn[dj + 1][di + 1] = in ? p[q] : 0.0;
+        cn[dj + 1][di + 1] = in ? c[q] : 0.0;
+      }
+    double box = 0.0;
+#pragma unroll
+    for (int ej = -1; ej <= 0; ++ej)
+#pragma unroll
+      for (int ei = -1; ei <= 0; ++ei) {
+        const int xi = i + ei, xj = j + ej;
+        if (xi < 0 || xi >= E.nx || xj < 0 || xj >= E.ny) continue;
+        const size_t e = ((size_t)xj * E.nx + xi) * S + s;
+        const double phie = phi[e], Ke = K[e];
+        box += 0.25 * P.hx * P.hy * phie;
+        const int kv = ei == 0 ? (ej == 0 ? 0 : 3) : (ej == 0 ? 1 : 2);   // local index of v
+        double pk[4], ck[4];
+        int dik[4], djk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          dik[k] = ei + ((k == 1 || k == 2) ? 1 : 0);
+          djk[k] = ej + ((k == 2 || k == 3) ? 1 : 0);
+          pk[k] = pn[djk[k] + 1][dik[k] + 1];
+          ck[k] = cn[djk[k] + 1][dik[k] + 1];
+        }
+        // the two faces of this element that touch local vertex kv
+        const int f0 = kv == 0 ? 0 : kv == 1 ? 0 : kv == 2 ? 1 : 2;
+        const int f1 = kv == 0 ? 3 : kv == 1 ? 1 : kv == 2 ? 2 : 3;
+#pragma unroll
+        for (int ff = 0; ff < 2; ++ff) {
+          const int f = ff == 0 ? f0 : f1;
+          int a, b, axis;
+          double s_, t_;
+          vc_face_geom(f, a, b, axis, s_, t_);
+          const double sgn = a == kv ? 1.0 : -1.0;   // out of v's box
+          double F, G, dFp[4], dFc[4], dGp[4], dGc[4];
+          vc_face(f, pk, ck, Ke, phie, P, F, G, dFp, dFc, dGp, dGc);
+          Rp += sgn * F;
+          Rc += sgn * G;
+          if (WRITE_J) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int bl = (djk[k] + 1) * 3 + (dik[k] + 1);
+              Jb[bl * 4 + 0] += sgn * dFp[k];
+              Jb[bl * 4 + 1] += sgn * dFc[k];
+              Jb[bl * 4 + 2] += sgn * dGp[k];
+              Jb[bl * 4 + 3] += sgn * dGc[k];
+            }
+          }
+        }
+      }
+    const double cv = c[id], co = c_old[id];
+    Rp += box * (P.drho * (cv - co)) / P.tau;
+    Rc += box * ((P.rho0 + P.drho * cv) * cv - (P.rho0 + P.drho * co) * co) / P.tau;
+    Jb[17] += box * P.drho / P.tau;
+    Jb[19] += box * (P.rho0 + 2.0 * P.drho * cv) / P.tau;
+    if (i == 0) {   // inflow side: mass flux rho(c_left) u_in enters; c = c_left
+      const double len = (j == 0 || j == E.ny) ? 0.5 * P.hy : P.hy;
+      Rp -= (P.rho0 + P.drho * P.c_left) * uin[s] * P.uin_fac * len;
+      Rc = cv - P.c_left;
+#pragma unroll
+      for (int bl = 0; bl < VC_BLK; ++bl) {
+        Jb[bl * 4 + 2] = 0.0;
+        Jb[bl * 4 + 3] = 0.0;
+      }
+      Jb[19] = 1.0;
+    }
+  }
+  R[id] = Rp;
+  R[NV + id] = Rc;
+  if (WRITE_J) {
+#pragma unroll
+    for (int q = 0; q < 36; ++q) J[(size_t)q * NV + id] = Jb[q];
+  }
+}
+
+// y = J x (9 blocks), one thread per (vertex, sample)
+__global__ void __launch_bounds__(256) k_vc_spmv(Map m, Grid2 E, const double* __restrict__ J,
+                                                 const double* __restrict__ x, double* __restrict__ y) {
+  const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
+  int s, v, sb, cb;
+  if (!map_cell(m, nv, s, v, sb, cb)) return;
+  const int S = m.S;
+  const size_t NV = (size_t)nv * S;
+  const int j = v / nvx, i = v - j * nvx;
+  const size_t id = (size_t)v * S + s;
+  double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int qi = i + di, qj = j + dj;
+      if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
+      const int bl = (dj + 1) * 3 + (di + 1);
+      const size_t q = ((size_t)qj * nvx + qi) * S + s;
+      const double x0 = x[q], x1 = x[NV + q];
+      y0 += J[(size_t)(bl * 4 + 0) * NV + id] * x0 + J[(size_t)(bl * 4 + 1) * NV + id] * x1;
+      y1 += J[(size_t)(bl * 4 + 2) * NV + id] * x0 + J[(size_t)(bl * 4 + 3) * NV + id] * x1;
+    }
+  y[id] = y0;
+  y[NV + id] = y1;
+}
+
+// One colour ((i & 1) + 2 (j & 1)) of a four-colour block Gauss-Seidel sweep:
+// x_v = D_v^{-1} (b_v - sum over the other 8 blocks A_vq x_q); vertices of one colour do not
+// touch each other in the nine-point stencil.
+__global__ void __launch_bounds__(256) k_vc_gs(Map m, Grid2 E, int colour, const double* __restrict__ J,
+                                               const double* __restrict__ b, double* __restrict__ x) {
+  const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
+  int s, v, sb, cb;
+  if (!map_cell(m, nv, s, v, sb, cb)) return;
+  const int j = v / nvx, i = v - j * nvx;
+  if ((i & 1) + 2 * (j & 1) != colour) return;
+  const int S = m.S;
+  const size_t NV = (size_t)nv * S;
+  const size_t id = (size_t)v * S + s;
+  double r0 = b[id], r1 = b[NV + id];
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      if (di == 0 && dj == 0) continue;
+      const int qi = i + di, qj = j + dj;
+      if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
+      const int bl = (dj + 1) * 3 + (di + 1);
+      const size_t q = ((size_t)qj * nvx + qi) * S + s;
+      const double x0 = x[q], x1 = x[NV + q];
+      r0 -= J[(size_t)(bl * 4 + 0) * NV + id] * x0 + J[(size_t)(bl * 4 + 1) * NV + id] * x1;
+      r1 -= J[(size_t)(bl * 4 + 2) * NV + id] * x0 + J[(size_t)(bl * 4 + 3) * NV + id] * x1;
+    }
+  const double d00 = J[(size_t)16 * NV + id], d01 = J[(size_t)17 * NV + id];
+  const double d10 = J[(size_t)18 * NV + id], d11 = J[(size_t)19 * NV + id];
+  const double det = d00 * d11 - d01 * d10;
+  x[id] = (d11 * r0 - d01 * r1) / det;
+  x[NV + id] = (d00 * r1 - d10 * r0) / det;
+}
+
+// Partial sums over vertex blocks of NQ per-sample dot products sum_v (a_q . b_q) (both
+// components), written as part[q][cell block][S] for reduce_partials.
+struct VCPairs {
+  const double* a[3];
+  const double* b[3];
+};
+template <int NQ>
+__global__ void __launch_bounds__(256) k_vc_dots(Map m, int nv, VCPairs ab, double* __restrict__ part) {
+  __shared__ double lds[NQ * 256];
+  const int sblk = blockIdx.x % m.nsb, cblk = blockIdx.x / m.nsb;
+  const int s = sblk * m.SX + threadIdx.x;
+  const bool sv = s < m.S;
+  const size_t NV = (size_t)nv * m.S;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int k = 0; k < m.CPT; ++k) {
+    const int v = (cblk * m.CPT + k) * m.CY + threadIdx.y;
+    if (!sv || v >= nv) continue;
+    const size_t id = (size_t)v * m.S + s;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double* a = ab.a[q];
+      const double* b = ab.b[q];
+      acc[q] += a[id] * b[id] + a[NV + id] * b[NV + id];
+    }
+  }
+  block_sum_y<NQ>(acc, lds);
+  if (threadIdx.y == 0 && sv)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) part[((size_t)q * m.ncb + cblk) * m.S + s] = acc[q];
+}
+
+// Per-sample max |dp| and |dc| partials (for the Newton damping and stopping test)
+__global__ void __launch_bounds__(256) k_vc_absmax(Map m, int nv, const double* __restrict__ d,
+                                                   double* __restrict__ part) {
+  __shared__ double lds[2 * 256];
+  const int sblk = blockIdx.x % m.nsb, cblk = blockIdx.x / m.nsb;
+  const int s = sblk * m.SX + threadIdx.x;
+  const bool sv = s < m.S;
+  const size_t NV = (size_t)nv * m.S;
+  double acc[2] = {0.0, 0.0};
+  for (int k = 0; k < m.CPT; ++k) {
+    const int v = (cblk * m.CPT + k) * m.CY + threadIdx.y;
+    if (!sv || v >= nv) continue;
+    const size_t id = (size_t)v * m.S + s;
+    const double a = fabs(d[id]), b = fabs(d[NV + id]);
+    acc[0] = (a > acc[0] || a != a) ? a : acc[0];
+    acc[1] = (b > acc[1] || b != b) ? b : acc[1];
+  }
+  // block max over y (NaN wins)
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  lds[tid] = acc[0];
+  lds[256 + tid] = acc[1];
+  __syncthreads();
+  if (threadIdx.y == 0) {
+    for (int yy = 1; yy < (int)blockDim.y; ++yy) {
+      const double a = lds[yy * blockDim.x + threadIdx.x], b = lds[256 + yy * blockDim.x + threadIdx.x];
+      acc[0] = (a > acc[0] || a != a) ? a : acc[0];
+      acc[1] = (b > acc[1] || b != b) ? b : acc[1];
+    }
+    if (sv) {
+      part[(size_t)cblk * m.S + s] = acc[0];
+      part[((size_t)m.ncb + cblk) * m.S + s] = acc[1];
+    }
+  }
+}
+
+// ---- BiCGStab per sample (right preconditioned, x0 = 0, r-hat = r0) -----------------------
+// sc[q * S + s]: VC_RHO, VC_ALPHA, VC_OMEGA, VC_R0 (|r0|^2), VC_ACTIVE, VC_ITS; ctrl[0]: samples
+// still iterating after the kernel.
+
+// after dots (r, r): rho = |r0|^2, active where it is > 0
+__global__ void k_vc_bicg_start(Map m, const double* __restrict__ part, double* __restrict__ sc,
+                                int* __restrict__ ctrl) {
+  __shared__ double lds[64 * FIN_Y];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1];
+  reduce_partials<1>(m, part, s, v, lds);
+  if (threadIdx.y != 0 || s >= m.S) return;
+  const int S = m.S;
+  const bool act = v[0] > 0.0 && isfinite(v[0]) && sc[VC_DONE * S + s] == 0.0;
+  sc[VC_RHO * S + s] = v[0];
+  sc[VC_R0 * S + s] = v[0];
+  sc[VC_ACTIVE * S + s] = act ? 1.0 : 0.0;
+  sc[VC_ALPHA * S + s] = 0.0;
+  sc[VC_OMEGA * S + s] = 0.0;
+  if (act) atomicAdd(&ctrl[0], 1);
+}
+
+// after dots (r-hat, v): alpha = rho / (r-hat, v); 0 (and inactive) on breakdown
+__global__ void k_vc_bicg_alpha(Map m, const double* __restrict__ part, double* __restrict__ sc,
+                                int* __restrict__ status) {
+  __shared__ double lds[64 * FIN_Y];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1];
+  reduce_partials<1>(m, part, s, v, lds);
+  if (threadIdx.y != 0 || s >= m.S) return;
+  const int S = m.S;
+  double al = 0.0;
+  if (sc[VC_ACTIVE * S + s] != 0.0) {
+    if (v[0] != 0.0 && isfinite(v[0])) {
+      al = sc[VC_RHO * S + s] / v[0];
+    } else {
+      sc[VC_ACTIVE * S + s] = 0.0;
+      if (status[s] == 0) status[s] = 2;
+    }
+  }
+  sc[VC_ALPHA * S + s] = al;
+}
+
+// after dots (s, s), (t, s), (t, t): omega (0 when s already meets the tolerance)
+__global__ void k_vc_bicg_omega(Map m, const double* __restrict__ part, double* __restrict__ sc, double rtol2) {
+  __shared__ double lds[3 * 64 * FIN_Y];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[3];
+  reduce_partials<3>(m, part, s, v, lds);
+  if (threadIdx.y != 0 || s >= m.S) return;
+  const int S = m.S;
+  double om = 0.0;
+  if (sc[VC_ACTIVE * S + s] != 0.0 && !(v[0] <= rtol2 * sc[VC_R0 * S + s]) && v[2] > 0.0) om = v[1] / v[2];
+  sc[VC_OMEGA * S + s] = om;
+  if (sc[VC_ACTIVE * S + s] != 0.0 && v[0] <= rtol2 * sc[VC_R0 * S + s]) sc[VC_ACTIVE * S + s] = 2.0;   // done
+}
+
+// after dots (r-hat, r), (r, r): convergence, beta; ctrl[0] counts samples still iterating
+__global__ void k_vc_bicg_beta(Map m, const double* __restrict__ part, double* __restrict__ sc, double rtol2,
+                               int* __restrict__ status, int* __restrict__ ctrl) {
+  __shared__ double lds[2 * 64 * FIN_Y];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[2];
+  reduce_partials<2>(m, part, s, v, lds);
+  if (threadIdx.y != 0 || s >= m.S) return;
+  const int S = m.S;
+  const double act = sc[VC_ACTIVE * S + s];
+  if (act == 0.0) return;
+  sc[VC_ITS * S + s] += 1.0;
+  if (act == 2.0 || v[1] <= rtol2 * sc[VC_R0 * S + s]) {
+    sc[VC_ACTIVE * S + s] = 0.0;
+    return;
+  }
+  const double om = sc[VC_OMEGA * S + s];
+  if (om == 0.0 || v[0] == 0.0 || !isfinite(v[0])) {
+    sc[VC_ACTIVE * S + s] = 0.0;
+    if (status[s] == 0) status[s] = 2;
+    return;
+  }
+  sc[VC_ALPHA * S + s] = (v[0] / sc[VC_RHO * S + s]) * (sc[VC_ALPHA * S + s] / om);   // beta, kept in ALPHA
+  sc[VC_RHO * S + s] = v[0];
+  atomicAdd(&ctrl[0], 1);
+}
+
+// elementwise updates over [2][nv][S] with per-sample coefficients
+__device__ __forceinline__ size_t vc_sample_of(size_t e, size_t NV, int S, int& s) {
+  const size_t id = e < NV ? e : e - NV;
+  s = (int)(id % (size_t)S);
+  return id;
+}
+
+// s = r - alpha v
+__global__ void k_vc_axpy_s(size_t n2, size_t NV, int S, const double* __restrict__ sc, const double* __restrict__ r,
+                            const double* __restrict__ v, double* __restrict__ sv) {
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e >= n2) return;
+  int s;
+  vc_sample_of(e, NV, S, s);
+  sv[e] = r[e] - sc[VC_ALPHA * S + s] * v[e];
+}
+
+// x += alpha p-hat + omega s-hat; r = s - omega t (samples that iterate)
+__global__ void k_vc_update_xr(size_t n2, size_t NV, int S, const double* __restrict__ sc,
+                               const double* __restrict__ ph, const double* __restrict__ sh,
+                               const double* __restrict__ sv, const double* __restrict__ t, double* __restrict__ x,
+                               double* __restrict__ r) {
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e >= n2) return;
+  int s;
+  vc_sample_of(e, NV, S, s);
+  if (sc[VC_ACTIVE * S + s] == 0.0) return;
+  const double al = sc[VC_ALPHA * S + s], om = sc[VC_OMEGA * S + s];
+  x[e] += al * ph[e] + om * sh[e];
+  r[e] = sv[e] - om * t[e];
+}
+
+// p = r + beta (p - omega v) for samples still iterating (beta kept in ALPHA)
+__global__ void k_vc_update_p(size_t n2, size_t NV, int S, const double* __restrict__ sc,
+                              const double* __restrict__ r, const double* __restrict__ v, double* __restrict__ p) {
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e >= n2) return;
+  int s;
+  vc_sample_of(e, NV, S, s);
+  if (sc[VC_ACTIVE * S + s] == 0.0) return;
+  p[e] = r[e] + sc[VC_ALPHA * S + s] * (p[e] - sc[VC_OMEGA * S + s] * v[e]);
+}
+
+// right-hand side b = -R for samples still in Newton (0 for converged ones); x = 0, r = p = b
+__global__ void k_vc_rhs(size_t n2, size_t NV, int S, const double* __restrict__ sc, const double* __restrict__ R,
+                         double* __restrict__ x, double* __restrict__ r, double* __restrict__ p,
+                         double* __restrict__ rh) {
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e >= n2) return;
+  int s;
+  vc_sample_of(e, NV, S, s);
+  const double b = sc[VC_DONE * S + s] != 0.0 ? 0.0 : -R[e];
+  x[e] = 0.0;
+  r[e] = b;
+  p[e] = b;
+  rh[e] = b;
+}
+
+// Newton: after |dp|_inf, |dc|_inf partials, damp by min(1, dc_max / |dc|_inf), stop on the
+// unscaled update (as the oracle does); ctrl[0] counts samples still iterating.
+__global__ void k_vc_newton_fin(Map m, const double* __restrict__ part, double* __restrict__ sc, double tol,
+                                double p_ref, double dc_max, int* __restrict__ status, int* __restrict__ ctrl) {
+  __shared__ double lds[2 * 64 * FIN_Y];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double e[2];
+  reduce_partials_max<2>(m, part, s, e, lds);
+  if (threadIdx.y != 0 || s >= m.S) return;
+  const int S = m.S;
+  if (sc[VC_DONE * S + s] != 0.0) {
+    sc[VC_ALPHA * S + s] = 0.0;
+    return;
+  }
+  const double dp = e[0], dc = e[1];
+  if (!isfinite(dp) || !isfinite(dc)) {
+    status[s] = 3;
+    sc[VC_DONE * S + s] = 1.0;
+    sc[VC_ALPHA * S + s] = 0.0;
+    return;
+  }
+  sc[VC_ALPHA * S + s] = dc > 0.0 ? fmin(1.0, dc_max / dc) : 1.0;   // damping factor
+  sc[VC_NEWTON * S + s] += 1.0;
+  if (fmax(dc, dp / p_ref) <= tol) sc[VC_DONE * S + s] = 1.0;
+  else atomicAdd(&ctrl[0], 1);
+}
+
+// p += lambda dp, c += lambda dc (lambda in ALPHA, 0 for samples that had converged)
+__global__ void k_vc_newton_update(size_t NV, int S, const double* __restrict__ sc, const double* __restrict__ d,
+                                   double* __restrict__ p, double* __restrict__ c) {
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e >= NV) return;
+  const int s = (int)(e % (size_t)S);
+  const double lam = sc[VC_ALPHA * S + s];
+  p[e] += lam * d[e];
+  c[e] += lam * d[NV + e];
+}
+
+// initial state: p = -rho0 g y (-rho1 g y on x = Lx), c = 0 (1 on x = Lx, c_left on x = 0)
+__global__ void k_vc_init(Map m, Grid2 E, Phys P, double* __restrict__ p, double* __restrict__ c) {
+  const int nvx = E.nx + 1, nv = nvx * (E.ny + 1);
+  int s, v, sb, cb;
+  if (!map_cell(m, nv, s, v, sb, cb)) return;
+  const int j = v / nvx, i = v - j * nvx;
+  const size_t id = (size_t)v * m.S + s;
+  const double y = -P.Ly + j * P.hy;
+  p[id] = -(i == E.nx ? P.rho1 : P.rho0) * P.g * y;
+  c[id] = i == E.nx ? 1.0 : (i == 0 ? P.c_left : 0.0);
+}
+
+// QoI partials: sum_v c rho(c) |box_v n {x > qoi_xmin}|
+__global__ void __launch_bounds__(256) k_vc_qoi(Map m, Grid2 E, Phys P, const double* __restrict__ c,
+                                                double* __restrict__ part) {
+  __shared__ double lds[256];
+  const int nvx = E.nx + 1, nv = nvx * (E.ny + 1);
+  const int sblk = blockIdx.x % m.nsb, cblk = blockIdx.x / m.nsb;
+  const int s = sblk * m.SX + threadIdx.x;
+  const bool sv = s < m.S;
+  double acc[1] = {0.0};
+  for (int k = 0; k < m.CPT; ++k) {
+    const int v = (cblk * m.CPT + k) * m.CY + threadIdx.y;
+    if (!sv || v >= nv) continue;
+    const int j = v / nvx, i = v - j * nvx;
+    const double x = i * P.hx;
+    const double lo = fmax(x - 0.5 * P.hx, 0.0), hi = fmin(x + 0.5 * P.hx, P.Lx);
+    const double wx = fmax(0.0, hi - fmax(lo, P.qoi_xmin));
+    const double wy = (j == 0 || j == E.ny) ? 0.5 * P.hy : P.hy;
+    const double cv = c[(size_t)v * m.S + s];
+    acc[0] += cv * (P.rho0 + P.drho * cv) * wx * wy;
+  }
+  block_sum_y<1>(acc, lds);
+  if (threadIdx.y == 0 && sv) part[(size_t)cblk * m.S + s] = acc[0];
+}
+
+// per-sample step bookkeeping (fin launch shape: threadIdx.y == 0 acts)
+__global__ void k_vc_step_start(int S, const int* __restrict__ status, double* __restrict__ sc) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.y != 0 || s >= S) return;
+  sc[VC_DONE * S + s] = status[s] == 3 ? 1.0 : 0.0;   // a frozen (non-finite) sample stays frozen
+}
+__global__ void k_vc_step_end(int S, int* __restrict__ status, const double* __restrict__ sc) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.y != 0 || s >= S) return;
+  if (sc[VC_DONE * S + s] == 0.0 && status[s] == 0) status[s] = 1;   // Newton did not converge
+}
+// stats[s][0..1]: Newton and BiCGStab iterations over the run
+__global__ void k_vc_stats(int S, const double* __restrict__ sc, double* __restrict__ stats) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.y != 0 || s >= S) return;
+  stats[2 * (size_t)s] = sc[VC_NEWTON * S + s];
+  stats[2 * (size_t)s + 1] = sc[VC_ITS * S + s];
+}
+
+}  // namespace henry

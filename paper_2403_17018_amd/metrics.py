@@ -60,7 +60,7 @@ def kernel_classes(prof: dict, mg_precision: int = 64) -> dict:
 def batch_record(label: str, grid, result, seconds: float | None = None, prof: dict | None = None,
                  mg_precision: int = 64, **extra) -> dict:
     """One JSON-ready record for a SolveResult on henry_grid `grid`."""
-    st = result.stats.detach().cpu().numpy().astype(np.float64)       # [S, 4]
+    st = result.stats.detach().cpu().numpy().astype(np.float64)       # [S, 4] (or [S, 2])
     status = result.status.detach().cpu().numpy()
     S = st.shape[0]
     newton = st[:, 0]
@@ -70,8 +70,8 @@ def batch_record(label: str, grid, result, seconds: float | None = None, prof: d
                newton_per_step=_hist(newton / max(grid.nsteps, 1), 0.25),
                krylov_per_newton=_hist(st[:, 1] / np.maximum(newton, 1.0), 0.25),
                failed=int(result.nfailed), status_counts={str(int(k)): int(v) for k, v in zip(codes, counts)},
-               max_fluid_defect=float(st[:, 2].max()) if S else None,
-               max_salt_defect=float(st[:, 3].max()) if S else None)
+               max_fluid_defect=float(st[:, 2].max()) if S and st.shape[1] > 3 else None,
+               max_salt_defect=float(st[:, 3].max()) if S and st.shape[1] > 3 else None)
     if seconds is not None and seconds > 0:
         rec.update(seconds=float(seconds), sample_timesteps_per_s=S * grid.nsteps / seconds)
     if prof is not None:

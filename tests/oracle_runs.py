@@ -55,6 +55,40 @@ def _run(theta, nx, ny, nsteps, prob_kw, procs, series=False):
                 **extra)
 
 
+def _vc_one(args):
+    from oracle import vertex as V
+    pr, g, th = args
+    return V.solve_sample(pr, g, th)
+
+
+def _run_vertex(theta, nx, ny, nsteps, prob_kw, procs):
+    import multiprocessing as mp
+    from oracle import henry as H
+    pr = H.Problem(**(prob_kw or {}))
+    g = H.Grid(nx, ny, nsteps)
+    jobs = [(pr, g, t) for t in np.asarray(theta)]
+    with mp.get_context("fork").Pool(max(1, min(procs, len(jobs)))) as pool:
+        rs = pool.map(_vc_one, jobs)
+    return dict(c=np.stack([r.c.reshape(ny + 1, nx + 1) for r in rs]), p=np.stack([r.p.reshape(ny + 1, nx + 1) for r in rs]),
+                qoi=np.array([r.qoi for r in rs]), its=np.array([r.newton_its for r in rs]),
+                conv=np.array([r.converged for r in rs]),
+                dsalt=np.array([r.max_salt_defect for r in rs]), dfluid=np.array([r.max_fluid_defect for r in rs]))
+
+
+def vc_oracle_batch(theta, nx, ny, nsteps, prob_kw=None, procs=NPROC):
+    """The vertex-centred oracle (oracle.vertex) on nx x ny elements: c, p [S, ny+1, nx+1], qoi,
+    its, conv, dsalt, dfluid [S]."""
+    with tempfile.TemporaryDirectory() as d:
+        np.save(os.path.join(d, "theta.npy"), np.asarray(theta, dtype=np.float64))
+        spec = dict(nx=nx, ny=ny, nsteps=nsteps, prob_kw=prob_kw or {}, procs=procs, scheme="vertex")
+        with open(os.path.join(d, "spec.json"), "w") as f:
+            json.dump(spec, f)
+        env = dict(os.environ, PYTHONPATH=ROOT + os.pathsep + os.environ.get("PYTHONPATH", ""))
+        subprocess.run([sys.executable, "-m", "tests.oracle_runs", d], check=True, cwd=ROOT, env=env)
+        z = np.load(os.path.join(d, "out.npz"))
+        return {k: z[k] for k in z.files}
+
+
 def oracle_batch(theta, nx, ny, nsteps, prob_kw=None, procs=NPROC, series=False):
     """dict of arrays c [S,ny,nx], p, qoi [S], its, conv, dsalt, dfluid; with series=True
     also series [S, nsteps, 17] and fw_ambiguous [S, nsteps] (see _series_one)."""
@@ -123,5 +157,8 @@ if __name__ == "__main__":
     d = sys.argv[1]
     spec = json.load(open(os.path.join(d, "spec.json")))
     th = np.load(os.path.join(d, "theta.npy"))
-    out = _run(th, spec["nx"], spec["ny"], spec["nsteps"], spec["prob_kw"], spec["procs"], spec.get("series", False))
+    if spec.get("scheme") == "vertex":
+        out = _run_vertex(th, spec["nx"], spec["ny"], spec["nsteps"], spec["prob_kw"], spec["procs"])
+    else:
+        out = _run(th, spec["nx"], spec["ny"], spec["nsteps"], spec["prob_kw"], spec["procs"], spec.get("series", False))
     np.savez(os.path.join(d, "out.npz"), **out)

@@ -1,0 +1,146 @@
+"""GPU parity of the vertex-centred discretisation (the paper's, section 2.3) against the
+vertex-centred oracle (oracle.vertex) on the same seeded inputs.
+
+Tolerances: the residual entrywise to 1e-12 of its scale; the Jacobian entrywise against the
+oracle's central-difference Jacobian to 1e-7 of each row's scale (the differences' own error
+is about 1e-9 of it); whole runs per sample to 1e-8 normwise in c and p, and the QoI to 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+from henry_inputs import draw_theta
+from tests.oracle_runs import rel_inf, vc_oracle_batch
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def hx():
+    import paper_2403_17018_amd as P
+    h = P.Henry(0)
+    yield h
+    h.close()
+
+
+def _cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _sample_major(a):   # [.., ny+1, nx+1, S] -> [S, .., ny+1, nx+1]
+    return np.moveaxis(a, -1, 0)
+
+
+@pytest.mark.parametrize("model", ["kl", "paper"])
+def test_vc_assembly_matches_oracle(hx, model):
+    import paper_2403_17018_amd as P
+    from oracle import henry as H
+    from oracle import vertex as V
+    nx, ny, S, step = 10, 6, 3, 4
+    kw = dict(field_model="paper", q_in_amp=0.5, recharge_omega=np.pi / 40.0, T=6016.0) if model == "paper" else {}
+    prob = P.paper_problem() if model == "paper" else P.problem()
+    pr = H.Problem(**kw)
+    g = H.Grid(nx, ny, 30)
+    th = draw_theta(81, S)
+    rng = np.random.default_rng(82)
+    nv = (nx + 1) * (ny + 1)
+    yv = np.repeat(-pr.Ly + np.arange(ny + 1) * pr.Ly / ny, nx + 1)
+    p = np.stack([-pr.rho0 * pr.g * yv + rng.normal(size=nv) * 30.0 for _ in range(S)], axis=-1)
+    c = rng.uniform(0.05, 0.95, size=(nv, S))
+    co = rng.uniform(0.05, 0.95, size=(nv, S))
+    R, J = hx.vc_assemble(_cu(th), P.grid(nx, ny, 30), _cu(p.reshape(ny + 1, nx + 1, S)),
+                          _cu(c.reshape(ny + 1, nx + 1, S)), _cu(co.reshape(ny + 1, nx + 1, S)), step, prob)
+    torch.cuda.synchronize()
+    R = R.cpu().numpy().reshape(2, nv, S)
+    J = J.cpu().numpy().reshape(36, nv, S)
+    nvx = nx + 1
+    for s in range(S):
+        phi, K, u = H.sample_fields(pr, g, th[s])
+        d = V.VCDiscretisation(pr, g, phi, K, u)
+        d.set_time((step + 1) * d.tau)
+        Rp, Rc = d.residual(p[:, s], c[:, s], co[:, s])
+        scale = max(np.abs(Rp).max(), np.abs(Rc).max())
+        assert np.abs(R[0, :, s] - Rp).max() <= 1e-12 * scale
+        assert np.abs(R[1, :, s] - Rc).max() <= 1e-12 * scale
+        Jo = d.jacobian_fd(p[:, s], c[:, s], co[:, s]).toarray()
+        # faces near the upwind fraction's kink (|F| = 2 D_f) have no derivative there
+        near = np.zeros(nv, bool)
+        for f in d.faces(p[:, s], c[:, s]):
+            bad = np.abs(np.abs(f["F"]) - 2.0 * f["Df"]) <= 1e-3 * np.abs(f["F"])
+            near[f["a"][bad]] = near[f["b"][bad]] = True
+        for v in range(nv):
+            if near[v]:
+                continue
+            vi, vj = v % nvx, v // nvx
+            for a in range(2):
+                row = Jo[2 * v + a]
+                rs = np.abs(row).max()
+                got = np.zeros_like(row)
+                for dj in (-1, 0, 1):
+                    for di in (-1, 0, 1):
+                        qi, qj = vi + di, vj + dj
+                        if 0 <= qi <= nx and 0 <= qj <= ny:
+                            q = qj * nvx + qi
+                            for k in range(2):
+                                got[2 * q + k] = J[((dj + 1) * 3 + di + 1) * 4 + a * 2 + k, v, s]
+                assert np.abs(got - row).max() <= 1e-7 * rs, (model, s, v, a)
+
+
+def _check_run(r, ref, nx, ny):
+    assert r.nfailed == 0, r.status
+    c = _sample_major(r.c_T.cpu().numpy())
+    p = _sample_major(r.p_T.cpu().numpy())
+    assert rel_inf(c, ref["c"]).max() <= TOL
+    assert rel_inf(p, ref["p"]).max() <= TOL
+    q = r.qoi.cpu().numpy()
+    assert np.abs(q - ref["qoi"]).max() <= TOL * np.abs(ref["qoi"]).max()
+
+
+@pytest.mark.parametrize("model", ["kl", "paper"])
+def test_vc_level0_run_matches_oracle(hx, model):
+    """Level 0 of Table 2 (16 x 8 elements, 153 vertices, 94 steps), four samples."""
+    import paper_2403_17018_amd as P
+    kw = dict(field_model="paper", q_in_amp=0.5, recharge_omega=np.pi / 40.0, T=6016.0) if model == "paper" else {}
+    prob = P.paper_problem() if model == "paper" else P.problem()
+    th = draw_theta(83, 4)
+    g = P.vc_level_grid(0)
+    ref = vc_oracle_batch(th, g.nx, g.ny, g.nsteps, kw)
+    assert ref["conv"].all()
+    o = P.solver_opts(krylov_maxit=300)
+    r = hx.vc_solve(_cu(th), g, prob, o, want_c=True, want_p=True)
+    torch.cuda.synchronize()
+    _check_run(r, ref, g.nx, g.ny)
+
+
+def test_vc_level1_first_steps_match_oracle(hx):
+    """Level 1 of Table 2 (64 x 32 elements, 2145 vertices) over its first 16 steps of 16 s
+    (the paper's model, T = 6016 s, 376 steps), two samples."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(84, 2)
+    T = 6016.0 * 16 / 376
+    kw = dict(field_model="paper", q_in_amp=0.5, recharge_omega=np.pi / 40.0, T=T)
+    ref = vc_oracle_batch(th, 64, 32, 16, kw)
+    assert ref["conv"].all()
+    o = P.solver_opts(krylov_maxit=600)
+    r = hx.vc_solve(_cu(th), P.grid(64, 32, 16), P.paper_problem(T=T), o, want_c=True, want_p=True)
+    torch.cuda.synchronize()
+    _check_run(r, ref, 64, 32)
+
+
+def test_vc_ragged_sample_count_and_errors(hx):
+    """S = 37 (a partial sample block) equals the same samples solved alone; NaN theta is refused."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(85, 37)
+    g = P.grid(16, 8, 6)
+    o = P.solver_opts(krylov_maxit=300)
+    r = hx.vc_solve(_cu(th), g, P.problem(), o, want_c=True)
+    r3 = hx.vc_solve(_cu(th[[0, 17, 36]]), g, P.problem(), o, want_c=True)
+    torch.cuda.synchronize()
+    a = r.c_T.cpu().numpy()[..., [0, 17, 36]]
+    b = r3.c_T.cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-9
+    bad = th.copy()
+    bad[3, 2] = np.nan
+    with pytest.raises(P.HenryError):
+        hx.vc_solve(_cu(bad), g, P.problem(), o)
