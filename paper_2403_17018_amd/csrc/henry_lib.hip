@@ -2416,6 +2416,31 @@ int mlmc_optimal_samples(int L, const double* V_l, const double* s_l, double eps
 // ---------------------------------------------------------------------------
 namespace {
 
+// The coarsest vertex grid is factored with partial pivoting in one workgroup per sample; its
+// dense matrix may need more LDS than a launch gets by default: raise the limit once per device.
+template <typename K>
+static void vc_lds_prepare(K* kernel, size_t bytes) {
+  static std::mutex mu;
+  static bool done[64] = {};
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev >= 0 && dev < 64 && done[dev]) return;
+  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes));
+  if (dev >= 0 && dev < 64) done[dev] = true;
+}
+static size_t vc_dense_lds(int n) { return (size_t)n * n * sizeof(double) + (size_t)n * sizeof(double) + 16; }
+
+// one coarse level of the vertex-grid multigrid (the finest level is the solver's own data)
+struct VCLevel {
+  int nx, ny, nv, ne;
+  Map m, me;
+  Grid2 E;
+  Phys P;
+  DevBuf phi, K, p, c, co, Rs, J, b, x, r;
+};
+
 struct VCSolver {
   henry_ctx* ctx;
   const henry_problem& pr;
@@ -2426,8 +2451,10 @@ struct VCSolver {
   Grid2 E;
   Phys P;
   size_t NV;
-  DevBuf phi, K, uin, p, c, c_old, R, J, x, r, rh, pv, ph, v, sv, sh, t, part, sc, ctrl, status;
+  DevBuf phi, K, uin, p, c, c_old, R, J, x, r, rh, pv, ph, v, sv, sh, t, part, sc, ctrl, status, mgr, LUc, pivc;
+  DevBuf hp1, hp2, hp3, hc1, hc2, hc3;   // states of the last steps (first Newton guess)
   int* h_ctrl = nullptr;
+  std::vector<std::unique_ptr<VCLevel>> lv;   // coarse levels 1.. of the multigrid preconditioner
 
   VCSolver(henry_ctx* c_, const henry_problem& pr_, const henry_solver_opts& o_, henry_grid g, int S_)
       : ctx(c_), pr(pr_), o(o_), nx(g.nx), ny(g.ny), nsteps(g.nsteps), S(S_) {
@@ -2442,7 +2469,7 @@ struct VCSolver {
     phi.alloc((size_t)ne * S * 8);
     K.alloc((size_t)ne * S * 8);
     uin.alloc((size_t)S * 8);
-    for (DevBuf* b : {&p, &c, &c_old}) b->alloc(NV * 8);
+    for (DevBuf* b : {&p, &c, &c_old, &hp1, &hp2, &hp3, &hc1, &hc2, &hc3}) b->alloc(NV * 8);
     for (DevBuf* b : {&R, &x, &r, &rh, &pv, &ph, &v, &sv, &sh, &t}) b->alloc(2 * NV * 8);
     J.alloc(36 * NV * 8);
     part.alloc((size_t)3 * m.ncb * S * 8);
@@ -2450,6 +2477,39 @@ struct VCSolver {
     ctrl.alloc(sizeof(int));
     status.alloc((size_t)S * sizeof(int));
     HIPCHK(hipHostMalloc((void**)&h_ctrl, sizeof(int), hipHostMallocDefault));
+    // halve while both element counts are even and stay at or above the coarse grid; the
+    // coarsest grid is smoothed in LDS by one workgroup per sample (at most 256 vertices)
+    int gx = nx, gy = ny;
+    while (gx % 2 == 0 && gy % 2 == 0 && gx / 2 >= o.coarse_nx && gy / 2 >= o.coarse_ny) {
+      gx /= 2;
+      gy /= 2;
+      auto L = std::make_unique<VCLevel>();
+      L->nx = gx;
+      L->ny = gy;
+      L->nv = (gx + 1) * (gy + 1);
+      L->ne = gx * gy;
+      L->m = make_map(S, L->nv, o.red_blocks);
+      L->me = make_map(S, L->ne, 0);
+      L->E = Grid2{gx, gy, L->ne};
+      L->P = make_phys(pr, gx, gy, nsteps);
+      const size_t n = (size_t)L->nv * S;
+      L->phi.alloc((size_t)L->ne * S * 8);
+      L->K.alloc((size_t)L->ne * S * 8);
+      for (DevBuf* b : {&L->p, &L->c, &L->co}) b->alloc(n * 8);
+      for (DevBuf* b : {&L->Rs, &L->b, &L->x, &L->r}) b->alloc(2 * n * 8);
+      L->J.alloc(36 * n * 8);
+      lv.push_back(std::move(L));
+    }
+    // the coarsest grid's dense matrix must fit the LDS of one workgroup
+    if (!lv.empty() && 2 * lv.back()->nv > VC_DENSE_MAX) lv.clear();
+    if (!lv.empty()) {
+      const int n = 2 * lv.back()->nv;
+      mgr.alloc(2 * NV * 8);
+      LUc.alloc((size_t)n * n * S * 8);
+      pivc.alloc((size_t)n * S * sizeof(int));
+      vc_lds_prepare(&k_vc_dense_factor, vc_dense_lds(VC_DENSE_MAX));
+      vc_lds_prepare(&k_vc_dense_solve, vc_dense_lds(VC_DENSE_MAX));
+    }
   }
   ~VCSolver() {
     if (h_ctrl) (void)hipHostFree(h_ctrl);
@@ -2458,6 +2518,70 @@ struct VCSolver {
   void fields(const double* theta) {
     hipLaunchKernelGGL(k_fields, grid_cells(me, ne), block_of(me), 0, st, me, E, P, make_kl(pr), make_fp(pr), theta,
                        phi.as<double>(), K.as<double>(), uin.as<double>());
+    const double* pf = phi.as<double>();
+    const double* kf = K.as<double>();
+    Grid2 Ef = E;
+    for (auto& L : lv) {
+      hipLaunchKernelGGL(k_vc_coarse_fields, grid_cells(L->me, L->ne), block_of(L->me), 0, st, L->me, L->E, Ef, pf, kf,
+                         L->phi.as<double>(), L->K.as<double>());
+      pf = L->phi.as<double>();
+      kf = L->K.as<double>();
+      Ef = L->E;
+    }
+  }
+  // coarse operators: rediscretised at the injected state (after the fine assembly)
+  void coarse_assemble() {
+    const double *pf = p.as<double>(), *cf = c.as<double>(), *cof = c_old.as<double>();
+    Grid2 Ef = E;
+    for (auto& L : lv) {
+      hipLaunchKernelGGL(k_vc_inject, grid_cells(L->m, L->nv), block_of(L->m), 0, st, L->m, L->E, Ef, pf, cf, cof,
+                         L->p.as<double>(), L->c.as<double>(), L->co.as<double>());
+      Phys Pl = L->P;
+      Pl.uin_fac = P.uin_fac;
+      hipLaunchKernelGGL((k_vc_assemble<true>), grid_cells(L->m, L->nv), block_of(L->m), 0, st, L->m, L->E, Pl,
+                         (const double*)L->phi.as<double>(), (const double*)L->K.as<double>(),
+                         (const double*)uin.as<double>(), (const double*)L->p.as<double>(),
+                         (const double*)L->c.as<double>(), (const double*)L->co.as<double>(), L->Rs.as<double>(),
+                         L->J.as<double>());
+      pf = L->p.as<double>();
+      cf = L->c.as<double>();
+      cof = L->co.as<double>();
+      Ef = L->E;
+    }
+    if (!lv.empty()) {
+      const VCLevel& Lc = *lv.back();
+      hipLaunchKernelGGL(k_vc_dense_factor, dim3(S), dim3(256), vc_dense_lds(2 * Lc.nv), st, S, Lc.E,
+                         (const double*)Lc.J.as<double>(), LUc.as<double>(), pivc.as<int>());
+    }
+  }
+  // one V-cycle on level k (0: the fine grid) for J_k x = b from x = 0
+  void vcycle(int k, const double* b, double* xo) {
+    const VCLevel* L = k > 0 ? lv[k - 1].get() : nullptr;
+    const Map& mk = k > 0 ? L->m : m;
+    const Grid2& Ek = k > 0 ? L->E : E;
+    const int nvk = k > 0 ? L->nv : nv;
+    const double* Jk = k > 0 ? L->J.as<double>() : J.as<double>();
+    const size_t n2 = 2 * (size_t)nvk * S;
+    if (k == (int)lv.size()) {   // coarsest: the direct solve with this Newton iteration's factors
+      hipLaunchKernelGGL(k_vc_dense_solve, dim3(S), dim3(256), vc_dense_lds(2 * nvk), st, S, Ek,
+                         (const double*)LUc.as<double>(), (const int*)pivc.as<int>(), b, xo);
+      return;
+    }
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, n2, xo);
+    for (int sw = 0; sw < std::max(1, o.nu_pre); ++sw)
+      for (int col = 0; col < 4; ++col)
+        hipLaunchKernelGGL(k_vc_gs, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, col, Jk, b, xo);
+    double* rk = k > 0 ? L->r.as<double>() : mgr.as<double>();
+    hipLaunchKernelGGL(k_vc_resid, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, Jk, b, (const double*)xo, rk);
+    VCLevel* C = lv[k].get();
+    hipLaunchKernelGGL(k_vc_restrict, grid_cells(C->m, C->nv), block_of(C->m), 0, st, C->m, C->E, Ek,
+                       (const double*)rk, C->b.as<double>());
+    vcycle(k + 1, C->b.as<double>(), C->x.as<double>());
+    hipLaunchKernelGGL(k_vc_prolong_add, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, C->E,
+                       (const double*)C->x.as<double>(), xo);
+    for (int sw = 0; sw < std::max(1, o.nu_post); ++sw)
+      for (int col = 3; col >= 0; --col)
+        hipLaunchKernelGGL(k_vc_gs, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, col, Jk, b, xo);
   }
   void assemble(bool with_j, const double* pp, const double* cc, const double* co, double* RR, double* JJ) {
     if (with_j)
@@ -2480,8 +2604,12 @@ struct VCSolver {
     hipLaunchKernelGGL((k_vc_dots<NQ>), grid_red(m), block_of(m), 0, st, m, nv, ab, part.as<double>());
   }
   dim3 g2() const { return dim3((unsigned)((2 * NV + 255) / 256)); }
-  // x = M^{-1} b: symmetric four-colour sweeps from zero
+  // x = M^{-1} b: a multigrid V-cycle where the grid coarsens, else symmetric four-colour sweeps
   void precond(const double* b, double* xo) {
+    if (!lv.empty()) {
+      vcycle(0, b, xo);
+      return;
+    }
     hipLaunchKernelGGL(k_zero_f64, g2(), dim3(256), 0, st, 2 * NV, xo);
     const int sweeps = std::max(1, o.nu_pre + o.nu_post);
     for (int k = 0; k < sweeps; ++k) {
@@ -2535,6 +2663,32 @@ struct VCSolver {
     }
     return it;
   }
+  // First Newton guess of step n, as henry_solve_batch makes it (newton_extrapolate): a
+  // polynomial through the last steps, or under a periodic recharge p moved along the inflow
+  // factor's change and c kept; the step's fixed point does not depend on it.
+  void guess(int n) {
+    if (!o.newton_extrapolate) return;
+    const dim3 g((unsigned)((NV + 255) / 256));
+    const bool rech = pr.recharge_omega != 0.0;
+    if (o.newton_extrapolate >= 3 && !rech) {
+      const int order = std::min(n, o.newton_extrapolate - 1);
+      const bool h3 = o.newton_extrapolate == 4;
+      hipLaunchKernelGGL(k_extrapolate_poly, g, dim3(256), 0, st, NV, order, p.as<double>(), hp1.as<double>(),
+                         hp2.as<double>(), h3 ? hp3.as<double>() : nullptr);
+      hipLaunchKernelGGL(k_extrapolate_poly, g, dim3(256), 0, st, NV, order, c.as<double>(), hc1.as<double>(),
+                         hc2.as<double>(), h3 ? hc3.as<double>() : nullptr);
+      return;
+    }
+    double gp = n == 0 ? 0.0 : 1.0, gc = gp;
+    if (n > 0 && rech && o.newton_extrapolate >= 2) {
+      auto f = [&](int k) { return 1.0 + std::sin(pr.recharge_omega * k * P.tau); };
+      const double d0 = f(n) - f(n - 1), d1 = f(n + 1) - f(n);
+      gp = std::fabs(d0) > 1e-3 ? std::max(-3.0, std::min(3.0, d1 / d0)) : 1.0;
+      gc = 0.0;
+    }
+    hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, NV, gp, p.as<double>(), hp1.as<double>());
+    hipLaunchKernelGGL(k_extrapolate, g, dim3(256), 0, st, NV, gc, c.as<double>(), hc1.as<double>());
+  }
   void run(const double* theta, double* c_T, double* p_T, double* qoi, int* status_out, double* stats) {
     fields(theta);
     hipLaunchKernelGGL(k_vc_init, grid_cells(m, nv), block_of(m), 0, st, m, E, P, p.as<double>(), c.as<double>());
@@ -2547,10 +2701,12 @@ struct VCSolver {
       const Range range("henry vc step %d/%d %dx%d S=%d", n + 1, nsteps, nx, ny, S);
       P.uin_fac = 1.0 + std::sin(pr.recharge_omega * (n + 1) * P.tau);
       HIPCHK(hipMemcpyAsync(c_old.p, c.p, NV * 8, hipMemcpyDeviceToDevice, st));
+      guess(n);
       hipLaunchKernelGGL(k_vc_step_start, fg, fb, 0, st, S, (const int*)status.as<int>(), scp);
       bool done = false;
       for (int it = 0; it < o.newton_maxit && !done; ++it) {
         assemble(true, p.as<double>(), c.as<double>(), c_old.as<double>(), R.as<double>(), J.as<double>());
+        coarse_assemble();
         bicgstab();
         hipLaunchKernelGGL(k_vc_absmax, grid_red(m), block_of(m), 0, st, m, nv, (const double*)x.as<double>(),
                            part.as<double>());

@@ -534,6 +534,230 @@ __global__ void __launch_bounds__(256) k_vc_qoi(Map m, Grid2 E, Phys P, const do
   if (threadIdx.y == 0 && sv) part[(size_t)cblk * m.S + s] = acc[0];
 }
 
+// ---- geometric multigrid on the vertex grids ----------------------------------------------
+// Coarse vertex (I, J) is fine vertex (2I, 2J); prolongation is bilinear interpolation and the
+// residual restriction its transpose (weights 1, 1/2, 1/4: the mass residuals of the fine boxes
+// are shared out to the coarse boxes they overlap, so their sum is kept).  Dirichlet components
+// (both on x = Lx, c on x = 0) get no coarse right-hand side and no correction.
+
+// r = b - J x
+__global__ void __launch_bounds__(256) k_vc_resid(Map m, Grid2 E, const double* __restrict__ J,
+                                                  const double* __restrict__ b, const double* __restrict__ x,
+                                                  double* __restrict__ r) {
+  const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
+  int s, v, sb, cb;
+  if (!map_cell(m, nv, s, v, sb, cb)) return;
+  const int S = m.S;
+  const size_t NV = (size_t)nv * S;
+  const int j = v / nvx, i = v - j * nvx;
+  const size_t id = (size_t)v * S + s;
+  double y0 = b[id], y1 = b[NV + id];
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int qi = i + di, qj = j + dj;
+      if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
+      const int bl = (dj + 1) * 3 + (di + 1);
+      const size_t q = ((size_t)qj * nvx + qi) * S + s;
+      const double x0 = x[q], x1 = x[NV + q];
+      y0 -= J[(size_t)(bl * 4 + 0) * NV + id] * x0 + J[(size_t)(bl * 4 + 1) * NV + id] * x1;
+      y1 -= J[(size_t)(bl * 4 + 2) * NV + id] * x0 + J[(size_t)(bl * 4 + 3) * NV + id] * x1;
+    }
+  r[id] = y0;
+  r[NV + id] = y1;
+}
+
+// coarse right-hand side: full weighting of the fine residual (mc: the coarse grid's map)
+__global__ void __launch_bounds__(256) k_vc_restrict(Map mc, Grid2 Ec, Grid2 Ef, const double* __restrict__ rf,
+                                                     double* __restrict__ bc) {
+  const int nvxc = Ec.nx + 1, nvc = nvxc * (Ec.ny + 1);
+  const int nvxf = Ef.nx + 1, nvyf = Ef.ny + 1;
+  int s, v, sb, cb;
+  if (!map_cell(mc, nvc, s, v, sb, cb)) return;
+  const int S = mc.S;
+  const size_t NVc = (size_t)nvc * S, NVf = (size_t)nvxf * nvyf * S;
+  const int J = v / nvxc, I = v - J * nvxc;
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int fi = 2 * I + di, fj = 2 * J + dj;
+      if (fi < 0 || fi >= nvxf || fj < 0 || fj >= nvyf) continue;
+      const double w = (di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5);
+      const size_t q = ((size_t)fj * nvxf + fi) * S + s;
+      a0 += w * rf[q];
+      a1 += w * rf[NVf + q];
+    }
+  const size_t id = (size_t)v * S + s;
+  bc[id] = I == Ec.nx ? 0.0 : a0;
+  bc[NVc + id] = (I == Ec.nx || I == 0) ? 0.0 : a1;
+}
+
+// x_f += P x_c (bilinear), Dirichlet components untouched (mf: the fine grid's map)
+__global__ void __launch_bounds__(256) k_vc_prolong_add(Map mf, Grid2 Ef, Grid2 Ec, const double* __restrict__ xc,
+                                                        double* __restrict__ xf) {
+  const int nvxf = Ef.nx + 1, nvf = nvxf * (Ef.ny + 1);
+  const int nvxc = Ec.nx + 1, nvc = nvxc * (Ec.ny + 1);
+  int s, v, sb, cb;
+  if (!map_cell(mf, nvf, s, v, sb, cb)) return;
+  const int S = mf.S;
+  const size_t NVf = (size_t)nvf * S, NVc = (size_t)nvc * S;
+  const int j = v / nvxf, i = v - j * nvxf;
+  if (i == Ef.nx) return;
+  // the four (possibly coinciding) coarse vertices around (i, j), each with weight 1/4: a
+  // coinciding vertex counted 4 or 2 times gives the bilinear weights 1 and 1/2
+  const int I0 = i >> 1, J0 = j >> 1, I1 = I0 + (i & 1), J1 = J0 + (j & 1);
+  const double w = 0.25;
+  const size_t c00 = ((size_t)J0 * nvxc + I0) * S + s, c10 = ((size_t)J0 * nvxc + I1) * S + s;
+  const size_t c01 = ((size_t)J1 * nvxc + I0) * S + s, c11 = ((size_t)J1 * nvxc + I1) * S + s;
+  const double e0 = w * (xc[c00] + xc[c10] + xc[c01] + xc[c11]);
+  const double e1 = w * (xc[NVc + c00] + xc[NVc + c10] + xc[NVc + c01] + xc[NVc + c11]);
+  const size_t id = (size_t)v * S + s;
+  xf[id] += e0;
+  if (i != 0) xf[NVf + id] += e1;
+}
+
+// coarse state by injection (coarse vertex = fine vertex (2I, 2J))
+__global__ void __launch_bounds__(256) k_vc_inject(Map mc, Grid2 Ec, Grid2 Ef, const double* __restrict__ pf,
+                                                   const double* __restrict__ cf, const double* __restrict__ cof,
+                                                   double* __restrict__ pc, double* __restrict__ cc,
+                                                   double* __restrict__ coc) {
+  const int nvxc = Ec.nx + 1, nvc = nvxc * (Ec.ny + 1);
+  int s, v, sb, cb;
+  if (!map_cell(mc, nvc, s, v, sb, cb)) return;
+  const int J = v / nvxc, I = v - J * nvxc;
+  const size_t q = ((size_t)(2 * J) * (Ef.nx + 1) + 2 * I) * mc.S + s, id = (size_t)v * mc.S + s;
+  pc[id] = pf[q];
+  cc[id] = cf[q];
+  coc[id] = cof[q];
+}
+
+// coarse element fields: phi the mean, K the geometric mean of the four children
+__global__ void __launch_bounds__(256) k_vc_coarse_fields(Map mce, Grid2 Ec, Grid2 Ef, const double* __restrict__ phif,
+                                                          const double* __restrict__ Kf, double* __restrict__ phic,
+                                                          double* __restrict__ Kc) {
+  int s, e, sb, cb;
+  if (!map_cell(mce, Ec.ncell, s, e, sb, cb)) return;
+  const int J = e / Ec.nx, I = e - J * Ec.nx;
+  double ph = 0.0, lk = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const size_t f = ((size_t)(2 * J + (q >> 1)) * Ef.nx + 2 * I + (q & 1)) * mce.S + s;
+    ph += phif[f];
+    lk += log(Kf[f]);
+  }
+  const size_t id = (size_t)e * mce.S + s;
+  phic[id] = 0.25 * ph;
+  Kc[id] = exp(0.25 * lk);
+}
+
+// Coarsest grid solved directly (Gaussian elimination with partial pivoting, section 2.3): the
+// dense matrix of its n = 2 nv unknowns (unknown 2 v + component) per sample, one workgroup
+// per sample with the matrix in LDS; the factors (LAPACK form: L below the diagonal, unit
+// diagonal implied, U on and above it, row interchanges in piv) go to global memory once per
+// Newton iteration, and every V-cycle solves with them.  n <= VC_DENSE_MAX.
+constexpr int VC_DENSE_MAX = 140;
+__global__ void __launch_bounds__(256) k_vc_dense_factor(int S, Grid2 E, const double* __restrict__ J,
+                                                         double* __restrict__ LU, int* __restrict__ piv) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy, n = 2 * nv;
+  const int s = blockIdx.x, t = threadIdx.x;
+  const size_t NV = (size_t)nv * S;
+  double* A = reinterpret_cast<double*>(smem_raw);   // [n][n]
+  int* sp = reinterpret_cast<int*>(A + (size_t)n * n);
+  for (int e = t; e < n * n; e += blockDim.x) A[e] = 0.0;
+  __syncthreads();
+  for (int e = t; e < nv * 36; e += blockDim.x) {   // scatter the nine blocks of every vertex row
+    const int v = e / 36, q = e - v * 36, bl = q >> 2, a = (q >> 1) & 1, k = q & 1;
+    const int i = v % nvx, j = v / nvx, di = bl % 3 - 1, dj = bl / 3 - 1;
+    const int qi = i + di, qj = j + dj;
+    if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
+    A[(size_t)(2 * v + a) * n + 2 * (qj * nvx + qi) + k] = J[(size_t)q * NV + (size_t)v * S + s];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (t < 64) {   // pivot: first row of largest magnitude in column k
+      double vmax = -1.0;
+      int imax = n;
+      for (int i = k + t; i < n; i += 64) {
+        const double a = fabs(A[(size_t)i * n + k]);
+        if (a > vmax) {
+          vmax = a;
+          imax = i;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double v2 = __shfl_xor(vmax, off);
+        const int i2 = __shfl_xor(imax, off);
+        if (v2 > vmax || (v2 == vmax && i2 < imax)) {
+          vmax = v2;
+          imax = i2;
+        }
+      }
+      if (t == 0) *sp = imax < n ? imax : k;
+    }
+    __syncthreads();
+    const int pr = *sp;
+    if (pr != k)
+      for (int c = t; c < n; c += blockDim.x) {
+        const double a = A[(size_t)k * n + c];
+        A[(size_t)k * n + c] = A[(size_t)pr * n + c];
+        A[(size_t)pr * n + c] = a;
+      }
+    if (t == 0) piv[(size_t)s * n + k] = pr;
+    __syncthreads();
+    const double rp = 1.0 / A[(size_t)k * n + k];
+    for (int i = k + 1 + t; i < n; i += blockDim.x) A[(size_t)i * n + k] *= rp;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int e = t; e < m * m; e += blockDim.x) {
+      const int i = k + 1 + e / m, c = k + 1 + e % m;
+      A[(size_t)i * n + c] -= A[(size_t)i * n + k] * A[(size_t)k * n + c];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += blockDim.x) LU[(size_t)s * n * n + e] = A[e];
+}
+
+// x = A^{-1} b with the factors of k_vc_dense_factor (both [2][nv][S] vectors)
+__global__ void __launch_bounds__(256) k_vc_dense_solve(int S, Grid2 E, const double* __restrict__ LU,
+                                                        const int* __restrict__ piv, const double* __restrict__ b,
+                                                        double* __restrict__ x) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nv = (E.nx + 1) * (E.ny + 1), n = 2 * nv;
+  const int s = blockIdx.x, t = threadIdx.x;
+  const size_t NV = (size_t)nv * S;
+  double* A = reinterpret_cast<double*>(smem_raw);   // [n][n]
+  double* y = A + (size_t)n * n;                       // [n]
+  for (int e = t; e < n * n; e += blockDim.x) A[e] = LU[(size_t)s * n * n + e];
+  for (int e = t; e < n; e += blockDim.x) y[e] = b[(size_t)(e & 1) * NV + (size_t)(e >> 1) * S + s];
+  __syncthreads();
+  if (t == 0)
+    for (int k = 0; k < n; ++k) {   // the row interchanges in order
+      const int pr = piv[(size_t)s * n + k];
+      const double a = y[k];
+      y[k] = y[pr];
+      y[pr] = a;
+    }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {   // L y = P b (unit lower), column by column
+    const double yk = y[k];
+    for (int i = k + 1 + t; i < n; i += blockDim.x) y[i] -= A[(size_t)i * n + k] * yk;
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {   // U x = y, column by column
+    const double xk = y[k] / A[(size_t)k * n + k];
+    __syncthreads();
+    if (t == 0) y[k] = xk;
+    for (int i = t; i < k; i += blockDim.x) y[i] -= A[(size_t)i * n + k] * xk;
+    __syncthreads();
+  }
+  for (int e = t; e < n; e += blockDim.x) x[(size_t)(e & 1) * NV + (size_t)(e >> 1) * S + s] = y[e];
+}
+
 // per-sample step bookkeeping (fin launch shape: threadIdx.y == 0 acts)
 __global__ void k_vc_step_start(int S, const int* __restrict__ status, double* __restrict__ sc) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;

@@ -144,3 +144,16 @@ def test_vc_ragged_sample_count_and_errors(hx):
     bad[3, 2] = np.nan
     with pytest.raises(P.HenryError):
         hx.vc_solve(_cu(bad), g, P.problem(), o)
+
+
+def test_vc_gauss_seidel_preconditioner_path(hx):
+    """A grid that does not coarsen to the coarse grid (12 x 6 elements) uses the plain four-colour
+    sweeps as the preconditioner: same fixed point as the oracle."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(86, 3)
+    ref = vc_oracle_batch(th, 12, 6, 20, dict(T=36000.0 * 20 / 94))
+    assert ref["conv"].all()
+    r = hx.vc_solve(_cu(th), P.grid(12, 6, 20), P.problem(T=36000.0 * 20 / 94), P.solver_opts(krylov_maxit=300),
+                    want_c=True, want_p=True)
+    torch.cuda.synchronize()
+    _check_run(r, ref, 12, 6)
