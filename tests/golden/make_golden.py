@@ -19,7 +19,12 @@ porosity contrast over the grid, the last index of the batch).  Two level-3 samp
 keep the states after steps 1, 96, 192 and 288: the CPU baseline of the benchmark times
 short oracle windows started from them, so that the whole horizon is represented.
 
-usage: python tests/golden/make_golden.py {c2|c3|c4|c5|f1|f1l3|span|all} [--procs N]
+"f3" runs the vertex-centred oracle (the paper's own discretisation, section 2.3) on level 1
+of Table 2 (64 x 32 elements, 376 steps, T = 6016 s) with the paper's model, seed 5: the
+first sample, the smallest and largest recharge zeta of the 128-sample batch (7, 63) and its
+last index (127).
+
+usage: python tests/golden/make_golden.py {c2|c3|c4|c5|f1|f1l3|f3|span|all} [--procs N]
 """
 import argparse
 import os
@@ -65,6 +70,24 @@ def _forward(args):
     print(out, r.qoi, r.newton_its, f"{time.time() - t:.0f}s", flush=True)
 
 
+SPAN_F3 = (0, 7, 63, 127)                   # first, min zeta, max zeta, last
+
+
+def _forward_vc(args):
+    level, seed, s = args
+    from oracle import vertex as V
+    pr = H.paper_problem()
+    g = V.level_grid(level)
+    th = draw_theta(seed, s + 1)[s]
+    t = time.time()
+    r = V.solve_sample(pr, g, th)
+    out = os.path.join(HERE, f"oracle_f3_l{level}_s{s}.npz")
+    np.savez_compressed(out, theta=th, c_T=r.c, p_T=r.p, qoi=r.qoi, newton_its=r.newton_its, converged=r.converged,
+                        max_salt_defect=r.max_salt_defect, max_fluid_defect=r.max_fluid_defect,
+                        nx=g.nx, ny=g.ny, nsteps=g.nsteps, seconds=time.time() - t)
+    print(out, r.qoi, r.newton_its, f"{time.time() - t:.0f}s", flush=True)
+
+
 def _adjoint(args):
     name, level, seed, s = args
     pr = H.Problem()
@@ -81,7 +104,7 @@ def _adjoint(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "f1", "f1l3", "span", "all"])
+    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "f1", "f1l3", "f3", "span", "all"])
     ap.add_argument("--procs", type=int, default=3)
     a = ap.parse_args()
     jobs = []
@@ -103,6 +126,8 @@ def main():
     if a.which in ("c3", "all"):
         w = WORKLOADS["c3_mixed_level4"]
         jobs += [(_forward, ("c3", w["level"], w["seed"], 0))]
+    if a.which in ("f3", "all"):
+        jobs += [(_forward_vc, (1, 5, s)) for s in SPAN_F3]
     if a.which in ("span", "all"):
         w2, w3, w5 = WORKLOADS["c2_fp64_level3"], WORKLOADS["c3_mixed_level4"], WORKLOADS["c5_adjoint_level3"]
         # longest first: the level-4 solves take hours

@@ -157,3 +157,30 @@ def test_vc_gauss_seidel_preconditioner_path(hx):
                     want_c=True, want_p=True)
     torch.cuda.synchronize()
     _check_run(r, ref, 12, 6)
+
+
+def test_mlmc_run_vc_matches_oracle(hx):
+    """mlmc_run_vc over levels 0 and 1 of Table 2 (the paper's model): level-0 samples and the
+    level-1 coarse partners against the live vertex oracle, level-1 sample 0 against its stored
+    oracle run (seed 5), and the estimate against the oracle's estimator on the same QoIs."""
+    import os
+    import paper_2403_17018_amd as P
+    from oracle import mlmc as M
+    kw = dict(field_model="paper", q_in_amp=0.5, recharge_omega=np.pi / 40.0, T=6016.0)
+    th0, th1 = draw_theta(87, 8), draw_theta(5, 4)
+    est = P.mlmc_run_vc(hx, [_cu(th0), _cu(th1)], [0, 1], P.paper_problem(), P.solver_opts(krylov_maxit=1000))
+    torch.cuda.synchronize()
+    assert est["nfailed"] == 0
+    q0, q1, q1c = (r.qoi.cpu().numpy() for r in est["results"])
+    ref = vc_oracle_batch(np.concatenate([th0, th1]), 16, 8, 94, kw)
+    assert ref["conv"].all()
+    assert np.abs(q0 - ref["qoi"][:8]).max() <= TOL * np.abs(ref["qoi"]).max()
+    assert np.abs(q1c - ref["qoi"][8:]).max() <= TOL * np.abs(ref["qoi"]).max()
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_f3_l1_s0.npz"))
+    assert np.array_equal(z["theta"], th1[0])
+    assert abs(q1[0] - float(z["qoi"])) <= TOL * abs(float(z["qoi"]))
+    m = M.estimate([q0, q1], [None, q1c], alpha=2.0)
+    assert est["mean"] == pytest.approx(m["mean"], rel=1e-12)
+    assert est["var_of_estimator"] == pytest.approx(m["var_of_estimator"], rel=1e-10)
+    assert est["rmse"] == pytest.approx(m["rmse"], rel=1e-10)
+    assert np.allclose(est["V"], m["V"], rtol=1e-10, atol=0.0)
