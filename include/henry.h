@@ -406,9 +406,12 @@ HENRY_API int henry_vc_assemble(henry_ctx* ctx, const henry_problem* prob, henry
  * cells of the swept colour x samples) and the summed event time in ms.  Both calls
  * synchronise the stream. */
 enum henry_prof_class {
-  HENRY_PROF_ASSEMBLE = 0,    /* fine-grid residual + Jacobian assembly */
-  HENRY_PROF_GS = 1,          /* fine-grid red-black GS passes that read neighbours */
-  HENRY_PROF_SPMV = 2,        /* fine-grid FP64 block SpMV with fused dots */
+  HENRY_PROF_ASSEMBLE = 0,    /* fine-grid residual + Jacobian assembly (henry_vc_solve: its
+                                 vertex-centred assembly, units vertex-samples) */
+  HENRY_PROF_GS = 1,          /* fine-grid red-black GS passes that read neighbours (henry_vc_solve:
+                                 each four-colour pass, units the colour's vertex-samples) */
+  HENRY_PROF_SPMV = 2,        /* fine-grid FP64 block SpMV with fused dots (henry_vc_solve: the
+                                 nine-point SpMV, units vertex-samples) */
   HENRY_PROF_RESTRICT = 3,    /* fine-grid fused residual + restriction */
   HENRY_PROF_PROLONG = 4,     /* prolongation + correction onto the fine grid */
   HENRY_PROF_BAND_FACTOR = 5, /* coarse banded LU factorisation */

@@ -6,6 +6,7 @@
 // (damping, convergence, breakdown) are taken on the device; the host reads one
 // counter per iteration to decide whether to launch another.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <array>
@@ -433,10 +434,20 @@ static hipError_t scratch_init(int device) {
   return hipSuccess;
 }
 
-// Launch `f` on stream `st` and, when profiling (and not capturing a graph), bracket
-// it with events of class `cls`.
+// Launch `f` on stream `st` and, when profiling (and not capturing a graph), time its
+// first kernel with events of class `cls`: `f` launches through launch_timed, whose first
+// call hands the events to hipExtLaunchKernelGGL, so they hold that kernel's own start and
+// end timestamps (no event-record gaps around it).
 static thread_local bool tl_capturing = false;
 static thread_local bool tl_untimed = false;   // compacted sub-batches are not timed
+static thread_local hipEvent_t tl_ev_start = nullptr, tl_ev_stop = nullptr;
+template <typename K, typename... Args>
+static void launch_timed(K kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t st, Args... args) {
+  hipEvent_t a = tl_ev_start, b = tl_ev_stop;
+  tl_ev_start = tl_ev_stop = nullptr;
+  if (a) hipExtLaunchKernelGGL(kernel, grid, block, lds, st, a, b, 0, args...);
+  else hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+}
 template <typename F>
 static void timed(henry_ctx* ctx, hipStream_t st, int cls, long long units, F&& f) {
   if (!ctx->prof.on || tl_capturing || tl_untimed) {
@@ -445,11 +456,39 @@ static void timed(henry_ctx* ctx, hipStream_t st, int cls, long long units, F&& 
   }
   std::lock_guard<std::mutex> lk(ctx->prof.mu);
   auto& sl = ctx->prof.acquire(cls);
-  HIPCHK(hipEventRecord(sl.a, st));
+  tl_ev_start = sl.a;
+  tl_ev_stop = sl.b;
   f();
-  HIPCHK(hipEventRecord(sl.b, st));
+  if (tl_ev_start) {
+    tl_ev_start = tl_ev_stop = nullptr;
+    fail(HENRY_EDEVICE, "internal: a timed launch did not go through launch_timed");
+  }
   ctx->prof.c[cls].launches++;
   ctx->prof.c[cls].units += units;
+}
+
+// Capture the launches `f` makes on stream `st` (thread-local capture mode; the library's
+// event timing is off meanwhile) as an instantiated graph.
+template <typename F>
+static hipGraphExec_t capture_graph(hipStream_t st, F&& f) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  tl_capturing = true;
+  try {
+    f();
+  } catch (...) {
+    tl_capturing = false;
+    (void)hipStreamEndCapture(st, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  tl_capturing = false;
+  HIPCHK(hipStreamEndCapture(st, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(e);
+  return ex;
 }
 
 template <typename T>
@@ -706,15 +745,15 @@ struct Solver {
     const Map& m = P.m;
     timed(ctx, st, HENRY_PROF_ASSEMBLE, (long long)P.N, [&] {
       if (spmv32())   // only the FP32 Jacobian: the multigrid and the Krylov products read it
-        hipLaunchKernelGGL((k_assemble<true, float, false>), asm_grid(m, P.G), asm_block(m), asm_lds(m.SX), st, m, P.G,
+        launch_timed((k_assemble<true, float, false>), asm_grid(m, P.G), asm_block(m), asm_lds(m.SX), st, m, P.G,
                            phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
                            P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J32.as<float>(), (float*)nullptr);
       else if (P.prec == 32)
-        hipLaunchKernelGGL((k_assemble<true, double, true>), asm_grid(m, P.G), asm_block(m), asm_lds(m.SX), st, m, P.G,
+        launch_timed((k_assemble<true, double, true>), asm_grid(m, P.G), asm_block(m), asm_lds(m.SX), st, m, P.G,
                            phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
                            P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J.as<double>(), P.J32.as<float>());
       else
-        hipLaunchKernelGGL((k_assemble<true, double, false>), asm_grid(m, P.G), asm_block(m), asm_lds(m.SX), st, m, P.G,
+        launch_timed((k_assemble<true, double, false>), asm_grid(m, P.G), asm_block(m), asm_lds(m.SX), st, m, P.G,
                            phys, P.p.as<double>(), P.c.as<double>(), P.c_old.as<double>(), P.phi.as<double>(),
                            P.K.as<double>(), P.uin.as<double>(), P.R.as<double>(), P.J.as<double>(), (float*)nullptr);
     });
@@ -744,21 +783,21 @@ struct Solver {
       hipLaunchKernelGGL((k_dense_build<T>), dim3(n, P.S), dim3(256), 0, st, P.S, Cc.nx, Cc.ny,
                          level_J<T>(P.nlev - 1), P.LU.as<T>());
       timed(ctx, st, HENRY_PROF_DENSE_FACTOR, (long long)P.S, [&] {
-        hipLaunchKernelGGL((k_dense_factor<T, 16>), dim3(P.S), dim3(DENSE_THREADS), lds, st, n, P.LU.as<T>(),
+        launch_timed((k_dense_factor<T, 16>), dim3(P.S), dim3(DENSE_THREADS), lds, st, n, P.LU.as<T>(),
                            P.perm.as<int>());
       });
       return;
     }
     if (P.csolver == 2) {
       timed(ctx, st, HENRY_PROF_BAND_FACTOR, (long long)Cc.ncell * P.S, [&] {
-        hipLaunchKernelGGL((k_gb_factor<T>), dim3(P.S), dim3(GB_THREADS), gb_factor_lds<T>(Cc.ny), st, P.S, Cc.nx,
+        launch_timed((k_gb_factor<T>), dim3(P.S), dim3(GB_THREADS), gb_factor_lds<T>(Cc.ny), st, P.S, Cc.nx,
                            Cc.ny, level_J<T>(P.nlev - 1), P.LU.as<T>(), P.perm.as<int>());
       });
       return;
     }
     const size_t lds = (size_t)(P.mb + 1) * (P.mb + 1) * 4 * sizeof(T);
     timed(ctx, st, HENRY_PROF_BAND_FACTOR, (long long)Cc.ncell * P.S, [&] {
-      hipLaunchKernelGGL((k_band_factor<T>), dim3(P.S), dim3(64), lds, st, P.S, Cc.nx, Cc.ny, level_J<T>(P.nlev - 1),
+      launch_timed((k_band_factor<T>), dim3(P.S), dim3(64), lds, st, P.S, Cc.nx, Cc.ny, level_J<T>(P.nlev - 1),
                          P.LU.as<T>());
     });
   }
@@ -779,14 +818,14 @@ struct Solver {
     MGLevel& L = *P.lv[k];
     if (k == P.nlev - 1 && P.csolver == 1) {
       timed(ctx, st, HENRY_PROF_DENSE_SOLVE, (long long)P.S, [&] {
-        hipLaunchKernelGGL((k_dense_solve<T, TR>), dim3(P.S), dim3(DENSE_SOLVE_THREADS), dense_solve_lds<T>(2 * L.ncell), st,
+        launch_timed((k_dense_solve<T, TR>), dim3(P.S), dim3(DENSE_SOLVE_THREADS), dense_solve_lds<T>(2 * L.ncell), st,
                            P.S, L.ncell, P.LU.as<T>(), (const int*)P.perm.as<int>(), b, x);
       });
       return;
     }
     if (k == P.nlev - 1 && P.csolver == 2) {
       timed(ctx, st, HENRY_PROF_BAND_SOLVE, (long long)L.ncell * P.S, [&] {
-        hipLaunchKernelGGL((k_gb_solve<T, TR>), dim3(P.S), dim3(64), gb_solve_lds<T>(L.nx, L.ny), st, P.S, L.nx, L.ny,
+        launch_timed((k_gb_solve<T, TR>), dim3(P.S), dim3(64), gb_solve_lds<T>(L.nx, L.ny), st, P.S, L.nx, L.ny,
                            (const T*)P.LU.as<T>(), (const int*)P.perm.as<int>(), b, x);
       });
       return;
@@ -796,10 +835,10 @@ struct Solver {
       const size_t lds = band_solve_lds<T>(L.ncell, P.mb, CH);
       timed(ctx, st, HENRY_PROF_BAND_SOLVE, (long long)L.ncell * P.S, [&] {
         if (TR)
-          hipLaunchKernelGGL((k_band_solve_T<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, CH, P.LU.as<T>(), b,
+          launch_timed((k_band_solve_T<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, CH, P.LU.as<T>(), b,
                              x);
         else
-          hipLaunchKernelGGL((k_band_solve<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, CH, P.LU.as<T>(), b, x);
+          launch_timed((k_band_solve<T>), dim3(P.S), dim3(64), lds, st, P.S, L.nx, L.ny, CH, P.LU.as<T>(), b, x);
       });
       return;
     }
@@ -812,16 +851,16 @@ struct Solver {
     auto gs = [&](int colour, int mode) {
       auto f = [&] {
         if (mode == 1)
-          hipLaunchKernelGGL((k_gs_colour<T, TR, 1>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
+          launch_timed((k_gs_colour<T, TR, 1>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
                              (const T*)nullptr);
         else if (mode == 2)
-          hipLaunchKernelGGL((k_gs_colour<T, TR, 2>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
+          launch_timed((k_gs_colour<T, TR, 2>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
                              (const T*)C.x.as<T>());
         else if (mode == 3)
-          hipLaunchKernelGGL((k_gs_colour<T, TR, 3>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
+          launch_timed((k_gs_colour<T, TR, 3>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
                              (const T*)nullptr);
         else
-          hipLaunchKernelGGL((k_gs_colour<T, TR, 0>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
+          launch_timed((k_gs_colour<T, TR, 0>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
                              (const T*)nullptr);
       };
       if (k == 0 && mode == 0) timed(ctx, st, HENRY_PROF_GS, half_units, f);
@@ -840,7 +879,7 @@ struct Solver {
       }
     }
     auto rr = [&] {
-      hipLaunchKernelGGL((k_residual_restrict<T, TR>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G,
+      launch_timed((k_residual_restrict<T, TR>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G,
                          implicit_red ? 2 : 1, J, b, x, C.b.as<T>());
     };
     if (k == 0) timed(ctx, st, HENRY_PROF_RESTRICT, (long long)L.ncell * P.S, rr);
@@ -851,7 +890,7 @@ struct Solver {
       // separate prolongation and correction of every cell, then plain post-smoothing passes
       // (the red pass overwrites red x from the black neighbours alone)
       auto pc = [&] {
-        hipLaunchKernelGGL((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G,
+        launch_timed((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G,
                            C.x.as<T>(), x);
       };
       if (k == 0) timed(ctx, st, HENRY_PROF_PROLONG, (long long)L.ncell * P.S, pc);
@@ -980,10 +1019,10 @@ struct Solver {
   void spmv(const TX* x, double* y, const double* d0, const double* yb) {
     const Map& m = P.m;
     if (spmv32())
-      hipLaunchKernelGGL((k_spmv_dot<NDOT, TR, float, TX>), grid_red(m), block_of(m), 0, st, m, P.G,
+      launch_timed((k_spmv_dot<NDOT, TR, float, TX>), grid_red(m), block_of(m), 0, st, m, P.G,
                          (const float*)P.J32.as<float>(), x, y, d0, P.part.as<double>(), yb);
     else
-      hipLaunchKernelGGL((k_spmv_dot<NDOT, TR, double, TX>), grid_red(m), block_of(m), 0, st, m, P.G,
+      launch_timed((k_spmv_dot<NDOT, TR, double, TX>), grid_red(m), block_of(m), 0, st, m, P.G,
                          (const double*)P.J.as<double>(), x, y, d0, P.part.as<double>(), yb);
   }
   // y = J M^{-1}-output: the preconditioned vector is FP32 in the FP32-multigrid path
@@ -1059,24 +1098,7 @@ struct Solver {
   // Capture the launches `f` makes on this solver's stream as an instantiated graph.
   template <typename F>
   hipGraphExec_t capture(F&& f) {
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    tl_capturing = true;
-    try {
-      f();
-    } catch (...) {
-      tl_capturing = false;
-      (void)hipStreamEndCapture(st, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    tl_capturing = false;
-    HIPCHK(hipStreamEndCapture(st, &g));
-    hipGraphExec_t ex = nullptr;
-    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    HIPCHK(e);
-    return ex;
+    return capture_graph(st, std::forward<F>(f));
   }
 
   // fields, coarse coefficients, initial state, cleared status/stats
@@ -2455,10 +2477,12 @@ struct VCSolver {
   DevBuf hp1, hp2, hp3, hc1, hc2, hc3;   // states of the last steps (first Newton guess)
   int* h_ctrl = nullptr;
   std::vector<std::unique_ptr<VCLevel>> lv;   // coarse levels 1.. of the multigrid preconditioner
+  hipGraphExec_t gbody = nullptr;             // one BiCGStab iteration (use_graphs)
 
-  VCSolver(henry_ctx* c_, const henry_problem& pr_, const henry_solver_opts& o_, henry_grid g, int S_)
+  VCSolver(henry_ctx* c_, const henry_problem& pr_, const henry_solver_opts& o_, henry_grid g, int S_,
+           hipStream_t stream)
       : ctx(c_), pr(pr_), o(o_), nx(g.nx), ny(g.ny), nsteps(g.nsteps), S(S_) {
-    st = ctx->stream;
+    st = stream;
     nv = (nx + 1) * (ny + 1);
     ne = nx * ny;
     m = make_map(S, nv, o.red_blocks);
@@ -2512,6 +2536,7 @@ struct VCSolver {
     }
   }
   ~VCSolver() {
+    if (gbody) (void)hipGraphExecDestroy(gbody);
     if (h_ctrl) (void)hipHostFree(h_ctrl);
   }
 
@@ -2563,14 +2588,13 @@ struct VCSolver {
     const double* Jk = k > 0 ? L->J.as<double>() : J.as<double>();
     const size_t n2 = 2 * (size_t)nvk * S;
     if (k == (int)lv.size()) {   // coarsest: the direct solve with this Newton iteration's factors
-      hipLaunchKernelGGL(k_vc_dense_solve, dim3(S), dim3(256), vc_dense_lds(2 * nvk), st, S, Ek,
+      hipLaunchKernelGGL(k_vc_dense_solve, dim3(S), dim3(64), vc_dense_lds(2 * nvk), st, S, Ek,
                          (const double*)LUc.as<double>(), (const int*)pivc.as<int>(), b, xo);
       return;
     }
     hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, n2, xo);
     for (int sw = 0; sw < std::max(1, o.nu_pre); ++sw)
-      for (int col = 0; col < 4; ++col)
-        hipLaunchKernelGGL(k_vc_gs, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, col, Jk, b, xo);
+      for (int col = 0; col < 4; ++col) gs_pass(k, mk, Ek, col, Jk, b, xo);
     double* rk = k > 0 ? L->r.as<double>() : mgr.as<double>();
     hipLaunchKernelGGL(k_vc_resid, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, Jk, b, (const double*)xo, rk);
     VCLevel* C = lv[k].get();
@@ -2580,22 +2604,37 @@ struct VCSolver {
     hipLaunchKernelGGL(k_vc_prolong_add, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, C->E,
                        (const double*)C->x.as<double>(), xo);
     for (int sw = 0; sw < std::max(1, o.nu_post); ++sw)
-      for (int col = 3; col >= 0; --col)
-        hipLaunchKernelGGL(k_vc_gs, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, col, Jk, b, xo);
+      for (int col = 3; col >= 0; --col) gs_pass(k, mk, Ek, col, Jk, b, xo);
+  }
+  // one colour pass on level k; fine-grid passes are timed as HENRY_PROF_GS (units: the
+  // colour's vertex-samples)
+  void gs_pass(int k, const Map& mk, const Grid2& Ek, int col, const double* Jk, const double* b, double* xo) {
+    const int nc = vc_colour_cells(Ek.nx, Ek.ny, col);
+    auto f = [&] {
+      launch_timed(k_vc_gs, grid_cells(mk, vc_colour_cells(Ek.nx, Ek.ny, 0)), block_of(mk), 0, st, mk, Ek, col, Jk,
+                         b, xo);
+    };
+    if (k == 0) timed(ctx, st, HENRY_PROF_GS, (long long)nc * S, f);
+    else f();
   }
   void assemble(bool with_j, const double* pp, const double* cc, const double* co, double* RR, double* JJ) {
     if (with_j)
-      hipLaunchKernelGGL((k_vc_assemble<true>), grid_cells(m, nv), block_of(m), 0, st, m, E, P,
-                         (const double*)phi.as<double>(), (const double*)K.as<double>(),
-                         (const double*)uin.as<double>(), pp, cc, co, RR, JJ);
+      timed(ctx, st, HENRY_PROF_ASSEMBLE, (long long)NV, [&] {
+        launch_timed((k_vc_assemble<true>), grid_cells(m, nv), block_of(m), 0, st, m, E, P,
+                           (const double*)phi.as<double>(), (const double*)K.as<double>(),
+                           (const double*)uin.as<double>(), pp, cc, co, RR, JJ);
+      });
     else
       hipLaunchKernelGGL((k_vc_assemble<false>), grid_cells(m, nv), block_of(m), 0, st, m, E, P,
                          (const double*)phi.as<double>(), (const double*)K.as<double>(),
                          (const double*)uin.as<double>(), pp, cc, co, RR, JJ);
   }
   int read_ctrl() {
+    const auto t0 = std::chrono::steady_clock::now();
     HIPCHK(hipMemcpyAsync(h_ctrl, ctrl.p, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    ctx->host_syncs++;
+    ctx->host_sync_ns += std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
     return *h_ctrl;
   }
   void zero_ctrl() { hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, (size_t)1, ctrl.as<int>()); }
@@ -2613,55 +2652,65 @@ struct VCSolver {
     hipLaunchKernelGGL(k_zero_f64, g2(), dim3(256), 0, st, 2 * NV, xo);
     const int sweeps = std::max(1, o.nu_pre + o.nu_post);
     for (int k = 0; k < sweeps; ++k) {
-      for (int col = 0; col < 4; ++col)
-        hipLaunchKernelGGL(k_vc_gs, grid_cells(m, nv), block_of(m), 0, st, m, E, col, (const double*)J.as<double>(), b,
-                           xo);
-      for (int col = 3; col >= 0; --col)
-        hipLaunchKernelGGL(k_vc_gs, grid_cells(m, nv), block_of(m), 0, st, m, E, col, (const double*)J.as<double>(), b,
-                           xo);
+      for (int col = 0; col < 4; ++col) gs_pass(0, m, E, col, (const double*)J.as<double>(), b, xo);
+      for (int col = 3; col >= 0; --col) gs_pass(0, m, E, col, (const double*)J.as<double>(), b, xo);
     }
   }
   void spmv(const double* xi, double* yo) {
-    hipLaunchKernelGGL(k_vc_spmv, grid_cells(m, nv), block_of(m), 0, st, m, E, (const double*)J.as<double>(), xi, yo);
+    timed(ctx, st, HENRY_PROF_SPMV, (long long)NV, [&] {
+      launch_timed(k_vc_spmv, grid_cells(m, nv), block_of(m), 0, st, m, E, (const double*)J.as<double>(), xi, yo);
+    });
   }
   // J x = -R (masked by the Newton flags); returns the iterations run
   int bicgstab() {
     double* scp = sc.as<double>();
     const dim3 fg = fin_grid(S), fb = fin_block(S);
-    const double rtol2 = o.krylov_rtol * o.krylov_rtol;
     hipLaunchKernelGGL(k_vc_rhs, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp, (const double*)R.as<double>(),
                        x.as<double>(), r.as<double>(), pv.as<double>(), rh.as<double>());
     dots<1>(VCPairs{{r.as<double>(), nullptr, nullptr}, {r.as<double>(), nullptr, nullptr}});
     zero_ctrl();
     hipLaunchKernelGGL(k_vc_bicg_start, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, ctrl.as<int>());
     if (read_ctrl() == 0) return 0;
+    // the iteration's launches use fixed buffers and constants, so with use_graphs they are
+    // captured once per solver and replayed
+    const bool graphs = o.use_graphs && !ctx->prof.on;
+    if (graphs && !gbody) gbody = capture_graph(st, [&] { iteration(); });
     int it = 0;
     for (; it < o.krylov_maxit; ++it) {
-      precond(pv.as<double>(), ph.as<double>());
-      spmv(ph.as<double>(), v.as<double>());
-      dots<1>(VCPairs{{rh.as<double>(), nullptr, nullptr}, {v.as<double>(), nullptr, nullptr}});
-      hipLaunchKernelGGL(k_vc_bicg_alpha, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, status.as<int>());
-      hipLaunchKernelGGL(k_vc_axpy_s, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp,
-                         (const double*)r.as<double>(), (const double*)v.as<double>(), sv.as<double>());
-      precond(sv.as<double>(), sh.as<double>());
-      spmv(sh.as<double>(), t.as<double>());
-      dots<3>(VCPairs{{sv.as<double>(), t.as<double>(), t.as<double>()}, {sv.as<double>(), sv.as<double>(), t.as<double>()}});
-      hipLaunchKernelGGL(k_vc_bicg_omega, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, rtol2);
-      hipLaunchKernelGGL(k_vc_update_xr, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp,
-                         (const double*)ph.as<double>(), (const double*)sh.as<double>(), (const double*)sv.as<double>(),
-                         (const double*)t.as<double>(), x.as<double>(), r.as<double>());
-      dots<2>(VCPairs{{rh.as<double>(), r.as<double>(), nullptr}, {r.as<double>(), r.as<double>(), nullptr}});
-      zero_ctrl();
-      hipLaunchKernelGGL(k_vc_bicg_beta, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, rtol2,
-                         status.as<int>(), ctrl.as<int>());
-      hipLaunchKernelGGL(k_vc_update_p, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp,
-                         (const double*)r.as<double>(), (const double*)v.as<double>(), pv.as<double>());
+      if (graphs) HIPCHK(hipGraphLaunch(gbody, st));
+      else iteration();
       if (read_ctrl() == 0) {
         ++it;
         break;
       }
     }
     return it;
+  }
+  // one BiCGStab iteration for every sample still iterating; ends with the count of those
+  // still iterating in ctrl
+  void iteration() {
+    double* scp = sc.as<double>();
+    const dim3 fg = fin_grid(S), fb = fin_block(S);
+    const double rtol2 = o.krylov_rtol * o.krylov_rtol;
+    precond(pv.as<double>(), ph.as<double>());
+    spmv(ph.as<double>(), v.as<double>());
+    dots<1>(VCPairs{{rh.as<double>(), nullptr, nullptr}, {v.as<double>(), nullptr, nullptr}});
+    hipLaunchKernelGGL(k_vc_bicg_alpha, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, status.as<int>());
+    hipLaunchKernelGGL(k_vc_axpy_s, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp,
+                       (const double*)r.as<double>(), (const double*)v.as<double>(), sv.as<double>());
+    precond(sv.as<double>(), sh.as<double>());
+    spmv(sh.as<double>(), t.as<double>());
+    dots<3>(VCPairs{{sv.as<double>(), t.as<double>(), t.as<double>()}, {sv.as<double>(), sv.as<double>(), t.as<double>()}});
+    hipLaunchKernelGGL(k_vc_bicg_omega, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, rtol2);
+    hipLaunchKernelGGL(k_vc_update_xr, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp,
+                       (const double*)ph.as<double>(), (const double*)sh.as<double>(), (const double*)sv.as<double>(),
+                       (const double*)t.as<double>(), x.as<double>(), r.as<double>());
+    dots<2>(VCPairs{{rh.as<double>(), r.as<double>(), nullptr}, {r.as<double>(), r.as<double>(), nullptr}});
+    zero_ctrl();
+    hipLaunchKernelGGL(k_vc_bicg_beta, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, rtol2,
+                       status.as<int>(), ctrl.as<int>());
+    hipLaunchKernelGGL(k_vc_update_p, g2(), dim3(256), 0, st, 2 * NV, NV, S, (const double*)scp,
+                       (const double*)r.as<double>(), (const double*)v.as<double>(), pv.as<double>());
   }
   // First Newton guess of step n, as henry_solve_batch makes it (newton_extrapolate): a
   // polynomial through the last steps, or under a periodic recharge p moved along the inflow
@@ -2752,7 +2801,7 @@ int henry_vc_assemble(henry_ctx* ctx, const henry_problem* prob, henry_grid grid
     if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
     henry_solver_opts o;
     henry_solver_opts_default(&o);
-    VCSolver sv(ctx, *prob, o, grid, S);
+    VCSolver sv(ctx, *prob, o, grid, S, ctx->stream);
     sv.P.uin_fac = 1.0 + std::sin(prob->recharge_omega * (step + 1) * sv.P.tau);
     sv.fields(theta);
     sv.assemble(true, p, c, c_old, R, J);
@@ -2774,13 +2823,21 @@ int henry_vc_solve(henry_ctx* ctx, const henry_problem* prob, const henry_solver
     if (S < 1 || !theta) fail(HENRY_EINVAL, "S < 1 or theta NULL");
     if (theta_check(ctx, theta, S)) fail(HENRY_EINVAL, "theta contains non-finite values");
     const Range range("henry_vc_solve %dx%d S=%d steps=%d", grid.nx, grid.ny, S, grid.nsteps);
-    VCSolver sv(ctx, *prob, o, grid, S);
+    // the solve runs on the library's own stream (graphs cannot be captured on the legacy
+    // default stream), ordered after the caller's stream and synchronised before returning
+    hipStream_t st = ctx_stream(ctx, 0);
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(st, ev, 0));
+    HIPCHK(hipEventDestroy(ev));
+    VCSolver sv(ctx, *prob, o, grid, S, st);
     sv.run(theta, c_T, p_T, qoi, status, stats);
     HIPCHK(hipGetLastError());
     int nf = 0;
     std::vector<int> hs(S);
-    HIPCHK(hipMemcpyAsync(hs.data(), sv.status.p, (size_t)S * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpyAsync(hs.data(), sv.status.p, (size_t)S * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     for (int s = 0; s < S; ++s) nf += hs[s] != 0;
     return nf;
   });

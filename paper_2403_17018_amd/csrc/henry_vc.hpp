@@ -218,14 +218,21 @@ __global__ void __launch_bounds__(256) k_vc_spmv(Map m, Grid2 E, const double* _
 
 // One colour ((i & 1) + 2 (j & 1)) of a four-colour block Gauss-Seidel sweep:
 // x_v = D_v^{-1} (b_v - sum over the other 8 blocks A_vq x_q); vertices of one colour do not
-// touch each other in the nine-point stencil.
+// touch each other in the nine-point stencil.  The launch covers only the colour's vertices
+// (i = 2 u_i + colour & 1, j = 2 u_j + colour >> 1): vc_colour_cells() of colour 0, the largest.
+__host__ __device__ inline int vc_colour_cells(int nx, int ny, int colour) {
+  return ((nx + 2 - (colour & 1)) >> 1) * ((ny + 2 - (colour >> 1)) >> 1);
+}
 __global__ void __launch_bounds__(256) k_vc_gs(Map m, Grid2 E, int colour, const double* __restrict__ J,
                                                const double* __restrict__ b, double* __restrict__ x) {
   const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
-  int s, v, sb, cb;
-  if (!map_cell(m, nv, s, v, sb, cb)) return;
-  const int j = v / nvx, i = v - j * nvx;
-  if ((i & 1) + 2 * (j & 1) != colour) return;
+  const int ci = colour & 1, cj = colour >> 1;
+  const int nci = (nvx + 1 - ci) >> 1, ncj = (nvy + 1 - cj) >> 1;
+  int s, u, sb, cb;
+  if (!map_cell(m, nci * ncj, s, u, sb, cb)) return;
+  const int uj = u / nci;
+  const int i = 2 * (u - uj * nci) + ci, j = 2 * uj + cj;
+  const int v = j * nvx + i;
   const int S = m.S;
   const size_t NV = (size_t)nv * S;
   const size_t id = (size_t)v * S + s;
@@ -654,108 +661,226 @@ __global__ void __launch_bounds__(256) k_vc_coarse_fields(Map mce, Grid2 Ec, Gri
 }
 
 // Coarsest grid solved directly (Gaussian elimination with partial pivoting, section 2.3): the
-// dense matrix of its n = 2 nv unknowns (unknown 2 v + component) per sample, one workgroup
-// per sample with the matrix in LDS; the factors (LAPACK form: L below the diagonal, unit
-// diagonal implied, U on and above it, row interchanges in piv) go to global memory once per
-// Newton iteration, and every V-cycle solves with them.  n <= VC_DENSE_MAX.
+// dense matrix of its n = 2 nv unknowns (unknown 2 v + component) per sample, held
+// column-major in LDS (A[c n + r]).  The factors (P A = L U: L below the diagonal with its
+// unit diagonal implied, U on and above it) go to global memory column-major once per Newton
+// iteration with the row order perm (row i of P A is row perm[i] of A), and every V-cycle
+// solves with them.  Lanes own rows l, l + 64 and l + 128.  n <= VC_DENSE_MAX.
 constexpr int VC_DENSE_MAX = 140;
+constexpr int VC_DENSE_SLOTS = 3;   // rows per lane
+static_assert(VC_DENSE_SLOTS == 3 && 64 * VC_DENSE_SLOTS >= VC_DENSE_MAX, "vc_slot selects among three slots");
+
+// lane `lane`'s value of v (lane uniform across the wavefront)
+__device__ __forceinline__ double vc_bcast(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// the slot holding row r (r uniform); scalar arguments keep the slots in registers
+__device__ __forceinline__ double vc_slot(double v0, double v1, double v2, int r) {
+  return r < 64 ? v0 : (r < 128 ? v1 : v2);
+}
+
+// Factorisation, one workgroup of four wavefronts per sample.  Wavefront w owns the columns
+// c = w (mod 4).  Step k: every wavefront reads column k and finds the pivot row p (the first
+// row of largest magnitude at or below the diagonal) and the multipliers itself; each swaps rows
+// k and p in its own columns and updates its own trailing columns; one barrier ends the step,
+// after which the owner of column k stores its multipliers (no wavefront reads column k again).
 __global__ void __launch_bounds__(256) k_vc_dense_factor(int S, Grid2 E, const double* __restrict__ J,
-                                                         double* __restrict__ LU, int* __restrict__ piv) {
+                                                         double* __restrict__ LU, int* __restrict__ perm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy, n = 2 * nv;
-  const int s = blockIdx.x, t = threadIdx.x;
+  const int s = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
   const size_t NV = (size_t)nv * S;
-  double* A = reinterpret_cast<double*>(smem_raw);   // [n][n]
-  int* sp = reinterpret_cast<int*>(A + (size_t)n * n);
-  for (int e = t; e < n * n; e += blockDim.x) A[e] = 0.0;
+  double* A = reinterpret_cast<double*>(smem_raw);   // A[c * n + r]
+  int* pr = reinterpret_cast<int*>(A + (size_t)n * n);
+  for (int e = t; e < n * n; e += 256) A[e] = 0.0;
+  for (int r = t; r < n; r += 256) pr[r] = r;
   __syncthreads();
-  for (int e = t; e < nv * 36; e += blockDim.x) {   // scatter the nine blocks of every vertex row
-    const int v = e / 36, q = e - v * 36, bl = q >> 2, a = (q >> 1) & 1, k = q & 1;
-    const int i = v % nvx, j = v / nvx, di = bl % 3 - 1, dj = bl / 3 - 1;
-    const int qi = i + di, qj = j + dj;
-    if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
-    A[(size_t)(2 * v + a) * n + 2 * (qj * nvx + qi) + k] = J[(size_t)q * NV + (size_t)v * S + s];
+  // scatter the nine blocks of every vertex row, four independent loads in flight per thread
+  for (int e0 = 0; e0 < nv * 36; e0 += 4 * 256) {
+    double val[4];
+    int dst[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * 256 + t;
+      dst[u] = -1;
+      val[u] = 0.0;
+      if (e < nv * 36) {
+        const int v = e / 36, q = e - v * 36, bl = q >> 2, a = (q >> 1) & 1, k = q & 1;
+        const int i = v % nvx, j = v / nvx, qi = i + bl % 3 - 1, qj = j + bl / 3 - 1;
+        if (qi >= 0 && qi < nvx && qj >= 0 && qj < nvy) {
+          dst[u] = (2 * (qj * nvx + qi) + k) * n + 2 * v + a;
+          val[u] = J[(size_t)q * NV + (size_t)v * S + s];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (dst[u] >= 0) A[dst[u]] = val[u];
   }
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    if (t < 64) {   // pivot: first row of largest magnitude in column k
-      double vmax = -1.0;
-      int imax = n;
-      for (int i = k + t; i < n; i += 64) {
-        const double a = fabs(A[(size_t)i * n + k]);
-        if (a > vmax) {
-          vmax = a;
-          imax = i;
-        }
-      }
+    const double* Ak = A + (size_t)k * n;
+    double ck[VC_DENSE_SLOTS];
+    double vmax = -1.0;
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double v2 = __shfl_xor(vmax, off);
-        const int i2 = __shfl_xor(imax, off);
-        if (v2 > vmax || (v2 == vmax && i2 < imax)) {
-          vmax = v2;
-          imax = i2;
+    for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
+      const int r = lane + 64 * q;
+      ck[q] = r < n ? Ak[r] : 0.0;
+      if (r >= k && r < n) vmax = fmax(vmax, fabs(ck[q]));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
+    int p = k;
+#pragma unroll
+    for (int q = VC_DENSE_SLOTS - 1; q >= 0; --q) {   // the smallest row attaining the maximum
+      const int r = lane + 64 * q;
+      const unsigned long long hit = __ballot(r >= k && r < n && fabs(ck[q]) == vmax);
+      if (hit) p = 64 * q + __ffsll((long long)hit) - 1;
+    }
+    const double akk = vc_bcast(vc_slot(ck[0], ck[1], ck[2], k), k & 63);
+    const double apk = vc_bcast(vc_slot(ck[0], ck[1], ck[2], p), p & 63);
+    const double rp = 1.0 / apk;
+    double l[VC_DENSE_SLOTS];
+    bool below[VC_DENSE_SLOTS];
+#pragma unroll
+    for (int q = 0; q < VC_DENSE_SLOTS; ++q) {   // multipliers of the interchanged column k
+      const int r = lane + 64 * q;
+      below[q] = r > k && r < n;
+      l[q] = below[q] ? (r == p ? akk : ck[q]) * rp : 0.0;
+    }
+    if (p != k) {
+      for (int c = w + 4 * lane; c < n; c += 256)   // interchange rows k and p in own columns
+        if (c != k) {
+          const double a = A[(size_t)c * n + k];
+          A[(size_t)c * n + k] = A[(size_t)c * n + p];
+          A[(size_t)c * n + p] = a;
         }
+      if (t == 0) {
+        const int a = pr[k];
+        pr[k] = pr[p];
+        pr[p] = a;
       }
-      if (t == 0) *sp = imax < n ? imax : k;
+    }
+    for (int c = k + 1 + ((w - k - 1) & 3); c < n; c += 4) {   // own trailing columns
+      double* Ac = A + (size_t)c * n;
+      const double u = Ac[k];
+#pragma unroll
+      for (int q = 0; q < VC_DENSE_SLOTS; ++q)
+        if (below[q]) Ac[lane + 64 * q] -= l[q] * u;
     }
     __syncthreads();
-    const int pr = *sp;
-    if (pr != k)
-      for (int c = t; c < n; c += blockDim.x) {
-        const double a = A[(size_t)k * n + c];
-        A[(size_t)k * n + c] = A[(size_t)pr * n + c];
-        A[(size_t)pr * n + c] = a;
+    if ((k & 3) == w) {
+      double* Akw = A + (size_t)k * n;
+#pragma unroll
+      for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
+        const int r = lane + 64 * q;
+        if (r == k) Akw[r] = apk;
+        else if (below[q]) Akw[r] = l[q];
       }
-    if (t == 0) piv[(size_t)s * n + k] = pr;
-    __syncthreads();
-    const double rp = 1.0 / A[(size_t)k * n + k];
-    for (int i = k + 1 + t; i < n; i += blockDim.x) A[(size_t)i * n + k] *= rp;
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int e = t; e < m * m; e += blockDim.x) {
-      const int i = k + 1 + e / m, c = k + 1 + e % m;
-      A[(size_t)i * n + c] -= A[(size_t)i * n + k] * A[(size_t)k * n + c];
     }
-    __syncthreads();
   }
-  for (int e = t; e < n * n; e += blockDim.x) LU[(size_t)s * n * n + e] = A[e];
+  __syncthreads();
+  for (int e = t; e < n * n; e += 256) LU[(size_t)s * n * n + e] = A[e];
+  for (int r = t; r < n; r += 256) perm[(size_t)s * n + r] = pr[r];
 }
 
-// x = A^{-1} b with the factors of k_vc_dense_factor (both [2][nv][S] vectors)
-__global__ void __launch_bounds__(256) k_vc_dense_solve(int S, Grid2 E, const double* __restrict__ LU,
-                                                        const int* __restrict__ piv, const double* __restrict__ b,
-                                                        double* __restrict__ x) {
+// x = A^{-1} b with the factors of k_vc_dense_factor (both [2][nv][S] vectors), one wavefront
+// per sample: the factors staged into LDS (a wavefront's LDS operations complete in issue
+// order, so no barrier is needed), y = P b gathered into registers, then forward and back
+// substitution column by column with the pivot row's value broadcast from its lane; each
+// chunk of VC_SOLVE_CH columns is read from LDS ahead of its dependent steps.
+constexpr int VC_SOLVE_CH = 8;
+__global__ void __launch_bounds__(64) k_vc_dense_solve(int S, Grid2 E, const double* __restrict__ LU,
+                                                       const int* __restrict__ perm, const double* __restrict__ b,
+                                                       double* __restrict__ x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nv = (E.nx + 1) * (E.ny + 1), n = 2 * nv;
   const int s = blockIdx.x, t = threadIdx.x;
   const size_t NV = (size_t)nv * S;
-  double* A = reinterpret_cast<double*>(smem_raw);   // [n][n]
-  double* y = A + (size_t)n * n;                       // [n]
-  for (int e = t; e < n * n; e += blockDim.x) A[e] = LU[(size_t)s * n * n + e];
-  for (int e = t; e < n; e += blockDim.x) y[e] = b[(size_t)(e & 1) * NV + (size_t)(e >> 1) * S + s];
-  __syncthreads();
-  if (t == 0)
-    for (int k = 0; k < n; ++k) {   // the row interchanges in order
-      const int pr = piv[(size_t)s * n + k];
-      const double a = y[k];
-      y[k] = y[pr];
-      y[pr] = a;
+  double* A = reinterpret_cast<double*>(smem_raw);   // A[c * n + r]
+  {   // n is even, so each sample's factors start 16-byte aligned; 16 loads in flight per lane
+    const double2* src = reinterpret_cast<const double2*>(LU + (size_t)s * n * n);
+    double2* dst = reinterpret_cast<double2*>(A);
+    const int n2 = n * n / 2;
+    for (int e0 = 0; e0 < n2; e0 += 16 * 64) {
+      double2 v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = e0 + u * 64 + t;
+        v[u] = e < n2 ? src[e] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = e0 + u * 64 + t;
+        if (e < n2) dst[e] = v[u];
+      }
     }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {   // L y = P b (unit lower), column by column
-    const double yk = y[k];
-    for (int i = k + 1 + t; i < n; i += blockDim.x) y[i] -= A[(size_t)i * n + k] * yk;
-    __syncthreads();
   }
-  for (int k = n - 1; k >= 0; --k) {   // U x = y, column by column
-    const double xk = y[k] / A[(size_t)k * n + k];
-    __syncthreads();
-    if (t == 0) y[k] = xk;
-    for (int i = t; i < k; i += blockDim.x) y[i] -= A[(size_t)i * n + k] * xk;
-    __syncthreads();
+  double y[VC_DENSE_SLOTS];
+#pragma unroll
+  for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
+    const int r = t + 64 * q;
+    y[q] = 0.0;
+    if (r < n) {
+      const int g = perm[(size_t)s * n + r];
+      y[q] = b[(size_t)(g & 1) * NV + (size_t)(g >> 1) * S + s];
+    }
   }
-  for (int e = t; e < n; e += blockDim.x) x[(size_t)(e & 1) * NV + (size_t)(e >> 1) * S + s] = y[e];
+  __builtin_amdgcn_wave_barrier();
+  for (int k0 = 0; k0 < n - 1; k0 += VC_SOLVE_CH) {   // L y = P b (unit lower)
+    double a[VC_SOLVE_CH][VC_DENSE_SLOTS];
+#pragma unroll
+    for (int j = 0; j < VC_SOLVE_CH; ++j)
+#pragma unroll
+      for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
+        const int k = k0 + j, r = t + 64 * q;
+        a[j][q] = (k < n - 1 && r > k && r < n) ? A[(size_t)k * n + r] : 0.0;
+      }
+#pragma unroll
+    for (int j = 0; j < VC_SOLVE_CH; ++j) {
+      const int k = k0 + j;
+      if (k < n - 1) {
+        const double yk = vc_bcast(vc_slot(y[0], y[1], y[2], k), k & 63);
+#pragma unroll
+        for (int q = 0; q < VC_DENSE_SLOTS; ++q)
+          if (t + 64 * q > k) y[q] -= a[j][q] * yk;
+      }
+    }
+  }
+  for (int k0 = n - 1; k0 >= 0; k0 -= VC_SOLVE_CH) {   // U x = y
+    double a[VC_SOLVE_CH][VC_DENSE_SLOTS], dk[VC_SOLVE_CH];
+#pragma unroll
+    for (int j = 0; j < VC_SOLVE_CH; ++j) {
+      const int k = k0 - j;
+      dk[j] = k >= 0 ? A[(size_t)k * n + k] : 1.0;
+#pragma unroll
+      for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
+        const int r = t + 64 * q;
+        a[j][q] = (k >= 0 && r < k) ? A[(size_t)k * n + r] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < VC_SOLVE_CH; ++j) {
+      const int k = k0 - j;
+      if (k >= 0) {
+        const double xk = vc_bcast(vc_slot(y[0], y[1], y[2], k), k & 63) / dk[j];
+#pragma unroll
+        for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
+          const int r = t + 64 * q;
+          if (r == k) y[q] = xk;
+          else if (r < k) y[q] -= a[j][q] * xk;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
+    const int r = t + 64 * q;
+    if (r < n) x[(size_t)(r & 1) * NV + (size_t)(r >> 1) * S + s] = y[q];
+  }
 }
 
 // per-sample step bookkeeping (fin launch shape: threadIdx.y == 0 acts)

@@ -28,6 +28,11 @@ BYTES_PER_UNIT = {
     64: dict(gs=208, spmv=136, assemble=216, restrict=76, prolong=216),
     32: dict(gs=104, spmv=96, assemble=136, restrict=38, prolong=108),
 }
+# The vertex-centred path (henry_vc_solve), per vertex-sample: the four-colour pass reads the
+# 36-entry Jacobian row and b, writes x and reads the other three colours' x once (3 x 16 B
+# per swept vertex); the SpMV reads J and x and writes y; the assembly reads p, c, c_old and
+# one element's phi and K per vertex and writes R and J.
+VC_BYTES_PER_UNIT = dict(gs=288 + 16 + 16 + 48, spmv=288 + 16 + 16, assemble=16 + 8 + 16 + 16 + 288)
 
 
 def _hist(x: np.ndarray, width: float) -> dict:

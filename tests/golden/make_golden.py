@@ -21,8 +21,8 @@ short oracle windows started from them, so that the whole horizon is represented
 
 "f3" runs the vertex-centred oracle (the paper's own discretisation, section 2.3) on level 1
 of Table 2 (64 x 32 elements, 376 steps, T = 6016 s) with the paper's model, seed 5: the
-first sample, the smallest and largest recharge zeta of the 128-sample batch (7, 63) and its
-last index (127).
+first sample, the smallest and largest recharge zeta of the first 128 samples (7, 63) and of
+all 512 (300, 389), and the last indices of both (127, 511).
 
 usage: python tests/golden/make_golden.py {c2|c3|c4|c5|f1|f1l3|f3|span|all} [--procs N]
 """
@@ -70,7 +70,7 @@ def _forward(args):
     print(out, r.qoi, r.newton_its, f"{time.time() - t:.0f}s", flush=True)
 
 
-SPAN_F3 = (0, 7, 63, 127)                   # first, min zeta, max zeta, last
+SPAN_F3 = (0, 7, 63, 127, 300, 389, 511)    # first; min, max zeta and last of 128 and of 512
 
 
 def _forward_vc(args):

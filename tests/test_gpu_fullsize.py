@@ -147,11 +147,12 @@ def test_mlmc_hierarchy_full_run():
 
 def test_vc_level1_paper_full_batch():
     """The paper's vertex-centred discretisation on level 1 of Table 2 (64 x 32 elements, 2145
-    vertices, 376 steps) with its section-4 model: all 128 samples of seed 5 in one batch (the
-    benchmark's configuration), against the stored vertex-oracle runs of samples 0, 7 (smallest
-    recharge zeta), 63 (largest) and 127 (the last); every sample converged with c in [0, 1]."""
+    vertices, 376 steps) with its section-4 model: all 512 samples of seed 5 in one batch (the
+    benchmark's configuration), against the stored vertex-oracle runs of samples 0, the smallest
+    and largest recharge zeta of the first 128 (7, 63) and of all 512 (300, 389), and the last
+    indices 127 and 511; every sample converged with c in [0, 1]."""
     import paper_2403_17018_amd as P
-    th = draw_theta(5, 128)
+    th = draw_theta(5, 512)
     hx = P.Henry(0)
     g = P.vc_level_grid(1)
     r = hx.vc_solve(torch.from_numpy(th).cuda(), g, P.paper_problem(), P.solver_opts(krylov_maxit=1000),
@@ -160,7 +161,7 @@ def test_vc_level1_paper_full_batch():
     c, p, q = r.c_T.cpu().numpy(), r.p_T.cpu().numpy(), r.qoi.cpu().numpy()
     hx.close()
     assert r.nfailed == 0
-    for s in (0, 7, 63, 127):
+    for s in (0, 7, 63, 127, 300, 389, 511):
         z = np.load(os.path.join(GOLD, f"oracle_f3_l1_s{s}.npz"))
         assert np.array_equal(z["theta"], th[s]) and bool(z["converged"])
         assert np.abs(c[..., s].ravel() - z["c_T"]).max() <= TOL * np.abs(z["c_T"]).max(), s

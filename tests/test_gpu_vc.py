@@ -184,3 +184,18 @@ def test_mlmc_run_vc_matches_oracle(hx):
     assert est["var_of_estimator"] == pytest.approx(m["var_of_estimator"], rel=1e-10)
     assert est["rmse"] == pytest.approx(m["rmse"], rel=1e-10)
     assert np.allclose(est["V"], m["V"], rtol=1e-10, atol=0.0)
+
+
+def test_vc_graph_replay_is_bitwise_identical(hx):
+    """use_graphs = 1 replays one captured BiCGStab iteration per iteration: the same kernels in
+    the same order, so the results equal the stream-launched run bit for bit (level 0, the
+    paper's model)."""
+    import paper_2403_17018_amd as P
+    th = _cu(draw_theta(88, 24))
+    g = P.vc_level_grid(0)
+    a = hx.vc_solve(th, g, P.paper_problem(), P.solver_opts(krylov_maxit=300, use_graphs=0), want_c=True, want_p=True)
+    b = hx.vc_solve(th, g, P.paper_problem(), P.solver_opts(krylov_maxit=300, use_graphs=1), want_c=True, want_p=True)
+    torch.cuda.synchronize()
+    assert a.nfailed == 0 and b.nfailed == 0
+    assert torch.equal(a.c_T, b.c_T) and torch.equal(a.p_T, b.p_T) and torch.equal(a.qoi, b.qoi)
+    assert torch.equal(a.stats, b.stats)
