@@ -2586,17 +2586,17 @@ struct VCSolver {
     const Grid2& Ek = k > 0 ? L->E : E;
     const int nvk = k > 0 ? L->nv : nv;
     const double* Jk = k > 0 ? L->J.as<double>() : J.as<double>();
-    const size_t n2 = 2 * (size_t)nvk * S;
     if (k == (int)lv.size()) {   // coarsest: the direct solve with this Newton iteration's factors
       hipLaunchKernelGGL(k_vc_dense_solve, dim3(S), dim3(64), vc_dense_lds(2 * nvk), st, S, Ek,
                          (const double*)LUc.as<double>(), (const int*)pivc.as<int>(), b, xo);
       return;
     }
-    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, n2, xo);
+    // x starts at zero: the first forward sweep skips the colours not yet swept, so x is not
+    // cleared; the last colour swept (3) has a zero residual
     for (int sw = 0; sw < std::max(1, o.nu_pre); ++sw)
-      for (int col = 0; col < 4; ++col) gs_pass(k, mk, Ek, col, Jk, b, xo);
+      for (int col = 0; col < 4; ++col) gs_pass(k, mk, Ek, col, Jk, b, xo, sw == 0);
     double* rk = k > 0 ? L->r.as<double>() : mgr.as<double>();
-    hipLaunchKernelGGL(k_vc_resid, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, Jk, b, (const double*)xo, rk);
+    hipLaunchKernelGGL(k_vc_resid, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, 3, Jk, b, (const double*)xo, rk);
     VCLevel* C = lv[k].get();
     hipLaunchKernelGGL(k_vc_restrict, grid_cells(C->m, C->nv), block_of(C->m), 0, st, C->m, C->E, Ek,
                        (const double*)rk, C->b.as<double>());
@@ -2606,15 +2606,17 @@ struct VCSolver {
     for (int sw = 0; sw < std::max(1, o.nu_post); ++sw)
       for (int col = 3; col >= 0; --col) gs_pass(k, mk, Ek, col, Jk, b, xo);
   }
-  // one colour pass on level k; fine-grid passes are timed as HENRY_PROF_GS (units: the
-  // colour's vertex-samples)
-  void gs_pass(int k, const Map& mk, const Grid2& Ek, int col, const double* Jk, const double* b, double* xo) {
-    const int nc = vc_colour_cells(Ek.nx, Ek.ny, col);
-    auto f = [&] {
-      launch_timed(k_vc_gs, grid_cells(mk, vc_colour_cells(Ek.nx, Ek.ny, 0)), block_of(mk), 0, st, mk, Ek, col, Jk,
-                         b, xo);
-    };
-    if (k == 0) timed(ctx, st, HENRY_PROF_GS, (long long)nc * S, f);
+  // one colour pass on level k (first: of the first forward sweep from x = 0); the fine
+  // grid's full passes are timed as HENRY_PROF_GS (units: the colour's vertex-samples)
+  void gs_pass(int k, const Map& mk, const Grid2& Ek, int col, const double* Jk, const double* b, double* xo,
+               bool first = false) {
+    const dim3 g = grid_cells(mk, vc_colour_cells(Ek.nx, Ek.ny, 0));
+    if (first) {
+      hipLaunchKernelGGL(k_vc_gs<true>, g, block_of(mk), 0, st, mk, Ek, col, Jk, b, xo);
+      return;
+    }
+    auto f = [&] { launch_timed(k_vc_gs<false>, g, block_of(mk), 0, st, mk, Ek, col, Jk, b, xo); };
+    if (k == 0) timed(ctx, st, HENRY_PROF_GS, (long long)vc_colour_cells(Ek.nx, Ek.ny, col) * S, f);
     else f();
   }
   void assemble(bool with_j, const double* pp, const double* cc, const double* co, double* RR, double* JJ) {
@@ -2649,10 +2651,9 @@ struct VCSolver {
       vcycle(0, b, xo);
       return;
     }
-    hipLaunchKernelGGL(k_zero_f64, g2(), dim3(256), 0, st, 2 * NV, xo);
     const int sweeps = std::max(1, o.nu_pre + o.nu_post);
     for (int k = 0; k < sweeps; ++k) {
-      for (int col = 0; col < 4; ++col) gs_pass(0, m, E, col, (const double*)J.as<double>(), b, xo);
+      for (int col = 0; col < 4; ++col) gs_pass(0, m, E, col, (const double*)J.as<double>(), b, xo, k == 0);
       for (int col = 3; col >= 0; --col) gs_pass(0, m, E, col, (const double*)J.as<double>(), b, xo);
     }
   }

@@ -220,9 +220,12 @@ __global__ void __launch_bounds__(256) k_vc_spmv(Map m, Grid2 E, const double* _
 // x_v = D_v^{-1} (b_v - sum over the other 8 blocks A_vq x_q); vertices of one colour do not
 // touch each other in the nine-point stencil.  The launch covers only the colour's vertices
 // (i = 2 u_i + colour & 1, j = 2 u_j + colour >> 1): vc_colour_cells() of colour 0, the largest.
+// FIRST: the first forward sweep (colours 0, 1, 2, 3) from x = 0, in which the colours after
+// this one still hold zero: their blocks are skipped and x need not be cleared beforehand.
 __host__ __device__ inline int vc_colour_cells(int nx, int ny, int colour) {
   return ((nx + 2 - (colour & 1)) >> 1) * ((ny + 2 - (colour >> 1)) >> 1);
 }
+template <bool FIRST>
 __global__ void __launch_bounds__(256) k_vc_gs(Map m, Grid2 E, int colour, const double* __restrict__ J,
                                                const double* __restrict__ b, double* __restrict__ x) {
   const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
@@ -242,6 +245,7 @@ __global__ void __launch_bounds__(256) k_vc_gs(Map m, Grid2 E, int colour, const
 #pragma unroll
     for (int di = -1; di <= 1; ++di) {
       if (di == 0 && dj == 0) continue;
+      if (FIRST && ((ci ^ (di & 1)) + 2 * (cj ^ (dj & 1))) > colour) continue;   // still zero
       const int qi = i + di, qj = j + dj;
       if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
       const int bl = (dj + 1) * 3 + (di + 1);
@@ -548,7 +552,9 @@ __global__ void __launch_bounds__(256) k_vc_qoi(Map m, Grid2 E, Phys P, const do
 // (both on x = Lx, c on x = 0) get no coarse right-hand side and no correction.
 
 // r = b - J x
-__global__ void __launch_bounds__(256) k_vc_resid(Map m, Grid2 E, const double* __restrict__ J,
+// zero_colour: the colour swept last, whose residual is zero up to rounding (its rows were
+// just solved against the current neighbours): written as 0 without reading J
+__global__ void __launch_bounds__(256) k_vc_resid(Map m, Grid2 E, int zero_colour, const double* __restrict__ J,
                                                   const double* __restrict__ b, const double* __restrict__ x,
                                                   double* __restrict__ r) {
   const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
@@ -558,6 +564,11 @@ __global__ void __launch_bounds__(256) k_vc_resid(Map m, Grid2 E, const double* 
   const size_t NV = (size_t)nv * S;
   const int j = v / nvx, i = v - j * nvx;
   const size_t id = (size_t)v * S + s;
+  if ((i & 1) + 2 * (j & 1) == zero_colour) {
+    r[id] = 0.0;
+    r[NV + id] = 0.0;
+    return;
+  }
   double y0 = b[id], y1 = b[NV + id];
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj)
@@ -663,9 +674,10 @@ __global__ void __launch_bounds__(256) k_vc_coarse_fields(Map mce, Grid2 Ec, Gri
 // Coarsest grid solved directly (Gaussian elimination with partial pivoting, section 2.3): the
 // dense matrix of its n = 2 nv unknowns (unknown 2 v + component) per sample, held
 // column-major in LDS (A[c n + r]).  The factors (P A = L U: L below the diagonal with its
-// unit diagonal implied, U on and above it) go to global memory column-major once per Newton
-// iteration with the row order perm (row i of P A is row perm[i] of A), and every V-cycle
-// solves with them.  Lanes own rows l, l + 64 and l + 128.  n <= VC_DENSE_MAX.
+// unit diagonal implied, U above it and the reciprocals of U's diagonal on it) go to global
+// memory column-major once per Newton iteration with the row order perm (row i of P A is row
+// perm[i] of A), and every V-cycle solves with them.  Lanes own rows l, l + 64 and l + 128.
+// n <= VC_DENSE_MAX.
 constexpr int VC_DENSE_MAX = 140;
 constexpr int VC_DENSE_SLOTS = 3;   // rows per lane
 static_assert(VC_DENSE_SLOTS == 3 && 64 * VC_DENSE_SLOTS >= VC_DENSE_MAX, "vc_slot selects among three slots");
@@ -764,7 +776,27 @@ __global__ void __launch_bounds__(256) k_vc_dense_factor(int S, Grid2 E, const d
         pr[p] = a;
       }
     }
-    for (int c = k + 1 + ((w - k - 1) & 3); c < n; c += 4) {   // own trailing columns
+    // own trailing columns, four at a time: all their reads issued before any write, so the
+    // LDS latency is paid once per four columns
+    int c = k + 1 + ((w - k - 1) & 3);
+    for (; c + 12 < n; c += 16) {
+      double u[4], a[4][VC_DENSE_SLOTS];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const double* Ac = A + (size_t)(c + 4 * h) * n;
+        u[h] = Ac[k];
+#pragma unroll
+        for (int q = 0; q < VC_DENSE_SLOTS; ++q) a[h][q] = below[q] ? Ac[lane + 64 * q] : 0.0;
+      }
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        double* Ac = A + (size_t)(c + 4 * h) * n;
+#pragma unroll
+        for (int q = 0; q < VC_DENSE_SLOTS; ++q)
+          if (below[q]) Ac[lane + 64 * q] = a[h][q] - l[q] * u[h];
+      }
+    }
+    for (; c < n; c += 4) {
       double* Ac = A + (size_t)c * n;
       const double u = Ac[k];
 #pragma unroll
@@ -772,12 +804,12 @@ __global__ void __launch_bounds__(256) k_vc_dense_factor(int S, Grid2 E, const d
         if (below[q]) Ac[lane + 64 * q] -= l[q] * u;
     }
     __syncthreads();
-    if ((k & 3) == w) {
+    if ((k & 3) == w) {   // U's diagonal is stored as its reciprocal, which the solve multiplies by
       double* Akw = A + (size_t)k * n;
 #pragma unroll
       for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
         const int r = lane + 64 * q;
-        if (r == k) Akw[r] = apk;
+        if (r == k) Akw[r] = rp;
         else if (below[q]) Akw[r] = l[q];
       }
     }
@@ -855,7 +887,7 @@ __global__ void __launch_bounds__(64) k_vc_dense_solve(int S, Grid2 E, const dou
 #pragma unroll
     for (int j = 0; j < VC_SOLVE_CH; ++j) {
       const int k = k0 - j;
-      dk[j] = k >= 0 ? A[(size_t)k * n + k] : 1.0;
+      dk[j] = k >= 0 ? A[(size_t)k * n + k] : 1.0;   // 1 / U_kk
 #pragma unroll
       for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
         const int r = t + 64 * q;
@@ -866,7 +898,7 @@ __global__ void __launch_bounds__(64) k_vc_dense_solve(int S, Grid2 E, const dou
     for (int j = 0; j < VC_SOLVE_CH; ++j) {
       const int k = k0 - j;
       if (k >= 0) {
-        const double xk = vc_bcast(vc_slot(y[0], y[1], y[2], k), k & 63) / dk[j];
+        const double xk = vc_bcast(vc_slot(y[0], y[1], y[2], k), k & 63) * dk[j];
 #pragma unroll
         for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
           const int r = t + 64 * q;

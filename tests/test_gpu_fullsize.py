@@ -155,7 +155,8 @@ def test_vc_level1_paper_full_batch():
     th = draw_theta(5, 512)
     hx = P.Henry(0)
     g = P.vc_level_grid(1)
-    r = hx.vc_solve(torch.from_numpy(th).cuda(), g, P.paper_problem(), P.solver_opts(krylov_maxit=1000),
+    r = hx.vc_solve(torch.from_numpy(th).cuda(), g, P.paper_problem(),
+                    P.solver_opts(krylov_maxit=1000, nu_pre=1, nu_post=1, use_graphs=1),
                     want_c=True, want_p=True)
     torch.cuda.synchronize()
     c, p, q = r.c_T.cpu().numpy(), r.p_T.cpu().numpy(), r.qoi.cpu().numpy()
