@@ -387,6 +387,13 @@ HENRY_API int henry_coarse_solve(henry_ctx* ctx, int solver, int precision, henr
  *   sum c rho(c) |box n {x > qoi_xmin}| or NULL; status: device [S] (1 Newton, 2 Krylov
  *   breakdown, 3 non-finite) or NULL; stats: device [S][2] Newton and BiCGStab iterations or NULL.
  *   Returns the number of samples with a non-zero status, or a negative error.
+ * henry_vc_solve_batch: several batches (grids and sample counts may differ: the levels and
+ *   coarse partners of an MLMC estimate over Table 2's hierarchy) in one call, each on its own
+ *   library stream from its own host thread (one after another with ragged_threads = 1), all
+ *   ordered after the context's stream and finished on return.  Each henry_batch holds the
+ *   outputs of henry_vc_solve with its shapes (c_T, p_T [ny+1][nx+1][S], stats [S][2]); series
+ *   must be NULL.  Returns the total number of samples with a non-zero status, or the first
+ *   batch's error.
  * henry_vc_assemble: residual R [2][ny+1][nx+1][S] and Jacobian J [36][ny+1][nx+1][S] of step
  *   `step` at (p, c) with previous state c_old; J holds the 2x2 blocks d R^a_v / d u^k_q for the
  *   3 x 3 vertices q = v + (di, dj) around v at [((dj+1) * 3 + di+1) * 4 + a * 2 + k] (0 where q
@@ -394,6 +401,8 @@ HENRY_API int henry_coarse_solve(henry_ctx* ctx, int solver, int precision, henr
 HENRY_API int henry_vc_solve(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts, henry_grid grid,
                              int S, const double* theta, double* c_T, double* p_T, double* qoi, int* status,
                              double* stats);
+HENRY_API int henry_vc_solve_batch(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts,
+                                   henry_batch* batches, int nbatches);
 HENRY_API int henry_vc_assemble(henry_ctx* ctx, const henry_problem* prob, henry_grid grid, int S, const double* theta,
                                 const double* p, const double* c, const double* c_old, int step, double* R, double* J);
 

@@ -277,6 +277,30 @@ class Henry:
         r.nfailed = rc
         return r
 
+    def vc_solve_batch(self, items, prob=None, opts=None, want_c=True, want_p=False):
+        """items: list of (theta [S,13], henry_grid) for the vertex-centred discretisation, solved
+        in one call (henry_vc_solve_batch: each batch on its own stream and host thread).
+        Returns a list of SolveResult as vc_solve gives."""
+        kw = dict(dtype=torch.float64, device=self.device)
+        arr = (henry_batch * len(items))()
+        res = []
+        for b, (theta, g) in enumerate(items):
+            _check_theta(theta, self.device)
+            S = theta.shape[0]
+            r = SolveResult(c_T=torch.empty((g.ny + 1, g.nx + 1, S), **kw) if want_c else None,
+                            p_T=torch.empty((g.ny + 1, g.nx + 1, S), **kw) if want_p else None,
+                            qoi=torch.empty((S,), **kw), status=torch.zeros((S,), dtype=torch.int32, device=self.device),
+                            stats=torch.zeros((S, 2), **kw), nfailed=0)
+            arr[b] = henry_batch(g, S, theta.data_ptr(), _ptr(r.c_T), _ptr(r.p_T), _ptr(r.qoi), _ptr(r.status),
+                                 _ptr(r.stats), None)
+            res.append(r)
+        rc = self._check(self._lib.henry_vc_solve_batch(self._h, C.byref(prob or problem()),
+                                                        C.byref(opts or solver_opts()), arr, len(items)))
+        for r in res:
+            r.nfailed = int((r.status != 0).sum().item())
+        assert sum(r.nfailed for r in res) == rc
+        return res
+
     def vc_assemble(self, theta, g: henry_grid, p, c, c_old, step: int, prob=None):
         """(R [2, ny+1, nx+1, S], J [36, ny+1, nx+1, S]) of the vertex-centred step `step`."""
         _check_theta(theta, self.device)
@@ -412,23 +436,24 @@ def mlmc_run(hx: "Henry", thetas, levels, prob=None, opts=None, alpha: float = 1
 def mlmc_run_vc(hx: "Henry", thetas, levels, prob=None, opts=None, alpha: float = 2.0):
     """Multilevel Monte Carlo (section 3, eq. A) over the paper's own hierarchy (Table 2) with
     the vertex-centred discretisation: level l is solved on vc_level_grid(levels[l]) and, for
-    l > 0, with the same theta on vc_level_grid(levels[l - 1]).  Each level refines the mesh
+    l > 0, with the same theta on vc_level_grid(levels[l - 1]); all of them in one
+    henry_vc_solve_batch call, concurrently.  Each level refines the mesh
     4x per direction, so alpha (the bias term's base-2 rate) defaults to 2 for a first-order
     error in h.  QoI-only: the vertex grids do not nest by 2x, so no field moments.  Returns
     the estimator dict of Henry.mlmc_estimate plus the solve results and failure count."""
-    res, gf, gc, grids = [], [], [], []
+    items, idx = [], []
     for l, (th, lev) in enumerate(zip(thetas, levels)):
-        g = vc_level_grid(lev)
-        rf = hx.vc_solve(th, g, prob, opts, want_c=False)
-        res.append(rf)
-        gf.append(rf.qoi)
-        grids.append(g)
-        if l == 0:
-            gc.append(None)
-        else:
-            rc = hx.vc_solve(th, vc_level_grid(levels[l - 1]), prob, opts, want_c=False)
-            res.append(rc)
-            gc.append(rc.qoi)
+        items.append((th, vc_level_grid(lev)))
+        f = len(items) - 1
+        c = None
+        if l > 0:
+            items.append((th, vc_level_grid(levels[l - 1])))
+            c = len(items) - 1
+        idx.append((f, c))
+    res = hx.vc_solve_batch(items, prob, opts, want_c=False)
+    grids = [vc_level_grid(lev) for lev in levels]
+    gf = [res[f].qoi for f, _ in idx]
+    gc = [None if c is None else res[c].qoi for _, c in idx]
     est = hx.mlmc_estimate(grids, gf, gc, None, None, alpha)
     est["results"] = res
     est["nfailed"] = sum(r.nfailed for r in res)

@@ -12,7 +12,7 @@ EXPORTS = ("henry_problem_default", "henry_solver_opts_default", "henry_ctx_crea
            "henry_last_error", "henry_sample_fields", "henry_solve_batch", "henry_adjoint_batch",
            "mlmc_estimate", "mlmc_optimal_samples", "henry_autotune", "henry_profile", "henry_profile_read",
            "mlmc_estimate_series", "mlmc_plan", "mlmc_estimate_noalloc", "henry_assemble", "henry_jacobian_apply",
-           "henry_gs_pass", "henry_coarse_solve", "henry_vc_solve", "henry_vc_assemble")
+           "henry_gs_pass", "henry_coarse_solve", "henry_vc_solve", "henry_vc_solve_batch", "henry_vc_assemble")
 PROF_CLASSES = ("assemble", "gs", "spmv", "restrict", "prolong", "band_factor", "band_solve", "dense_factor",
                 "dense_solve", "host_sync")
 
@@ -112,6 +112,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.henry_coarse_solve.restype = i
     lib.henry_vc_solve.argtypes = [vp, P(henry_problem), P(henry_solver_opts), henry_grid, i, vp, vp, vp, vp, vp, vp]
     lib.henry_vc_solve.restype = i
+    lib.henry_vc_solve_batch.argtypes = [vp, P(henry_problem), P(henry_solver_opts), P(henry_batch), i]
+    lib.henry_vc_solve_batch.restype = i
     lib.henry_vc_assemble.argtypes = [vp, P(henry_problem), henry_grid, i, vp, vp, vp, vp, i, vp, vp]
     lib.henry_vc_assemble.restype = i
     _lib = lib

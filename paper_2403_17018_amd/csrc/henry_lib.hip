@@ -2812,6 +2812,78 @@ int henry_vc_assemble(henry_ctx* ctx, const henry_problem* prob, henry_grid grid
   });
 }
 
+int henry_vc_solve_batch(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts,
+                         henry_batch* batches, int nbatches) {
+  return guarded(ctx, [&]() -> int {
+    check_problem(prob);
+    henry_solver_opts o;
+    if (opts) o = *opts;
+    else henry_solver_opts_default(&o);
+    check_opts(o);
+    if (nbatches < 0 || (nbatches > 0 && !batches)) fail(HENRY_EINVAL, "nbatches < 0 or batches NULL");
+    for (int k = 0; k < nbatches; ++k) {
+      const henry_batch& B = batches[k];
+      check_vc_grid(*prob, B.grid);
+      if (B.nsamples < 1 || !B.theta) fail(HENRY_EINVAL, "batch %d: nsamples < 1 or theta NULL", k);
+      if (B.series) fail(HENRY_EINVAL, "batch %d: the vertex-centred solve has no series output", k);
+      if (theta_check(ctx, B.theta, B.nsamples)) fail(HENRY_EINVAL, "batch %d: theta contains non-finite values", k);
+    }
+    if (nbatches == 0) return 0;
+    const Range range("henry_vc_solve_batch %d batches", nbatches);
+    // one library stream per batch (created here, before any worker starts), each ordered after
+    // the caller's stream; the batches run from their own host threads unless ragged_threads is 1
+    std::vector<hipStream_t> streams(nbatches);
+    for (int k = 0; k < nbatches; ++k) streams[k] = ctx_stream(ctx, (size_t)k);
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, ctx->stream));
+    for (int k = 0; k < nbatches; ++k) HIPCHK(hipStreamWaitEvent(streams[k], ev, 0));
+    HIPCHK(hipEventDestroy(ev));
+    std::vector<int> nfail(nbatches, 0), ok(nbatches, 1);
+    std::vector<HenryError> err(nbatches, HenryError{0, ""});
+    auto work = [&](int k) {
+      try {
+        HIPCHK(hipSetDevice(ctx->device));
+        const henry_batch& B = batches[k];
+        const Range r("henry vc grid %dx%d S=%d steps=%d", B.grid.nx, B.grid.ny, B.nsamples, B.grid.nsteps);
+        VCSolver sv(ctx, *prob, o, B.grid, B.nsamples, streams[k]);
+        sv.run(B.theta, B.c_T, B.p_T, B.qoi, B.status, B.stats);
+        HIPCHK(hipGetLastError());
+        std::vector<int> hs(B.nsamples);
+        HIPCHK(hipMemcpyAsync(hs.data(), sv.status.p, (size_t)B.nsamples * sizeof(int), hipMemcpyDeviceToHost,
+                              streams[k]));
+        HIPCHK(hipStreamSynchronize(streams[k]));
+        for (int v : hs) nfail[k] += v != 0;
+      } catch (const HenryError& e) {
+        ok[k] = 0;
+        err[k] = e;
+      } catch (const std::bad_alloc&) {
+        ok[k] = 0;
+        err[k] = HenryError{HENRY_ENOMEM, "host allocation failed"};
+      } catch (const std::exception& e) {
+        ok[k] = 0;
+        err[k] = HenryError{HENRY_EDEVICE, std::string("host runtime error: ") + e.what()};
+      } catch (...) {
+        ok[k] = 0;
+        err[k] = HenryError{HENRY_EDEVICE, "unknown host exception"};
+      }
+    };
+    if (nbatches == 1 || o.ragged_threads == 1) {
+      for (int k = 0; k < nbatches; ++k) work(k);
+    } else {
+      std::vector<std::thread> th;
+      for (int k = 0; k < nbatches; ++k) th.emplace_back(work, k);
+      for (auto& t : th) t.join();
+    }
+    int failed = 0;
+    for (int k = 0; k < nbatches; ++k) {
+      if (!ok[k]) throw err[k];
+      failed += nfail[k];
+    }
+    return failed;
+  });
+}
+
 int henry_vc_solve(henry_ctx* ctx, const henry_problem* prob, const henry_solver_opts* opts, henry_grid grid, int S,
                    const double* theta, double* c_T, double* p_T, double* qoi, int* status, double* stats) {
   return guarded(ctx, [&]() -> int {

@@ -199,3 +199,27 @@ def test_vc_graph_replay_is_bitwise_identical(hx):
     assert a.nfailed == 0 and b.nfailed == 0
     assert torch.equal(a.c_T, b.c_T) and torch.equal(a.p_T, b.p_T) and torch.equal(a.qoi, b.qoi)
     assert torch.equal(a.stats, b.stats)
+
+
+@pytest.mark.parametrize("threads", [0, 1])
+def test_vc_solve_batch_equals_single_solves(hx, threads):
+    """henry_vc_solve_batch: three batches on different grids and sample counts, concurrently
+    (ragged_threads 0) or one after another (1), equal the same batches solved alone bit for bit;
+    a batch with a NaN theta refuses the whole call."""
+    import paper_2403_17018_amd as P
+    o = P.solver_opts(krylov_maxit=300, ragged_threads=threads)
+    prob = P.paper_problem(T=6016.0 * 24 / 94)
+    items = [(_cu(draw_theta(89, 40)), P.grid(16, 8, 24)), (_cu(draw_theta(90, 7)), P.grid(32, 16, 24)),
+             (_cu(draw_theta(91, 65)), P.grid(12, 6, 24))]
+    res = hx.vc_solve_batch(items, prob, o, want_c=True, want_p=True)
+    torch.cuda.synchronize()
+    for (th, g), r in zip(items, res):
+        a = hx.vc_solve(th, g, prob, o, want_c=True, want_p=True)
+        torch.cuda.synchronize()
+        assert r.nfailed == 0 and a.nfailed == 0
+        assert torch.equal(a.c_T, r.c_T) and torch.equal(a.p_T, r.p_T) and torch.equal(a.qoi, r.qoi)
+        assert torch.equal(a.stats, r.stats)
+    bad = draw_theta(92, 5)
+    bad[2, 4] = np.nan
+    with pytest.raises(P.HenryError):
+        hx.vc_solve_batch(items[:1] + [(_cu(bad), P.grid(16, 8, 4))], prob, o)
