@@ -381,8 +381,9 @@ HENRY_API int henry_coarse_solve(henry_ctx* ctx, int solver, int precision, henr
  * grids halved while both element counts are even and at least coarse_nx x coarse_ny:
  * nu_pre forward and nu_post backward four-colour block Gauss-Seidel sweeps, full-weighting
  * restriction and bilinear prolongation, operators rediscretised at the injected state, and
- * Gaussian elimination with partial pivoting on the coarsest grid (at most 70 vertices).  A
- * grid that does not coarsen that far uses nu_pre + nu_post symmetric sweeps instead.
+ * Gaussian elimination with partial pivoting on the coarsest grid (at most 70 vertices; its
+ * factors are refreshed at the first Newton iteration of each step).  A grid that does not
+ * coarsen that far uses nu_pre + nu_post symmetric sweeps instead.
  *   theta: device [S][13]; c_T, p_T: device [ny+1][nx+1][S] or NULL; qoi: device [S] salt mass
  *   sum c rho(c) |box n {x > qoi_xmin}| or NULL; status: device [S] (1 Newton, 2 Krylov
  *   breakdown, 3 non-finite) or NULL; stats: device [S][2] Newton and BiCGStab iterations or NULL.

@@ -2555,10 +2555,14 @@ struct VCSolver {
     }
   }
   // coarse operators: rediscretised at the injected state (after the fine assembly)
-  void coarse_assemble() {
+  // Coarse operators at the injected state.  The coarsest grid's operator serves only its LU
+  // factors, which are refreshed at the first Newton iteration of each step (refresh_coarsest)
+  // and kept for the step's later iterations: the preconditioner changes, not the fixed point.
+  void coarse_assemble(bool refresh_coarsest) {
     const double *pf = p.as<double>(), *cf = c.as<double>(), *cof = c_old.as<double>();
     Grid2 Ef = E;
     for (auto& L : lv) {
+      if (L == lv.back() && !refresh_coarsest) return;
       hipLaunchKernelGGL(k_vc_inject, grid_cells(L->m, L->nv), block_of(L->m), 0, st, L->m, L->E, Ef, pf, cf, cof,
                          L->p.as<double>(), L->c.as<double>(), L->co.as<double>());
       Phys Pl = L->P;
@@ -2756,7 +2760,7 @@ struct VCSolver {
       bool done = false;
       for (int it = 0; it < o.newton_maxit && !done; ++it) {
         assemble(true, p.as<double>(), c.as<double>(), c_old.as<double>(), R.as<double>(), J.as<double>());
-        coarse_assemble();
+        coarse_assemble(it == 0);
         bicgstab();
         hipLaunchKernelGGL(k_vc_absmax, grid_red(m), block_of(m), 0, st, m, nv, (const double*)x.as<double>(),
                            part.as<double>());
