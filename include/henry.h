@@ -376,7 +376,7 @@ HENRY_API int henry_coarse_solve(henry_ctx* ctx, int solver, int precision, henr
  *
  * henry_vc_solve: the whole run per sample from c = 0 (c = 1 on x = Lx), damped Newton as in
  * henry_solve_batch (newton_tol, newton_dc_max, newton_maxit, the first guess by
- * newton_extrapolate), each Newton system solved by right-preconditioned BiCGStab (krylov_rtol,
+ * newton_extrapolate, the predictive stop by newton_predict), each Newton system solved by right-preconditioned BiCGStab (krylov_rtol,
  * krylov_maxit).  The preconditioner is a geometric multigrid V-cycle (section 2.3) on vertex
  * grids halved while both element counts are even and at least coarse_nx x coarse_ny:
  * nu_pre forward and nu_post backward four-colour block Gauss-Seidel sweeps, full-weighting

@@ -2674,7 +2674,8 @@ struct VCSolver {
                        x.as<double>(), r.as<double>(), pv.as<double>(), rh.as<double>());
     dots<1>(VCPairs{{r.as<double>(), nullptr, nullptr}, {r.as<double>(), nullptr, nullptr}});
     zero_ctrl();
-    hipLaunchKernelGGL(k_vc_bicg_start, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, ctrl.as<int>());
+    hipLaunchKernelGGL(k_vc_bicg_start, fg, fb, 0, st, m, (const double*)part.as<double>(), scp, ctrl.as<int>(),
+                       o.newton_tol * o.newton_predict);
     if (read_ctrl() == 0) return 0;
     // the iteration's launches use fixed buffers and constants, so with use_graphs they are
     // captured once per solver and replayed
@@ -2843,21 +2844,27 @@ int henry_vc_solve_batch(henry_ctx* ctx, const henry_problem* prob, const henry_
     HIPCHK(hipEventRecord(ev, ctx->stream));
     for (int k = 0; k < nbatches; ++k) HIPCHK(hipStreamWaitEvent(streams[k], ev, 0));
     HIPCHK(hipEventDestroy(ev));
+    // every solver's device and pinned memory is allocated here and freed after the join, so no
+    // worker allocates or frees while another captures a graph or synchronises its stream
+    std::vector<std::unique_ptr<VCSolver>> solvers;
+    for (int k = 0; k < nbatches; ++k)
+      solvers.push_back(std::make_unique<VCSolver>(ctx, *prob, o, batches[k].grid, batches[k].nsamples, streams[k]));
     std::vector<int> nfail(nbatches, 0), ok(nbatches, 1);
+    std::vector<std::vector<int>> hs(nbatches);
+    for (int k = 0; k < nbatches; ++k) hs[k].resize(batches[k].nsamples);
     std::vector<HenryError> err(nbatches, HenryError{0, ""});
     auto work = [&](int k) {
       try {
         HIPCHK(hipSetDevice(ctx->device));
         const henry_batch& B = batches[k];
         const Range r("henry vc grid %dx%d S=%d steps=%d", B.grid.nx, B.grid.ny, B.nsamples, B.grid.nsteps);
-        VCSolver sv(ctx, *prob, o, B.grid, B.nsamples, streams[k]);
+        VCSolver& sv = *solvers[k];
         sv.run(B.theta, B.c_T, B.p_T, B.qoi, B.status, B.stats);
         HIPCHK(hipGetLastError());
-        std::vector<int> hs(B.nsamples);
-        HIPCHK(hipMemcpyAsync(hs.data(), sv.status.p, (size_t)B.nsamples * sizeof(int), hipMemcpyDeviceToHost,
+        HIPCHK(hipMemcpyAsync(hs[k].data(), sv.status.p, (size_t)B.nsamples * sizeof(int), hipMemcpyDeviceToHost,
                               streams[k]));
         HIPCHK(hipStreamSynchronize(streams[k]));
-        for (int v : hs) nfail[k] += v != 0;
+        for (int v : hs[k]) nfail[k] += v != 0;
       } catch (const HenryError& e) {
         ok[k] = 0;
         err[k] = e;

@@ -11,7 +11,9 @@
 namespace henry {
 
 constexpr int VC_BLK = 9;
-enum { VC_RHO = 0, VC_ALPHA, VC_OMEGA, VC_R0, VC_ACTIVE, VC_ITS, VC_NEWTON, VC_DONE, VC_NSC };
+// VC_LAST: size of the sample's last undamped Newton update in this step (0: none); VC_R2P: |R|^2
+// of its previous Newton iterate (the predictive stop of k_vc_bicg_start)
+enum { VC_RHO = 0, VC_ALPHA, VC_OMEGA, VC_R0, VC_ACTIVE, VC_ITS, VC_NEWTON, VC_DONE, VC_LAST, VC_R2P, VC_NSC };
 
 // Element faces: face f separates local vertices a -> b (0 = (i, j), 1 = (i+1, j),
 // 2 = (i+1, j+1), 3 = (i, j+1)), is crossed along +x (axis 0) or +y (axis 1), and has its
@@ -334,15 +336,25 @@ __global__ void __launch_bounds__(256) k_vc_absmax(Map m, int nv, const double* 
 // still iterating after the kernel.
 
 // after dots (r, r): rho = |r0|^2, active where it is > 0
+// Newton's predictive stop (pred_tol > 0): a sample whose predicted update, the last undamped
+// update's size times |R_k| / |R_{k-1}|, is at most pred_tol is converged without this solve.
 __global__ void k_vc_bicg_start(Map m, const double* __restrict__ part, double* __restrict__ sc,
-                                int* __restrict__ ctrl) {
+                                int* __restrict__ ctrl, double pred_tol) {
   __shared__ double lds[64 * FIN_Y];
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double v[1];
   reduce_partials<1>(m, part, s, v, lds);
   if (threadIdx.y != 0 || s >= m.S) return;
   const int S = m.S;
-  const bool act = v[0] > 0.0 && isfinite(v[0]) && sc[VC_DONE * S + s] == 0.0;
+  bool act = v[0] > 0.0 && isfinite(v[0]) && sc[VC_DONE * S + s] == 0.0;
+  if (act && pred_tol > 0.0) {
+    const double last = sc[VC_LAST * S + s], r2p = sc[VC_R2P * S + s];
+    if (last > 0.0 && r2p > 0.0 && last * sqrt(v[0] / r2p) <= pred_tol) {
+      act = false;
+      sc[VC_DONE * S + s] = 1.0;
+    }
+    sc[VC_R2P * S + s] = v[0];
+  }
   sc[VC_RHO * S + s] = v[0];
   sc[VC_R0 * S + s] = v[0];
   sc[VC_ACTIVE * S + s] = act ? 1.0 : 0.0;
@@ -493,6 +505,7 @@ __global__ void k_vc_newton_fin(Map m, const double* __restrict__ part, double* 
     return;
   }
   sc[VC_ALPHA * S + s] = dc > 0.0 ? fmin(1.0, dc_max / dc) : 1.0;   // damping factor
+  sc[VC_LAST * S + s] = dc > dc_max ? 0.0 : fmax(dc, dp / p_ref);     // no prediction after damping
   sc[VC_NEWTON * S + s] += 1.0;
   if (fmax(dc, dp / p_ref) <= tol) sc[VC_DONE * S + s] = 1.0;
   else atomicAdd(&ctrl[0], 1);
@@ -920,6 +933,8 @@ __global__ void k_vc_step_start(int S, const int* __restrict__ status, double* _
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (threadIdx.y != 0 || s >= S) return;
   sc[VC_DONE * S + s] = status[s] == 3 ? 1.0 : 0.0;   // a frozen (non-finite) sample stays frozen
+  sc[VC_LAST * S + s] = 0.0;                          // no prediction before a step's first update
+  sc[VC_R2P * S + s] = 0.0;
 }
 __global__ void k_vc_step_end(int S, int* __restrict__ status, const double* __restrict__ sc) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;

@@ -201,13 +201,14 @@ def test_vc_graph_replay_is_bitwise_identical(hx):
     assert torch.equal(a.stats, b.stats)
 
 
-@pytest.mark.parametrize("threads", [0, 1])
-def test_vc_solve_batch_equals_single_solves(hx, threads):
+@pytest.mark.parametrize("threads,graphs", [(0, 0), (1, 0), (0, 1)])
+def test_vc_solve_batch_equals_single_solves(hx, threads, graphs):
     """henry_vc_solve_batch: three batches on different grids and sample counts, concurrently
-    (ragged_threads 0) or one after another (1), equal the same batches solved alone bit for bit;
-    a batch with a NaN theta refuses the whole call."""
+    (ragged_threads 0, with or without graph capture on the workers) or one after another (1),
+    equal the same batches solved alone bit for bit; a batch with a NaN theta refuses the whole
+    call."""
     import paper_2403_17018_amd as P
-    o = P.solver_opts(krylov_maxit=300, ragged_threads=threads)
+    o = P.solver_opts(krylov_maxit=300, ragged_threads=threads, use_graphs=graphs)
     prob = P.paper_problem(T=6016.0 * 24 / 94)
     items = [(_cu(draw_theta(89, 40)), P.grid(16, 8, 24)), (_cu(draw_theta(90, 7)), P.grid(32, 16, 24)),
              (_cu(draw_theta(91, 65)), P.grid(12, 6, 24))]
