@@ -2501,8 +2501,7 @@ struct VCSolver {
     ctrl.alloc(sizeof(int));
     status.alloc((size_t)S * sizeof(int));
     HIPCHK(hipHostMalloc((void**)&h_ctrl, sizeof(int), hipHostMallocDefault));
-    // halve while both element counts are even and stay at or above the coarse grid; the
-    // coarsest grid is smoothed in LDS by one workgroup per sample (at most 256 vertices)
+    // halve while both element counts are even and stay at or above the coarse grid
     int gx = nx, gy = ny;
     while (gx % 2 == 0 && gy % 2 == 0 && gx / 2 >= o.coarse_nx && gy / 2 >= o.coarse_ny) {
       gx /= 2;
@@ -2554,7 +2553,6 @@ struct VCSolver {
       Ef = L->E;
     }
   }
-  // coarse operators: rediscretised at the injected state (after the fine assembly)
   // Coarse operators at the injected state.  The coarsest grid's operator serves only its LU
   // factors, which are refreshed at the first Newton iteration of each step (refresh_coarsest)
   // and kept for the step's later iterations: the preconditioner changes, not the fixed point.
