@@ -87,8 +87,13 @@ def test_vc_assembly_matches_oracle(hx, model):
                 assert np.abs(got - row).max() <= 1e-7 * rs, (model, s, v, a)
 
 
-def _check_run(r, ref, nx, ny):
+def _check_run(r, ref, nx, ny, max_krylov=3.0):
     assert r.nfailed == 0, r.status
+    # the multigrid preconditioner's effect: a wrong smoother or coarse solve keeps the fixed
+    # point but needs many more BiCGStab iterations per Newton iteration
+    if max_krylov is not None:
+        st = r.stats.cpu().numpy()
+        assert st[:, 1].sum() <= max_krylov * st[:, 0].sum(), st
     c = _sample_major(r.c_T.cpu().numpy())
     p = _sample_major(r.p_T.cpu().numpy())
     assert rel_inf(c, ref["c"]).max() <= TOL
@@ -156,7 +161,7 @@ def test_vc_gauss_seidel_preconditioner_path(hx):
     r = hx.vc_solve(_cu(th), P.grid(12, 6, 20), P.problem(T=36000.0 * 20 / 94), P.solver_opts(krylov_maxit=300),
                     want_c=True, want_p=True)
     torch.cuda.synchronize()
-    _check_run(r, ref, 12, 6)
+    _check_run(r, ref, 12, 6, max_krylov=None)   # plain sweeps: more iterations by design
 
 
 def test_mlmc_run_vc_matches_oracle(hx):
