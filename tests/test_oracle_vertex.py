@@ -174,3 +174,18 @@ def test_face_fluxes_at_their_integration_points():
         w = faces[k]["w"]
         conv = faces[k]["F"] * ((1 - w) * 0.5 * (ca + cb) + w * np.where(faces[k]["F"] >= 0, ca, cb))
         assert np.abs((conv - faces[k]["G"]) - Gd).max() <= 1e-12 * np.abs(Gd).max(), k
+
+
+def test_steady_seawater_column_is_hydrostatic():
+    """c = 1 on both sides and no inflow: the steady state is a resting column of seawater, so
+    c = 1 everywhere and p = -rho1 g y (zero at the top, the right side's hydrostatic datum)."""
+    pr = H.Problem(q_in=0.0, c_left=1.0)
+    g = H.Grid(8, 4, 1)
+    # one implicit step long enough that the storage term no longer moves the state (the mass
+    # balance defects, relative to the inflow, are undefined without inflow)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = V.solve_sample(pr, g, np.zeros(13), tau=1e17, opts=H.SolveOptions(newton_tol=1e-13, newton_maxit=60))
+    assert r.converged
+    yv = np.repeat(-pr.Ly + np.arange(5) * pr.Ly / 4, 9)
+    assert np.abs(r.c - 1.0).max() <= 1e-10
+    assert np.abs(r.p - (-pr.rho1 * pr.g * yv)).max() <= 1e-9 * pr.rho1 * pr.g * pr.Ly
