@@ -382,7 +382,7 @@ VC_SAMPLES = 512
 VC_OPTS = dict(krylov_maxit=1000, nu_pre=1, nu_post=1)
 
 
-def bench_vc(hx, P, S=VC_SAMPLES, graphs=1):
+def bench_vc(hx, P, S=VC_SAMPLES, graphs=1, prec=64):
     """The paper's own discretisation (vertex-centred finite volumes, section 2.3) on level 1
     of its Table 2 (64 x 32 elements, 2145 vertices, 376 steps of 16 s) with its own model:
     one untimed short run, then the timed run (BiCGStab iterations replayed from a hipGraph
@@ -392,7 +392,7 @@ def bench_vc(hx, P, S=VC_SAMPLES, graphs=1):
     import torch
     g = P.vc_level_grid(1)
     th = torch.from_numpy(draw_theta(5, S)).cuda()
-    o = P.solver_opts(use_graphs=graphs, **VC_OPTS)
+    o = P.solver_opts(use_graphs=graphs, mg_precision=prec, **VC_OPTS)
     hx.vc_solve(th, P.grid(g.nx, g.ny, 4), P.paper_problem(T=6016.0 * 4 / g.nsteps), o, want_c=False)
     torch.cuda.synchronize()
     hx.profile(True)      # resets the counters; event timing stays on only without graphs
@@ -407,7 +407,7 @@ def bench_vc(hx, P, S=VC_SAMPLES, graphs=1):
         torch.cuda.synchronize()
         hx.profile(True)
         t1 = time.perf_counter()
-        hx.vc_solve(th, g, P.paper_problem(), P.solver_opts(use_graphs=0, **VC_OPTS), want_c=False)
+        hx.vc_solve(th, g, P.paper_problem(), P.solver_opts(use_graphs=0, mg_precision=prec, **VC_OPTS), want_c=False)
         torch.cuda.synchronize()
         dt_prof = time.perf_counter() - t1
         prof_k = hx.profile_read()
@@ -417,23 +417,25 @@ def bench_vc(hx, P, S=VC_SAMPLES, graphs=1):
     st = r.stats.cpu()
     if METRICS is not None:
         METRICS.write(batch_record("f3_vc_level1_paper", g, r, seconds=dt))
-    cls = max(VC_BYTES_PER_UNIT, key=lambda k: prof_k[k][2])
+    table = VC_BYTES_PER_UNIT[prec]
+    cls = max(table, key=lambda k: prof_k[k][2])
     n, units, ms = prof_k[cls]
-    per_launch = units / n * VC_BYTES_PER_UNIT[cls]
+    per_launch = units / n * table[cls]
     achieved = per_launch / (ms / n * 1e-3) / 1e9
     return {
         "workload": "the paper's vertex-centred discretisation, level 1 of Table 2: 64x32 elements (2145 vertices), "
                     f"376 steps of 16 s, {S} samples (seed 5) of the section-4 model; BiCGStab preconditioned by a "
                     "vertex-grid multigrid V-cycle (1+1 four-colour Gauss-Seidel sweeps) with a pivoted LU on the "
                     "coarsest grid"
+                    + ("; FP32 multigrid and Jacobian" if prec == 32 else "")
                     + ("; BiCGStab iterations replayed from a hipGraph" if graphs else ""),
         "unit": "sample-timesteps/s", "value": S * g.nsteps / dt, "ms_per_step": dt * 1e3,
         "roofline": {"bound": "hbm", "kernel": VC_KERNEL_NAME[cls], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": pmc_traffic(VC_KERNEL_NAME[cls], 64, "f3_vc_level1_paper", "paper", "henry_vc.hpp"),
+                     "traffic": pmc_traffic(VC_KERNEL_NAME[cls], prec, "f3_vc_level1_paper", "paper", "henry_vc.hpp"),
                      "avg_launch_us": ms / n * 1e3, "launches": n, "algorithmic_bytes_per_launch": per_launch,
                      "timed_in": "a stream-launched repeat of the run" if graphs else "the timed run"},
-        "kernel_classes_ms": {k: round(prof_k[k][2], 3) for k in VC_BYTES_PER_UNIT},
+        "kernel_classes_ms": {k: round(prof_k[k][2], 3) for k in table},
         "profiled_repeat_ms": dt_prof * 1e3 if graphs else None,
         "host_syncs": prof["host_sync"][0], "host_sync_ms": round(prof["host_sync"][2], 3),
         "newton_its_per_step": float(st[:, 0].mean()) / g.nsteps,
@@ -534,6 +536,7 @@ def extra_lines(hx, P, args):
             "metric": "MLMC wall time to RMSE", "unit": "s", "value": time.perf_counter() - t0,
             "rmse": est["rmse"], "mlmc_mean_qoi": est["mean"], "failed_samples": est["nfailed"]}
     out["f3_vc_level1_paper"] = bench_vc(hx, P)
+    out["f3_vc_level1_paper_fp32mg"] = bench_vc(hx, P, prec=32)
     out["f3_mlmc_table3_eps0.05"] = bench_vc_mlmc(hx, P)
     return out
 
@@ -577,9 +580,11 @@ def main():
     if args.workload == "f3":
         import paper_2403_17018_amd as P
         hx = P.Henry(0)
-        m = bench_vc(hx, P, args.samples or VC_SAMPLES, 1 if args.graphs is None else args.graphs)
+        m = bench_vc(hx, P, args.samples or VC_SAMPLES, 1 if args.graphs is None else args.graphs,
+                     args.precision or 64)
         print(json.dumps({"metric": "sample-timesteps/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f64+f32mg" if args.precision == 32 else "f64",
                           "data": "synthetic", "config": {"workload": m.pop("workload")}, **m}))
         return
     name = {"c1": "c1_fp64_level0", "c2": "c2_fp64_level3", "c3": "c3_mixed_level4"}[args.workload]

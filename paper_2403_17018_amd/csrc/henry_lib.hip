@@ -2452,7 +2452,7 @@ static void vc_lds_prepare(K* kernel, size_t bytes) {
                              (int)bytes));
   if (dev >= 0 && dev < 64) done[dev] = true;
 }
-static size_t vc_dense_lds(int n) { return (size_t)n * n * sizeof(double) + (size_t)n * sizeof(double) + 16; }
+static size_t vc_dense_lds(int n, size_t tsz) { return (size_t)n * n * tsz + (size_t)n * sizeof(double) + 16; }
 
 // one coarse level of the vertex-grid multigrid (the finest level is the solver's own data)
 struct VCLevel {
@@ -2474,6 +2474,11 @@ struct VCSolver {
   Phys P;
   size_t NV;
   DevBuf phi, K, uin, p, c, c_old, R, J, x, r, rh, pv, ph, v, sv, sh, t, part, sc, ctrl, status, mgr, LUc, pivc;
+  // multigrid precision (mg_precision): 64, or 32 with the Jacobian stored in FP32 for the
+  // cycle and the Krylov products, and the cycle's input and output rounded at its ends (mb, mx)
+  int prec;
+  size_t tsz;
+  DevBuf mb, mx;
   DevBuf hp1, hp2, hp3, hc1, hc2, hc3;   // states of the last steps (first Newton guess)
   int* h_ctrl = nullptr;
   std::vector<std::unique_ptr<VCLevel>> lv;   // coarse levels 1.. of the multigrid preconditioner
@@ -2481,7 +2486,8 @@ struct VCSolver {
 
   VCSolver(henry_ctx* c_, const henry_problem& pr_, const henry_solver_opts& o_, henry_grid g, int S_,
            hipStream_t stream)
-      : ctx(c_), pr(pr_), o(o_), nx(g.nx), ny(g.ny), nsteps(g.nsteps), S(S_) {
+      : ctx(c_), pr(pr_), o(o_), nx(g.nx), ny(g.ny), nsteps(g.nsteps), S(S_), prec(o_.mg_precision),
+        tsz(o_.mg_precision == 32 ? 4 : 8) {
     st = stream;
     nv = (nx + 1) * (ny + 1);
     ne = nx * ny;
@@ -2495,7 +2501,7 @@ struct VCSolver {
     uin.alloc((size_t)S * 8);
     for (DevBuf* b : {&p, &c, &c_old, &hp1, &hp2, &hp3, &hc1, &hc2, &hc3}) b->alloc(NV * 8);
     for (DevBuf* b : {&R, &x, &r, &rh, &pv, &ph, &v, &sv, &sh, &t}) b->alloc(2 * NV * 8);
-    J.alloc(36 * NV * 8);
+    J.alloc(36 * NV * tsz);
     part.alloc((size_t)3 * m.ncb * S * 8);
     sc.alloc((size_t)VC_NSC * S * 8);
     ctrl.alloc(sizeof(int));
@@ -2519,19 +2525,29 @@ struct VCSolver {
       L->phi.alloc((size_t)L->ne * S * 8);
       L->K.alloc((size_t)L->ne * S * 8);
       for (DevBuf* b : {&L->p, &L->c, &L->co}) b->alloc(n * 8);
-      for (DevBuf* b : {&L->Rs, &L->b, &L->x, &L->r}) b->alloc(2 * n * 8);
-      L->J.alloc(36 * n * 8);
+      L->Rs.alloc(2 * n * 8);
+      for (DevBuf* b : {&L->b, &L->x, &L->r}) b->alloc(2 * n * tsz);
+      L->J.alloc(36 * n * tsz);
       lv.push_back(std::move(L));
     }
     // the coarsest grid's dense matrix must fit the LDS of one workgroup
     if (!lv.empty() && 2 * lv.back()->nv > VC_DENSE_MAX) lv.clear();
     if (!lv.empty()) {
       const int n = 2 * lv.back()->nv;
-      mgr.alloc(2 * NV * 8);
-      LUc.alloc((size_t)n * n * S * 8);
+      mgr.alloc(2 * NV * tsz);
+      LUc.alloc((size_t)n * n * S * tsz);
       pivc.alloc((size_t)n * S * sizeof(int));
-      vc_lds_prepare(&k_vc_dense_factor, vc_dense_lds(VC_DENSE_MAX));
-      vc_lds_prepare(&k_vc_dense_solve, vc_dense_lds(VC_DENSE_MAX));
+      if (prec == 32) {
+        vc_lds_prepare(&k_vc_dense_factor<float>, vc_dense_lds(VC_DENSE_MAX, 4));
+        vc_lds_prepare(&k_vc_dense_solve<float>, vc_dense_lds(VC_DENSE_MAX, 4));
+      } else {
+        vc_lds_prepare(&k_vc_dense_factor<double>, vc_dense_lds(VC_DENSE_MAX, 8));
+        vc_lds_prepare(&k_vc_dense_solve<double>, vc_dense_lds(VC_DENSE_MAX, 8));
+      }
+    }
+    if (prec == 32) {
+      mb.alloc(2 * NV * 4);
+      mx.alloc(2 * NV * 4);
     }
   }
   ~VCSolver() {
@@ -2557,6 +2573,11 @@ struct VCSolver {
   // factors, which are refreshed at the first Newton iteration of each step (refresh_coarsest)
   // and kept for the step's later iterations: the preconditioner changes, not the fixed point.
   void coarse_assemble(bool refresh_coarsest) {
+    if (prec == 32) coarse_assemble_t<float>(refresh_coarsest);
+    else coarse_assemble_t<double>(refresh_coarsest);
+  }
+  template <typename T>
+  void coarse_assemble_t(bool refresh_coarsest) {
     const double *pf = p.as<double>(), *cf = c.as<double>(), *cof = c_old.as<double>();
     Grid2 Ef = E;
     for (auto& L : lv) {
@@ -2565,11 +2586,11 @@ struct VCSolver {
                          L->p.as<double>(), L->c.as<double>(), L->co.as<double>());
       Phys Pl = L->P;
       Pl.uin_fac = P.uin_fac;
-      hipLaunchKernelGGL((k_vc_assemble<true>), grid_cells(L->m, L->nv), block_of(L->m), 0, st, L->m, L->E, Pl,
+      hipLaunchKernelGGL((k_vc_assemble<true, T>), grid_cells(L->m, L->nv), block_of(L->m), 0, st, L->m, L->E, Pl,
                          (const double*)L->phi.as<double>(), (const double*)L->K.as<double>(),
                          (const double*)uin.as<double>(), (const double*)L->p.as<double>(),
                          (const double*)L->c.as<double>(), (const double*)L->co.as<double>(), L->Rs.as<double>(),
-                         L->J.as<double>());
+                         L->J.as<T>());
       pf = L->p.as<double>();
       cf = L->c.as<double>();
       cof = L->co.as<double>();
@@ -2577,61 +2598,68 @@ struct VCSolver {
     }
     if (!lv.empty()) {
       const VCLevel& Lc = *lv.back();
-      hipLaunchKernelGGL(k_vc_dense_factor, dim3(S), dim3(256), vc_dense_lds(2 * Lc.nv), st, S, Lc.E,
-                         (const double*)Lc.J.as<double>(), LUc.as<double>(), pivc.as<int>());
+      hipLaunchKernelGGL(k_vc_dense_factor<T>, dim3(S), dim3(256), vc_dense_lds(2 * Lc.nv, sizeof(T)), st, S, Lc.E,
+                         (const T*)Lc.J.as<T>(), LUc.as<T>(), pivc.as<int>());
     }
   }
-  // one V-cycle on level k (0: the fine grid) for J_k x = b from x = 0
-  void vcycle(int k, const double* b, double* xo) {
+  // one V-cycle on level k (0: the fine grid) for J_k x = b from x = 0, in precision T
+  template <typename T>
+  void vcycle(int k, const T* b, T* xo) {
     const VCLevel* L = k > 0 ? lv[k - 1].get() : nullptr;
     const Map& mk = k > 0 ? L->m : m;
     const Grid2& Ek = k > 0 ? L->E : E;
     const int nvk = k > 0 ? L->nv : nv;
-    const double* Jk = k > 0 ? L->J.as<double>() : J.as<double>();
-    if (k == (int)lv.size()) {   // coarsest: the direct solve with this Newton iteration's factors
-      hipLaunchKernelGGL(k_vc_dense_solve, dim3(S), dim3(64), vc_dense_lds(2 * nvk), st, S, Ek,
-                         (const double*)LUc.as<double>(), (const int*)pivc.as<int>(), b, xo);
+    const T* Jk = k > 0 ? L->J.as<T>() : J.as<T>();
+    if (k == (int)lv.size()) {   // coarsest: the direct solve with this step's factors
+      hipLaunchKernelGGL(k_vc_dense_solve<T>, dim3(S), dim3(64), vc_dense_lds(2 * nvk, sizeof(T)), st, S, Ek,
+                         (const T*)LUc.as<T>(), (const int*)pivc.as<int>(), b, xo);
       return;
     }
     // x starts at zero: the first forward sweep skips the colours not yet swept, so x is not
     // cleared; the last colour swept (3) has a zero residual
     for (int sw = 0; sw < std::max(1, o.nu_pre); ++sw)
-      for (int col = 0; col < 4; ++col) gs_pass(k, mk, Ek, col, Jk, b, xo, sw == 0);
-    double* rk = k > 0 ? L->r.as<double>() : mgr.as<double>();
-    hipLaunchKernelGGL(k_vc_resid, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, 3, Jk, b, (const double*)xo, rk);
+      for (int col = 0; col < 4; ++col) gs_pass<T>(k, mk, Ek, col, Jk, b, xo, sw == 0);
+    T* rk = k > 0 ? L->r.as<T>() : mgr.as<T>();
+    hipLaunchKernelGGL(k_vc_resid<T>, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, 3, Jk, b, (const T*)xo, rk);
     VCLevel* C = lv[k].get();
-    hipLaunchKernelGGL(k_vc_restrict, grid_cells(C->m, C->nv), block_of(C->m), 0, st, C->m, C->E, Ek,
-                       (const double*)rk, C->b.as<double>());
-    vcycle(k + 1, C->b.as<double>(), C->x.as<double>());
-    hipLaunchKernelGGL(k_vc_prolong_add, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, C->E,
-                       (const double*)C->x.as<double>(), xo);
+    hipLaunchKernelGGL(k_vc_restrict<T>, grid_cells(C->m, C->nv), block_of(C->m), 0, st, C->m, C->E, Ek, (const T*)rk,
+                       C->b.as<T>());
+    vcycle<T>(k + 1, C->b.as<T>(), C->x.as<T>());
+    hipLaunchKernelGGL(k_vc_prolong_add<T>, grid_cells(mk, nvk), block_of(mk), 0, st, mk, Ek, C->E,
+                       (const T*)C->x.as<T>(), xo);
     for (int sw = 0; sw < std::max(1, o.nu_post); ++sw)
-      for (int col = 3; col >= 0; --col) gs_pass(k, mk, Ek, col, Jk, b, xo);
+      for (int col = 3; col >= 0; --col) gs_pass<T>(k, mk, Ek, col, Jk, b, xo);
   }
   // one colour pass on level k (first: of the first forward sweep from x = 0); the fine
   // grid's full passes are timed as HENRY_PROF_GS (units: the colour's vertex-samples)
-  void gs_pass(int k, const Map& mk, const Grid2& Ek, int col, const double* Jk, const double* b, double* xo,
-               bool first = false) {
+  template <typename T>
+  void gs_pass(int k, const Map& mk, const Grid2& Ek, int col, const T* Jk, const T* b, T* xo, bool first = false) {
     const dim3 g = grid_cells(mk, vc_colour_cells(Ek.nx, Ek.ny, 0));
     if (first) {
-      hipLaunchKernelGGL(k_vc_gs<true>, g, block_of(mk), 0, st, mk, Ek, col, Jk, b, xo);
+      hipLaunchKernelGGL((k_vc_gs<true, T>), g, block_of(mk), 0, st, mk, Ek, col, Jk, b, xo);
       return;
     }
-    auto f = [&] { launch_timed(k_vc_gs<false>, g, block_of(mk), 0, st, mk, Ek, col, Jk, b, xo); };
+    auto f = [&] { launch_timed(k_vc_gs<false, T>, g, block_of(mk), 0, st, mk, Ek, col, Jk, b, xo); };
     if (k == 0) timed(ctx, st, HENRY_PROF_GS, (long long)vc_colour_cells(Ek.nx, Ek.ny, col) * S, f);
     else f();
   }
-  void assemble(bool with_j, const double* pp, const double* cc, const double* co, double* RR, double* JJ) {
+  // residual R and, with_j, the Jacobian JJ (stored in the multigrid precision: FP64 or FP32)
+  void assemble(bool with_j, const double* pp, const double* cc, const double* co, double* RR, void* JJ) {
     if (with_j)
       timed(ctx, st, HENRY_PROF_ASSEMBLE, (long long)NV, [&] {
-        launch_timed((k_vc_assemble<true>), grid_cells(m, nv), block_of(m), 0, st, m, E, P,
-                           (const double*)phi.as<double>(), (const double*)K.as<double>(),
-                           (const double*)uin.as<double>(), pp, cc, co, RR, JJ);
+        if (prec == 32)
+          launch_timed((k_vc_assemble<true, float>), grid_cells(m, nv), block_of(m), 0, st, m, E, P,
+                       (const double*)phi.as<double>(), (const double*)K.as<double>(),
+                       (const double*)uin.as<double>(), pp, cc, co, RR, static_cast<float*>(JJ));
+        else
+          launch_timed((k_vc_assemble<true, double>), grid_cells(m, nv), block_of(m), 0, st, m, E, P,
+                       (const double*)phi.as<double>(), (const double*)K.as<double>(),
+                       (const double*)uin.as<double>(), pp, cc, co, RR, static_cast<double*>(JJ));
       });
     else
-      hipLaunchKernelGGL((k_vc_assemble<false>), grid_cells(m, nv), block_of(m), 0, st, m, E, P,
+      hipLaunchKernelGGL((k_vc_assemble<false, double>), grid_cells(m, nv), block_of(m), 0, st, m, E, P,
                          (const double*)phi.as<double>(), (const double*)K.as<double>(),
-                         (const double*)uin.as<double>(), pp, cc, co, RR, JJ);
+                         (const double*)uin.as<double>(), pp, cc, co, RR, (double*)nullptr);
   }
   int read_ctrl() {
     const auto t0 = std::chrono::steady_clock::now();
@@ -2647,21 +2675,38 @@ struct VCSolver {
     hipLaunchKernelGGL((k_vc_dots<NQ>), grid_red(m), block_of(m), 0, st, m, nv, ab, part.as<double>());
   }
   dim3 g2() const { return dim3((unsigned)((2 * NV + 255) / 256)); }
-  // x = M^{-1} b: a multigrid V-cycle where the grid coarsens, else symmetric four-colour sweeps
+  // x = M^{-1} b: a multigrid V-cycle where the grid coarsens, else symmetric four-colour sweeps;
+  // with the FP32 multigrid, b is rounded to FP32 on entry and the result widened on exit
   void precond(const double* b, double* xo) {
+    if (prec == 64) {
+      precond_t<double>(b, xo);
+      return;
+    }
+    const dim3 g = g2();
+    hipLaunchKernelGGL((k_convert<double, float>), g, dim3(256), 0, st, 2 * NV, b, mb.as<float>());
+    precond_t<float>(mb.as<float>(), mx.as<float>());
+    hipLaunchKernelGGL((k_convert<float, double>), g, dim3(256), 0, st, 2 * NV, (const float*)mx.as<float>(), xo);
+  }
+  template <typename T>
+  void precond_t(const T* b, T* xo) {
     if (!lv.empty()) {
-      vcycle(0, b, xo);
+      vcycle<T>(0, b, xo);
       return;
     }
     const int sweeps = std::max(1, o.nu_pre + o.nu_post);
     for (int k = 0; k < sweeps; ++k) {
-      for (int col = 0; col < 4; ++col) gs_pass(0, m, E, col, (const double*)J.as<double>(), b, xo, k == 0);
-      for (int col = 3; col >= 0; --col) gs_pass(0, m, E, col, (const double*)J.as<double>(), b, xo);
+      for (int col = 0; col < 4; ++col) gs_pass<T>(0, m, E, col, (const T*)J.as<T>(), b, xo, k == 0);
+      for (int col = 3; col >= 0; --col) gs_pass<T>(0, m, E, col, (const T*)J.as<T>(), b, xo);
     }
   }
+  // y = J x with the stored Jacobian (FP32 with the FP32 multigrid), accumulated in FP64
   void spmv(const double* xi, double* yo) {
     timed(ctx, st, HENRY_PROF_SPMV, (long long)NV, [&] {
-      launch_timed(k_vc_spmv, grid_cells(m, nv), block_of(m), 0, st, m, E, (const double*)J.as<double>(), xi, yo);
+      if (prec == 32)
+        launch_timed(k_vc_spmv<float>, grid_cells(m, nv), block_of(m), 0, st, m, E, (const float*)J.as<float>(), xi, yo);
+      else
+        launch_timed(k_vc_spmv<double>, grid_cells(m, nv), block_of(m), 0, st, m, E, (const double*)J.as<double>(), xi,
+                     yo);
     });
   }
   // J x = -R (masked by the Newton flags); returns the iterations run
@@ -2758,7 +2803,7 @@ struct VCSolver {
       hipLaunchKernelGGL(k_vc_step_start, fg, fb, 0, st, S, (const int*)status.as<int>(), scp);
       bool done = false;
       for (int it = 0; it < o.newton_maxit && !done; ++it) {
-        assemble(true, p.as<double>(), c.as<double>(), c_old.as<double>(), R.as<double>(), J.as<double>());
+        assemble(true, p.as<double>(), c.as<double>(), c_old.as<double>(), R.as<double>(), J.p);
         coarse_assemble(it == 0);
         bicgstab();
         hipLaunchKernelGGL(k_vc_absmax, grid_red(m), block_of(m), 0, st, m, nv, (const double*)x.as<double>(),

@@ -85,12 +85,13 @@ __device__ __forceinline__ void vc_face(int f, const double (&pk)[4], const doub
 // Residual (and Jacobian) of one implicit-Euler step at every vertex: a thread per (vertex,
 // sample) gathers the two faces of each element around its vertex that bound its box.
 // E: the element grid; phi, K: [element][S]; uin: [S] (times P.uin_fac).
-template <bool WRITE_J>
+// TJ: the Jacobian's storage type (float for the FP32 multigrid and its Krylov products)
+template <bool WRITE_J, typename TJ = double>
 __global__ void __launch_bounds__(256) k_vc_assemble(Map m, Grid2 E, Phys P, const double* __restrict__ phi,
                                                      const double* __restrict__ K, const double* __restrict__ uin,
                                                      const double* __restrict__ p, const double* __restrict__ c,
                                                      const double* __restrict__ c_old, double* __restrict__ R,
-                                                     double* __restrict__ J) {
+                                                     TJ* __restrict__ J) {
   const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
   int s, v, sb, cb;
   if (!map_cell(m, nv, s, v, sb, cb)) return;
@@ -187,12 +188,13 @@ __global__ void __launch_bounds__(256) k_vc_assemble(Map m, Grid2 E, Phys P, con
   R[NV + id] = Rc;
   if (WRITE_J) {
 #pragma unroll
-    for (int q = 0; q < 36; ++q) J[(size_t)q * NV + id] = Jb[q];
+    for (int q = 0; q < 36; ++q) J[(size_t)q * NV + id] = (TJ)Jb[q];
   }
 }
 
-// y = J x (9 blocks), one thread per (vertex, sample)
-__global__ void __launch_bounds__(256) k_vc_spmv(Map m, Grid2 E, const double* __restrict__ J,
+// y = J x (9 blocks), one thread per (vertex, sample); J stored as TJ, the product in FP64
+template <typename TJ>
+__global__ void __launch_bounds__(256) k_vc_spmv(Map m, Grid2 E, const TJ* __restrict__ J,
                                                  const double* __restrict__ x, double* __restrict__ y) {
   const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
   int s, v, sb, cb;
@@ -211,8 +213,8 @@ __global__ void __launch_bounds__(256) k_vc_spmv(Map m, Grid2 E, const double* _
       const int bl = (dj + 1) * 3 + (di + 1);
       const size_t q = ((size_t)qj * nvx + qi) * S + s;
       const double x0 = x[q], x1 = x[NV + q];
-      y0 += J[(size_t)(bl * 4 + 0) * NV + id] * x0 + J[(size_t)(bl * 4 + 1) * NV + id] * x1;
-      y1 += J[(size_t)(bl * 4 + 2) * NV + id] * x0 + J[(size_t)(bl * 4 + 3) * NV + id] * x1;
+      y0 += (double)J[(size_t)(bl * 4 + 0) * NV + id] * x0 + (double)J[(size_t)(bl * 4 + 1) * NV + id] * x1;
+      y1 += (double)J[(size_t)(bl * 4 + 2) * NV + id] * x0 + (double)J[(size_t)(bl * 4 + 3) * NV + id] * x1;
     }
   y[id] = y0;
   y[NV + id] = y1;
@@ -227,9 +229,9 @@ __global__ void __launch_bounds__(256) k_vc_spmv(Map m, Grid2 E, const double* _
 __host__ __device__ inline int vc_colour_cells(int nx, int ny, int colour) {
   return ((nx + 2 - (colour & 1)) >> 1) * ((ny + 2 - (colour >> 1)) >> 1);
 }
-template <bool FIRST>
-__global__ void __launch_bounds__(256) k_vc_gs(Map m, Grid2 E, int colour, const double* __restrict__ J,
-                                               const double* __restrict__ b, double* __restrict__ x) {
+template <bool FIRST, typename T>
+__global__ void __launch_bounds__(256) k_vc_gs(Map m, Grid2 E, int colour, const T* __restrict__ J,
+                                               const T* __restrict__ b, T* __restrict__ x) {
   const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
   const int ci = colour & 1, cj = colour >> 1;
   const int nci = (nvx + 1 - ci) >> 1, ncj = (nvy + 1 - cj) >> 1;
@@ -241,7 +243,7 @@ __global__ void __launch_bounds__(256) k_vc_gs(Map m, Grid2 E, int colour, const
   const int S = m.S;
   const size_t NV = (size_t)nv * S;
   const size_t id = (size_t)v * S + s;
-  double r0 = b[id], r1 = b[NV + id];
+  T r0 = b[id], r1 = b[NV + id];
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
@@ -252,13 +254,13 @@ __global__ void __launch_bounds__(256) k_vc_gs(Map m, Grid2 E, int colour, const
       if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
       const int bl = (dj + 1) * 3 + (di + 1);
       const size_t q = ((size_t)qj * nvx + qi) * S + s;
-      const double x0 = x[q], x1 = x[NV + q];
+      const T x0 = x[q], x1 = x[NV + q];
       r0 -= J[(size_t)(bl * 4 + 0) * NV + id] * x0 + J[(size_t)(bl * 4 + 1) * NV + id] * x1;
       r1 -= J[(size_t)(bl * 4 + 2) * NV + id] * x0 + J[(size_t)(bl * 4 + 3) * NV + id] * x1;
     }
-  const double d00 = J[(size_t)16 * NV + id], d01 = J[(size_t)17 * NV + id];
-  const double d10 = J[(size_t)18 * NV + id], d11 = J[(size_t)19 * NV + id];
-  const double det = d00 * d11 - d01 * d10;
+  const T d00 = J[(size_t)16 * NV + id], d01 = J[(size_t)17 * NV + id];
+  const T d10 = J[(size_t)18 * NV + id], d11 = J[(size_t)19 * NV + id];
+  const T det = d00 * d11 - d01 * d10;
   x[id] = (d11 * r0 - d01 * r1) / det;
   x[NV + id] = (d00 * r1 - d10 * r0) / det;
 }
@@ -567,9 +569,10 @@ __global__ void __launch_bounds__(256) k_vc_qoi(Map m, Grid2 E, Phys P, const do
 // r = b - J x
 // zero_colour: the colour swept last, whose residual is zero up to rounding (its rows were
 // just solved against the current neighbours): written as 0 without reading J
-__global__ void __launch_bounds__(256) k_vc_resid(Map m, Grid2 E, int zero_colour, const double* __restrict__ J,
-                                                  const double* __restrict__ b, const double* __restrict__ x,
-                                                  double* __restrict__ r) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_vc_resid(Map m, Grid2 E, int zero_colour, const T* __restrict__ J,
+                                                  const T* __restrict__ b, const T* __restrict__ x,
+                                                  T* __restrict__ r) {
   const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy;
   int s, v, sb, cb;
   if (!map_cell(m, nv, s, v, sb, cb)) return;
@@ -578,11 +581,11 @@ __global__ void __launch_bounds__(256) k_vc_resid(Map m, Grid2 E, int zero_colou
   const int j = v / nvx, i = v - j * nvx;
   const size_t id = (size_t)v * S + s;
   if ((i & 1) + 2 * (j & 1) == zero_colour) {
-    r[id] = 0.0;
-    r[NV + id] = 0.0;
+    r[id] = 0;
+    r[NV + id] = 0;
     return;
   }
-  double y0 = b[id], y1 = b[NV + id];
+  T y0 = b[id], y1 = b[NV + id];
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
@@ -591,7 +594,7 @@ __global__ void __launch_bounds__(256) k_vc_resid(Map m, Grid2 E, int zero_colou
       if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
       const int bl = (dj + 1) * 3 + (di + 1);
       const size_t q = ((size_t)qj * nvx + qi) * S + s;
-      const double x0 = x[q], x1 = x[NV + q];
+      const T x0 = x[q], x1 = x[NV + q];
       y0 -= J[(size_t)(bl * 4 + 0) * NV + id] * x0 + J[(size_t)(bl * 4 + 1) * NV + id] * x1;
       y1 -= J[(size_t)(bl * 4 + 2) * NV + id] * x0 + J[(size_t)(bl * 4 + 3) * NV + id] * x1;
     }
@@ -600,8 +603,9 @@ __global__ void __launch_bounds__(256) k_vc_resid(Map m, Grid2 E, int zero_colou
 }
 
 // coarse right-hand side: full weighting of the fine residual (mc: the coarse grid's map)
-__global__ void __launch_bounds__(256) k_vc_restrict(Map mc, Grid2 Ec, Grid2 Ef, const double* __restrict__ rf,
-                                                     double* __restrict__ bc) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_vc_restrict(Map mc, Grid2 Ec, Grid2 Ef, const T* __restrict__ rf,
+                                                     T* __restrict__ bc) {
   const int nvxc = Ec.nx + 1, nvc = nvxc * (Ec.ny + 1);
   const int nvxf = Ef.nx + 1, nvyf = Ef.ny + 1;
   int s, v, sb, cb;
@@ -609,26 +613,27 @@ __global__ void __launch_bounds__(256) k_vc_restrict(Map mc, Grid2 Ec, Grid2 Ef,
   const int S = mc.S;
   const size_t NVc = (size_t)nvc * S, NVf = (size_t)nvxf * nvyf * S;
   const int J = v / nvxc, I = v - J * nvxc;
-  double a0 = 0.0, a1 = 0.0;
+  T a0 = 0, a1 = 0;
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
     for (int di = -1; di <= 1; ++di) {
       const int fi = 2 * I + di, fj = 2 * J + dj;
       if (fi < 0 || fi >= nvxf || fj < 0 || fj >= nvyf) continue;
-      const double w = (di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5);
+      const T w = (T)((di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5));
       const size_t q = ((size_t)fj * nvxf + fi) * S + s;
       a0 += w * rf[q];
       a1 += w * rf[NVf + q];
     }
   const size_t id = (size_t)v * S + s;
-  bc[id] = I == Ec.nx ? 0.0 : a0;
-  bc[NVc + id] = (I == Ec.nx || I == 0) ? 0.0 : a1;
+  bc[id] = I == Ec.nx ? (T)0 : a0;
+  bc[NVc + id] = (I == Ec.nx || I == 0) ? (T)0 : a1;
 }
 
 // x_f += P x_c (bilinear), Dirichlet components untouched (mf: the fine grid's map)
-__global__ void __launch_bounds__(256) k_vc_prolong_add(Map mf, Grid2 Ef, Grid2 Ec, const double* __restrict__ xc,
-                                                        double* __restrict__ xf) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_vc_prolong_add(Map mf, Grid2 Ef, Grid2 Ec, const T* __restrict__ xc,
+                                                        T* __restrict__ xf) {
   const int nvxf = Ef.nx + 1, nvf = nvxf * (Ef.ny + 1);
   const int nvxc = Ec.nx + 1, nvc = nvxc * (Ec.ny + 1);
   int s, v, sb, cb;
@@ -640,11 +645,11 @@ __global__ void __launch_bounds__(256) k_vc_prolong_add(Map mf, Grid2 Ef, Grid2 
   // the four (possibly coinciding) coarse vertices around (i, j), each with weight 1/4: a
   // coinciding vertex counted 4 or 2 times gives the bilinear weights 1 and 1/2
   const int I0 = i >> 1, J0 = j >> 1, I1 = I0 + (i & 1), J1 = J0 + (j & 1);
-  const double w = 0.25;
+  const T w = (T)0.25;
   const size_t c00 = ((size_t)J0 * nvxc + I0) * S + s, c10 = ((size_t)J0 * nvxc + I1) * S + s;
   const size_t c01 = ((size_t)J1 * nvxc + I0) * S + s, c11 = ((size_t)J1 * nvxc + I1) * S + s;
-  const double e0 = w * (xc[c00] + xc[c10] + xc[c01] + xc[c11]);
-  const double e1 = w * (xc[NVc + c00] + xc[NVc + c10] + xc[NVc + c01] + xc[NVc + c11]);
+  const T e0 = w * (xc[c00] + xc[c10] + xc[c01] + xc[c11]);
+  const T e1 = w * (xc[NVc + c00] + xc[NVc + c10] + xc[NVc + c01] + xc[NVc + c11]);
   const size_t id = (size_t)v * S + s;
   xf[id] += e0;
   if (i != 0) xf[NVf + id] += e1;
@@ -702,8 +707,12 @@ __device__ __forceinline__ double vc_bcast(double v, int lane) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+__device__ __forceinline__ float vc_bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
 // the slot holding row r (r uniform); scalar arguments keep the slots in registers
-__device__ __forceinline__ double vc_slot(double v0, double v1, double v2, int r) {
+template <typename T>
+__device__ __forceinline__ T vc_slot(T v0, T v1, T v2, int r) {
   return r < 64 ? v0 : (r < 128 ? v1 : v2);
 }
 
@@ -712,26 +721,27 @@ __device__ __forceinline__ double vc_slot(double v0, double v1, double v2, int r
 // row of largest magnitude at or below the diagonal) and the multipliers itself; each swaps rows
 // k and p in its own columns and updates its own trailing columns; one barrier ends the step,
 // after which the owner of column k stores its multipliers (no wavefront reads column k again).
-__global__ void __launch_bounds__(256) k_vc_dense_factor(int S, Grid2 E, const double* __restrict__ J,
-                                                         double* __restrict__ LU, int* __restrict__ perm) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_vc_dense_factor(int S, Grid2 E, const T* __restrict__ J,
+                                                         T* __restrict__ LU, int* __restrict__ perm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nvx = E.nx + 1, nvy = E.ny + 1, nv = nvx * nvy, n = 2 * nv;
   const int s = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
   const size_t NV = (size_t)nv * S;
-  double* A = reinterpret_cast<double*>(smem_raw);   // A[c * n + r]
+  T* A = reinterpret_cast<T*>(smem_raw);   // A[c * n + r]
   int* pr = reinterpret_cast<int*>(A + (size_t)n * n);
-  for (int e = t; e < n * n; e += 256) A[e] = 0.0;
+  for (int e = t; e < n * n; e += 256) A[e] = 0;
   for (int r = t; r < n; r += 256) pr[r] = r;
   __syncthreads();
   // scatter the nine blocks of every vertex row, four independent loads in flight per thread
   for (int e0 = 0; e0 < nv * 36; e0 += 4 * 256) {
-    double val[4];
+    T val[4];
     int dst[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = e0 + u * 256 + t;
       dst[u] = -1;
-      val[u] = 0.0;
+      val[u] = 0;
       if (e < nv * 36) {
         const int v = e / 36, q = e - v * 36, bl = q >> 2, a = (q >> 1) & 1, k = q & 1;
         const int i = v % nvx, j = v / nvx, qi = i + bl % 3 - 1, qj = j + bl / 3 - 1;
@@ -747,13 +757,13 @@ __global__ void __launch_bounds__(256) k_vc_dense_factor(int S, Grid2 E, const d
   }
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    const double* Ak = A + (size_t)k * n;
-    double ck[VC_DENSE_SLOTS];
-    double vmax = -1.0;
+    const T* Ak = A + (size_t)k * n;
+    T ck[VC_DENSE_SLOTS];
+    T vmax = -1;
 #pragma unroll
     for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
       const int r = lane + 64 * q;
-      ck[q] = r < n ? Ak[r] : 0.0;
+      ck[q] = r < n ? Ak[r] : (T)0;
       if (r >= k && r < n) vmax = fmax(vmax, fabs(ck[q]));
     }
 #pragma unroll
@@ -765,21 +775,21 @@ __global__ void __launch_bounds__(256) k_vc_dense_factor(int S, Grid2 E, const d
       const unsigned long long hit = __ballot(r >= k && r < n && fabs(ck[q]) == vmax);
       if (hit) p = 64 * q + __ffsll((long long)hit) - 1;
     }
-    const double akk = vc_bcast(vc_slot(ck[0], ck[1], ck[2], k), k & 63);
-    const double apk = vc_bcast(vc_slot(ck[0], ck[1], ck[2], p), p & 63);
-    const double rp = 1.0 / apk;
-    double l[VC_DENSE_SLOTS];
+    const T akk = vc_bcast(vc_slot(ck[0], ck[1], ck[2], k), k & 63);
+    const T apk = vc_bcast(vc_slot(ck[0], ck[1], ck[2], p), p & 63);
+    const T rp = (T)1 / apk;
+    T l[VC_DENSE_SLOTS];
     bool below[VC_DENSE_SLOTS];
 #pragma unroll
     for (int q = 0; q < VC_DENSE_SLOTS; ++q) {   // multipliers of the interchanged column k
       const int r = lane + 64 * q;
       below[q] = r > k && r < n;
-      l[q] = below[q] ? (r == p ? akk : ck[q]) * rp : 0.0;
+      l[q] = below[q] ? (r == p ? akk : ck[q]) * rp : (T)0;
     }
     if (p != k) {
       for (int c = w + 4 * lane; c < n; c += 256)   // interchange rows k and p in own columns
         if (c != k) {
-          const double a = A[(size_t)c * n + k];
+          const T a = A[(size_t)c * n + k];
           A[(size_t)c * n + k] = A[(size_t)c * n + p];
           A[(size_t)c * n + p] = a;
         }
@@ -793,32 +803,32 @@ __global__ void __launch_bounds__(256) k_vc_dense_factor(int S, Grid2 E, const d
     // LDS latency is paid once per four columns
     int c = k + 1 + ((w - k - 1) & 3);
     for (; c + 12 < n; c += 16) {
-      double u[4], a[4][VC_DENSE_SLOTS];
+      T u[4], a[4][VC_DENSE_SLOTS];
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        const double* Ac = A + (size_t)(c + 4 * h) * n;
+        const T* Ac = A + (size_t)(c + 4 * h) * n;
         u[h] = Ac[k];
 #pragma unroll
-        for (int q = 0; q < VC_DENSE_SLOTS; ++q) a[h][q] = below[q] ? Ac[lane + 64 * q] : 0.0;
+        for (int q = 0; q < VC_DENSE_SLOTS; ++q) a[h][q] = below[q] ? Ac[lane + 64 * q] : (T)0;
       }
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        double* Ac = A + (size_t)(c + 4 * h) * n;
+        T* Ac = A + (size_t)(c + 4 * h) * n;
 #pragma unroll
         for (int q = 0; q < VC_DENSE_SLOTS; ++q)
           if (below[q]) Ac[lane + 64 * q] = a[h][q] - l[q] * u[h];
       }
     }
     for (; c < n; c += 4) {
-      double* Ac = A + (size_t)c * n;
-      const double u = Ac[k];
+      T* Ac = A + (size_t)c * n;
+      const T u = Ac[k];
 #pragma unroll
       for (int q = 0; q < VC_DENSE_SLOTS; ++q)
         if (below[q]) Ac[lane + 64 * q] -= l[q] * u;
     }
     __syncthreads();
     if ((k & 3) == w) {   // U's diagonal is stored as its reciprocal, which the solve multiplies by
-      double* Akw = A + (size_t)k * n;
+      T* Akw = A + (size_t)k * n;
 #pragma unroll
       for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
         const int r = lane + 64 * q;
@@ -838,24 +848,26 @@ __global__ void __launch_bounds__(256) k_vc_dense_factor(int S, Grid2 E, const d
 // substitution column by column with the pivot row's value broadcast from its lane; each
 // chunk of VC_SOLVE_CH columns is read from LDS ahead of its dependent steps.
 constexpr int VC_SOLVE_CH = 8;
-__global__ void __launch_bounds__(64) k_vc_dense_solve(int S, Grid2 E, const double* __restrict__ LU,
-                                                       const int* __restrict__ perm, const double* __restrict__ b,
-                                                       double* __restrict__ x) {
+template <typename T>
+__global__ void __launch_bounds__(64) k_vc_dense_solve(int S, Grid2 E, const T* __restrict__ LU,
+                                                       const int* __restrict__ perm, const T* __restrict__ b,
+                                                       T* __restrict__ x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nv = (E.nx + 1) * (E.ny + 1), n = 2 * nv;
   const int s = blockIdx.x, t = threadIdx.x;
   const size_t NV = (size_t)nv * S;
-  double* A = reinterpret_cast<double*>(smem_raw);   // A[c * n + r]
-  {   // n is even, so each sample's factors start 16-byte aligned; 16 loads in flight per lane
-    const double2* src = reinterpret_cast<const double2*>(LU + (size_t)s * n * n);
-    double2* dst = reinterpret_cast<double2*>(A);
-    const int n2 = n * n / 2;
+  T* A = reinterpret_cast<T*>(smem_raw);   // A[c * n + r]
+  {   // n is even, so n^2 sizeof(T) is a multiple of 16 bytes and each sample's factors start
+      // 16-byte aligned: staged in 16-byte chunks, 16 loads in flight per lane
+    const uint4* src = reinterpret_cast<const uint4*>(LU + (size_t)s * n * n);
+    uint4* dst = reinterpret_cast<uint4*>(A);
+    const int n2 = (int)((size_t)n * n * sizeof(T) / 16);
     for (int e0 = 0; e0 < n2; e0 += 16 * 64) {
-      double2 v[16];
+      uint4 v[16];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int e = e0 + u * 64 + t;
-        v[u] = e < n2 ? src[e] : make_double2(0.0, 0.0);
+        v[u] = e < n2 ? src[e] : make_uint4(0, 0, 0, 0);
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
@@ -864,11 +876,11 @@ __global__ void __launch_bounds__(64) k_vc_dense_solve(int S, Grid2 E, const dou
       }
     }
   }
-  double y[VC_DENSE_SLOTS];
+  T y[VC_DENSE_SLOTS];
 #pragma unroll
   for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
     const int r = t + 64 * q;
-    y[q] = 0.0;
+    y[q] = 0;
     if (r < n) {
       const int g = perm[(size_t)s * n + r];
       y[q] = b[(size_t)(g & 1) * NV + (size_t)(g >> 1) * S + s];
@@ -876,19 +888,19 @@ __global__ void __launch_bounds__(64) k_vc_dense_solve(int S, Grid2 E, const dou
   }
   __builtin_amdgcn_wave_barrier();
   for (int k0 = 0; k0 < n - 1; k0 += VC_SOLVE_CH) {   // L y = P b (unit lower)
-    double a[VC_SOLVE_CH][VC_DENSE_SLOTS];
+    T a[VC_SOLVE_CH][VC_DENSE_SLOTS];
 #pragma unroll
     for (int j = 0; j < VC_SOLVE_CH; ++j)
 #pragma unroll
       for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
         const int k = k0 + j, r = t + 64 * q;
-        a[j][q] = (k < n - 1 && r > k && r < n) ? A[(size_t)k * n + r] : 0.0;
+        a[j][q] = (k < n - 1 && r > k && r < n) ? A[(size_t)k * n + r] : (T)0;
       }
 #pragma unroll
     for (int j = 0; j < VC_SOLVE_CH; ++j) {
       const int k = k0 + j;
       if (k < n - 1) {
-        const double yk = vc_bcast(vc_slot(y[0], y[1], y[2], k), k & 63);
+        const T yk = vc_bcast(vc_slot(y[0], y[1], y[2], k), k & 63);
 #pragma unroll
         for (int q = 0; q < VC_DENSE_SLOTS; ++q)
           if (t + 64 * q > k) y[q] -= a[j][q] * yk;
@@ -896,22 +908,22 @@ __global__ void __launch_bounds__(64) k_vc_dense_solve(int S, Grid2 E, const dou
     }
   }
   for (int k0 = n - 1; k0 >= 0; k0 -= VC_SOLVE_CH) {   // U x = y
-    double a[VC_SOLVE_CH][VC_DENSE_SLOTS], dk[VC_SOLVE_CH];
+    T a[VC_SOLVE_CH][VC_DENSE_SLOTS], dk[VC_SOLVE_CH];
 #pragma unroll
     for (int j = 0; j < VC_SOLVE_CH; ++j) {
       const int k = k0 - j;
-      dk[j] = k >= 0 ? A[(size_t)k * n + k] : 1.0;   // 1 / U_kk
+      dk[j] = k >= 0 ? A[(size_t)k * n + k] : (T)1;   // 1 / U_kk
 #pragma unroll
       for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
         const int r = t + 64 * q;
-        a[j][q] = (k >= 0 && r < k) ? A[(size_t)k * n + r] : 0.0;
+        a[j][q] = (k >= 0 && r < k) ? A[(size_t)k * n + r] : (T)0;
       }
     }
 #pragma unroll
     for (int j = 0; j < VC_SOLVE_CH; ++j) {
       const int k = k0 - j;
       if (k >= 0) {
-        const double xk = vc_bcast(vc_slot(y[0], y[1], y[2], k), k & 63) * dk[j];
+        const T xk = vc_bcast(vc_slot(y[0], y[1], y[2], k), k & 63) * dk[j];
 #pragma unroll
         for (int q = 0; q < VC_DENSE_SLOTS; ++q) {
           const int r = t + 64 * q;

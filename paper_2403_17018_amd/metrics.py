@@ -32,7 +32,12 @@ BYTES_PER_UNIT = {
 # 36-entry Jacobian row and b, writes x and reads the other three colours' x once (3 x 16 B
 # per swept vertex); the SpMV reads J and x and writes y; the assembly reads p, c, c_old and
 # one element's phi and K per vertex and writes R and J.
-VC_BYTES_PER_UNIT = dict(gs=288 + 16 + 16 + 48, spmv=288 + 16 + 16, assemble=16 + 8 + 16 + 16 + 288)
+# With the FP32 multigrid the Jacobian and the cycle's vectors are FP32 (the SpMV's x and y stay
+# FP64).
+VC_BYTES_PER_UNIT = {
+    64: dict(gs=288 + 16 + 16 + 48, spmv=288 + 16 + 16, assemble=16 + 8 + 16 + 16 + 288),
+    32: dict(gs=144 + 8 + 8 + 24, spmv=144 + 16 + 16, assemble=16 + 8 + 16 + 16 + 144),
+}
 
 
 def _hist(x: np.ndarray, width: float) -> dict:

@@ -102,9 +102,10 @@ def _check_run(r, ref, nx, ny, max_krylov=3.0):
     assert np.abs(q - ref["qoi"]).max() <= TOL * np.abs(ref["qoi"]).max()
 
 
-@pytest.mark.parametrize("model", ["kl", "paper"])
-def test_vc_level0_run_matches_oracle(hx, model):
-    """Level 0 of Table 2 (16 x 8 elements, 153 vertices, 94 steps), four samples."""
+@pytest.mark.parametrize("model,prec", [("kl", 64), ("paper", 64), ("kl", 32), ("paper", 32)])
+def test_vc_level0_run_matches_oracle(hx, model, prec):
+    """Level 0 of Table 2 (16 x 8 elements, 153 vertices, 94 steps), four samples; with the FP64
+    or the FP32 multigrid (the Newton fixed point does not depend on the preconditioner)."""
     import paper_2403_17018_amd as P
     kw = dict(field_model="paper", q_in_amp=0.5, recharge_omega=np.pi / 40.0, T=6016.0) if model == "paper" else {}
     prob = P.paper_problem() if model == "paper" else P.problem()
@@ -112,22 +113,23 @@ def test_vc_level0_run_matches_oracle(hx, model):
     g = P.vc_level_grid(0)
     ref = vc_oracle_batch(th, g.nx, g.ny, g.nsteps, kw)
     assert ref["conv"].all()
-    o = P.solver_opts(krylov_maxit=300)
+    o = P.solver_opts(krylov_maxit=300, mg_precision=prec)
     r = hx.vc_solve(_cu(th), g, prob, o, want_c=True, want_p=True)
     torch.cuda.synchronize()
     _check_run(r, ref, g.nx, g.ny)
 
 
-def test_vc_level1_first_steps_match_oracle(hx):
+@pytest.mark.parametrize("prec", [64, 32])
+def test_vc_level1_first_steps_match_oracle(hx, prec):
     """Level 1 of Table 2 (64 x 32 elements, 2145 vertices) over its first 16 steps of 16 s
-    (the paper's model, T = 6016 s, 376 steps), two samples."""
+    (the paper's model, T = 6016 s, 376 steps), two samples, FP64 or FP32 multigrid."""
     import paper_2403_17018_amd as P
     th = draw_theta(84, 2)
     T = 6016.0 * 16 / 376
     kw = dict(field_model="paper", q_in_amp=0.5, recharge_omega=np.pi / 40.0, T=T)
     ref = vc_oracle_batch(th, 64, 32, 16, kw)
     assert ref["conv"].all()
-    o = P.solver_opts(krylov_maxit=600)
+    o = P.solver_opts(krylov_maxit=600, mg_precision=prec)
     r = hx.vc_solve(_cu(th), P.grid(64, 32, 16), P.paper_problem(T=T), o, want_c=True, want_p=True)
     torch.cuda.synchronize()
     _check_run(r, ref, 64, 32)
@@ -151,15 +153,16 @@ def test_vc_ragged_sample_count_and_errors(hx):
         hx.vc_solve(_cu(bad), g, P.problem(), o)
 
 
-def test_vc_gauss_seidel_preconditioner_path(hx):
+@pytest.mark.parametrize("prec", [64, 32])
+def test_vc_gauss_seidel_preconditioner_path(hx, prec):
     """A grid that does not coarsen to the coarse grid (12 x 6 elements) uses the plain four-colour
     sweeps as the preconditioner: same fixed point as the oracle."""
     import paper_2403_17018_amd as P
     th = draw_theta(86, 3)
     ref = vc_oracle_batch(th, 12, 6, 20, dict(T=36000.0 * 20 / 94))
     assert ref["conv"].all()
-    r = hx.vc_solve(_cu(th), P.grid(12, 6, 20), P.problem(T=36000.0 * 20 / 94), P.solver_opts(krylov_maxit=300),
-                    want_c=True, want_p=True)
+    r = hx.vc_solve(_cu(th), P.grid(12, 6, 20), P.problem(T=36000.0 * 20 / 94),
+                    P.solver_opts(krylov_maxit=300, mg_precision=prec), want_c=True, want_p=True)
     torch.cuda.synchronize()
     _check_run(r, ref, 12, 6, max_krylov=None)   # plain sweeps: more iterations by design
 
@@ -191,15 +194,17 @@ def test_mlmc_run_vc_matches_oracle(hx):
     assert np.allclose(est["V"], m["V"], rtol=1e-10, atol=0.0)
 
 
-def test_vc_graph_replay_is_bitwise_identical(hx):
+@pytest.mark.parametrize("prec", [64, 32])
+def test_vc_graph_replay_is_bitwise_identical(hx, prec):
     """use_graphs = 1 replays one captured BiCGStab iteration per iteration: the same kernels in
     the same order, so the results equal the stream-launched run bit for bit (level 0, the
     paper's model)."""
     import paper_2403_17018_amd as P
     th = _cu(draw_theta(88, 24))
     g = P.vc_level_grid(0)
-    a = hx.vc_solve(th, g, P.paper_problem(), P.solver_opts(krylov_maxit=300, use_graphs=0), want_c=True, want_p=True)
-    b = hx.vc_solve(th, g, P.paper_problem(), P.solver_opts(krylov_maxit=300, use_graphs=1), want_c=True, want_p=True)
+    kw = dict(krylov_maxit=300, mg_precision=prec)
+    a = hx.vc_solve(th, g, P.paper_problem(), P.solver_opts(use_graphs=0, **kw), want_c=True, want_p=True)
+    b = hx.vc_solve(th, g, P.paper_problem(), P.solver_opts(use_graphs=1, **kw), want_c=True, want_p=True)
     torch.cuda.synchronize()
     assert a.nfailed == 0 and b.nfailed == 0
     assert torch.equal(a.c_T, b.c_T) and torch.equal(a.p_T, b.p_T) and torch.equal(a.qoi, b.qoi)
