@@ -64,6 +64,47 @@ __device__ __forceinline__ bool map_cell(const Map& m, int ncell, int& s, int& c
   return s < m.S && cell < ncell;
 }
 
+// SP adjacent samples per thread (the stencil kernels' wide form): a Map built by
+// make_map_wide holds SX threads of SP samples each per row, and the batch size is a
+// multiple of SP, so a thread's first sample s < S brings s + 1 .. s + SP - 1 with it.
+// Its values are held as a vector of SP lanes, loaded and stored in one access each.
+template <int SP>
+__device__ __forceinline__ bool map_cell_sp(const Map& m, int ncell, int& s, int& cell, int& sblk, int& cblk) {
+  const int bid = blockIdx.x;
+  sblk = bid % m.nsb;
+  cblk = bid / m.nsb;
+  s = SP * (sblk * m.SX + (int)threadIdx.x);
+  cell = cblk * m.CY + (int)threadIdx.y;
+  return s < m.S && cell < ncell;
+}
+
+template <typename T, int SP> struct VecOf { typedef T __attribute__((ext_vector_type(SP))) type; };
+template <typename T> struct VecOf<T, 1> { typedef T type; };
+// load SP consecutive samples of type T at p as the value type VA (converted lane by lane)
+template <int SP, typename VA, typename T>
+__device__ __forceinline__ VA ldv(const T* p) {
+  if constexpr (SP == 1) {
+    return (VA)*p;
+  } else {
+    const typename VecOf<T, SP>::type v = *(const typename VecOf<T, SP>::type*)p;
+    return __builtin_convertvector(v, VA);
+  }
+}
+template <int SP, typename VA, typename T>
+__device__ __forceinline__ VA ldv_nt(const T* p) {
+  if constexpr (SP == 1) {
+    return (VA)__builtin_nontemporal_load(p);
+  } else {
+    const typename VecOf<T, SP>::type v = __builtin_nontemporal_load((const typename VecOf<T, SP>::type*)p);
+    return __builtin_convertvector(v, VA);
+  }
+}
+template <int SP, typename T, typename V>
+__device__ __forceinline__ void stv(T* p, V v) {
+  if constexpr (SP == 1) *p = v;
+  else *(typename VecOf<T, SP>::type*)p = v;
+}
+
 // --------------------------------------------------------------------------
 // Block reduction over threadIdx.y for each threadIdx.x (fixed order).
 template <int NV>
@@ -377,7 +418,8 @@ __global__ void __launch_bounds__(1024) k_assemble(Map m, Grid2 G, Phys P, const
 // TR: (A^T x)_P, gathering the transposed blocks A_{Q,P} stored in the neighbours'
 // rows (Q east of P holds A_{Q,P} in its west slot, and so on), so no atomics.
 // xv(q, dir) returns the 2-vector x at row index q (dir: 0 centre, 1 W, 2 E, 3 S, 4 N).
-template <typename T, typename TA, bool TR, typename XV>
+// SP > 1: the row of SP adjacent samples at once, TA a vector of SP lanes.
+template <typename T, typename TA, bool TR, int SP = 1, typename XV>
 __device__ __forceinline__ void apply_row_f(const T* __restrict__ J, XV&& xv, size_t N, size_t id, int i, int j,
                                             int nx, int ny, int S, TA& y0, TA& y1, bool skip_centre) {
   TA a0 = 0, a1 = 0;
@@ -386,10 +428,10 @@ __device__ __forceinline__ void apply_row_f(const T* __restrict__ J, XV&& xv, si
     xv(xq, dir, x0, x1);
     // each Jacobian entry is read once per kernel: non-temporal loads keep the cache for
     // the neighbours' x, which other threads read again
-    const TA b0 = (TA)__builtin_nontemporal_load(J + (slot * 4 + 0) * N + q);
-    const TA b1 = (TA)__builtin_nontemporal_load(J + (slot * 4 + 1) * N + q);
-    const TA b2 = (TA)__builtin_nontemporal_load(J + (slot * 4 + 2) * N + q);
-    const TA b3 = (TA)__builtin_nontemporal_load(J + (slot * 4 + 3) * N + q);
+    const TA b0 = ldv_nt<SP, TA>(J + (slot * 4 + 0) * N + q);
+    const TA b1 = ldv_nt<SP, TA>(J + (slot * 4 + 1) * N + q);
+    const TA b2 = ldv_nt<SP, TA>(J + (slot * 4 + 2) * N + q);
+    const TA b3 = ldv_nt<SP, TA>(J + (slot * 4 + 3) * N + q);
     if (TR) {
       a0 += b0 * x0 + b2 * x1;
       a1 += b1 * x0 + b3 * x1;
@@ -408,22 +450,22 @@ __device__ __forceinline__ void apply_row_f(const T* __restrict__ J, XV&& xv, si
   y1 = a1;
 }
 
-template <typename T, typename TA, bool TR = false>
+template <typename T, typename TA, bool TR = false, int SP = 1>
 __device__ __forceinline__ void apply_row(const T* __restrict__ J, const T* __restrict__ x, size_t N, size_t id, int i,
                                           int j, int nx, int ny, int S, TA& y0, TA& y1, bool skip_centre) {
   auto xv = [&](size_t q, int, TA& x0, TA& x1) {
-    x0 = x[q];
-    x1 = x[N + q];
+    x0 = ldv<SP, TA>(x + q);
+    x1 = ldv<SP, TA>(x + N + q);
   };
-  apply_row_f<T, TA, TR>(J, xv, N, id, i, j, nx, ny, S, y0, y1, skip_centre);
+  apply_row_f<T, TA, TR, SP>(J, xv, N, id, i, j, nx, ny, S, y0, y1, skip_centre);
 }
 
 // Bilinear cell-centred prolongation of the coarse correction e to fine cell (i, j):
 // weights 9/16, 3/16, 3/16, 1/16, a missing neighbour at the boundary replaced by the
 // cell itself.
-template <typename T>
+template <typename T, int SP = 1, typename V = T>
 __device__ __forceinline__ void prolong_at(const T* __restrict__ e, size_t Nc, int S, int s, int i, int j, Grid2 Gc,
-                                           T& v0, T& v1) {
+                                           V& v0, V& v1) {
   const int I = i >> 1, Jc = j >> 1;
   int I2 = I + ((i & 1) ? 1 : -1), J2 = Jc + ((j & 1) ? 1 : -1);
   I2 = I2 < 0 ? 0 : (I2 >= Gc.nx ? Gc.nx - 1 : I2);
@@ -431,8 +473,9 @@ __device__ __forceinline__ void prolong_at(const T* __restrict__ e, size_t Nc, i
   const size_t c00 = ((size_t)Jc * Gc.nx + I) * S + s, c10 = ((size_t)Jc * Gc.nx + I2) * S + s;
   const size_t c01 = ((size_t)J2 * Gc.nx + I) * S + s, c11 = ((size_t)J2 * Gc.nx + I2) * S + s;
   const T w9 = (T)0.5625, w3 = (T)0.1875, w1 = (T)0.0625;
-  v0 = w9 * e[c00] + w3 * e[c10] + w3 * e[c01] + w1 * e[c11];
-  v1 = w9 * e[Nc + c00] + w3 * e[Nc + c10] + w3 * e[Nc + c01] + w1 * e[Nc + c11];
+  v0 = w9 * ldv<SP, V>(e + c00) + w3 * ldv<SP, V>(e + c10) + w3 * ldv<SP, V>(e + c01) + w1 * ldv<SP, V>(e + c11);
+  v1 = w9 * ldv<SP, V>(e + Nc + c00) + w3 * ldv<SP, V>(e + Nc + c10) + w3 * ldv<SP, V>(e + Nc + c01) +
+       w1 * ldv<SP, V>(e + Nc + c11);
 }
 
 // One colour of a red-black 2x2-block Gauss-Seidel sweep: x_P = D_P^{-1}(b_P - sum_nb A_nb x_nb)
@@ -446,58 +489,62 @@ __device__ __forceinline__ void prolong_at(const T* __restrict__ e, size_t Nc, i
 // single pre-smoothing sweep from x = 0: the other colour's x is D^{-1} b there, and is
 // formed on the fly from the neighbours' diagonal blocks and right-hand sides instead of
 // being stored by a first pass (the next value of that colour is computed without it).
-template <typename T, bool TR = false, int MODE = 0>
+// SP > 1: SP adjacent samples per thread (a Map from make_map_wide), the same arithmetic
+// lane by lane.
+template <typename T, bool TR = false, int MODE = 0, int SP = 1>
 __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, Grid2 Gc, int colour, const T* __restrict__ J,
                                                    const T* __restrict__ b, T* __restrict__ x,
                                                    const T* __restrict__ e) {
+  typedef typename VecOf<T, SP>::type V;
   int s, mc, sb, cb;
   const int half = (G.nx + 1) >> 1;
-  if (!map_cell(m, G.ny * half, s, mc, sb, cb)) return;
+  if (!map_cell_sp<SP>(m, G.ny * half, s, mc, sb, cb)) return;
   const int j = mc / half;
   const int i = 2 * (mc - j * half) + ((j + colour) & 1);
   if (i >= G.nx) return;
   const int S = m.S;
   const size_t N = (size_t)G.ncell * S;
   const size_t id = ((size_t)j * G.nx + i) * S + s;
-  T r0 = __builtin_nontemporal_load(b + id), r1 = __builtin_nontemporal_load(b + N + id);
+  V r0 = ldv_nt<SP, V>(b + id), r1 = ldv_nt<SP, V>(b + N + id);
   if (MODE == 0) {
-    T a0, a1;
-    apply_row<T, T, TR>(J, x, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
+    V a0, a1;
+    apply_row<T, V, TR, SP>(J, x, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
     r0 -= a0;
     r1 -= a1;
   } else if (MODE == 2) {
     const size_t Nc = (size_t)Gc.ncell * S;
-    auto xv = [&](size_t q, int dir, T& x0, T& x1) {
+    auto xv = [&](size_t q, int dir, V& x0, V& x1) {
       const int qi = i + (dir == 1 ? -1 : dir == 2 ? 1 : 0), qj = j + (dir == 3 ? -1 : dir == 4 ? 1 : 0);
-      T v0, v1;
-      prolong_at<T>(e, Nc, S, s, qi, qj, Gc, v0, v1);
-      x0 = x[q] + v0;
-      x1 = x[N + q] + v1;
+      V v0, v1;
+      prolong_at<T, SP, V>(e, Nc, S, s, qi, qj, Gc, v0, v1);
+      x0 = ldv<SP, V>(x + q) + v0;
+      x1 = ldv<SP, V>(x + N + q) + v1;
     };
-    T a0, a1;
-    apply_row_f<T, T, TR>(J, xv, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
+    V a0, a1;
+    apply_row_f<T, V, TR, SP>(J, xv, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
     r0 -= a0;
     r1 -= a1;
   } else if (MODE == 3) {
-    auto xv = [&](size_t q, int, T& x0, T& x1) {
-      const T q00 = J[q], q11 = J[3 * N + q];
-      const T q01 = TR ? J[2 * N + q] : J[N + q], q10 = TR ? J[N + q] : J[2 * N + q];
-      const T c0 = b[q], c1 = b[N + q];
-      const T qdet = q00 * q11 - q01 * q10;
+    auto xv = [&](size_t q, int, V& x0, V& x1) {
+      const V q00 = ldv<SP, V>(J + q), q11 = ldv<SP, V>(J + 3 * N + q);
+      const V q01 = TR ? ldv<SP, V>(J + 2 * N + q) : ldv<SP, V>(J + N + q);
+      const V q10 = TR ? ldv<SP, V>(J + N + q) : ldv<SP, V>(J + 2 * N + q);
+      const V c0 = ldv<SP, V>(b + q), c1 = ldv<SP, V>(b + N + q);
+      const V qdet = q00 * q11 - q01 * q10;
       x0 = (q11 * c0 - q01 * c1) / qdet;
       x1 = (q00 * c1 - q10 * c0) / qdet;
     };
-    T a0, a1;
-    apply_row_f<T, T, TR>(J, xv, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
+    V a0, a1;
+    apply_row_f<T, V, TR, SP>(J, xv, N, id, i, j, G.nx, G.ny, S, a0, a1, true);
     r0 -= a0;
     r1 -= a1;
   }
-  const T d00 = __builtin_nontemporal_load(J + id), d11 = __builtin_nontemporal_load(J + 3 * N + id);
-  const T j1 = __builtin_nontemporal_load(J + N + id), j2 = __builtin_nontemporal_load(J + 2 * N + id);
-  const T d01 = TR ? j2 : j1, d10 = TR ? j1 : j2;
-  const T det = d00 * d11 - d01 * d10;
-  x[id] = (d11 * r0 - d01 * r1) / det;
-  x[N + id] = (d00 * r1 - d10 * r0) / det;
+  const V d00 = ldv_nt<SP, V>(J + id), d11 = ldv_nt<SP, V>(J + 3 * N + id);
+  const V j1 = ldv_nt<SP, V>(J + N + id), j2 = ldv_nt<SP, V>(J + 2 * N + id);
+  const V d01 = TR ? j2 : j1, d10 = TR ? j1 : j2;
+  const V det = d00 * d11 - d01 * d10;
+  stv<SP>(x + id, (d11 * r0 - d01 * r1) / det);
+  stv<SP>(x + N + id, (d00 * r1 - d10 * r0) / det);
 }
 
 // Fused residual and restriction: b_H(I,J) = sum over the 2x2 children of (b - A x).
@@ -505,52 +552,54 @@ __global__ void __launch_bounds__(256) k_gs_colour(Map m, Grid2 G, Grid2 Gc, int
 // on black cells, so only the two red children are evaluated.  red_only == 2: in
 // addition the red cells hold x = D^{-1} b (one pre-smoothing sweep from x = 0, its
 // red half never stored), so their residual is minus the off-diagonal part alone.
-template <typename T, bool TR = false>
+template <typename T, bool TR = false, int SP = 1>
 __global__ void __launch_bounds__(256) k_residual_restrict(Map m, Grid2 Gf, Grid2 Gc, int red_only,
                                                            const T* __restrict__ J, const T* __restrict__ b,
                                                            const T* __restrict__ x, T* __restrict__ bH) {
+  typedef typename VecOf<T, SP>::type V;
   int s, cc, sb, cb;
-  if (!map_cell(m, Gc.ncell, s, cc, sb, cb)) return;
+  if (!map_cell_sp<SP>(m, Gc.ncell, s, cc, sb, cb)) return;
   const int S = m.S;
   const size_t Nf = (size_t)Gf.ncell * S, Nc = (size_t)Gc.ncell * S;
   const int Jc = cc / Gc.nx, Ic = cc - Jc * Gc.nx;
-  T s0 = 0, s1 = 0;
+  V s0 = 0, s1 = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int i = 2 * Ic + (q & 1), j = 2 * Jc + (q >> 1);
     if (red_only && ((i + j) & 1)) continue;
     const size_t id = ((size_t)j * Gf.nx + i) * S + s;
-    T a0, a1;
+    V a0, a1;
     if (red_only == 2) {
-      apply_row<T, T, TR>(J, x, Nf, id, i, j, Gf.nx, Gf.ny, S, a0, a1, true);
+      apply_row<T, V, TR, SP>(J, x, Nf, id, i, j, Gf.nx, Gf.ny, S, a0, a1, true);
       s0 -= a0;
       s1 -= a1;
     } else {
-      apply_row<T, T, TR>(J, x, Nf, id, i, j, Gf.nx, Gf.ny, S, a0, a1, false);
-      s0 += b[id] - a0;
-      s1 += b[Nf + id] - a1;
+      apply_row<T, V, TR, SP>(J, x, Nf, id, i, j, Gf.nx, Gf.ny, S, a0, a1, false);
+      s0 += ldv<SP, V>(b + id) - a0;
+      s1 += ldv<SP, V>(b + Nf + id) - a1;
     }
   }
   const size_t idc = (size_t)cc * S + s;
-  bH[idc] = s0;
-  bH[Nc + idc] = s1;
+  stv<SP>(bH + idc, s0);
+  stv<SP>(bH + Nc + idc, s1);
 }
 
 // Prolongation and correction x += P e (used only when there is no post-smoothing pass
 // to fuse it into).
-template <typename T>
+template <typename T, int SP = 1>
 __global__ void __launch_bounds__(256) k_prolong_correct(Map m, Grid2 Gf, Grid2 Gc, const T* __restrict__ e,
                                                          T* __restrict__ x) {
+  typedef typename VecOf<T, SP>::type V;
   int s, cell, sb, cb;
-  if (!map_cell(m, Gf.ncell, s, cell, sb, cb)) return;
+  if (!map_cell_sp<SP>(m, Gf.ncell, s, cell, sb, cb)) return;
   const int S = m.S;
   const size_t Nf = (size_t)Gf.ncell * S, Nc = (size_t)Gc.ncell * S;
   const int j = cell / Gf.nx, i = cell - j * Gf.nx;
   const size_t id = (size_t)cell * S + s;
-  T v0, v1;
-  prolong_at<T>(e, Nc, S, s, i, j, Gc, v0, v1);
-  x[id] += v0;
-  x[Nf + id] += v1;
+  V v0, v1;
+  prolong_at<T, SP, V>(e, Nc, S, s, i, j, Gc, v0, v1);
+  stv<SP>(x + id, ldv<SP, V>(x + id) + v0);
+  stv<SP>(x + Nf + id, ldv<SP, V>(x + Nf + id) + v1);
 }
 
 // Restriction of state and coefficients for rediscretised coarse Jacobians:

@@ -24,6 +24,7 @@
 #include <thread>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
@@ -199,6 +200,17 @@ static Map make_map(int S, int ncell, int red_blocks, int sample_block = 0) {
   return m;
 }
 
+// The multigrid stencil kernels' wide form: SP adjacent samples per thread, one 16-byte
+// access per value (SP = 2 in FP64, 4 in FP32), used when the batch size is a multiple of
+// SP and fills rows of 64 SP samples; the thread geometry is that of a batch of S / SP,
+// the sample count stays S.  Returns 1 (no wide form) otherwise.
+static int wide_samples(int S, int sp) { return (S % sp == 0 && S >= 64 * sp) ? sp : 1; }
+static Map make_map_wide(int S, int ncell, int sp, int sample_block) {
+  Map m = make_map(S / sp, ncell, 0, sample_block);
+  m.S = S;
+  return m;
+}
+
 static dim3 grid_cells(const Map& m, int ncell) {
   const long long nb = (long long)m.nsb * ((ncell + m.CY - 1) / m.CY);
   return dim3((unsigned)nb);
@@ -284,6 +296,8 @@ struct Plan {
                            // partial pivoting
   size_t N;
   Map m;
+  Map mw2, mw4;            // the stencil kernels' wide forms (make_map_wide): 2 and 4 samples
+  int sp2 = 1, sp4 = 1;    // per thread, where wide_samples allows them (else 1)
   Grid2 G;
   std::vector<std::unique_ptr<MGLevel>> lv;   // lv[0] = fine grid
   int nlev;
@@ -563,6 +577,13 @@ static void check_gb_size(int nxc, int nyc, int prec) {
          nyc);
 }
 
+static void plan_set_wide(Plan& Q, int sample_block) {
+  Q.sp2 = wide_samples(Q.S, 2);
+  Q.sp4 = wide_samples(Q.S, 4);
+  Q.mw2 = make_map_wide(Q.S, Q.nx * Q.ny, Q.sp2, sample_block);
+  Q.mw4 = make_map_wide(Q.S, Q.nx * Q.ny, Q.sp4, sample_block);
+}
+
 static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver_opts& o) {
   const int cnx = std::min(o.coarse_nx, nx), cny = std::min(o.coarse_ny, ny);
   auto P = std::make_unique<Plan>();
@@ -576,6 +597,7 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int S, const henry_solver
   P->G = Grid2{nx, ny, nx * ny};
   P->N = (size_t)nx * ny * S;
   P->m = make_map(S, nx * ny, o.red_blocks, o.sample_block);
+  plan_set_wide(*P, o.sample_block);
   // hierarchy: halve while above the coarse size and even
   int gx = nx, gy = ny;
   while (true) {
@@ -675,6 +697,7 @@ static void plan_set_samples(Plan& Q, int Sa, int red_blocks, int sample_block) 
   Q.S = Sa;
   Q.N = (size_t)Q.nx * Q.ny * Sa;
   Q.m = make_map(Sa, Q.nx * Q.ny, red_blocks, sample_block);
+  plan_set_wide(Q, sample_block);
   if ((size_t)NSERIES * Q.m.ncb * Sa * 8 > Q.part.bytes) fail(HENRY_EDEVICE, "internal: compact plan undersized");
   Q.drop_graphs();
 }
@@ -816,6 +839,16 @@ struct Solver {
   void vcycle(int k, const T* b, T* x, bool zero = true) {
     const Map& m = P.m;
     MGLevel& L = *P.lv[k];
+    // the stencil kernels' launch width: 4 samples per thread in FP32, 2 in FP64, where the
+    // batch allows it (16-byte accesses); f(integral_constant<int, SP>)
+    auto wide = [&](auto&& f) {
+      if constexpr (sizeof(T) == 4) {
+        if (P.sp4 == 4) return f(std::integral_constant<int, 4>{});
+      }
+      if (P.sp2 == 2) return f(std::integral_constant<int, 2>{});
+      return f(std::integral_constant<int, 1>{});
+    };
+    auto wide_map = [&](int sp) -> const Map& { return sp == 4 ? P.mw4 : sp == 2 ? P.mw2 : m; };
     if (k == P.nlev - 1 && P.csolver == 1) {
       timed(ctx, st, HENRY_PROF_DENSE_SOLVE, (long long)P.S, [&] {
         launch_timed((k_dense_solve<T, TR>), dim3(P.S), dim3(DENSE_SOLVE_THREADS), dense_solve_lds<T>(2 * L.ncell), st,
@@ -844,25 +877,25 @@ struct Solver {
     }
     const T* J = level_J<T>(k);
     const int half = (L.nx + 1) / 2;
-    const dim3 gg = grid_cells(m, L.ny * half);
     // fine-grid smoother passes that read neighbours are timed as one class
     const long long half_units = (long long)L.ny * half * P.S;
     MGLevel& C = *P.lv[k + 1];
+    auto gs_launch = [&](auto sp_tag, int colour, int mode) {
+      constexpr int SP = decltype(sp_tag)::value;
+      const Map& mg = wide_map(SP);
+      const dim3 gg = grid_cells(mg, L.ny * half), bb = block_of(mg);
+      if (mode == 1)
+        launch_timed((k_gs_colour<T, TR, 1, SP>), gg, bb, 0, st, mg, L.G, C.G, colour, J, b, x, (const T*)nullptr);
+      else if (mode == 2)
+        launch_timed((k_gs_colour<T, TR, 2, SP>), gg, bb, 0, st, mg, L.G, C.G, colour, J, b, x,
+                     (const T*)C.x.as<T>());
+      else if (mode == 3)
+        launch_timed((k_gs_colour<T, TR, 3, SP>), gg, bb, 0, st, mg, L.G, C.G, colour, J, b, x, (const T*)nullptr);
+      else
+        launch_timed((k_gs_colour<T, TR, 0, SP>), gg, bb, 0, st, mg, L.G, C.G, colour, J, b, x, (const T*)nullptr);
+    };
     auto gs = [&](int colour, int mode) {
-      auto f = [&] {
-        if (mode == 1)
-          launch_timed((k_gs_colour<T, TR, 1>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
-                             (const T*)nullptr);
-        else if (mode == 2)
-          launch_timed((k_gs_colour<T, TR, 2>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
-                             (const T*)C.x.as<T>());
-        else if (mode == 3)
-          launch_timed((k_gs_colour<T, TR, 3>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
-                             (const T*)nullptr);
-        else
-          launch_timed((k_gs_colour<T, TR, 0>), gg, block_of(m), 0, st, m, L.G, C.G, colour, J, b, x,
-                             (const T*)nullptr);
-      };
+      auto f = [&] { wide([&](auto sp_tag) { gs_launch(sp_tag, colour, mode); }); };
       if (k == 0 && mode == 0) timed(ctx, st, HENRY_PROF_GS, half_units, f);
       else f();
     };
@@ -879,8 +912,12 @@ struct Solver {
       }
     }
     auto rr = [&] {
-      launch_timed((k_residual_restrict<T, TR>), grid_cells(m, C.ncell), block_of(m), 0, st, m, L.G, C.G,
-                         implicit_red ? 2 : 1, J, b, x, C.b.as<T>());
+      wide([&](auto sp_tag) {
+        constexpr int SP = decltype(sp_tag)::value;
+        const Map& mg = wide_map(SP);
+        launch_timed((k_residual_restrict<T, TR, SP>), grid_cells(mg, C.ncell), block_of(mg), 0, st, mg, L.G, C.G,
+                     implicit_red ? 2 : 1, J, b, x, C.b.as<T>());
+      });
     };
     if (k == 0) timed(ctx, st, HENRY_PROF_RESTRICT, (long long)L.ncell * P.S, rr);
     else rr();
@@ -890,8 +927,12 @@ struct Solver {
       // separate prolongation and correction of every cell, then plain post-smoothing passes
       // (the red pass overwrites red x from the black neighbours alone)
       auto pc = [&] {
-        launch_timed((k_prolong_correct<T>), grid_cells(m, L.ncell), block_of(m), 0, st, m, L.G, C.G,
-                           C.x.as<T>(), x);
+        wide([&](auto sp_tag) {
+          constexpr int SP = decltype(sp_tag)::value;
+          const Map& mg = wide_map(SP);
+          launch_timed((k_prolong_correct<T, SP>), grid_cells(mg, L.ncell), block_of(mg), 0, st, mg, L.G, C.G,
+                       C.x.as<T>(), x);
+        });
       };
       if (k == 0) timed(ctx, st, HENRY_PROF_PROLONG, (long long)L.ncell * P.S, pc);
       else pc();

@@ -41,6 +41,33 @@ def test_batch_sizes_around_a_wavefront(hx, S, pick):
     assert np.abs(r.qoi.cpu().numpy()[pick] - ref["qoi"]).max() <= TOL * np.abs(ref["qoi"]).max()
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+def test_wide_stencil_kernels_match_one_sample_per_thread(hx, prec):
+    """A batch of 256 runs the multigrid's smoother, restriction and prolongation with
+    several adjacent samples per thread (2 in FP64, 4 in FP32); the same samples in a batch
+    of 255 (not a multiple of the width) run one sample per thread.  Samples are
+    independent, so each must come out the same to rounding, and both must match the
+    oracle."""
+    import paper_2403_17018_amd as P
+    th = draw_theta(10, 256, level=1)
+    g = P.grid(64, 32, 16)
+    kw = dict(T=6000.0)
+    o = P.solver_opts(mg_precision=prec, fuse_prolong=0)
+    o2 = P.solver_opts(mg_precision=prec)
+    for opts in (o, o2):
+        a = hx.solve(_cuda(th), g, P.problem(**kw), opts, want_c=True, want_p=True)
+        b = hx.solve(_cuda(th[:255]), g, P.problem(**kw), opts, want_c=True, want_p=True)
+        assert a.nfailed == 0 and b.nfailed == 0
+        for fa, fb in ((a.c_T, b.c_T), (a.p_T, b.p_T)):
+            fa = fa.permute(2, 0, 1).cpu().numpy()[:255]
+            fb = fb.permute(2, 0, 1).cpu().numpy()
+            assert rel_inf(fa, fb).max() <= 1e-12
+        pick = [0, 127, 254]
+        ref = oracle_batch(th[pick], g.nx, g.ny, g.nsteps, kw)
+        c = a.c_T.permute(2, 0, 1).cpu().numpy()[pick]
+        assert rel_inf(c, ref["c"]).max() <= TOL
+
+
 def test_odd_rows_single_level(hx):
     """34 x 17 cells: 17 rows cannot be halved, so the whole grid is the banded-LU level."""
     import paper_2403_17018_amd as P
