@@ -202,11 +202,26 @@ static Map make_map(int S, int ncell, int red_blocks, int sample_block = 0) {
 
 // The multigrid stencil kernels' wide form: SP adjacent samples per thread, one 16-byte
 // access per value (SP = 2 in FP64, 4 in FP32), used when the batch size is a multiple of
-// SP and fills rows of 64 SP samples; the thread geometry is that of a batch of S / SP,
-// the sample count stays S.  Returns 1 (no wide form) otherwise.
-static int wide_samples(int S, int sp) { return (S % sp == 0 && S >= 64 * sp) ? sp : 1; }
+// SP, at least 64 SP, and some row width of SX threads (the sample block or a half or
+// quarter of it) leaves no more samples idle in the last row than one sample per thread
+// does; the thread geometry is that of a batch of S / SP with that SX, the sample count
+// stays S.  wide_block returns that SX, 0 where there is no wide form.
+static int wide_block(int S, int sp, int sample_block) {
+  const int sb = sample_block > 0 ? sample_block : 64;
+  if (S % sp || S < 64 * sp) return 0;
+  const int sx1 = S <= sb ? S : sb;
+  const int idle1 = (S + sx1 - 1) / sx1 * sx1 - S;
+  for (int sx = sb; sx >= 16 && sx >= sb / 4; sx /= 2) {
+    const int row = sp * sx;
+    if ((S + row - 1) / row * row - S <= idle1) return sx;
+  }
+  return 0;
+}
+static int wide_samples(int S, int sp, int sample_block) { return wide_block(S, sp, sample_block) ? sp : 1; }
 static Map make_map_wide(int S, int ncell, int sp, int sample_block) {
-  Map m = make_map(S / sp, ncell, 0, sample_block);
+  const int sx = wide_block(S, sp, sample_block);
+  if (!sx) return make_map(S, ncell, 0, sample_block);
+  Map m = make_map(S / sp, ncell, 0, sx);
   m.S = S;
   return m;
 }
@@ -578,8 +593,8 @@ static void check_gb_size(int nxc, int nyc, int prec) {
 }
 
 static void plan_set_wide(Plan& Q, int sample_block) {
-  Q.sp2 = wide_samples(Q.S, 2);
-  Q.sp4 = wide_samples(Q.S, 4);
+  Q.sp2 = wide_samples(Q.S, 2, sample_block);
+  Q.sp4 = wide_samples(Q.S, 4, sample_block);
   Q.mw2 = make_map_wide(Q.S, Q.nx * Q.ny, Q.sp2, sample_block);
   Q.mw4 = make_map_wide(Q.S, Q.nx * Q.ny, Q.sp4, sample_block);
 }
