@@ -551,7 +551,8 @@ def main():
     ap.add_argument("--eps", type=float, default=0.002, help="relative accuracy of the adaptive workload")
     ap.add_argument("--level", type=int, default=None, help="level of the qmc workload (default 3)")
     ap.add_argument("--graphs", type=int, default=None, help="capture BiCGStab iterations in hipGraphs (c4 default 1)")
-    ap.add_argument("--step-graphs", type=int, default=0, help="replay each step's first Newton iteration from a graph (c4)")
+    ap.add_argument("--step-graphs", type=int, default=1,
+                    help="c4: replay each settled step's first Newton iteration from a graph (the library default)")
     ap.add_argument("--ragged-threads", type=int, default=0, help="c4: 1 runs the grids one after another on one thread")
     ap.add_argument("--precision", type=int, default=None, help="multigrid precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
