@@ -159,9 +159,13 @@ typedef struct {
   int ragged_threads;         /* ragged calls with several grids: 0: one host thread (and stream) per
                                  grid, run concurrently [0]; 1: the grids one after another from the
                                  calling thread (for tools that cannot follow several threads) */
-  int sample_block;           /* samples per thread-block row (the kernels' tile): 0: min(S, 64), a
+  int sample_block;           /* threads per thread-block row (the kernels' tile): 0: min(S, 64), a
                                  wavefront reads 64 samples of one cell [0]; 16 or 32: a wavefront
-                                 covers 4 or 2 neighbouring cells of 16 or 32 samples */
+                                 covers 4 or 2 neighbouring cells of 16 or 32 samples.  The
+                                 multigrid's smoother, restriction and prolongation take 2 (FP64)
+                                 or 4 (FP32) adjacent samples per thread when S is a multiple of
+                                 that width, at least 64 times it, and a row of this many threads
+                                 (or a half or quarter of it) leaves no more samples idle */
   int fuse_prolong;           /* 1: the coarse-grid correction is prolonged inside the first
                                  post-smoothing pass and never stored [1]; 0: a separate prolongation
                                  and correction of every cell, then plain passes */
