@@ -204,18 +204,29 @@ __global__ void __launch_bounds__(256) k_vc_spmv(Map m, Grid2 E, const TJ* __res
   const int j = v / nvx, i = v - j * nvx;
   const size_t id = (size_t)v * S + s;
   double y0 = 0.0, y1 = 0.0;
+  // all nine blocks' loads first, as in k_vc_gs (absent neighbours read the vertex's own
+  // data and are selected away)
+  double xa[9], xb[9];
+  TJ jb[9][4];
+  bool use[9];
 #pragma unroll
-  for (int dj = -1; dj <= 1; ++dj)
+  for (int bl = 0; bl < 9; ++bl) {
+    const int qi = i + bl % 3 - 1, qj = j + bl / 3 - 1;
+    use[bl] = qi >= 0 && qi < nvx && qj >= 0 && qj < nvy;
+    const size_t q = use[bl] ? ((size_t)qj * nvx + qi) * S + s : id;
+    const size_t jo = (size_t)(use[bl] ? bl * 4 : 16) * NV + id;
+    xa[bl] = x[q];
+    xb[bl] = x[NV + q];
 #pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      const int qi = i + di, qj = j + dj;
-      if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
-      const int bl = (dj + 1) * 3 + (di + 1);
-      const size_t q = ((size_t)qj * nvx + qi) * S + s;
-      const double x0 = x[q], x1 = x[NV + q];
-      y0 += (double)J[(size_t)(bl * 4 + 0) * NV + id] * x0 + (double)J[(size_t)(bl * 4 + 1) * NV + id] * x1;
-      y1 += (double)J[(size_t)(bl * 4 + 2) * NV + id] * x0 + (double)J[(size_t)(bl * 4 + 3) * NV + id] * x1;
-    }
+    for (int e = 0; e < 4; ++e) jb[bl][e] = J[jo + (size_t)e * NV];
+  }
+#pragma unroll
+  for (int bl = 0; bl < 9; ++bl) {
+    const double a0 = (double)jb[bl][0] * xa[bl] + (double)jb[bl][1] * xb[bl];
+    const double a1 = (double)jb[bl][2] * xa[bl] + (double)jb[bl][3] * xb[bl];
+    y0 += use[bl] ? a0 : 0.0;
+    y1 += use[bl] ? a1 : 0.0;
+  }
   y[id] = y0;
   y[NV + id] = y1;
 }
@@ -244,20 +255,32 @@ __global__ void __launch_bounds__(256) k_vc_gs(Map m, Grid2 E, int colour, const
   const size_t NV = (size_t)nv * S;
   const size_t id = (size_t)v * S + s;
   T r0 = b[id], r1 = b[NV + id];
+  // Every neighbour's loads are issued before any is used: a block that is absent (outside
+  // the grid) or still zero (FIRST) reads the vertex's own x and diagonal block instead,
+  // addresses that are valid and cached, and its term is selected away (a select, so
+  // whatever those values hold cannot leak in).  With a few wavefronts per SIMD, the nine
+  // blocks' loads in flight together rather than one block's at a time decide the time.
+  T xa[8], xb[8], jb[8][4];
+  bool use[8];
 #pragma unroll
-  for (int dj = -1; dj <= 1; ++dj)
+  for (int n = 0; n < 8; ++n) {
+    const int bl = n < 4 ? n : n + 1, di = bl % 3 - 1, dj = bl / 3 - 1;
+    const int qi = i + di, qj = j + dj;
+    use[n] = qi >= 0 && qi < nvx && qj >= 0 && qj < nvy &&
+             !(FIRST && ((ci ^ (di & 1)) + 2 * (cj ^ (dj & 1))) > colour);
+    const size_t q = use[n] ? ((size_t)qj * nvx + qi) * S + s : id;
+    const size_t jo = (size_t)(use[n] ? bl * 4 : 16) * NV + id;
+    xa[n] = x[q];
+    xb[n] = x[NV + q];
 #pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      if (di == 0 && dj == 0) continue;
-      if (FIRST && ((ci ^ (di & 1)) + 2 * (cj ^ (dj & 1))) > colour) continue;   // still zero
-      const int qi = i + di, qj = j + dj;
-      if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
-      const int bl = (dj + 1) * 3 + (di + 1);
-      const size_t q = ((size_t)qj * nvx + qi) * S + s;
-      const T x0 = x[q], x1 = x[NV + q];
-      r0 -= J[(size_t)(bl * 4 + 0) * NV + id] * x0 + J[(size_t)(bl * 4 + 1) * NV + id] * x1;
-      r1 -= J[(size_t)(bl * 4 + 2) * NV + id] * x0 + J[(size_t)(bl * 4 + 3) * NV + id] * x1;
-    }
+    for (int e = 0; e < 4; ++e) jb[n][e] = J[jo + (size_t)e * NV];
+  }
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    const T a0 = jb[n][0] * xa[n] + jb[n][1] * xb[n], a1 = jb[n][2] * xa[n] + jb[n][3] * xb[n];
+    r0 -= use[n] ? a0 : (T)0;
+    r1 -= use[n] ? a1 : (T)0;
+  }
   const T d00 = J[(size_t)16 * NV + id], d01 = J[(size_t)17 * NV + id];
   const T d10 = J[(size_t)18 * NV + id], d11 = J[(size_t)19 * NV + id];
   const T det = d00 * d11 - d01 * d10;
@@ -586,18 +609,27 @@ __global__ void __launch_bounds__(256) k_vc_resid(Map m, Grid2 E, int zero_colou
     return;
   }
   T y0 = b[id], y1 = b[NV + id];
+  // all nine blocks' loads first, as in k_vc_gs (absent neighbours read the vertex's own
+  // data and are selected away)
+  T xa[9], xb[9], jb[9][4];
+  bool use[9];
 #pragma unroll
-  for (int dj = -1; dj <= 1; ++dj)
+  for (int bl = 0; bl < 9; ++bl) {
+    const int qi = i + bl % 3 - 1, qj = j + bl / 3 - 1;
+    use[bl] = qi >= 0 && qi < nvx && qj >= 0 && qj < nvy;
+    const size_t q = use[bl] ? ((size_t)qj * nvx + qi) * S + s : id;
+    const size_t jo = (size_t)(use[bl] ? bl * 4 : 16) * NV + id;
+    xa[bl] = x[q];
+    xb[bl] = x[NV + q];
 #pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      const int qi = i + di, qj = j + dj;
-      if (qi < 0 || qi >= nvx || qj < 0 || qj >= nvy) continue;
-      const int bl = (dj + 1) * 3 + (di + 1);
-      const size_t q = ((size_t)qj * nvx + qi) * S + s;
-      const T x0 = x[q], x1 = x[NV + q];
-      y0 -= J[(size_t)(bl * 4 + 0) * NV + id] * x0 + J[(size_t)(bl * 4 + 1) * NV + id] * x1;
-      y1 -= J[(size_t)(bl * 4 + 2) * NV + id] * x0 + J[(size_t)(bl * 4 + 3) * NV + id] * x1;
-    }
+    for (int e = 0; e < 4; ++e) jb[bl][e] = J[jo + (size_t)e * NV];
+  }
+#pragma unroll
+  for (int bl = 0; bl < 9; ++bl) {
+    const T a0 = jb[bl][0] * xa[bl] + jb[bl][1] * xb[bl], a1 = jb[bl][2] * xa[bl] + jb[bl][3] * xb[bl];
+    y0 -= use[bl] ? a0 : (T)0;
+    y1 -= use[bl] ? a1 : (T)0;
+  }
   r[id] = y0;
   r[NV + id] = y1;
 }
