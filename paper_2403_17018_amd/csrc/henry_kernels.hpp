@@ -422,30 +422,45 @@ __global__ void __launch_bounds__(1024) k_assemble(Map m, Grid2 G, Phys P, const
 template <typename T, typename TA, bool TR, int SP = 1, typename XV>
 __device__ __forceinline__ void apply_row_f(const T* __restrict__ J, XV&& xv, size_t N, size_t id, int i, int j,
                                             int nx, int ny, int S, TA& y0, TA& y1, bool skip_centre) {
-  TA a0 = 0, a1 = 0;
-  auto acc = [&](int slot, size_t q, size_t xq, int dir) {
-    TA x0, x1;
-    xv(xq, dir, x0, x1);
-    // each Jacobian entry is read once per kernel: non-temporal loads keep the cache for
-    // the neighbours' x, which other threads read again
-    const TA b0 = ldv_nt<SP, TA>(J + (slot * 4 + 0) * N + q);
-    const TA b1 = ldv_nt<SP, TA>(J + (slot * 4 + 1) * N + q);
-    const TA b2 = ldv_nt<SP, TA>(J + (slot * 4 + 2) * N + q);
-    const TA b3 = ldv_nt<SP, TA>(J + (slot * 4 + 3) * N + q);
-    if (TR) {
-      a0 += b0 * x0 + b2 * x1;
-      a1 += b1 * x0 + b3 * x1;
-    } else {
-      a0 += b0 * x0 + b1 * x1;
-      a1 += b2 * x0 + b3 * x1;
-    }
-  };
-  if (!skip_centre) acc(0, id, id, 0);
+  // All blocks' loads are issued before any is used: a neighbour outside the grid reads the
+  // cell's own x (dir 0) and centre block instead, valid addresses the cell reads anyway, and
+  // its term is selected away (a select, so whatever those values hold cannot leak in).
+  // Each Jacobian entry is read once per kernel: non-temporal loads keep the cache for the
+  // neighbours' x, which other threads read again.
   const size_t row = (size_t)nx * S;
-  if (i > 0) acc(TR ? 2 : 1, TR ? id - S : id, id - S, 1);
-  if (i < nx - 1) acc(TR ? 1 : 2, TR ? id + S : id, id + S, 2);
-  if (j > 0) acc(TR ? 4 : 3, TR ? id - row : id, id - row, 3);
-  if (j < ny - 1) acc(TR ? 3 : 4, TR ? id + row : id, id + row, 4);
+  const bool ok[4] = {i > 0, i < nx - 1, j > 0, j < ny - 1};
+  TA xa[5], xb[5], jb[5][4];
+#pragma unroll
+  for (int n = 0; n < 5; ++n) {
+    if (n == 0 && skip_centre) continue;
+    const bool on = n == 0 || ok[n - 1];
+    const long long d = n == 1 ? -(long long)S : n == 2 ? (long long)S : n == 3 ? -(long long)row : (long long)row;
+    const size_t xq = (n == 0 || !on) ? id : id + d;
+    // slot of the block: P's own row (W 1, E 2, S 3, N 4), or, transposed, the neighbour's
+    // row at the mirrored slot
+    const int slot = n == 0 ? 0 : TR ? (n == 1 ? 2 : n == 2 ? 1 : n == 3 ? 4 : 3) : n;
+    const size_t q = (TR && on) ? xq : id;
+    const size_t jo = (size_t)(on ? slot : 0) * 4 * N + q;
+    xv(xq, on ? n : 0, xa[n], xb[n]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) jb[n][e] = ldv_nt<SP, TA>(J + jo + (size_t)e * N);
+  }
+  TA a0 = 0, a1 = 0;
+#pragma unroll
+  for (int n = 0; n < 5; ++n) {
+    if (n == 0 && skip_centre) continue;
+    const bool on = n == 0 || ok[n - 1];
+    TA t0, t1;
+    if (TR) {
+      t0 = jb[n][0] * xa[n] + jb[n][2] * xb[n];
+      t1 = jb[n][1] * xa[n] + jb[n][3] * xb[n];
+    } else {
+      t0 = jb[n][0] * xa[n] + jb[n][1] * xb[n];
+      t1 = jb[n][2] * xa[n] + jb[n][3] * xb[n];
+    }
+    a0 += on ? t0 : (TA)0;
+    a1 += on ? t1 : (TA)0;
+  }
   y0 = a0;
   y1 = a1;
 }
