@@ -272,6 +272,11 @@ __global__ void __launch_bounds__(1024) k_assemble(Map m, Grid2 G, Phys P, const
   const bool inside = sv && i < G.nx && j < G.ny;
   auto slot = [&](int f, int q) -> double& { return asm_sh[((size_t)f * (ASM_T + ASM_H) + q) * SX + tx]; };
   const size_t id = ((size_t)j * G.nx + i) * S + s;
+  // the cell's own old concentration and its sample's inflow are loaded here, beside the
+  // tile's staging loads: issued later, their waits would also wait for every Jacobian store
+  // issued before them
+  const double co = (WRITE_R && inside) ? c_old[id] : 0.0;
+  const double u_in = (inside && i == 0) ? uin[s] : 0.0;
   if (inside) {
     slot(0, ty) = p[id];
     slot(1, ty) = c[id];
@@ -326,7 +331,6 @@ __global__ void __launch_bounds__(1024) k_assemble(Map m, Grid2 G, Phys P, const
     }
   };
   if (WRITE_R) {
-    const double co = c_old[id];
     const double ro = P.rho0 + P.drho * co;
     Rp = P.vol * phP * (rP - ro) / P.tau;
     Rc = P.vol * phP * (rP * cP - ro * co) / P.tau;
@@ -376,7 +380,7 @@ __global__ void __launch_bounds__(1024) k_assemble(Map m, Grid2 G, Phys P, const
   const double wb = P.hy / P.hx;
   // left boundary: prescribed inflow at c_left, diffusive Dirichlet c_left
   if (i == 0) {
-    const double F = -(P.rho0 + P.drho * P.c_left) * uin[s] * P.uin_fac * P.hy;
+    const double F = -(P.rho0 + P.drho * P.c_left) * u_in * P.uin_fac * P.hy;
     Rp += F;
     Rc += F * P.c_left + 2.0 * rP * phP * P.Dm * (cP - P.c_left) * wb;
     D[3] += 2.0 * phP * P.Dm * wb * (P.drho * (cP - P.c_left) + rP);
