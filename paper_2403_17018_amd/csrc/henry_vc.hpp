@@ -121,6 +121,22 @@ __global__ void __launch_bounds__(256) k_vc_assemble(Map m, Grid2 E, Phys P, con
         pn[dj + 1][di + 1] = in ? p[q] : 0.0;
         cn[dj + 1][di + 1] = in ? c[q] : 0.0;
       }
+    // every load of the vertex is issued here, before any arithmetic: the four elements'
+    // phi and K (an element outside the grid reads element 0 of the sample and is skipped
+    // below), the old concentration and the sample's inflow.  Issued where they are used,
+    // each would be a separate trip to memory, and at two wavefronts per SIMD little of
+    // that latency is hidden.
+    double phi_e[4], K_e[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int xi = i + (t & 1) - 1, xj = j + (t >> 1) - 1;
+      const bool ok = xi >= 0 && xi < E.nx && xj >= 0 && xj < E.ny;
+      const size_t e = ok ? ((size_t)xj * E.nx + xi) * S + s : (size_t)s;
+      phi_e[t] = phi[e];
+      K_e[t] = K[e];
+    }
+    const double co = c_old[id];
+    const double u_in = uin[s];
     double box = 0.0;
 #pragma unroll
     for (int ej = -1; ej <= 0; ++ej)
@@ -128,8 +144,8 @@ __global__ void __launch_bounds__(256) k_vc_assemble(Map m, Grid2 E, Phys P, con
       for (int ei = -1; ei <= 0; ++ei) {
         const int xi = i + ei, xj = j + ej;
         if (xi < 0 || xi >= E.nx || xj < 0 || xj >= E.ny) continue;
-        const size_t e = ((size_t)xj * E.nx + xi) * S + s;
-        const double phie = phi[e], Ke = K[e];
+        const int t = (ej + 1) * 2 + (ei + 1);
+        const double phie = phi_e[t], Ke = K_e[t];
         box += 0.25 * P.hx * P.hy * phie;
         const int kv = ei == 0 ? (ej == 0 ? 0 : 3) : (ej == 0 ? 1 : 2);   // local index of v
         double pk[4], ck[4];
@@ -167,14 +183,14 @@ __global__ void __launch_bounds__(256) k_vc_assemble(Map m, Grid2 E, Phys P, con
           }
         }
       }
-    const double cv = c[id], co = c_old[id];
+    const double cv = cn[1][1];
     Rp += box * (P.drho * (cv - co)) / P.tau;
     Rc += box * ((P.rho0 + P.drho * cv) * cv - (P.rho0 + P.drho * co) * co) / P.tau;
     Jb[17] += box * P.drho / P.tau;
     Jb[19] += box * (P.rho0 + 2.0 * P.drho * cv) / P.tau;
     if (i == 0) {   // inflow side: mass flux rho(c_left) u_in enters; c = c_left
       const double len = (j == 0 || j == E.ny) ? 0.5 * P.hy : P.hy;
-      Rp -= (P.rho0 + P.drho * P.c_left) * uin[s] * P.uin_fac * len;
+      Rp -= (P.rho0 + P.drho * P.c_left) * u_in * P.uin_fac * len;
       Rc = cv - P.c_left;
 #pragma unroll
       for (int bl = 0; bl < VC_BLK; ++bl) {
